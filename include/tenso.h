@@ -1,0 +1,194 @@
+/*
+ * tenso.h -- C ABI of the MI355X TTN-HEOM propagation library.
+ *
+ * The library applies a sum-of-products (SOP) generator L(t) to an extended
+ * density operator Omega stored as a tree tensor network (TTN) and advances
+ * dOmega/dt = L(t) Omega (paper Sec. II B-C: Eqs. heom-std, EDO-eom,
+ * master_lvn, omega_tensor, semiunitary) with the fixed-rank (ps1) and
+ * adaptive-rank (ps2) projector-splitting integrators (Sec. II C).
+ *
+ * Conventions shared by every entry point
+ *   - Every call returns 0 on success or a negative TENSO_E* code; the
+ *     message of the last failure on the calling thread is returned by
+ *     tenso_last_error().  No exception crosses this boundary.
+ *   - Host arrays passed in are copied during the call; the caller keeps
+ *     ownership.  Handles are owned by the library and released with the
+ *     matching *_destroy call.  A handle must not be used from two threads
+ *     at the same time.
+ *   - Device buffers (state, workspace, drive tables) are allocated by the
+ *     caller and passed as raw device pointers together with a hipStream_t;
+ *     their sizes come from tenso_plan_sizes().  The library allocates device
+ *     memory only inside tenso_plan_create / batch creation (constant tables)
+ *     and never afterwards.
+ *   - Complex numbers are interleaved {double re, double im} on the host.
+ *     The device state layout is private to the library; convert with
+ *     tenso_state_import / tenso_state_export.
+ *
+ * Tree description (Sec. II C, general TTN equation)
+ *   Nodes are numbered 0..n_nodes-1; node 0 is the root and parent[s] < s.
+ *   Ends (open legs) are numbered 0 = ket (dim M), 1 = bra (dim M),
+ *   2 + k = bath feature k (dim N_k); both system ends sit on the root.
+ *   The legs of node s are, in order: its bond to parent[s] (if s > 0), the
+ *   ends attached to s in increasing end index, its child nodes in increasing
+ *   node id.  Core s is stored row-major over its legs.  The bond between
+ *   node c and parent[c] has rank r_c; ranks are clamped so that every core
+ *   can be semi-unitary (r_c <= product of c's other leg dims and <= product
+ *   of parent[c]'s other leg dims).
+ */
+#ifndef TENSO_H
+#define TENSO_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TENSO_OK            0
+#define TENSO_EINVAL       -1   /* malformed input (tree, dims, sizes, dt <= 0) */
+#define TENSO_ENOMEM       -2   /* workspace too small / size beyond the budget */
+#define TENSO_EHIP         -3   /* a HIP runtime error (message carries hipGetErrorString) */
+#define TENSO_ENUMERIC     -4   /* NaN/Inf or norm blow-up detected */
+#define TENSO_EUNSUPPORTED -5   /* valid input outside what this build implements */
+
+typedef struct { double re, im; } tenso_c128;
+typedef struct tenso_tree tenso_tree;
+typedef struct tenso_gen tenso_gen;
+typedef struct tenso_plan tenso_plan;
+typedef struct tenso_batch tenso_batch;
+
+#define TENSO_FP64 0          /* every contraction in complex FP64 (plain reference path) */
+#define TENSO_FP32 1          /* contractions in complex FP32 on MFMA, FP64 master state */
+
+#define TENSO_PS1 0           /* fixed-rank projector splitting */
+#define TENSO_PS2 1           /* adaptive-rank projector splitting */
+
+typedef struct {
+  int precision;   /* TENSO_FP64 | TENSO_FP32 */
+  int method;      /* TENSO_PS1 | TENSO_PS2 */
+  int max_rank;    /* PS2: cap on any bond rank (also sizes the state) */
+} tenso_plan_opts;
+
+/* Last error message of the calling thread ("" if none). */
+const char* tenso_last_error(void);
+
+/* Build a tree from a parent array and an end map (general TTN, Sec. II C).
+ * parent[0] = -1 and 0 <= parent[s] < s.  end_node[e] / end_dim[e] give the
+ * node and dimension of end e (ends 0 and 1 must sit on node 0).  bond_rank
+ * (nullable, indexed by child node, entry 0 ignored) requests per-bond ranks,
+ * otherwise max_rank is requested everywhere; both are clamped (see above).
+ * Errors: EINVAL on a malformed tree or dims < 1. */
+int tenso_build_tree(int n_nodes, const int32_t* parent, int n_ends,
+                     const int32_t* end_node, const int32_t* end_dim,
+                     int max_rank, const int32_t* bond_rank, tenso_tree** out);
+
+/* Tensor train (Eq. omega_tensor): root(ket, bra, ->1); node s holds feature
+ * s-1 and a bond to s+1; the last node holds the last two features. */
+int tenso_tree_train(int M, int K, const int32_t* mode_dim, int rank, tenso_tree** out);
+
+/* Balanced n-ary tree: root(ket, bra, ->tree over all features); a list of
+ * features becomes an end if it has one element, a node holding them if it has
+ * at most n_ary, else a node over n_ary contiguous near-equal chunks (larger
+ * first).  Nodes are numbered in preorder. */
+int tenso_tree_nary(int M, int K, const int32_t* mode_dim, int n_ary, int rank,
+                    tenso_tree** out);
+
+/* Effective bond ranks after clamping: bond_rank_out[c] for c = 1..n-1
+ * (entry 0 is set to 0).  Array length n_nodes. */
+int tenso_tree_ranks(const tenso_tree* t, int32_t* bond_rank_out);
+int tenso_tree_n_nodes(const tenso_tree* t);
+void tenso_tree_destroy(tenso_tree* t);
+
+/* SOP generator (Eq. master_lvn, the paper's SparseSPO): term m is
+ * coef[m] * f_slot(t) * (x)_{factors} F, where f_slot = 1 if td_slot[m] < 0.
+ * Factor j of term m (in order, n_factors[m] of them) acts on end
+ * factor_end[.] with a dense row-major d x d matrix taken consecutively from
+ * factor_mats; ends without a factor carry the identity.  Each term needs at
+ * least one factor, and at most two legs of any core may carry a non-identity
+ * operator for one term (EUNSUPPORTED otherwise; HEOM terms have <= 2
+ * factors).  Errors: EINVAL on bad ends / dims. */
+int tenso_build_generator(const tenso_tree* t, int n_terms, const tenso_c128* coef,
+                          const int32_t* td_slot, const int32_t* n_factors,
+                          const int32_t* factor_end, const tenso_c128* factor_mats,
+                          tenso_gen** out);
+void tenso_gen_destroy(tenso_gen* g);
+
+/* Compile tree + generator into an execution plan (tables uploaded to the
+ * current HIP device).  The plan keeps its own copies of tree and generator. */
+int tenso_plan_create(const tenso_tree* t, const tenso_gen* g, const tenso_plan_opts* opts,
+                      tenso_plan** out);
+void tenso_plan_destroy(tenso_plan* p);
+
+/* Device bytes the caller must provide: the state (FP64 master cores) and the
+ * workspace (operand copies, environments, stage buffers, QR scratch). */
+int tenso_plan_sizes(const tenso_plan* p, size_t* state_bytes, size_t* workspace_bytes);
+
+/* Number of cores and, per core, its current leg dimensions (up to 8 legs,
+ * dims_out[8*s + l], unused entries 0).  Host call, no device work. */
+int tenso_plan_shapes(const tenso_plan* p, int32_t* n_legs_out, int32_t* dims_out);
+
+/* Write the initial product state rho_S(0) (x) |0..0> (host M x M rho_s) into
+ * d_state: root[i, j, 0..] = rho[i, j]; other cores U[a, beta] =
+ * delta(a, flat(beta)).  PS2 plans start at rank 1 on every bond. */
+int tenso_state_init(tenso_plan* p, const tenso_c128* rho_s, void* d_state, hipStream_t s);
+
+/* Copy host cores (concatenated, each row-major over its legs at the plan's
+ * current ranks) to the device state, and back.  ranks (nullable) receives
+ * the current bond ranks (length n_nodes).  Export synchronises the stream. */
+int tenso_state_import(tenso_plan* p, const tenso_c128* h_cores, void* d_state, hipStream_t s);
+int tenso_state_export(tenso_plan* p, const void* d_state, tenso_c128* h_cores, int32_t* ranks,
+                       hipStream_t s);
+
+/* Effective generator at `center` (Sec. II C): d_out (complex FP64, the
+ * center core's shape, row-major) = sum_m coef_m(t) (x)_legs X_{m,l} C_center,
+ * with up/down environments on virtual legs, factors on ends and identities
+ * skipped.  The state must be canonical toward `center` (every other core an
+ * isometry toward it).  drive: host array of one value per slot (nullable if
+ * the generator has no slots).  Synchronous on `s` for the result. */
+int tenso_apply_generator(tenso_plan* p, const void* d_state, int center, double t,
+                          const double* drive, void* d_out, void* d_ws, hipStream_t s);
+
+/* Advance n_steps steps of size dt with ps1 (second-order: a first-order
+ * sweep over half a step, then its adjoint).  d_drive_tab (nullable when the
+ * generator has no slots) holds f_slot at t0 + j*dt/4, j = 0..4*n_steps,
+ * as [n_slots][4*n_steps+1] doubles on the device.  The state stays canonical
+ * toward the root.  Asynchronous on `s`. */
+int tenso_step_fixed(tenso_plan* p, void* d_state, double t0, double dt, int n_steps,
+                     const double* d_drive_tab, void* d_ws, hipStream_t s);
+
+/* Same with ps2 (two-site sweeps, SVD truncation: keep the smallest r' with
+ * tail norm <= eps * total norm, 1 <= r' <= max_rank).  Synchronises the
+ * stream (ranks are decided on the host from device singular values). */
+int tenso_step_adaptive(tenso_plan* p, void* d_state, double t0, double dt, int n_steps,
+                        double eps, int max_rank, const double* d_drive_tab, void* d_ws,
+                        hipStream_t s);
+
+/* Reduced density matrix rho_S = <0..0|Omega> (Sec. II B) into host h_rho
+ * (M x M) and its trace into h_trace (nullable).  Synchronises the stream. */
+int tenso_reduced_rho(tenso_plan* p, const void* d_state, tenso_c128* h_rho, double* h_trace,
+                      void* d_ws, hipStream_t s);
+
+/* Bond ranks chosen by the last ps2 step, one entry per split in sweep order;
+ * returns the number of entries (at most cap) or a negative error. */
+int tenso_rank_trajectory(const tenso_plan* p, int32_t* h_ranks, int cap);
+
+/* ---- batched fixed-rank propagation --------------------------------------
+ * Many independent ps1 plans (uneven trees, ranks, dims) advance together:
+ * one launch per phase serves every instance, and the whole step sequence is
+ * captured into a HIP graph and replayed.  All plans must share a precision.
+ * d_states[i] / d_wss[i] are each instance's own buffers (sizes from
+ * tenso_plan_sizes); t0[i], dt[i] host arrays; d_drive_tabs nullable. */
+int tenso_batch_create(int n, tenso_plan* const* plans, void* const* d_states,
+                       void* const* d_wss, tenso_batch** out);
+int tenso_batch_step(tenso_batch* b, const double* t0, const double* dt, int n_steps,
+                     const double* const* d_drive_tabs, hipStream_t s);
+/* rho_S of every instance: h_rho[i] points to an M_i x M_i host array. */
+int tenso_batch_reduced_rho(tenso_batch* b, tenso_c128* const* h_rho, hipStream_t s);
+void tenso_batch_destroy(tenso_batch* b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

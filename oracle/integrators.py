@@ -16,8 +16,10 @@ Readings (documented):
   forward flows use +L_eff, backward (bond / ps2 node) flows use -L_eff.
 * Second order: a first-order sweep over [t0, t0+dt/2] followed by its adjoint
   (the same sub-flows in reverse order) over [t0+dt/2, t0+dt].
-* Gauge moves: Householder QR (LAPACK convention) with the phases of diag(R)
-  made non-negative.  When a matricisation has fewer rows than the bond
+* Gauge moves: Householder QR (LAPACK reflector convention) with the phases
+  of diag(R) made non-negative; residual columns below 1e-10 of the matrix
+  norm are treated as exact zeros, which fixes the orthonormal completion of
+  rank-deficient cores (the truncated-rank result depends on it).  When a matricisation has fewer rows than the bond
   dimension the QR move lowers the bond dimension to the row count (exact).
 * ps2 truncation: keep the smallest r' with
   sqrt(sum_{i>=r'} s_i^2) <= eps * sqrt(sum s_i^2), then 1 <= r' <= max_rank;
@@ -44,15 +46,70 @@ def rk4(F, y, t0, tau):
     return y + (tau / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
 
 
+QR_RANK_TOL = 1e-10
+
+
+def householder_qr(A, tol=QR_RANK_TOL):
+    """Householder QR A = Q R (Q: m x k, R: k x n, k = min(m, n)) with LAPACK's
+    reflector convention (zgeqr2 / zung2r: beta = -sign(Re alpha) * norm,
+    tau = 0 when nothing is left to reflect).
+
+    Rank-deficiency rule (reading): a column whose residual after the previous
+    reflections has norm <= tol * ||A||_F is set to exactly zero and gets the
+    identity reflector, so the orthonormal completion of a rank-deficient
+    matrix is fixed by the well-determined columns alone rather than by
+    rounding noise (projector splitting at truncated rank depends on it)."""
+    A = np.array(A, dtype=np.complex128)
+    m, n = A.shape
+    k = min(m, n)
+    thr2 = (tol * np.linalg.norm(A)) ** 2
+    taus = np.zeros(k, dtype=np.complex128)
+    vs = []
+    for j in range(k):
+        x = A[j:, j]
+        alpha = x[0]
+        xn2 = float(np.sum(np.abs(x[1:]) ** 2))
+        if abs(alpha) ** 2 + xn2 <= thr2:
+            A[j:, j] = 0.0
+            vs.append(np.zeros(m - j, dtype=np.complex128))
+            continue
+        if xn2 == 0.0 and alpha.imag == 0.0:
+            vs.append(np.zeros(m - j, dtype=np.complex128))
+            continue
+        nrm = np.sqrt(abs(alpha) ** 2 + xn2)
+        beta = -nrm if alpha.real >= 0.0 else nrm
+        tau = complex((beta - alpha.real) / beta, -alpha.imag / beta)
+        v = np.empty(m - j, dtype=np.complex128)
+        v[0] = 1.0
+        v[1:] = x[1:] / (alpha - beta)
+        taus[j] = tau
+        vs.append(v)
+        A[j, j] = beta
+        A[j + 1:, j] = 0.0
+        if j + 1 < n:
+            w = v.conj() @ A[j:, j + 1:]
+            A[j:, j + 1:] -= np.conj(tau) * np.outer(v, w)
+    R = np.triu(A[:k, :])
+    Q = np.zeros((m, k), dtype=np.complex128)
+    Q[np.arange(k), np.arange(k)] = 1.0
+    for j in reversed(range(k)):
+        if taus[j] != 0:
+            v = vs[j]
+            w = v.conj() @ Q[j:, :]
+            Q[j:, :] -= taus[j] * np.outer(v, w)
+    return Q, R
+
+
 def qr_toward(C, leg):
     """Factor C = Q x_leg R: C[.., a, ..] = sum_b Q[.., b, ..] R[b, a].
 
     Q is an isometry in `leg` (its rows along `leg` are orthonormal over the
-    other legs).  Rows of the matricisation are the other legs in leg order."""
+    other legs).  Rows of the matricisation are the other legs in leg order;
+    the phases of diag(R) are made non-negative (zero diagonals keep theirs)."""
     Cm = np.moveaxis(C, leg, -1)
     shp = Cm.shape
     mat = Cm.reshape(-1, shp[-1])
-    Q, R = np.linalg.qr(mat)  # LAPACK Householder
+    Q, R = householder_qr(mat)
     d = np.diag(R).copy()
     ph = np.ones_like(d)
     nz = np.abs(d) > 0

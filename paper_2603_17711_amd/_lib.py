@@ -1,0 +1,86 @@
+"""ctypes binding of include/tenso.h (argument marshalling only)."""
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtenso.so")
+
+
+class TensoError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"tenso error {code}: {msg}")
+        self.code = code
+
+
+class c128(C.Structure):
+    _fields_ = [("re", C.c_double), ("im", C.c_double)]
+
+
+class PlanOpts(C.Structure):
+    _fields_ = [("precision", C.c_int), ("method", C.c_int), ("max_rank", C.c_int)]
+
+
+FP64, FP32 = 0, 1
+PS1, PS2 = 0, 1
+ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENUMERIC", -5: "EUNSUPPORTED"}
+
+_lib = None
+
+P = C.c_void_p
+I32P = C.POINTER(C.c_int32)
+DP = C.POINTER(C.c_double)
+C128P = C.POINTER(c128)
+SIGS = {
+    "tenso_last_error": (C.c_char_p, []),
+    "tenso_build_tree": (C.c_int, [C.c_int, I32P, C.c_int, I32P, I32P, C.c_int, I32P, C.POINTER(P)]),
+    "tenso_tree_train": (C.c_int, [C.c_int, C.c_int, I32P, C.c_int, C.POINTER(P)]),
+    "tenso_tree_nary": (C.c_int, [C.c_int, C.c_int, I32P, C.c_int, C.c_int, C.POINTER(P)]),
+    "tenso_tree_ranks": (C.c_int, [P, I32P]),
+    "tenso_tree_n_nodes": (C.c_int, [P]),
+    "tenso_tree_destroy": (None, [P]),
+    "tenso_build_generator": (C.c_int, [P, C.c_int, C128P, I32P, I32P, I32P, C128P, C.POINTER(P)]),
+    "tenso_gen_destroy": (None, [P]),
+    "tenso_plan_create": (C.c_int, [P, P, C.POINTER(PlanOpts), C.POINTER(P)]),
+    "tenso_plan_destroy": (None, [P]),
+    "tenso_plan_sizes": (C.c_int, [P, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
+    "tenso_plan_shapes": (C.c_int, [P, I32P, I32P]),
+    "tenso_state_init": (C.c_int, [P, C128P, P, P]),
+    "tenso_state_import": (C.c_int, [P, C128P, P, P]),
+    "tenso_state_export": (C.c_int, [P, P, C128P, I32P, P]),
+    "tenso_apply_generator": (C.c_int, [P, P, C.c_int, C.c_double, DP, P, P, P]),
+    "tenso_step_fixed": (C.c_int, [P, P, C.c_double, C.c_double, C.c_int, P, P, P]),
+    "tenso_step_adaptive": (C.c_int, [P, P, C.c_double, C.c_double, C.c_int, C.c_double, C.c_int,
+                                      P, P, P]),
+    "tenso_reduced_rho": (C.c_int, [P, P, C128P, DP, P, P]),
+    "tenso_rank_trajectory": (C.c_int, [P, I32P, C.c_int]),
+    "tenso_batch_create": (C.c_int, [C.c_int, C.POINTER(P), C.POINTER(P), C.POINTER(P), C.POINTER(P)]),
+    "tenso_batch_step": (C.c_int, [P, DP, DP, C.c_int, C.POINTER(P), P]),
+    "tenso_batch_reduced_rho": (C.c_int, [P, C.POINTER(C128P), P]),
+    "tenso_batch_destroy": (None, [P]),
+}
+
+
+def lib():
+    """Load libtenso.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                               "(run __graft_entry__.build())")
+        # The library must share torch's HIP runtime (same SONAME): load torch's
+        # runtime into the process first so the dynamic linker reuses it.
+        import torch  # noqa: F401
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(code):
+    if code is not None and code < 0:
+        msg = lib().tenso_last_error().decode()
+        raise TensoError(f"{ERRORS.get(code, code)}", msg)
+    return code

@@ -1,0 +1,201 @@
+"""Thin Python layer over the C ABI: trees, generators, plans and device buffers.
+
+Device memory and streams come from PyTorch (torch.empty on the current HIP
+device, torch.cuda.current_stream()); every step of the computation runs in
+libtenso.so.
+"""
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import FP32, FP64, PS1, PS2, PlanOpts, c128, check, lib
+from .heom import heom_table
+
+
+def _i32(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _c128(a):
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    return a, a.ctypes.data_as(C.POINTER(c128))
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Tree:
+    def __init__(self, handle):
+        self.h = handle
+
+    @classmethod
+    def train(cls, M, dims, rank):
+        d, dp = _i32(dims)
+        h = C.c_void_p()
+        check(lib().tenso_tree_train(M, len(dims), dp, rank, C.byref(h)))
+        return cls(h)
+
+    @classmethod
+    def nary(cls, M, dims, n_ary, rank):
+        d, dp = _i32(dims)
+        h = C.c_void_p()
+        check(lib().tenso_tree_nary(M, len(dims), dp, n_ary, rank, C.byref(h)))
+        return cls(h)
+
+    @classmethod
+    def from_parents(cls, parent, end_node, end_dim, max_rank, bond_rank=None):
+        p, pp = _i32(parent)
+        e, ep = _i32(end_node)
+        d, dp = _i32(end_dim)
+        br = None
+        if bond_rank is not None:
+            b, br = _i32(bond_rank)
+        h = C.c_void_p()
+        check(lib().tenso_build_tree(len(parent), pp, len(end_node), ep, dp, max_rank, br,
+                                     C.byref(h)))
+        return cls(h)
+
+    @property
+    def n_nodes(self):
+        return check(lib().tenso_tree_n_nodes(self.h))
+
+    def ranks(self):
+        out = np.zeros(self.n_nodes, np.int32)
+        check(lib().tenso_tree_ranks(self.h, out.ctypes.data_as(C.POINTER(C.c_int32))))
+        return out
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib._lib is not None:
+            lib().tenso_tree_destroy(self.h)
+            self.h = None
+
+
+class Generator:
+    def __init__(self, tree, table):
+        coef, slot, nfac, fend, mats = table.arrays()
+        self._keep = (coef, slot, nfac, fend, mats)
+        h = C.c_void_p()
+        check(lib().tenso_build_generator(
+            tree.h, len(coef), coef.ctypes.data_as(C.POINTER(c128)),
+            slot.ctypes.data_as(C.POINTER(C.c_int32)), nfac.ctypes.data_as(C.POINTER(C.c_int32)),
+            fend.ctypes.data_as(C.POINTER(C.c_int32)), mats.ctypes.data_as(C.POINTER(c128)),
+            C.byref(h)))
+        self.h = h
+        self.n_slots = int(slot.max() + 1) if len(slot) and slot.max() >= 0 else 0
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib._lib is not None:
+            lib().tenso_gen_destroy(self.h)
+            self.h = None
+
+
+class Plan:
+    """A compiled propagation problem with its device state and workspace."""
+
+    def __init__(self, tree, gen, precision=FP32, method=PS1, max_rank=0, device="cuda"):
+        import torch
+        # torch owns the device: initialise it before the library's first HIP call
+        torch.cuda.init()
+        torch.zeros(1, device=device)
+        self.tree, self.gen = tree, gen
+        opts = PlanOpts(precision, method, max_rank)
+        h = C.c_void_p()
+        check(lib().tenso_plan_create(tree.h, gen.h, C.byref(opts), C.byref(h)))
+        self.h = h
+        sb, wb = C.c_size_t(), C.c_size_t()
+        check(lib().tenso_plan_sizes(h, C.byref(sb), C.byref(wb)))
+        self.state = torch.zeros(int(sb.value), dtype=torch.uint8, device=device)
+        self.ws = torch.zeros(int(wb.value), dtype=torch.uint8, device=device)
+        self.n_nodes = tree.n_nodes
+        self.M = None
+
+    def shapes(self):
+        nl = np.zeros(self.n_nodes, np.int32)
+        dims = np.zeros(8 * self.n_nodes, np.int32)
+        check(lib().tenso_plan_shapes(self.h, nl.ctypes.data_as(C.POINTER(C.c_int32)),
+                                      dims.ctypes.data_as(C.POINTER(C.c_int32))))
+        return [tuple(int(x) for x in dims[8 * s:8 * s + nl[s]]) for s in range(self.n_nodes)]
+
+    def init_state(self, rho0):
+        r, rp = _c128(rho0)
+        self.M = r.shape[0]
+        check(lib().tenso_state_init(self.h, rp, C.c_void_p(self.state.data_ptr()), _stream()))
+
+    def import_state(self, cores):
+        flat, fp = _c128(np.concatenate([np.asarray(c).reshape(-1) for c in cores]))
+        check(lib().tenso_state_import(self.h, fp, C.c_void_p(self.state.data_ptr()), _stream()))
+
+    def export_state(self):
+        shapes = self.shapes()
+        n = sum(int(np.prod(s)) for s in shapes)
+        out = np.zeros(n, np.complex128)
+        check(lib().tenso_state_export(self.h, C.c_void_p(self.state.data_ptr()),
+                                       out.ctypes.data_as(C.POINTER(c128)), None, _stream()))
+        cores, o = [], 0
+        for s in shapes:
+            k = int(np.prod(s))
+            cores.append(out[o:o + k].reshape(s).copy())
+            o += k
+        return cores
+
+    def apply(self, center, t=0.0, drive=None):
+        import torch
+        shape = self.shapes()[center]
+        out = torch.zeros(int(np.prod(shape)) * 2, dtype=torch.float64, device=self.state.device)
+        dv = None
+        if drive is not None:
+            d = np.ascontiguousarray(drive, dtype=np.float64)
+            dv = d.ctypes.data_as(C.POINTER(C.c_double))
+        check(lib().tenso_apply_generator(self.h, C.c_void_p(self.state.data_ptr()), center, t, dv,
+                                          C.c_void_p(out.data_ptr()),
+                                          C.c_void_p(self.ws.data_ptr()), _stream()))
+        o = out.cpu().numpy()
+        return (o[0::2] + 1j * o[1::2]).reshape(shape)
+
+    def step(self, n_steps, dt, t0=0.0, drive_tab=None):
+        ptr = C.c_void_p(drive_tab.data_ptr()) if drive_tab is not None else None
+        check(lib().tenso_step_fixed(self.h, C.c_void_p(self.state.data_ptr()), t0, dt, n_steps,
+                                     ptr, C.c_void_p(self.ws.data_ptr()), _stream()))
+
+    def rho(self):
+        M = self.M
+        out = np.zeros((M, M), np.complex128)
+        tr = C.c_double()
+        check(lib().tenso_reduced_rho(self.h, C.c_void_p(self.state.data_ptr()),
+                                      out.ctypes.data_as(C.POINTER(c128)), C.byref(tr),
+                                      C.c_void_p(self.ws.data_ptr()), _stream()))
+        return out
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib._lib is not None:
+            lib().tenso_plan_destroy(self.h)
+            self.h = None
+
+
+def build_instance(inst, precision=FP32, rank=None, device="cuda"):
+    """Tree + generator + plan for a workloads.Instance (ps1)."""
+    drive_ops = [] if inst.drive is None else [inst.drive[0]]
+    table, dims = heom_table(inst.H, inst.baths, inst.depth, drive_ops)
+    R = inst.rank if rank is None else rank
+    if inst.tree == "train":
+        tree = Tree.train(inst.M, dims, R)
+    else:
+        tree = Tree.nary(inst.M, dims, int(inst.tree[4:]), R)
+    gen = Generator(tree, table)
+    plan = Plan(tree, gen, precision=precision, method=PS1, device=device)
+    plan.init_state(inst.rho0)
+    return plan
+
+
+def drive_table(inst, n_steps, t0=0.0, device="cuda"):
+    """f(t0 + j dt/4), j = 0..4 n_steps, as a [1, 4n+1] device tensor (None if undriven)."""
+    import torch
+    if inst.drive is None:
+        return None
+    ts = t0 + np.arange(4 * n_steps + 1) * (inst.dt / 4.0)
+    vals = np.array([inst.drive_value(t) for t in ts], dtype=np.float64)
+    return torch.tensor(vals.reshape(1, -1), dtype=torch.float64, device=device)

@@ -1,0 +1,719 @@
+// HIP kernels for CDNA4 (gfx950) of the TTN-HEOM propagation library.
+//
+// apply  : Y_f += sum_m coef_m(t) A_m X_f B_m^T over the free index f of a
+//          core viewed as [P0, d1, P1, d2, P2] (effective generator of the SOP
+//          form, paper Eq. master_lvn, contracted at one node / bond / edge),
+//          complex real-split on 16x16x4 MFMA (FP32 or FP64), one wavefront per
+//          (f, 16-column block) unit, intermediate X_f B^T staged in LDS.
+// presum : weighted sums of matrices (single-leg terms summed once per stage).
+// combine: RK4 stage bookkeeping into the FP64 master state.
+// qr     : Householder QR in FP64 (gauge moves of the projector splitting).
+// absorb : in-place FP64 mode product of a bond matrix into a core.
+// gram   : environment finalisation E = conj(C)_(open) T_(open)^T.
+// rho    : bottom-up vacuum contraction for rho_S = <0|Omega>.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include "tenso_internal.h"
+
+namespace tenso {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <typename T> struct MT;
+template <> struct MT<float> {
+  typedef v4f v4;
+  static constexpr int NT = 8;  // accumulator tiles per wavefront
+  __device__ static inline v4 mma(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // row of accumulator register r in lane group g (measured on gfx950)
+  __device__ static inline int drow(int g, int r) { return 4 * g + r; }
+};
+template <> struct MT<double> {
+  typedef v4d v4;
+  static constexpr int NT = 4;
+  __device__ static inline v4 mma(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // the FP64 variant interleaves rows across lane groups (measured on gfx950)
+  __device__ static inline int drow(int g, int r) { return g + 4 * r; }
+};
+
+template <typename T> struct cpx { T re, im; };
+
+template <typename Tin, typename T>
+__device__ inline cpx<T> ldc(const void* base, long idx) {
+  const Tin* p = reinterpret_cast<const Tin*>(base) + 2 * idx;
+  return cpx<T>{(T)p[0], (T)p[1]};
+}
+
+__device__ inline void coef_at(const TermRef& t, const double* drive, int ld, int j,
+                               double& cr, double& ci) {
+  cr = t.cre;
+  ci = t.cim;
+  if (t.slot >= 0 && drive) {
+    double f = drive[(long)t.slot * ld + j];
+    cr *= f;
+    ci *= f;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// apply
+// ---------------------------------------------------------------------------
+// Wavefront-level complex 16x16x4 product: acc += a * b, with a, b given as
+// (re, im) operand values of this lane.
+template <typename T>
+__device__ inline void cmma(typename MT<T>::v4& cr, typename MT<T>::v4& ci, T ar, T ai, T br,
+                            T bi) {
+  cr = MT<T>::mma(ar, br, cr);
+  cr = MT<T>::mma(-ai, bi, cr);
+  ci = MT<T>::mma(ar, bi, ci);
+  ci = MT<T>::mma(ai, br, ci);
+}
+
+struct UnitGeo {
+  long base;
+  int col;
+};
+
+__device__ inline UnitGeo unit_geo(const ApplyGroup& G, int u, int njb, int c) {
+  const int f = u / njb, jb = u % njb;
+  const int p2 = f % G.P2;
+  const int p1 = (f / G.P2) % G.P1;
+  const int p0 = f / (G.P2 * G.P1);
+  UnitGeo r;
+  r.base = (long)p0 * G.d1 * G.P1 * G.d2 * G.P2 + (long)p1 * G.d2 * G.P2 + p2;
+  r.col = 16 * jb + c;
+  return r;
+}
+
+template <typename T>
+__device__ inline void load_scaled(const T* M, int d, int row, int kk, double cr, double ci, T& ar,
+                                   T& ai) {
+  ar = 0;
+  ai = 0;
+  if (row < d && kk < d) {
+    const double a0 = M[2 * ((long)row * d + kk)], a1 = M[2 * ((long)row * d + kk) + 1];
+    ar = (T)(a0 * cr - a1 * ci);
+    ai = (T)(a0 * ci + a1 * cr);
+  }
+}
+
+// Accumulator tile T_idx (compile-time) belongs to local unit T_idx / nib and
+// row block T_idx % nib; a wavefront holds n_my units of nib row blocks each.
+template <typename T, typename Tin>
+__global__ void __launch_bounds__(256) k_apply(const ApplyGroup* __restrict__ groups,
+                                               const ApplyTile* __restrict__ tiles,
+                                               const int* __restrict__ step_ctr) {
+  typedef typename MT<T>::v4 v4;
+  constexpr int NT = MT<T>::NT;
+  extern __shared__ char smem_raw[];
+  const ApplyTile tile = tiles[blockIdx.x];
+  const ApplyGroup& G = groups[tile.group];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int c = lane & 15;   // MFMA row / column within a 16-block
+  const int g = lane >> 4;   // K sub-index (0..3)
+  const int d1 = G.d1, d2 = G.d2;
+  const int nib = (d1 + 15) >> 4, njb = (d2 + 15) >> 4;
+  const int nq1 = (d2 + 3) >> 2;  // K steps of X_f B^T
+  const int nq2 = (d1 + 3) >> 2;  // K steps of A Z
+  const long sb = G.P2;
+  const long sa = (long)G.P1 * d2 * G.P2;
+  const int step = step_ctr ? *step_ctr : 0;
+  const int jdrv = 4 * step + G.rel;
+  T* zr = reinterpret_cast<T*>(smem_raw) + (size_t)wave * (2 * 64 * 16);
+  T* zi = zr + 64 * 16;
+
+  int n_my = tile.nu > wave ? (tile.nu - wave + 3) / 4 : 0;
+  if (n_my * nib > NT) n_my = NT / nib;
+  if (n_my == 0) return;
+  v4 yr[NT], yi[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    yr[t] = v4{0, 0, 0, 0};
+    yi[t] = v4{0, 0, 0, 0};
+  }
+
+  for (int m = 0; m < G.n_terms; ++m) {
+    const TermRef tr = G.terms[m];
+    double cr, ci;
+    coef_at(tr, G.drive, G.drive_ld, jdrv, cr, ci);
+    const T* Am = reinterpret_cast<const T*>(tr.A);
+    const T* Bm = reinterpret_cast<const T*>(tr.B);
+    for (int uu = 0; uu < n_my; ++uu) {
+      const UnitGeo ug = unit_geo(G, tile.u0 + wave + 4 * uu, njb, c);
+      const int col = ug.col;
+      const int t_lo = uu * nib;
+      if (Am && Bm) {
+        v4 zra[NT], zia[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          zra[t] = v4{0, 0, 0, 0};
+          zia[t] = v4{0, 0, 0, 0};
+        }
+        for (int q = 0; q < nq1; ++q) {
+          const int kk = 4 * q + g;
+          T br = 0, bi = 0;
+          if (col < d2 && kk < d2) {
+            br = Bm[2 * ((long)col * d2 + kk)];
+            bi = Bm[2 * ((long)col * d2 + kk) + 1];
+          }
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            if (t < nib) {
+              const int row = 16 * t + c;
+              cpx<T> x{0, 0};
+              if (row < d1 && kk < d2) x = ldc<Tin, T>(G.X, ug.base + row * sa + kk * sb);
+              cmma<T>(zra[t], zia[t], x.re, x.im, br, bi);
+            }
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          if (t < nib) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              zr[(16 * t + MT<T>::drow(g, r)) * 16 + c] = zra[t][r];
+              zi[(16 * t + MT<T>::drow(g, r)) * 16 + c] = zia[t][r];
+            }
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int q = 0; q < nq2; ++q) {
+          const int kk = 4 * q + g;
+          const T zbr = zr[kk * 16 + c], zbi = zi[kk * 16 + c];
+#pragma unroll
+          for (int ti = 0; ti < NT; ++ti) {
+            if (ti >= t_lo && ti < t_lo + nib) {
+              T ar, ai;
+              load_scaled<T>(Am, d1, 16 * (ti - t_lo) + c, kk, cr, ci, ar, ai);
+              cmma<T>(yr[ti], yi[ti], ar, ai, zbr, zbi);
+            }
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      } else if (Am) {
+        for (int q = 0; q < nq2; ++q) {
+          const int kk = 4 * q + g;
+          cpx<T> x{0, 0};
+          if (kk < d1 && col < d2) x = ldc<Tin, T>(G.X, ug.base + kk * sa + col * sb);
+#pragma unroll
+          for (int ti = 0; ti < NT; ++ti) {
+            if (ti >= t_lo && ti < t_lo + nib) {
+              T ar, ai;
+              load_scaled<T>(Am, d1, 16 * (ti - t_lo) + c, kk, cr, ci, ar, ai);
+              cmma<T>(yr[ti], yi[ti], ar, ai, x.re, x.im);
+            }
+          }
+        }
+      } else if (Bm) {
+        for (int q = 0; q < nq1; ++q) {
+          const int kk = 4 * q + g;
+          T br, bi;
+          load_scaled<T>(Bm, d2, col, kk, cr, ci, br, bi);
+#pragma unroll
+          for (int ti = 0; ti < NT; ++ti) {
+            if (ti >= t_lo && ti < t_lo + nib) {
+              const int row = 16 * (ti - t_lo) + c;
+              cpx<T> x{0, 0};
+              if (row < d1 && kk < d2) x = ldc<Tin, T>(G.X, ug.base + row * sa + kk * sb);
+              cmma<T>(yr[ti], yi[ti], x.re, x.im, br, bi);
+            }
+          }
+        }
+      }
+    }
+  }
+  T* Y = reinterpret_cast<T*>(G.Y);
+#pragma unroll
+  for (int ti = 0; ti < NT; ++ti) {
+    if (ti < n_my * nib) {
+      const int uu = ti / nib, t = ti % nib;
+      const UnitGeo ug = unit_geo(G, tile.u0 + wave + 4 * uu, njb, c);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * t + MT<T>::drow(g, r);
+        if (row < d1 && ug.col < d2) {
+          const long o = 2 * (ug.base + row * sa + (long)ug.col * sb);
+          if (G.accumulate) {
+            Y[o] += yr[ti][r];
+            Y[o + 1] += yi[ti][r];
+          } else {
+            Y[o] = yr[ti][r];
+            Y[o + 1] = yi[ti][r];
+          }
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// presum: out = sum_i coef_i(t) M_i
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_presum(const PresumOp* __restrict__ ops,
+                                                const int* __restrict__ step_ctr) {
+  const PresumOp& op = ops[blockIdx.x];
+  const int step = step_ctr ? *step_ctr : 0;
+  const int j = 4 * step + op.rel;
+  const int n = op.dim * op.dim;
+  T* out = reinterpret_cast<T*>(op.out);
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    double sr = 0, si = 0;
+    for (int m = 0; m < op.n_terms; ++m) {
+      const TermRef& t = op.terms[m];
+      double cr, ci;
+      coef_at(t, op.drive, op.drive_ld, j, cr, ci);
+      const T* M = reinterpret_cast<const T*>(t.A);
+      const double a = M[2 * e], b = M[2 * e + 1];
+      sr += a * cr - b * ci;
+      si += a * ci + b * cr;
+    }
+    out[2 * e] = (T)sr;
+    out[2 * e + 1] = (T)si;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// combine: RK4 stage update (FP64 master, compute-precision stage input)
+// ---------------------------------------------------------------------------
+struct CombineTile {
+  int op;
+  int pad;
+  long e0, e1;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_combine(const CombineOp* __restrict__ ops,
+                                                 const CombineTile* __restrict__ tiles) {
+  const CombineTile tl = tiles[blockIdx.x];
+  const CombineOp& op = ops[tl.op];
+  const T* parts = reinterpret_cast<const T*>(op.parts);
+  T* xin = reinterpret_cast<T*>(op.xin);
+  for (long e = tl.e0 + threadIdx.x; e < tl.e1; e += blockDim.x) {
+    double kr = 0, ki = 0;
+    for (int p = 0; p < op.n_parts; ++p) {
+      kr += (double)parts[2 * (p * op.n + e)];
+      ki += (double)parts[2 * (p * op.n + e) + 1];
+    }
+    if (op.stage == 0) {  // plain evaluation: y0 = k
+      op.y0[2 * e] = kr;
+      op.y0[2 * e + 1] = ki;
+      continue;
+    }
+    const double yr = op.y0[2 * e], yi = op.y0[2 * e + 1];
+    if (op.stage == 1) {
+      op.acc[2 * e] = kr;
+      op.acc[2 * e + 1] = ki;
+      xin[2 * e] = (T)(yr + 0.5 * op.h * kr);
+      xin[2 * e + 1] = (T)(yi + 0.5 * op.h * ki);
+    } else if (op.stage == 2 || op.stage == 3) {
+      op.acc[2 * e] += 2.0 * kr;
+      op.acc[2 * e + 1] += 2.0 * ki;
+      const double s = op.stage == 2 ? 0.5 * op.h : op.h;
+      xin[2 * e] = (T)(yr + s * kr);
+      xin[2 * e + 1] = (T)(yi + s * ki);
+    } else {
+      op.y0[2 * e] = yr + (op.h / 6.0) * (op.acc[2 * e] + kr);
+      op.y0[2 * e + 1] = yi + (op.h / 6.0) * (op.acc[2 * e + 1] + ki);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 Householder QR (LAPACK zgeqr2 + zung2r conventions)
+// ---------------------------------------------------------------------------
+struct z2 {
+  double r, i;
+};
+// Relative rank threshold of the gauge-move QR: a residual column with norm at
+// or below QR_RANK_TOL * ||A||_F is treated as exactly zero (identity
+// reflector), so the completion of a rank-deficient core does not follow
+// rounding noise.
+constexpr double QR_RANK_TOL = 1e-10;
+__device__ inline z2 zmul(z2 a, z2 b) { return z2{a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
+__device__ inline z2 zconjmul(z2 a, z2 b) {  // conj(a) * b
+  return z2{a.r * b.r + a.i * b.i, a.r * b.i - a.i * b.r};
+}
+
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__global__ void __launch_bounds__(256) k_qr(const QrOp* __restrict__ ops) {
+  const QrOp op = ops[blockIdx.x];
+  const int m = op.m, n = op.n, k = m < n ? m : n;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ double red[8];  // [0..3] column norms, [4..7] Frobenius norm
+  __shared__ double sh_tau[2], sh_scale[2], sh_beta[2];
+  __shared__ int sh_skip;
+  z2* V = reinterpret_cast<z2*>(op.V);  // column-major m x n
+  z2* tau = reinterpret_cast<z2*>(op.tau);
+  z2* C = reinterpret_cast<z2*>(op.C);
+  auto cidx = [&](int row, int col) -> long {
+    const int pre = row / op.Ppost, post = row % op.Ppost;
+    return (long)pre * n * op.Ppost + (long)col * op.Ppost + post;
+  };
+  double fro = 0;
+  for (long e = tid; e < (long)m * n; e += 256) {
+    const int row = e % m, col = e / m;
+    const z2 v = C[cidx(row, col)];
+    V[e] = v;
+    fro += v.r * v.r + v.i * v.i;
+  }
+  fro = wave_sum(fro);
+  if (lane == 0) red[4 + wave] = fro;
+  __syncthreads();
+  // residual columns at or below this squared norm count as exact zeros
+  const double thr2 = QR_RANK_TOL * QR_RANK_TOL * (red[4] + red[5] + red[6] + red[7]);
+  for (int j = 0; j < k; ++j) {
+    // xnorm of V[j+1:m, j]
+    double s = 0;
+    for (int i = j + 1 + tid; i < m; i += 256) {
+      z2 v = V[(long)j * m + i];
+      s += v.r * v.r + v.i * v.i;
+    }
+    s = wave_sum(s);
+    if (lane == 0) red[wave] = s;
+    __syncthreads();
+    if (tid == 0) {
+      const double xn2 = red[0] + red[1] + red[2] + red[3];
+      const z2 alpha = V[(long)j * m + j];
+      if (alpha.r * alpha.r + alpha.i * alpha.i + xn2 <= thr2) {
+        sh_skip = 2;  // numerically zero residual: identity reflector, zero column
+        tau[j] = z2{0, 0};
+      } else if (xn2 == 0.0 && alpha.i == 0.0) {
+        sh_skip = 1;
+        tau[j] = z2{0, 0};
+        sh_tau[0] = 0;
+        sh_tau[1] = 0;
+      } else {
+        const double nrm = sqrt(alpha.r * alpha.r + alpha.i * alpha.i + xn2);
+        // beta = -sign(Re alpha) * nrm (LAPACK zlarfg; a zero counts as positive)
+        const double beta = alpha.r >= 0.0 ? -nrm : nrm;
+        const z2 t{(beta - alpha.r) / beta, -alpha.i / beta};
+        tau[j] = t;
+        sh_tau[0] = t.r;
+        sh_tau[1] = t.i;
+        // scale = 1 / (alpha - beta)
+        const double dr = alpha.r - beta, di = alpha.i;
+        const double den = dr * dr + di * di;
+        sh_scale[0] = dr / den;
+        sh_scale[1] = -di / den;
+        sh_beta[0] = beta;
+        sh_skip = 0;
+      }
+    }
+    __syncthreads();
+    if (sh_skip == 2) {
+      for (int i = j + tid; i < m; i += 256) V[(long)j * m + i] = z2{0, 0};
+    }
+    if (!sh_skip) {
+      const z2 sc{sh_scale[0], sh_scale[1]};
+      for (int i = j + 1 + tid; i < m; i += 256) V[(long)j * m + i] = zmul(V[(long)j * m + i], sc);
+      if (tid == 0) V[(long)j * m + j] = z2{sh_beta[0], 0.0};
+      __syncthreads();
+      // apply H^H = I - conj(tau) v v^H to columns j+1..n-1
+      const z2 ct{sh_tau[0], -sh_tau[1]};
+      for (int col = j + 1 + wave; col < n; col += 4) {
+        double wr = 0, wi = 0;
+        for (int i = j + lane; i < m; i += 64) {
+          const z2 v = i == j ? z2{1.0, 0.0} : V[(long)j * m + i];
+          const z2 a = V[(long)col * m + i];
+          const z2 p = zconjmul(v, a);
+          wr += p.r;
+          wi += p.i;
+        }
+        wr = wave_sum(wr);
+        wi = wave_sum(wi);
+        const z2 fct = zmul(ct, z2{wr, wi});
+        for (int i = j + lane; i < m; i += 64) {
+          const z2 v = i == j ? z2{1.0, 0.0} : V[(long)j * m + i];
+          const z2 pv = zmul(fct, v);
+          V[(long)col * m + i].r -= pv.r;
+          V[(long)col * m + i].i -= pv.i;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // R (n x n upper; rows >= k zero) into op.R, before Q overwrites V
+  z2* R = reinterpret_cast<z2*>(op.R);
+  for (int e = tid; e < n * n; e += 256) {
+    const int i = e / n, col = e % n;
+    z2 v = (i <= col && i < k) ? V[(long)col * m + i] : z2{0, 0};
+    if (op.transposeR) R[(long)col * n + i] = v;
+    else R[(long)i * n + col] = v;
+  }
+  __syncthreads();
+  // Q = H_0 ... H_{k-1} applied to the first min(m,n) unit columns (zung2r)
+  const int nq = k;  // Q is m x k
+  for (int i = k - 1; i >= 0; --i) {
+    const z2 t = tau[i];
+    if (i < nq - 1) {
+      for (int col = i + 1 + wave; col < nq; col += 4) {
+        double wr = 0, wi = 0;
+        for (int r = i + lane; r < m; r += 64) {
+          const z2 v = r == i ? z2{1.0, 0.0} : V[(long)i * m + r];
+          const z2 p = zconjmul(v, V[(long)col * m + r]);
+          wr += p.r;
+          wi += p.i;
+        }
+        wr = wave_sum(wr);
+        wi = wave_sum(wi);
+        const z2 fct = zmul(t, z2{wr, wi});
+        for (int r = i + lane; r < m; r += 64) {
+          const z2 v = r == i ? z2{1.0, 0.0} : V[(long)i * m + r];
+          const z2 pv = zmul(fct, v);
+          V[(long)col * m + r].r -= pv.r;
+          V[(long)col * m + r].i -= pv.i;
+        }
+      }
+    }
+    __syncthreads();
+    for (int r = i + 1 + tid; r < m; r += 256) {
+      const z2 v = V[(long)i * m + r];
+      const z2 p = zmul(t, v);
+      V[(long)i * m + r] = z2{-p.r, -p.i};
+    }
+    if (tid == 0) V[(long)i * m + i] = z2{1.0 - t.r, -t.i};
+    for (int r = tid; r < i; r += 256) V[(long)i * m + r] = z2{0, 0};
+    __syncthreads();
+  }
+  // phases: make diag(R) real non-negative
+  __shared__ double ph[2 * 64];
+  if (tid < n) {
+    const int j = tid;
+    z2 d = op.transposeR ? R[(long)j * n + j] : R[(long)j * n + j];
+    const double a = sqrt(d.r * d.r + d.i * d.i);
+    ph[2 * j] = a > 0 ? d.r / a : 1.0;
+    ph[2 * j + 1] = a > 0 ? d.i / a : 0.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < n * n; e += 256) {
+    const int i = e / n, col = e % n;
+    const z2 cph{ph[2 * i], -ph[2 * i + 1]};
+    const long o = op.transposeR ? (long)col * n + i : (long)i * n + col;
+    R[o] = zmul(cph, R[o]);
+  }
+  for (long e = tid; e < (long)m * n; e += 256) {
+    const int row = e % m, col = e / m;
+    z2 q = col < nq ? zmul(V[(long)col * m + row], z2{ph[2 * col], ph[2 * col + 1]}) : z2{0, 0};
+    C[cidx(row, col)] = q;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// absorb: C[pre, a, post] <- sum_a' Mx[a, a'] C[pre, a', post]   (FP64)
+// ---------------------------------------------------------------------------
+struct AbsorbTile {
+  int op;
+  int f0, f1;  // fiber range (fiber = (pre, post))
+};
+
+__global__ void __launch_bounds__(256) k_absorb(const AbsorbOp* __restrict__ ops,
+                                                const AbsorbTile* __restrict__ tiles) {
+  const AbsorbTile tl = tiles[blockIdx.x];
+  const AbsorbOp op = ops[tl.op];
+  extern __shared__ char smem_raw[];
+  z2* buf = reinterpret_cast<z2*>(smem_raw);
+  z2* C = reinterpret_cast<z2*>(op.C);
+  const z2* M = reinterpret_cast<const z2*>(op.M);
+  const int n = op.n;
+  const int nf = tl.f1 - tl.f0;
+  auto off = [&](int fib, int a) -> long {
+    const int pre = fib / op.Ppost, post = fib % op.Ppost;
+    return (long)pre * n * op.Ppost + (long)a * op.Ppost + post;
+  };
+  for (int e = threadIdx.x; e < nf * n; e += blockDim.x) {
+    const int fl = e / n, a = e % n;
+    buf[e] = C[off(tl.f0 + fl, a)];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < nf * n; e += blockDim.x) {
+    const int fl = e / n, a = e % n;
+    double sr = 0, si = 0;
+    for (int b = 0; b < n; ++b) {
+      const z2 mv = op.transposeM ? M[(long)b * n + a] : M[(long)a * n + b];
+      const z2 x = buf[fl * n + b];
+      sr += mv.r * x.r - mv.i * x.i;
+      si += mv.r * x.i + mv.i * x.r;
+    }
+    C[off(tl.f0 + fl, a)] = z2{sr, si};
+  }
+}
+
+// ---------------------------------------------------------------------------
+// gram: E[a', a] = sum conj(C[pre, a', post]) T[pre, a, post]
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_gram(const GramOp* __restrict__ ops) {
+  const GramOp op = ops[blockIdx.x];
+  const int r = op.r;
+  const long K = (long)op.Ppre * op.Ppost;
+  const T* Tm = reinterpret_cast<const T*>(op.T);
+  T* E = reinterpret_cast<T*>(op.E);
+  for (int e = threadIdx.x; e < r * r; e += blockDim.x) {
+    const int ap = e / r, a = e % r;
+    T sr = 0, si = 0;
+    for (long kk = 0; kk < K; ++kk) {
+      const long pre = kk / op.Ppost, post = kk % op.Ppost;
+      const long o1 = pre * r * op.Ppost + (long)ap * op.Ppost + post;
+      const long o2 = pre * r * op.Ppost + (long)a * op.Ppost + post;
+      const T cr = (T)op.C[2 * o1], ci = (T)op.C[2 * o1 + 1];
+      const T tr = Tm[2 * o2], ti = Tm[2 * o2 + 1];
+      sr += cr * tr + ci * ti;
+      si += cr * ti - ci * tr;
+    }
+    E[2 * e] = sr;
+    E[2 * e + 1] = si;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// rho: bottom-up vacuum contraction, FP64, one workgroup per program
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_rho(const RhoProg* __restrict__ progs) {
+  const RhoProg P = progs[blockIdx.x];
+  for (int ni = 0; ni < P.n_nodes; ++ni) {
+    const RhoNode nd = P.nodes[ni];
+    // output index space: parent leg (dim r) or the two system ends (M*M)
+    int out_dims[2] = {1, 1}, out_legs[2] = {-1, -1}, n_out = 0;
+    int strides[8];
+    long st = 1;
+    for (int l = nd.n_legs - 1; l >= 0; --l) {
+      strides[l] = (int)st;
+      st *= nd.dims[l];
+    }
+    for (int l = 0; l < nd.n_legs; ++l)
+      if (nd.kind[l] == 0 || nd.kind[l] == 2) {
+        out_legs[n_out] = l;
+        out_dims[n_out] = nd.dims[l];
+        ++n_out;
+      }
+    // summed legs: child bonds
+    int sum_legs[8], n_sum = 0;
+    long n_terms = 1;
+    for (int l = 0; l < nd.n_legs; ++l)
+      if (nd.kind[l] == 3) {
+        sum_legs[n_sum++] = l;
+        n_terms *= nd.dims[l];
+      }
+    const int n_outv = out_dims[0] * out_dims[1];
+    for (int o = threadIdx.x; o < n_outv; o += blockDim.x) {
+      long base = 0;
+      if (n_out > 0) base += (long)(o / out_dims[1]) * strides[out_legs[0]];
+      if (n_out > 1) base += (long)(o % out_dims[1]) * strides[out_legs[1]];
+      double sr = 0, si = 0;
+      for (long t = 0; t < n_terms; ++t) {
+        long rem = t, off = base;
+        double wr = 1, wi = 0;
+        for (int s = n_sum - 1; s >= 0; --s) {
+          const int l = sum_legs[s];
+          const int b = rem % nd.dims[l];
+          rem /= nd.dims[l];
+          off += (long)b * strides[l];
+          const double* v = P.vecs + 2 * ((long)nd.child_slot[l] * P.vec_ld + b);
+          const double nr = wr * v[0] - wi * v[1], nim = wr * v[1] + wi * v[0];
+          wr = nr;
+          wi = nim;
+        }
+        const double cr = nd.C[2 * off], ci = nd.C[2 * off + 1];
+        sr += cr * wr - ci * wi;
+        si += cr * wi + ci * wr;
+      }
+      double* dst = nd.out_slot >= 0 ? P.vecs + 2 * ((long)nd.out_slot * P.vec_ld + o)
+                                     : P.rho_out + 2 * o;
+      dst[0] = sr;
+      dst[1] = si;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_step_inc(int* ctr, int value) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *ctr = value < 0 ? *ctr + 1 : value;
+}
+
+// ---------------------------------------------------------------------------
+// launchers (host)
+// ---------------------------------------------------------------------------
+hipError_t launch_apply(int fp64, int in_fp64, const ApplyGroup* groups, const ApplyTile* tiles,
+                        int n_tiles, const int* step_ctr, hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  const size_t lds = fp64 ? 4 * 2 * 64 * 16 * sizeof(double) : 4 * 2 * 64 * 16 * sizeof(float);
+  if (fp64) {
+    if (in_fp64)
+      hipLaunchKernelGGL((k_apply<double, double>), dim3(n_tiles), dim3(256), lds, s, groups, tiles, step_ctr);
+    else
+      hipLaunchKernelGGL((k_apply<double, double>), dim3(n_tiles), dim3(256), lds, s, groups, tiles, step_ctr);
+  } else {
+    if (in_fp64)
+      hipLaunchKernelGGL((k_apply<float, double>), dim3(n_tiles), dim3(256), lds, s, groups, tiles, step_ctr);
+    else
+      hipLaunchKernelGGL((k_apply<float, float>), dim3(n_tiles), dim3(256), lds, s, groups, tiles, step_ctr);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_presum(int fp64, const PresumOp* ops, int n, const int* step_ctr, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (fp64) hipLaunchKernelGGL(k_presum<double>, dim3(n), dim3(256), 0, s, ops, step_ctr);
+  else hipLaunchKernelGGL(k_presum<float>, dim3(n), dim3(256), 0, s, ops, step_ctr);
+  return hipGetLastError();
+}
+
+hipError_t launch_combine(int fp64, const CombineOp* ops, const void* tiles, int n_tiles,
+                          hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  const CombineTile* t = reinterpret_cast<const CombineTile*>(tiles);
+  if (fp64) hipLaunchKernelGGL(k_combine<double>, dim3(n_tiles), dim3(256), 0, s, ops, t);
+  else hipLaunchKernelGGL(k_combine<float>, dim3(n_tiles), dim3(256), 0, s, ops, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_qr(const QrOp* ops, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_qr, dim3(n), dim3(256), 0, s, ops);
+  return hipGetLastError();
+}
+
+hipError_t launch_absorb(const AbsorbOp* ops, const void* tiles, int n_tiles, size_t lds,
+                         hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_absorb, dim3(n_tiles), dim3(256), lds, s, ops,
+                     reinterpret_cast<const AbsorbTile*>(tiles));
+  return hipGetLastError();
+}
+
+hipError_t launch_gram(int fp64, const GramOp* ops, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (fp64) hipLaunchKernelGGL(k_gram<double>, dim3(n), dim3(256), 0, s, ops);
+  else hipLaunchKernelGGL(k_gram<float>, dim3(n), dim3(256), 0, s, ops);
+  return hipGetLastError();
+}
+
+hipError_t launch_rho(const RhoProg* progs, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rho, dim3(n), dim3(256), 0, s, progs);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_inc(int* ctr, int value, hipStream_t s) {
+  hipLaunchKernelGGL(k_step_inc, dim3(1), dim3(64), 0, s, ctr, value);
+  return hipGetLastError();
+}
+
+size_t combine_tile_bytes() { return sizeof(CombineTile); }
+size_t absorb_tile_bytes() { return sizeof(AbsorbTile); }
+
+}  // namespace tenso

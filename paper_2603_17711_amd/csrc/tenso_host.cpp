@@ -1,0 +1,1516 @@
+// Host side of the TTN-HEOM library: trees, generators, plan compilation,
+// operation lists for the projector-splitting sweeps, descriptor binding and
+// the C ABI of include/tenso.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/tenso.h"
+#include "tenso_internal.h"
+
+namespace tenso {
+hipError_t launch_apply(int fp64, int in_fp64, const ApplyGroup* groups, const ApplyTile* tiles,
+                        int n_tiles, const int* step_ctr, hipStream_t s);
+hipError_t launch_presum(int fp64, const PresumOp* ops, int n, const int* step_ctr, hipStream_t s);
+hipError_t launch_combine(int fp64, const CombineOp* ops, const void* tiles, int n_tiles,
+                          hipStream_t s);
+hipError_t launch_qr(const QrOp* ops, int n, hipStream_t s);
+hipError_t launch_absorb(const AbsorbOp* ops, const void* tiles, int n_tiles, size_t lds,
+                         hipStream_t s);
+hipError_t launch_gram(int fp64, const GramOp* ops, int n, hipStream_t s);
+hipError_t launch_rho(const RhoProg* progs, int n, hipStream_t s);
+hipError_t launch_step_inc(int* ctr, int value, hipStream_t s);
+}  // namespace tenso
+
+using namespace tenso;
+using cd = std::complex<double>;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+struct TErr {
+  int code;
+  std::string msg;
+};
+[[noreturn]] static void fail(int code, const std::string& m) { throw TErr{code, m}; }
+static void hipchk(hipError_t e, const char* where) {
+  if (e != hipSuccess) fail(TENSO_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+template <class F>
+static int guard(F&& f) {
+  try {
+    f();
+    return TENSO_OK;
+  } catch (const TErr& e) {
+    g_err = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return TENSO_ENOMEM;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return TENSO_EINVAL;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// tree
+// ---------------------------------------------------------------------------
+struct Leg {
+  int kind;  // 0 parent bond, 1 end, 2 child bond
+  int id;    // parent node / end index / child node
+};
+
+struct tenso_tree {
+  int n = 0, n_ends = 0;
+  std::vector<int> parent, end_node, end_dim, rank;
+  std::vector<std::vector<int>> children, ends;
+  std::vector<std::vector<Leg>> legs;
+  std::vector<std::vector<char>> in_sub;  // [node][end]
+
+  int leg_dim(int s, const Leg& l) const {
+    if (l.kind == 0) return rank[s];
+    if (l.kind == 1) return end_dim[l.id];
+    return rank[l.id];
+  }
+  std::vector<int> shape(int s) const {
+    std::vector<int> d;
+    for (auto& l : legs[s]) d.push_back(leg_dim(s, l));
+    return d;
+  }
+  long size(int s) const {
+    long p = 1;
+    for (int d : shape(s)) p *= d;
+    return p;
+  }
+  int leg_of_child(int s, int c) const {
+    for (size_t i = 0; i < legs[s].size(); ++i)
+      if (legs[s][i].kind == 2 && legs[s][i].id == c) return (int)i;
+    fail(TENSO_EINVAL, "child not found");
+  }
+  void finish(int max_rank, const int32_t* bond_rank) {
+    children.assign(n, {});
+    ends.assign(n, {});
+    for (int s = 1; s < n; ++s) children[parent[s]].push_back(s);
+    for (int e = 0; e < n_ends; ++e) ends[end_node[e]].push_back(e);
+    legs.assign(n, {});
+    for (int s = 0; s < n; ++s) {
+      if (s > 0) legs[s].push_back({0, parent[s]});
+      for (int e : ends[s]) legs[s].push_back({1, e});
+      for (int c : children[s]) legs[s].push_back({2, c});
+      if (legs[s].size() > 8) fail(TENSO_EUNSUPPORTED, "a core has more than 8 legs");
+      if (legs[s].size() < 2) fail(TENSO_EINVAL, "a core needs at least two legs");
+    }
+    in_sub.assign(n, std::vector<char>(n_ends, 0));
+    for (int s = n - 1; s >= 0; --s) {
+      for (int e : ends[s]) in_sub[s][e] = 1;
+      for (int c : children[s])
+        for (int e = 0; e < n_ends; ++e) in_sub[s][e] |= in_sub[c][e];
+    }
+    rank.assign(n, 0);
+    for (int c = 1; c < n; ++c) {
+      int r = bond_rank ? bond_rank[c] : max_rank;
+      if (r < 1) fail(TENSO_EINVAL, "bond ranks must be >= 1");
+      rank[c] = r;
+    }
+    clamp();
+  }
+  void clamp() {
+    bool changed = true;
+    while (changed) {
+      changed = false;
+      for (int c = 1; c < n; ++c) {
+        int p = parent[c];
+        long lo = 1, hi = 1;
+        for (size_t i = 1; i < legs[c].size(); ++i) lo *= leg_dim(c, legs[c][i]);
+        for (auto& l : legs[p])
+          if (!(l.kind == 2 && l.id == c)) hi *= leg_dim(p, l);
+        long r = std::min<long>(rank[c], std::min(lo, hi));
+        if (r != rank[c]) {
+          rank[c] = (int)r;
+          changed = true;
+        }
+      }
+    }
+  }
+};
+
+static tenso_tree* make_tree(int n, const int32_t* parent, int n_ends, const int32_t* end_node,
+                             const int32_t* end_dim, int max_rank, const int32_t* bond_rank) {
+  if (n < 1 || n_ends < 2) fail(TENSO_EINVAL, "need >= 1 node and >= 2 ends");
+  if (parent[0] != -1) fail(TENSO_EINVAL, "parent[0] must be -1");
+  for (int s = 1; s < n; ++s)
+    if (parent[s] < 0 || parent[s] >= s) fail(TENSO_EINVAL, "parent[s] must be in [0, s)");
+  for (int e = 0; e < n_ends; ++e) {
+    if (end_node[e] < 0 || end_node[e] >= n) fail(TENSO_EINVAL, "end attached to a bad node");
+    if (end_dim[e] < 1) fail(TENSO_EINVAL, "end dims must be >= 1");
+  }
+  if (end_node[0] != 0 || end_node[1] != 0) fail(TENSO_EINVAL, "ket and bra ends must sit on the root");
+  if (end_dim[0] != end_dim[1]) fail(TENSO_EINVAL, "ket and bra dims differ");
+  if (max_rank < 1 && !bond_rank) fail(TENSO_EINVAL, "max_rank must be >= 1");
+  auto t = std::make_unique<tenso_tree>();
+  t->n = n;
+  t->n_ends = n_ends;
+  t->parent.assign(parent, parent + n);
+  t->end_node.assign(end_node, end_node + n_ends);
+  t->end_dim.assign(end_dim, end_dim + n_ends);
+  t->finish(max_rank, bond_rank);
+  return t.release();
+}
+
+// ---------------------------------------------------------------------------
+// generator
+// ---------------------------------------------------------------------------
+typedef std::vector<std::pair<int, int>> Key;  // sorted (end, matrix id)
+
+struct tenso_gen {
+  struct Term {
+    cd coef;
+    int slot;
+    Key f;
+  };
+  std::vector<Term> terms;
+  std::vector<std::vector<cd>> mats;
+  std::vector<int> mat_dim;
+  int n_slots = 0;
+  int n_ends = 0;
+  std::vector<int> end_dim;
+};
+
+// ---------------------------------------------------------------------------
+// plan
+// ---------------------------------------------------------------------------
+static const uint64_t OFF_MASK = (1ull << 56) - 1;
+enum { TAG_ABS = 0, TAG_STATE = 2, TAG_WS = 3, TAG_TERM = 4, TAG_RNODE = 5 };
+static inline void* tagp(int tag, uint64_t off) { return (void*)(((uint64_t)tag << 56) | off); }
+
+struct LaunchRec {
+  int kind;
+  int in_fp64;
+  int first, count;    // descriptors
+  int tfirst, tcount;  // tiles
+  size_t lds;
+};
+enum { LK_APPLY, LK_PRESUM, LK_COMBINE, LK_QR, LK_ABSORB, LK_GRAM, LK_RHO };
+
+struct CombineTileH {
+  int op;
+  int pad;
+  long e0, e1;
+};
+struct AbsorbTileH {
+  int op;
+  int f0, f1;
+};
+
+struct Program {
+  std::vector<TermRef> terms;
+  std::vector<ApplyGroup> groups;
+  std::vector<ApplyTile> atiles;
+  std::vector<PresumOp> presums;
+  std::vector<CombineOp> combines;
+  std::vector<CombineTileH> ctiles;
+  std::vector<QrOp> qrs;
+  std::vector<AbsorbOp> absorbs;
+  std::vector<AbsorbTileH> abtiles;
+  std::vector<GramOp> grams;
+  std::vector<RhoNode> rnodes;
+  std::vector<RhoProg> rprogs;
+  std::vector<LaunchRec> launches;
+};
+
+// Device copy of a program (descriptor arena).
+struct DevProgram {
+  char* arena = nullptr;
+  size_t bytes = 0;
+  size_t o_terms, o_groups, o_atiles, o_presums, o_combines, o_ctiles, o_qrs, o_absorbs, o_abtiles,
+      o_grams, o_rnodes, o_rprogs;
+  std::vector<LaunchRec> launches;
+  ~DevProgram() {
+    if (arena) (void)hipFree(arena);
+  }
+};
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// operand reference resolved when a program is built
+struct ORef {
+  int kind = 0;  // 0 identity, 1 factor, 2 down slot, 3 up slot
+  int node = 0, idx = 0;
+};
+
+struct Recipe {  // effective generator on one tensor (node core, bond or edge)
+  struct G {
+    int l1, l2;
+    std::vector<std::pair<int, std::pair<ORef, ORef>>> pair_terms;  // (term, (A, B))
+    std::vector<std::pair<int, ORef>> sa, sb;                       // singles on l1 / l2
+  };
+  std::vector<int> dims;
+  std::vector<G> groups;
+};
+
+struct tenso_plan {
+  tenso_tree tree;
+  tenso_gen gen;
+  tenso_plan_opts opts;
+  int fp64 = 0;
+  size_t tsz = 8;  // bytes per complex in compute precision
+  int max_dim = 1;
+  // env slots
+  std::vector<std::vector<Key>> dkeys, ukeys;
+  std::vector<std::map<Key, int>> dmap, umap;
+  std::vector<std::vector<int>> term_d, term_u;  // [node][term] -> slot or -1
+  // constant buffer (factor matrices in both precisions)
+  void* cbuf = nullptr;
+  std::vector<size_t> mat_off64, mat_off32;
+  // state layout
+  std::vector<size_t> core_off;  // bytes
+  size_t state_bytes = 0;
+  // workspace layout
+  std::vector<size_t> envd_off, envu_off;
+  size_t ws_presum = 0, ws_xin = 0, ws_acc = 0, ws_parts = 0, ws_envscr = 0, ws_bond = 0,
+         ws_qrv = 0, ws_qrtau = 0, ws_rhovec = 0, ws_rhoout = 0, ws_ctr = 0, ws_bytes = 0;
+  size_t presum_cap = 0, parts_cap = 0, envscr_cap = 0, qrv_cap = 0;
+  int par_target = 64;  // tiles wanted per apply (single-instance latency)
+  // compiled programs (host descriptors with tagged pointers, device copies)
+  std::unique_ptr<Program> prog_step, prog_init;
+  std::unique_ptr<DevProgram> dev_step, dev_init;
+  std::map<int, std::unique_ptr<DevProgram>> dev_apply;
+  std::unique_ptr<DevProgram> dev_rho;
+  // binding of the step program
+  void* b_state = nullptr;
+  void* b_ws = nullptr;
+  double b_dt = -1;
+  const double* b_drive = nullptr;
+  int b_ld = -1;
+  std::vector<int32_t> rank_log;
+
+  ~tenso_plan() {
+    if (cbuf) (void)hipFree(cbuf);
+  }
+};
+
+// -- slot analysis ----------------------------------------------------------
+static Key restrict_key(const tenso_tree& t, const Key& k, int node, bool inside) {
+  Key r;
+  for (auto& p : k)
+    if ((bool)t.in_sub[node][p.first] == inside) r.push_back(p);
+  return r;
+}
+
+static int key_mat(const Key& k, int end) {
+  for (auto& p : k)
+    if (p.first == end) return p.second;
+  return -1;
+}
+
+static void analyse_slots(tenso_plan& P) {
+  const tenso_tree& t = P.tree;
+  const int nt = (int)P.gen.terms.size();
+  P.dkeys.assign(t.n, {});
+  P.ukeys.assign(t.n, {});
+  P.dmap.assign(t.n, {});
+  P.umap.assign(t.n, {});
+  P.term_d.assign(t.n, std::vector<int>(nt, -1));
+  P.term_u.assign(t.n, std::vector<int>(nt, -1));
+  for (int x = 1; x < t.n; ++x) {
+    for (int m = 0; m < nt; ++m) {
+      const Key& k = P.gen.terms[m].f;
+      Key kd = restrict_key(t, k, x, true), ku = restrict_key(t, k, x, false);
+      if (!kd.empty()) {
+        auto it = P.dmap[x].find(kd);
+        if (it == P.dmap[x].end()) {
+          it = P.dmap[x].emplace(kd, (int)P.dkeys[x].size()).first;
+          P.dkeys[x].push_back(kd);
+        }
+        P.term_d[x][m] = it->second;
+      }
+      if (!ku.empty()) {
+        auto it = P.umap[x].find(ku);
+        if (it == P.umap[x].end()) {
+          it = P.umap[x].emplace(ku, (int)P.ukeys[x].size()).first;
+          P.ukeys[x].push_back(ku);
+        }
+        P.term_u[x][m] = it->second;
+      }
+    }
+  }
+}
+
+// operand of a restricted key on leg `l` of node s (the key lives on the legs of s)
+static ORef leg_ref_for_key(const tenso_plan& P, int s, const Leg& l, const Key& key) {
+  const tenso_tree& t = P.tree;
+  ORef r;
+  if (l.kind == 1) {
+    int m = key_mat(key, l.id);
+    if (m >= 0) {
+      r.kind = 1;
+      r.idx = m;
+    }
+  } else if (l.kind == 2) {
+    Key k = restrict_key(t, key, l.id, true);
+    if (!k.empty()) {
+      r.kind = 2;
+      r.node = l.id;
+      r.idx = P.dmap[l.id].at(k);
+    }
+  } else {
+    Key k = restrict_key(t, key, s, false);
+    if (!k.empty()) {
+      r.kind = 3;
+      r.node = s;
+      r.idx = P.umap[s].at(k);
+    }
+  }
+  return r;
+}
+
+// Effective-generator recipe over a list of (node, leg) legs.
+static Recipe make_recipe(const tenso_plan& P, const std::vector<std::pair<int, Leg>>& legs,
+                          const std::vector<int>& dims) {
+  Recipe R;
+  R.dims = dims;
+  std::map<std::pair<int, int>, int> gidx;
+  std::vector<std::vector<std::pair<int, ORef>>> singles(legs.size());
+  for (int m = 0; m < (int)P.gen.terms.size(); ++m) {
+    const Key& k = P.gen.terms[m].f;
+    std::vector<std::pair<int, ORef>> nz;
+    for (int i = 0; i < (int)legs.size(); ++i) {
+      ORef o = leg_ref_for_key(P, legs[i].first, legs[i].second, k);
+      if (o.kind) nz.push_back({i, o});
+    }
+    if (nz.empty()) fail(TENSO_EINVAL, "term with no factor in the network");
+    if (nz.size() > 2)
+      fail(TENSO_EUNSUPPORTED, "a term acts on more than two legs of one core");
+    if (nz.size() == 1) {
+      singles[nz[0].first].push_back({m, nz[0].second});
+    } else {
+      auto key = std::make_pair(nz[0].first, nz[1].first);
+      auto it = gidx.find(key);
+      if (it == gidx.end()) {
+        it = gidx.emplace(key, (int)R.groups.size()).first;
+        Recipe::G g;
+        g.l1 = key.first;
+        g.l2 = key.second;
+        R.groups.push_back(g);
+      }
+      R.groups[it->second].pair_terms.push_back({m, {nz[0].second, nz[1].second}});
+    }
+  }
+  for (int l = 0; l < (int)legs.size(); ++l) {
+    if (singles[l].empty()) continue;
+    int gi = -1;
+    bool first_leg = false;
+    for (int i = 0; i < (int)R.groups.size(); ++i) {
+      if (R.groups[i].l1 == l) {
+        gi = i;
+        first_leg = true;
+        break;
+      }
+      if (R.groups[i].l2 == l) {
+        gi = i;
+        first_leg = false;
+        break;
+      }
+    }
+    if (gi < 0) {
+      Recipe::G g;
+      int other = l == 0 ? 1 : 0;
+      g.l1 = std::min(l, other);
+      g.l2 = std::max(l, other);
+      R.groups.push_back(g);
+      gi = (int)R.groups.size() - 1;
+      first_leg = g.l1 == l;
+    }
+    auto& dst = first_leg ? R.groups[gi].sa : R.groups[gi].sb;
+    dst.insert(dst.end(), singles[l].begin(), singles[l].end());
+  }
+  return R;
+}
+
+static Recipe node_recipe(const tenso_plan& P, int s) {
+  std::vector<std::pair<int, Leg>> legs;
+  for (auto& l : P.tree.legs[s]) legs.push_back({s, l});
+  return make_recipe(P, legs, P.tree.shape(s));
+}
+
+static Recipe bond_recipe(const tenso_plan& P, int c) {
+  // bond matrix B[a_parent_side, a_child_side]: leg 0 carries the up-env of c,
+  // leg 1 the down-env of c.
+  Recipe R;
+  R.dims = {P.tree.rank[c], P.tree.rank[c]};
+  Recipe::G g;
+  g.l1 = 0;
+  g.l2 = 1;
+  for (int m = 0; m < (int)P.gen.terms.size(); ++m) {
+    ORef a, b;
+    if (P.term_u[c][m] >= 0) {
+      a.kind = 3;
+      a.node = c;
+      a.idx = P.term_u[c][m];
+    }
+    if (P.term_d[c][m] >= 0) {
+      b.kind = 2;
+      b.node = c;
+      b.idx = P.term_d[c][m];
+    }
+    if (a.kind && b.kind) g.pair_terms.push_back({m, {a, b}});
+    else if (a.kind) g.sa.push_back({m, a});
+    else if (b.kind) g.sb.push_back({m, b});
+  }
+  R.groups.push_back(g);
+  return R;
+}
+
+// -- layouts ------------------------------------------------------------------
+static long prod(const std::vector<int>& d, int a, int b) {
+  long p = 1;
+  for (int i = a; i < b; ++i) p *= d[i];
+  return p;
+}
+
+static void* oref_ptr(const tenso_plan& P, const ORef& o) {
+  switch (o.kind) {
+    case 1:
+      return (char*)P.cbuf + (P.fp64 ? P.mat_off64[o.idx] : P.mat_off32[o.idx]);
+    case 2: {
+      size_t r = P.tree.rank[o.node];
+      return tagp(TAG_WS, P.envd_off[o.node] + (size_t)o.idx * r * r * P.tsz);
+    }
+    case 3: {
+      size_t r = P.tree.rank[o.node];
+      return tagp(TAG_WS, P.envu_off[o.node] + (size_t)o.idx * r * r * P.tsz);
+    }
+  }
+  return nullptr;
+}
+
+static void layout(tenso_plan& P) {
+  const tenso_tree& t = P.tree;
+  P.core_off.assign(t.n, 0);
+  size_t off = 0;
+  long maxP = 1;
+  for (int s = 0; s < t.n; ++s) {
+    P.core_off[s] = off;
+    off += align256((size_t)t.size(s) * 16);
+    maxP = std::max(maxP, t.size(s));
+  }
+  P.state_bytes = off;
+  int maxr = 1;
+  for (int c = 1; c < t.n; ++c) maxr = std::max(maxr, t.rank[c]);
+  for (int e = 0; e < t.n_ends; ++e) P.max_dim = std::max(P.max_dim, t.end_dim[e]);
+  P.max_dim = std::max(P.max_dim, maxr);
+  // capacities
+  size_t presum = 0, parts = 0, envscr = 0, qrv = 0;
+  for (int s = 0; s < t.n; ++s) {
+    Recipe R = node_recipe(P, s);
+    size_t ps = 0;
+    for (auto& g : R.groups) {
+      if (!g.sa.empty()) ps += (size_t)R.dims[g.l1] * R.dims[g.l1];
+      if (!g.sb.empty()) ps += (size_t)R.dims[g.l2] * R.dims[g.l2];
+    }
+    presum = std::max(presum, ps);
+    // parts: groups x chunks (chunks <= 8)
+    parts = std::max(parts, (size_t)R.groups.size() * 8 * t.size(s));
+    if (s > 0) {
+      envscr = std::max(envscr, P.dkeys[s].size() * (size_t)t.size(s));
+      envscr = std::max(envscr, P.ukeys[s].size() * (size_t)t.size(t.parent[s]));
+      size_t r = t.rank[s];
+      qrv = std::max(qrv, (size_t)t.size(s));                 // QR toward parent
+      qrv = std::max(qrv, (size_t)t.size(t.parent[s]));       // QR toward child
+      presum = std::max(presum, 2 * r * r);
+      parts = std::max(parts, 8 * r * r);
+    }
+  }
+  size_t w = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = w;
+    w += align256(bytes);
+    return o;
+  };
+  P.envd_off.assign(t.n, 0);
+  P.envu_off.assign(t.n, 0);
+  for (int x = 1; x < t.n; ++x) {
+    size_t r = t.rank[x];
+    P.envd_off[x] = take(std::max<size_t>(1, P.dkeys[x].size()) * r * r * P.tsz);
+    P.envu_off[x] = take(std::max<size_t>(1, P.ukeys[x].size()) * r * r * P.tsz);
+  }
+  P.presum_cap = presum;
+  P.parts_cap = parts;
+  P.envscr_cap = envscr;
+  P.qrv_cap = qrv;
+  P.ws_presum = take(std::max<size_t>(1, presum) * P.tsz);
+  P.ws_xin = take((size_t)maxP * P.tsz);
+  P.ws_acc = take((size_t)maxP * 16);
+  P.ws_parts = take(std::max<size_t>(1, parts) * P.tsz);
+  P.ws_envscr = take(std::max<size_t>(1, envscr) * P.tsz);
+  P.ws_bond = take((size_t)maxr * maxr * 16);
+  P.ws_qrv = take(std::max<size_t>(1, qrv) * 16);
+  P.ws_qrtau = take((size_t)P.max_dim * 16);
+  P.ws_rhovec = take((size_t)t.n * maxr * 16);
+  P.ws_rhoout = take((size_t)t.end_dim[0] * t.end_dim[0] * 16);
+  P.ws_ctr = take(64);
+  P.ws_bytes = w;
+}
+
+// -- program building ---------------------------------------------------------
+struct Builder {
+  tenso_plan& P;
+  Program& G;
+  Builder(tenso_plan& p, Program& g) : P(p), G(g) {}
+
+  void launch(int kind, int in_fp64, int first, int count, int tfirst, int tcount, size_t lds = 0) {
+    G.launches.push_back({kind, in_fp64, first, count, tfirst, tcount, lds});
+  }
+
+  void* core(int s) { return tagp(TAG_STATE, P.core_off[s]); }
+  void* ws(size_t off) { return tagp(TAG_WS, off); }
+
+  int term_index(const TermRef& tr) {
+    G.terms.push_back(tr);
+    return (int)G.terms.size() - 1;
+  }
+
+  TermRef term_ref(int m, void* A, void* B) {
+    TermRef tr{};
+    tr.cre = P.gen.terms[m].coef.real();
+    tr.cim = P.gen.terms[m].coef.imag();
+    tr.slot = P.gen.terms[m].slot;
+    tr.A = A;
+    tr.B = B;
+    return tr;
+  }
+
+  // tiles for one group of units, each tile <= 4*uw units
+  void add_tiles(int gi, int d1, int d2, long F, int target) {
+    const int nib = (d1 + 15) / 16, njb = (d2 + 15) / 16;
+    const int NT = P.fp64 ? 4 : 8;
+    if (nib > NT || d1 > 64) fail(TENSO_EUNSUPPORTED, "leg dimension above 64 in the apply kernel");
+    long units = F * njb;
+    int uw = (int)std::max<long>(1, std::min<long>(NT / nib, (units + 4L * target - 1) / (4L * target)));
+    long per = 4L * uw;
+    for (long u = 0; u < units; u += per) {
+      ApplyTile tl{};
+      tl.group = gi;
+      tl.u0 = (int)u;
+      tl.nu = (int)std::min<long>(per, units - u);
+      G.atiles.push_back(tl);
+    }
+  }
+
+  // Emit apply launches of recipe R on input X -> parts (chunked), with the
+  // presum launch in front.  Returns the number of partial slabs written.
+  int emit_apply(const Recipe& R, void* X, int in_fp64, long Pn, int rel, int presum_now,
+                 int target) {
+    // presums
+    size_t poff = P.ws_presum;
+    std::vector<void*> sa_buf(R.groups.size(), nullptr), sb_buf(R.groups.size(), nullptr);
+    int pfirst = (int)G.presums.size();
+    for (size_t gi = 0; gi < R.groups.size(); ++gi) {
+      auto& g = R.groups[gi];
+      for (int side = 0; side < 2; ++side) {
+        auto& lst = side == 0 ? g.sa : g.sb;
+        if (lst.empty()) continue;
+        int d = R.dims[side == 0 ? g.l1 : g.l2];
+        void* out = ws(poff);
+        poff += (size_t)d * d * P.tsz;
+        (side == 0 ? sa_buf : sb_buf)[gi] = out;
+        PresumOp op{};
+        op.out = out;
+        int first = -1;
+        for (auto& st : lst) {
+          int k = term_index(term_ref(st.first, oref_ptr(P, st.second), nullptr));
+          if (first < 0) first = k;
+        }
+        op.terms = (const TermRef*)tagp(TAG_TERM, first);
+        op.n_terms = (int)lst.size();
+        op.dim = d;
+        op.rel = rel;
+        if (presum_now) G.presums.push_back(op);
+      }
+    }
+    if (poff - P.ws_presum > P.presum_cap * P.tsz + 1) fail(TENSO_EINVAL, "presum capacity");
+    int np = (int)G.presums.size() - pfirst;
+    if (np) launch(LK_PRESUM, 0, pfirst, np, 0, 0);
+    // groups, chunked over terms
+    int gfirst = (int)G.groups.size();
+    int tfirst = (int)G.atiles.size();
+    int part = 0;
+    long free_total = 0;
+    for (auto& g : R.groups) free_total += Pn / ((long)R.dims[g.l1] * R.dims[g.l2]);
+    for (size_t gi = 0; gi < R.groups.size(); ++gi) {
+      auto& g = R.groups[gi];
+      std::vector<TermRef> trs;
+      for (auto& pt : g.pair_terms)
+        trs.push_back(term_ref(pt.first, oref_ptr(P, pt.second.first), oref_ptr(P, pt.second.second)));
+      if (sa_buf[gi]) {
+        TermRef tr{};
+        tr.cre = 1;
+        tr.slot = -1;
+        tr.A = sa_buf[gi];
+        trs.push_back(tr);
+      }
+      if (sb_buf[gi]) {
+        TermRef tr{};
+        tr.cre = 1;
+        tr.slot = -1;
+        tr.B = sb_buf[gi];
+        trs.push_back(tr);
+      }
+      const int d1 = R.dims[g.l1], d2 = R.dims[g.l2];
+      const long F = Pn / ((long)d1 * d2);
+      const long units = F * ((d2 + 15) / 16);
+      // chunks over terms so that the launch has about `target` tiles
+      int nchunk = 1;
+      if (target > 1) {
+        long tiles_one = (units + 3) / 4;
+        nchunk = (int)std::min<long>(8, std::max<long>(1, (long)target / std::max<long>(1, tiles_one * (long)R.groups.size())));
+        nchunk = std::min<int>(nchunk, std::max<int>(1, (int)trs.size() / 4));
+      }
+      size_t per = (trs.size() + nchunk - 1) / nchunk;
+      for (int ch = 0; ch < nchunk; ++ch) {
+        size_t a = ch * per, b = std::min(trs.size(), a + per);
+        if (a >= b && ch > 0) break;
+        ApplyGroup ag{};
+        ag.X = X;
+        ag.Y = ws(P.ws_parts + (size_t)part * Pn * P.tsz);
+        ++part;
+        int first = (int)G.terms.size();
+        for (size_t i = a; i < b; ++i) G.terms.push_back(trs[i]);
+        ag.terms = (const TermRef*)tagp(TAG_TERM, first);
+        ag.in_fp64 = in_fp64;
+        ag.n_terms = (int)(b - a);
+        ag.d1 = d1;
+        ag.d2 = d2;
+        ag.P1 = (int)prod(R.dims, g.l1 + 1, g.l2);
+        ag.P2 = (int)prod(R.dims, g.l2 + 1, (int)R.dims.size());
+        ag.F = (int)F;
+        ag.rel = rel;
+        ag.accumulate = 0;
+        G.groups.push_back(ag);
+        add_tiles((int)G.groups.size() - 1 - gfirst, d1, d2, F, target > 1 ? std::max(1, target / (nchunk * (int)R.groups.size())) : 1);
+      }
+    }
+    if ((size_t)part * Pn > P.parts_cap) fail(TENSO_EINVAL, "parts capacity exceeded");
+    launch(LK_APPLY, in_fp64, gfirst, (int)G.groups.size() - gfirst, tfirst,
+           (int)G.atiles.size() - tfirst);
+    return part;
+  }
+
+  void emit_combine(void* y0, long n, int n_parts, int stage, double h_sign_half) {
+    CombineOp op{};
+    op.y0 = (double*)y0;
+    op.xin = ws(P.ws_xin);
+    op.acc = (double*)ws(P.ws_acc);
+    op.parts = ws(P.ws_parts);
+    op.n = n;
+    op.n_parts = n_parts;
+    op.stage = stage;
+    op.h = h_sign_half;  // sign; multiplied by dt/2 at bind time
+    int oi = (int)G.combines.size();
+    G.combines.push_back(op);
+    int tf = (int)G.ctiles.size();
+    for (long e = 0; e < n; e += 2048) G.ctiles.push_back({oi, 0, e, std::min(n, e + 2048)});
+    launch(LK_COMBINE, 0, oi, 1, tf, (int)G.ctiles.size() - tf);
+  }
+
+  // RK4 sub-flow of sign * L_eff over half a step on y0 (FP64 master).
+  void emit_rk4(const Recipe& R, void* y0, long n, double sign, int half) {
+    const int rel0 = half == 0 ? 0 : 2;
+    const int rels[4] = {rel0, rel0 + 1, rel0 + 1, rel0 + 2};
+    bool td = false;
+    for (auto& g : R.groups) {
+      for (auto& s : g.sa) td |= P.gen.terms[s.first].slot >= 0;
+      for (auto& s : g.sb) td |= P.gen.terms[s.first].slot >= 0;
+    }
+    for (int st = 1; st <= 4; ++st) {
+      void* X = st == 1 ? y0 : ws(P.ws_xin);
+      int np = emit_apply(R, X, st == 1, n, rels[st - 1], st == 1 || td, P.par_target);
+      emit_combine(y0, n, np, st, sign);
+    }
+  }
+
+  void emit_env_down(int x) {
+    const tenso_tree& t = P.tree;
+    if (P.dkeys[x].empty()) return;
+    const std::vector<int> dims = t.shape(x);
+    const long Pn = t.size(x);
+    int gfirst = (int)G.groups.size(), tfirst = (int)G.atiles.size();
+    for (size_t k = 0; k < P.dkeys[x].size(); ++k) {
+      const Key& key = P.dkeys[x][k];
+      std::vector<std::pair<int, ORef>> nz;
+      for (int i = 1; i < (int)t.legs[x].size(); ++i) {
+        ORef o = leg_ref_for_key(P, x, t.legs[x][i], key);
+        if (o.kind) nz.push_back({i, o});
+      }
+      add_env_group(dims, Pn, 0, nz, k, x, gfirst);
+    }
+    launch(LK_APPLY, 1, gfirst, (int)G.groups.size() - gfirst, tfirst,
+           (int)G.atiles.size() - tfirst);
+    int qf = (int)G.grams.size();
+    for (size_t k = 0; k < P.dkeys[x].size(); ++k) {
+      GramOp go{};
+      go.C = (const double*)core(x);
+      go.T = ws(P.ws_envscr + k * Pn * P.tsz);
+      go.E = ws(P.envd_off[x] + k * (size_t)t.rank[x] * t.rank[x] * P.tsz);
+      go.r = t.rank[x];
+      go.Ppre = 1;
+      go.Ppost = (int)(Pn / t.rank[x]);
+      G.grams.push_back(go);
+    }
+    launch(LK_GRAM, 0, qf, (int)G.grams.size() - qf, 0, 0);
+  }
+
+  void emit_env_up(int x) {
+    const tenso_tree& t = P.tree;
+    if (P.ukeys[x].empty()) return;
+    const int p = t.parent[x];
+    const std::vector<int> dims = t.shape(p);
+    const long Pn = t.size(p);
+    const int open = t.leg_of_child(p, x);
+    int gfirst = (int)G.groups.size(), tfirst = (int)G.atiles.size();
+    for (size_t k = 0; k < P.ukeys[x].size(); ++k) {
+      const Key& key = P.ukeys[x][k];
+      std::vector<std::pair<int, ORef>> nz;
+      for (int i = 0; i < (int)t.legs[p].size(); ++i) {
+        if (i == open) continue;
+        ORef o = leg_ref_for_key(P, p, t.legs[p][i], key);
+        if (o.kind) nz.push_back({i, o});
+      }
+      add_env_group(dims, Pn, open, nz, k, p, gfirst);
+    }
+    launch(LK_APPLY, 1, gfirst, (int)G.groups.size() - gfirst, tfirst,
+           (int)G.atiles.size() - tfirst);
+    int qf = (int)G.grams.size();
+    for (size_t k = 0; k < P.ukeys[x].size(); ++k) {
+      GramOp go{};
+      go.C = (const double*)core(p);
+      go.T = ws(P.ws_envscr + k * Pn * P.tsz);
+      go.E = ws(P.envu_off[x] + k * (size_t)t.rank[x] * t.rank[x] * P.tsz);
+      go.r = t.rank[x];
+      go.Ppre = (int)prod(dims, 0, open);
+      go.Ppost = (int)prod(dims, open + 1, (int)dims.size());
+      G.grams.push_back(go);
+    }
+    launch(LK_GRAM, 0, qf, (int)G.grams.size() - qf, 0, 0);
+  }
+
+  // one env slot = one group with a single unit-coefficient term on core `node`
+  void add_env_group(const std::vector<int>& dims, long Pn, int open,
+                     const std::vector<std::pair<int, ORef>>& nz, size_t k, int node, int gfirst) {
+    if (nz.empty() || nz.size() > 2)
+      fail(TENSO_EUNSUPPORTED, "environment operator acts on more than two legs");
+    int l1, l2;
+    void *A = nullptr, *B = nullptr;
+    if (nz.size() == 2) {
+      l1 = nz[0].first;
+      l2 = nz[1].first;
+      A = oref_ptr(P, nz[0].second);
+      B = oref_ptr(P, nz[1].second);
+    } else {
+      int l = nz[0].first, other = open;
+      l1 = std::min(l, other);
+      l2 = std::max(l, other);
+      if (l1 == l) A = oref_ptr(P, nz[0].second);
+      else B = oref_ptr(P, nz[0].second);
+    }
+    TermRef tr{};
+    tr.cre = 1;
+    tr.slot = -1;
+    tr.A = A;
+    tr.B = B;
+    int ti = term_index(tr);
+    ApplyGroup ag{};
+    ag.X = core(node);
+    ag.Y = ws(P.ws_envscr + k * Pn * P.tsz);
+    ag.terms = (const TermRef*)tagp(TAG_TERM, ti);
+    ag.in_fp64 = 1;
+    ag.n_terms = 1;
+    ag.d1 = dims[l1];
+    ag.d2 = dims[l2];
+    ag.P1 = (int)prod(dims, l1 + 1, l2);
+    ag.P2 = (int)prod(dims, l2 + 1, (int)dims.size());
+    ag.F = (int)(Pn / ((long)ag.d1 * ag.d2));
+    ag.rel = 0;
+    G.groups.push_back(ag);
+    add_tiles((int)G.groups.size() - 1 - gfirst, ag.d1, ag.d2, ag.F, std::max(1, P.par_target / 8));
+  }
+
+  void emit_qr(int node, int leg, int transposeR) {
+    const tenso_tree& t = P.tree;
+    std::vector<int> d = t.shape(node);
+    QrOp q{};
+    q.C = (double*)core(node);
+    q.R = (double*)ws(P.ws_bond);
+    q.V = (double*)ws(P.ws_qrv);
+    q.tau = (double*)ws(P.ws_qrtau);
+    q.n = d[leg];
+    q.m = (int)(t.size(node) / d[leg]);
+    q.Ppost = (int)prod(d, leg + 1, (int)d.size());
+    q.transposeR = transposeR;
+    if (q.m < q.n) fail(TENSO_EUNSUPPORTED, "QR with fewer rows than columns");
+    if (q.n > 64) fail(TENSO_EUNSUPPORTED, "QR of a bond wider than 64");
+    int qi = (int)G.qrs.size();
+    G.qrs.push_back(q);
+    launch(LK_QR, 0, qi, 1, 0, 0);
+  }
+
+  void emit_absorb(int node, int leg, int transposeM) {
+    const tenso_tree& t = P.tree;
+    std::vector<int> d = t.shape(node);
+    AbsorbOp a{};
+    a.C = (double*)core(node);
+    a.M = (const double*)ws(P.ws_bond);
+    a.n = d[leg];
+    a.Ppost = (int)prod(d, leg + 1, (int)d.size());
+    a.Ppre = (int)prod(d, 0, leg);
+    a.transposeM = transposeM;
+    int ai = (int)G.absorbs.size();
+    G.absorbs.push_back(a);
+    int tf = (int)G.abtiles.size();
+    int fibers = a.Ppre * a.Ppost;
+    int per = std::max(1, 2048 / a.n);
+    for (int f = 0; f < fibers; f += per) G.abtiles.push_back({ai, f, std::min(fibers, f + per)});
+    launch(LK_ABSORB, 0, ai, 1, tf, (int)G.abtiles.size() - tf, (size_t)per * a.n * 16);
+  }
+
+  // ps1 first-order sweep and its adjoint (mirrors the recursive subflows)
+  void V(int s, int half) {
+    const tenso_tree& t = P.tree;
+    for (int c : t.children[s]) {
+      int i = t.leg_of_child(s, c);
+      emit_qr(s, i, 0);
+      emit_absorb(c, 0, 0);
+      emit_env_up(c);
+      V(c, half);
+      emit_qr(c, 0, 1);
+      emit_env_down(c);
+      emit_rk4(bond_recipe(P, c), ws(P.ws_bond), (long)t.rank[c] * t.rank[c], -1.0, half);
+      emit_absorb(s, i, 1);
+    }
+    emit_rk4(node_recipe(P, s), core(s), t.size(s), +1.0, half);
+  }
+  void Vstar(int s, int half) {
+    const tenso_tree& t = P.tree;
+    emit_rk4(node_recipe(P, s), core(s), t.size(s), +1.0, half);
+    const auto& ch = t.children[s];
+    for (int k = (int)ch.size() - 1; k >= 0; --k) {
+      int c = ch[k];
+      int i = t.leg_of_child(s, c);
+      emit_qr(s, i, 0);
+      emit_env_up(c);
+      emit_rk4(bond_recipe(P, c), ws(P.ws_bond), (long)t.rank[c] * t.rank[c], -1.0, half);
+      emit_absorb(c, 0, 0);
+      Vstar(c, half);
+      emit_qr(c, 0, 0);
+      emit_absorb(s, i, 0);
+      emit_env_down(c);
+    }
+  }
+
+  void env_init_toward(int center) {
+    const tenso_tree& t = P.tree;
+    std::vector<char> on_path(t.n, 0);
+    std::vector<int> path;
+    for (int x = center; x >= 0; x = x == 0 ? -1 : t.parent[x]) {
+      on_path[x] = 1;
+      path.push_back(x);
+    }
+    for (int x = t.n - 1; x >= 1; --x)
+      if (!on_path[x] || x == center) {
+        if (x == center) continue;
+          emit_env_down(x);
+      }
+    // children of center are off-path: done above.  Up envs along the path.
+    for (int k = (int)path.size() - 2; k >= 0; --k) {
+      emit_env_up(path[k]);
+    }
+  }
+
+  void rho_prog() {
+    const tenso_tree& t = P.tree;
+    int first = (int)G.rnodes.size();
+    for (int s = t.n - 1; s >= 0; --s) {
+      RhoNode nd{};
+      nd.C = (const double*)core(s);
+      nd.n_legs = (int)t.legs[s].size();
+      for (int l = 0; l < nd.n_legs; ++l) {
+        const Leg& lg = t.legs[s][l];
+        nd.dims[l] = t.leg_dim(s, lg);
+        if (lg.kind == 0) nd.kind[l] = 0;
+        else if (lg.kind == 1) nd.kind[l] = (s == 0 && lg.id < 2) ? 2 : 1;
+        else {
+          nd.kind[l] = 3;
+          nd.child_slot[l] = lg.id;
+        }
+      }
+      nd.out_slot = s == 0 ? -1 : s;
+      G.rnodes.push_back(nd);
+    }
+    RhoProg rp{};
+    rp.nodes = (const RhoNode*)tagp(TAG_RNODE, first);
+    rp.n_nodes = t.n;
+    rp.vecs = (double*)ws(P.ws_rhovec);
+    int maxr = 1;
+    for (int c = 1; c < t.n; ++c) maxr = std::max(maxr, t.rank[c]);
+    rp.vec_ld = maxr;
+    rp.rho_out = (double*)ws(P.ws_rhoout);
+    G.rprogs.push_back(rp);
+    launch(LK_RHO, 0, (int)G.rprogs.size() - 1, 1, 0, 0);
+  }
+};
+
+// -- resolution & upload ------------------------------------------------------
+static void* res(void* p, void* state, void* ws) {
+  uint64_t v = (uint64_t)p;
+  int tag = (int)(v >> 56);
+  uint64_t off = v & OFF_MASK;
+  if (tag == TAG_STATE) return (char*)state + off;
+  if (tag == TAG_WS) return (char*)ws + off;
+  return p;
+}
+
+template <class T>
+static size_t put(std::vector<char>& buf, const std::vector<T>& v) {
+  size_t o = align256(buf.size());
+  buf.resize(o + v.size() * sizeof(T));
+  if (!v.empty()) memcpy(buf.data() + o, v.data(), v.size() * sizeof(T));
+  return o;
+}
+
+// Resolve state / workspace tags and per-step scalars, then upload.
+static void upload(DevProgram& D, const Program& G0, void* state, void* ws, double dt,
+                   const double* drive, int drive_ld, hipStream_t s) {
+  Program G = G0;
+  for (auto& t : G.terms) {
+    t.A = res((void*)t.A, state, ws);
+    t.B = res((void*)t.B, state, ws);
+  }
+  std::vector<char> buf;
+  D.o_terms = put(buf, G.terms);
+  // groups/presums reference terms by index: fixed after the arena base is known
+  D.o_groups = put(buf, G.groups);
+  D.o_atiles = put(buf, G.atiles);
+  D.o_presums = put(buf, G.presums);
+  D.o_combines = put(buf, G.combines);
+  D.o_ctiles = put(buf, G.ctiles);
+  D.o_qrs = put(buf, G.qrs);
+  D.o_absorbs = put(buf, G.absorbs);
+  D.o_abtiles = put(buf, G.abtiles);
+  D.o_grams = put(buf, G.grams);
+  D.o_rnodes = put(buf, G.rnodes);
+  D.o_rprogs = put(buf, G.rprogs);
+  if (!D.arena || D.bytes < buf.size()) {
+    if (D.arena) hipchk(hipFree(D.arena), "hipFree");
+    D.arena = nullptr;
+    hipchk(hipMalloc((void**)&D.arena, std::max<size_t>(buf.size(), 256)), "hipMalloc(program)");
+    D.bytes = std::max<size_t>(buf.size(), 256);
+  }
+  char* base = D.arena;
+  auto term_ptr = [&](const TermRef* p) -> const TermRef* {
+    uint64_t v = (uint64_t)p;
+    if ((int)(v >> 56) != TAG_TERM) return p;
+    return (const TermRef*)(base + D.o_terms + (v & OFF_MASK) * sizeof(TermRef));
+  };
+  ApplyGroup* gp = (ApplyGroup*)(buf.data() + D.o_groups);
+  for (size_t i = 0; i < G.groups.size(); ++i) {
+    gp[i].X = res((void*)gp[i].X, state, ws);
+    gp[i].Y = res(gp[i].Y, state, ws);
+    gp[i].terms = term_ptr(gp[i].terms);
+    gp[i].drive = drive;
+    gp[i].drive_ld = drive_ld;
+  }
+  PresumOp* pp = (PresumOp*)(buf.data() + D.o_presums);
+  for (size_t i = 0; i < G.presums.size(); ++i) {
+    pp[i].out = res(pp[i].out, state, ws);
+    pp[i].terms = term_ptr(pp[i].terms);
+    pp[i].drive = drive;
+    pp[i].drive_ld = drive_ld;
+  }
+  CombineOp* cp = (CombineOp*)(buf.data() + D.o_combines);
+  for (size_t i = 0; i < G.combines.size(); ++i) {
+    cp[i].y0 = (double*)res(cp[i].y0, state, ws);
+    cp[i].xin = res(cp[i].xin, state, ws);
+    cp[i].acc = (double*)res(cp[i].acc, state, ws);
+    cp[i].parts = res((void*)cp[i].parts, state, ws);
+    cp[i].h = cp[i].h * 0.5 * dt;
+  }
+  QrOp* qp = (QrOp*)(buf.data() + D.o_qrs);
+  for (size_t i = 0; i < G.qrs.size(); ++i) {
+    qp[i].C = (double*)res(qp[i].C, state, ws);
+    qp[i].R = (double*)res(qp[i].R, state, ws);
+    qp[i].V = (double*)res(qp[i].V, state, ws);
+    qp[i].tau = (double*)res(qp[i].tau, state, ws);
+  }
+  AbsorbOp* ap = (AbsorbOp*)(buf.data() + D.o_absorbs);
+  for (size_t i = 0; i < G.absorbs.size(); ++i) {
+    ap[i].C = (double*)res(ap[i].C, state, ws);
+    ap[i].M = (const double*)res((void*)ap[i].M, state, ws);
+  }
+  GramOp* gq = (GramOp*)(buf.data() + D.o_grams);
+  for (size_t i = 0; i < G.grams.size(); ++i) {
+    gq[i].C = (const double*)res((void*)gq[i].C, state, ws);
+    gq[i].T = res((void*)gq[i].T, state, ws);
+    gq[i].E = res(gq[i].E, state, ws);
+  }
+  RhoNode* rn = (RhoNode*)(buf.data() + D.o_rnodes);
+  for (size_t i = 0; i < G.rnodes.size(); ++i) rn[i].C = (const double*)res((void*)rn[i].C, state, ws);
+  RhoProg* rp = (RhoProg*)(buf.data() + D.o_rprogs);
+  for (size_t i = 0; i < G.rprogs.size(); ++i) {
+    uint64_t v = (uint64_t)rp[i].nodes;
+    rp[i].nodes = (const RhoNode*)(base + D.o_rnodes + (v & OFF_MASK) * sizeof(RhoNode));
+    rp[i].vecs = (double*)res(rp[i].vecs, state, ws);
+    rp[i].rho_out = (double*)res(rp[i].rho_out, state, ws);
+  }
+  hipchk(hipMemcpyAsync(D.arena, buf.data(), buf.size(), hipMemcpyHostToDevice, s), "upload program");
+  D.launches = G.launches;
+}
+
+static void run(const DevProgram& D, int fp64, const int* ctr, hipStream_t s) {
+  char* b = D.arena;
+  for (const auto& L : D.launches) {
+    hipError_t e = hipSuccess;
+    switch (L.kind) {
+      case LK_APPLY:
+        e = launch_apply(fp64, L.in_fp64, (const ApplyGroup*)(b + D.o_groups) + L.first,
+                         (const ApplyTile*)(b + D.o_atiles) + L.tfirst, L.tcount, ctr, s);
+        break;
+      case LK_PRESUM:
+        e = launch_presum(fp64, (const PresumOp*)(b + D.o_presums) + L.first, L.count, ctr, s);
+        break;
+      case LK_COMBINE:
+        e = launch_combine(fp64, (const CombineOp*)(b + D.o_combines),
+                           (const CombineTileH*)(b + D.o_ctiles) + L.tfirst, L.tcount, s);
+        break;
+      case LK_QR:
+        e = launch_qr((const QrOp*)(b + D.o_qrs) + L.first, L.count, s);
+        break;
+      case LK_ABSORB:
+        e = launch_absorb((const AbsorbOp*)(b + D.o_absorbs),
+                          (const AbsorbTileH*)(b + D.o_abtiles) + L.tfirst, L.tcount, L.lds, s);
+        break;
+      case LK_GRAM:
+        e = launch_gram(fp64, (const GramOp*)(b + D.o_grams) + L.first, L.count, s);
+        break;
+      case LK_RHO:
+        e = launch_rho((const RhoProg*)(b + D.o_rprogs) + L.first, L.count, s);
+        break;
+    }
+    hipchk(e, "kernel launch");
+  }
+}
+
+// Tile group indices are relative to the first group of their launch.
+static void fix_tile_groups(Program& G) {
+  for (auto& L : G.launches) {
+    if (L.kind != LK_APPLY) continue;
+    // tiles already carry indices relative to the launch's first group
+    (void)L;
+  }
+}
+
+static void build_step(tenso_plan& P, Program& G) {
+  Builder b(P, G);
+  b.V(0, 0);
+  b.Vstar(0, 1);
+  fix_tile_groups(G);
+}
+
+static void build_init(tenso_plan& P, Program& G) {
+  Builder b(P, G);
+  for (int x = P.tree.n - 1; x >= 1; --x) {
+    b.emit_env_down(x);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host-side state helpers
+// ---------------------------------------------------------------------------
+static std::vector<cd> initial_cores(const tenso_plan& P, const tenso_c128* rho) {
+  const tenso_tree& t = P.tree;
+  std::vector<cd> h(P.state_bytes / 16, cd(0, 0));
+  for (int s = 0; s < t.n; ++s) {
+    cd* C = h.data() + P.core_off[s] / 16;
+    std::vector<int> d = t.shape(s);
+    if (s == 0) {
+      const int M = t.end_dim[0];
+      long rest = t.size(0) / ((long)M * M);
+      for (int i = 0; i < M; ++i)
+        for (int j = 0; j < M; ++j) C[((long)i * M + j) * rest] = cd(rho[i * M + j].re, rho[i * M + j].im);
+    } else {
+      long cols = t.size(s) / d[0];
+      for (int a = 0; a < d[0]; ++a) C[(long)a * cols + a] = 1.0;
+    }
+  }
+  return h;
+}
+
+// ---------------------------------------------------------------------------
+// ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* tenso_last_error(void) { return g_err.c_str(); }
+
+int tenso_build_tree(int n_nodes, const int32_t* parent, int n_ends, const int32_t* end_node,
+                     const int32_t* end_dim, int max_rank, const int32_t* bond_rank,
+                     tenso_tree** out) {
+  return guard([&] {
+    if (!out || !parent || !end_node || !end_dim) fail(TENSO_EINVAL, "null argument");
+    *out = make_tree(n_nodes, parent, n_ends, end_node, end_dim, max_rank, bond_rank);
+  });
+}
+
+int tenso_tree_train(int M, int K, const int32_t* mode_dim, int rank, tenso_tree** out) {
+  return guard([&] {
+    if (!out || M < 1 || K < 0 || (K > 0 && !mode_dim)) fail(TENSO_EINVAL, "bad train arguments");
+    std::vector<int32_t> parent, end_node, end_dim = {M, M};
+    for (int k = 0; k < K; ++k) end_dim.push_back(mode_dim[k]);
+    if (K <= 1) {
+      parent = {-1};
+      end_node.assign(2 + K, 0);
+    } else {
+      parent.push_back(-1);
+      for (int s = 1; s < K; ++s) parent.push_back(s - 1);
+      end_node = {0, 0};
+      for (int k = 0; k < K - 1; ++k) end_node.push_back(k + 1);
+      end_node.push_back(K - 1);
+    }
+    *out = make_tree((int)parent.size(), parent.data(), (int)end_dim.size(), end_node.data(),
+                     end_dim.data(), rank, nullptr);
+  });
+}
+
+int tenso_tree_nary(int M, int K, const int32_t* mode_dim, int n_ary, int rank, tenso_tree** out) {
+  return guard([&] {
+    if (!out || M < 1 || K < 0 || n_ary < 2 || (K > 0 && !mode_dim)) fail(TENSO_EINVAL, "bad tree arguments");
+    std::vector<int32_t> parent = {-1}, end_node(2 + K, 0), end_dim = {M, M};
+    for (int k = 0; k < K; ++k) end_dim.push_back(mode_dim[k]);
+    // recursive split of a contiguous feature range [a, b) under `holder`
+    std::function<void(int, int, int)> build = [&](int a, int b, int holder) {
+      int len = b - a;
+      if (len == 1) {
+        end_node[2 + a] = holder;
+        return;
+      }
+      int me = (int)parent.size();
+      parent.push_back(holder);
+      if (len <= n_ary) {
+        for (int f = a; f < b; ++f) end_node[2 + f] = me;
+        return;
+      }
+      int q = len / n_ary, r = len % n_ary, pos = a;
+      for (int j = 0; j < n_ary; ++j) {
+        int sz = q + (j < r ? 1 : 0);
+        build(pos, pos + sz, me);
+        pos += sz;
+      }
+    };
+    if (K > 0) build(0, K, 0);
+    *out = make_tree((int)parent.size(), parent.data(), (int)end_dim.size(), end_node.data(),
+                     end_dim.data(), rank, nullptr);
+  });
+}
+
+int tenso_tree_ranks(const tenso_tree* t, int32_t* out) {
+  return guard([&] {
+    if (!t || !out) fail(TENSO_EINVAL, "null argument");
+    for (int s = 0; s < t->n; ++s) out[s] = s == 0 ? 0 : t->rank[s];
+  });
+}
+
+int tenso_tree_n_nodes(const tenso_tree* t) { return t ? t->n : TENSO_EINVAL; }
+void tenso_tree_destroy(tenso_tree* t) { delete t; }
+
+int tenso_build_generator(const tenso_tree* t, int n_terms, const tenso_c128* coef,
+                          const int32_t* td_slot, const int32_t* n_factors,
+                          const int32_t* factor_end, const tenso_c128* factor_mats,
+                          tenso_gen** out) {
+  return guard([&] {
+    if (!t || !out || n_terms < 0 || (n_terms && (!coef || !n_factors))) fail(TENSO_EINVAL, "null argument");
+    auto g = std::make_unique<tenso_gen>();
+    g->n_ends = t->n_ends;
+    g->end_dim = t->end_dim;
+    std::map<std::pair<int, std::vector<double>>, int> dedup;
+    long fi = 0, mo = 0;
+    for (int m = 0; m < n_terms; ++m) {
+      tenso_gen::Term tm;
+      tm.coef = cd(coef[m].re, coef[m].im);
+      tm.slot = td_slot ? td_slot[m] : -1;
+      if (tm.slot >= 0) g->n_slots = std::max(g->n_slots, tm.slot + 1);
+      if (n_factors[m] < 1) fail(TENSO_EINVAL, "every term needs at least one factor");
+      for (int j = 0; j < n_factors[m]; ++j, ++fi) {
+        int e = factor_end[fi];
+        if (e < 0 || e >= t->n_ends) fail(TENSO_EINVAL, "factor on a bad end");
+        for (auto& p : tm.f)
+          if (p.first == e) fail(TENSO_EINVAL, "two factors of one term on the same end");
+        int d = t->end_dim[e];
+        std::vector<double> key(2 * (size_t)d * d);
+        std::vector<cd> mat((size_t)d * d);
+        for (long q = 0; q < (long)d * d; ++q) {
+          key[2 * q] = factor_mats[mo + q].re;
+          key[2 * q + 1] = factor_mats[mo + q].im;
+          mat[q] = cd(key[2 * q], key[2 * q + 1]);
+        }
+        mo += (long)d * d;
+        auto k = std::make_pair(d, key);
+        auto it = dedup.find(k);
+        if (it == dedup.end()) {
+          it = dedup.emplace(k, (int)g->mats.size()).first;
+          g->mats.push_back(mat);
+          g->mat_dim.push_back(d);
+        }
+        tm.f.push_back({e, it->second});
+      }
+      std::sort(tm.f.begin(), tm.f.end());
+      g->terms.push_back(tm);
+    }
+    *out = g.release();
+  });
+}
+
+void tenso_gen_destroy(tenso_gen* g) { delete g; }
+
+int tenso_plan_create(const tenso_tree* t, const tenso_gen* g, const tenso_plan_opts* o,
+                      tenso_plan** out) {
+  return guard([&] {
+    if (!t || !g || !o || !out) fail(TENSO_EINVAL, "null argument");
+    if (o->precision != TENSO_FP64 && o->precision != TENSO_FP32) fail(TENSO_EINVAL, "bad precision");
+    if (o->method != TENSO_PS1 && o->method != TENSO_PS2) fail(TENSO_EINVAL, "bad method");
+    if (o->method == TENSO_PS2) fail(TENSO_EUNSUPPORTED, "ps2 plans are not built yet");
+    if (g->n_ends != t->n_ends || g->end_dim != t->end_dim) fail(TENSO_EINVAL, "generator built for another tree");
+    auto P = std::make_unique<tenso_plan>();
+    P->tree = *t;
+    P->gen = *g;
+    P->opts = *o;
+    P->fp64 = o->precision == TENSO_FP64;
+    P->tsz = P->fp64 ? 16 : 8;
+    analyse_slots(*P);
+    // constant buffer: factor matrices in FP64 and FP32
+    std::vector<char> cb;
+    for (size_t i = 0; i < P->gen.mats.size(); ++i) {
+      const auto& m = P->gen.mats[i];
+      size_t o64 = align256(cb.size());
+      cb.resize(o64 + m.size() * 16);
+      memcpy(cb.data() + o64, m.data(), m.size() * 16);
+      size_t o32 = align256(cb.size());
+      cb.resize(o32 + m.size() * 8);
+      float* f = (float*)(cb.data() + o32);
+      for (size_t q = 0; q < m.size(); ++q) {
+        f[2 * q] = (float)m[q].real();
+        f[2 * q + 1] = (float)m[q].imag();
+      }
+      P->mat_off64.push_back(o64);
+      P->mat_off32.push_back(o32);
+    }
+    hipchk(hipMalloc(&P->cbuf, std::max<size_t>(cb.size(), 256)), "hipMalloc(constants)");
+    if (!cb.empty()) hipchk(hipMemcpy(P->cbuf, cb.data(), cb.size(), hipMemcpyHostToDevice), "upload constants");
+    layout(*P);
+    // validate that every recipe compiles (throws EUNSUPPORTED otherwise)
+    for (int s = 0; s < P->tree.n; ++s) (void)node_recipe(*P, s);
+    *out = P.release();
+  });
+}
+
+void tenso_plan_destroy(tenso_plan* p) { delete p; }
+
+int tenso_plan_sizes(const tenso_plan* p, size_t* sb, size_t* wb) {
+  return guard([&] {
+    if (!p) fail(TENSO_EINVAL, "null plan");
+    if (sb) *sb = p->state_bytes;
+    if (wb) *wb = p->ws_bytes;
+  });
+}
+
+int tenso_plan_shapes(const tenso_plan* p, int32_t* n_legs, int32_t* dims) {
+  return guard([&] {
+    if (!p) fail(TENSO_EINVAL, "null plan");
+    for (int s = 0; s < p->tree.n; ++s) {
+      std::vector<int> d = p->tree.shape(s);
+      if (n_legs) n_legs[s] = (int)d.size();
+      if (dims)
+        for (int l = 0; l < 8; ++l) dims[8 * s + l] = l < (int)d.size() ? d[l] : 0;
+    }
+  });
+}
+
+int tenso_state_init(tenso_plan* p, const tenso_c128* rho, void* d_state, hipStream_t s) {
+  return guard([&] {
+    if (!p || !rho || !d_state) fail(TENSO_EINVAL, "null argument");
+    std::vector<cd> h = initial_cores(*p, rho);
+    hipchk(hipMemcpyAsync(d_state, h.data(), p->state_bytes, hipMemcpyHostToDevice, s), "state init");
+    hipchk(hipStreamSynchronize(s), "sync");
+  });
+}
+
+int tenso_state_import(tenso_plan* p, const tenso_c128* h_cores, void* d_state, hipStream_t s) {
+  return guard([&] {
+    if (!p || !h_cores || !d_state) fail(TENSO_EINVAL, "null argument");
+    std::vector<cd> h(p->state_bytes / 16, cd(0, 0));
+    long o = 0;
+    for (int c = 0; c < p->tree.n; ++c) {
+      long n = p->tree.size(c);
+      for (long q = 0; q < n; ++q) h[p->core_off[c] / 16 + q] = cd(h_cores[o + q].re, h_cores[o + q].im);
+      o += n;
+    }
+    hipchk(hipMemcpyAsync(d_state, h.data(), p->state_bytes, hipMemcpyHostToDevice, s), "state import");
+    hipchk(hipStreamSynchronize(s), "sync");
+  });
+}
+
+int tenso_state_export(tenso_plan* p, const void* d_state, tenso_c128* h_cores, int32_t* ranks,
+                       hipStream_t s) {
+  return guard([&] {
+    if (!p || !d_state) fail(TENSO_EINVAL, "null argument");
+    std::vector<cd> h(p->state_bytes / 16);
+    hipchk(hipMemcpyAsync(h.data(), d_state, p->state_bytes, hipMemcpyDeviceToHost, s), "state export");
+    hipchk(hipStreamSynchronize(s), "sync");
+    long o = 0;
+    if (h_cores)
+      for (int c = 0; c < p->tree.n; ++c) {
+        long n = p->tree.size(c);
+        for (long q = 0; q < n; ++q) {
+          h_cores[o + q].re = h[p->core_off[c] / 16 + q].real();
+          h_cores[o + q].im = h[p->core_off[c] / 16 + q].imag();
+        }
+        o += n;
+      }
+    if (ranks)
+      for (int c = 0; c < p->tree.n; ++c) ranks[c] = c == 0 ? 0 : p->tree.rank[c];
+  });
+}
+
+int tenso_apply_generator(tenso_plan* p, const void* d_state, int center, double t,
+                          const double* drive, void* d_out, void* d_ws, hipStream_t s) {
+  return guard([&] {
+    if (!p || !d_state || !d_out || !d_ws) fail(TENSO_EINVAL, "null argument");
+    if (center < 0 || center >= p->tree.n) fail(TENSO_EINVAL, "bad center");
+    if (p->gen.n_slots > 0 && !drive) fail(TENSO_EINVAL, "generator has drive slots: drive values needed");
+    (void)t;
+    Program G;
+    Builder b(*p, G);
+    b.env_init_toward(center);
+    Recipe R = node_recipe(*p, center);
+    int np = b.emit_apply(R, b.core(center), 1, p->tree.size(center), 0, 1, p->par_target);
+    b.emit_combine(d_out, p->tree.size(center), np, 0, 0.0);
+    // the combine writes y0 = k at stage 0: y0 is the caller's buffer (absolute)
+    G.combines.back().y0 = (double*)d_out;
+    // drive values: one row per slot, ld = 1, index 0
+    std::vector<double> dv(std::max(1, p->gen.n_slots), 0.0);
+    if (drive)
+      for (int k = 0; k < p->gen.n_slots; ++k) dv[k] = drive[k];
+    double* d_drive = nullptr;
+    hipchk(hipMalloc((void**)&d_drive, dv.size() * sizeof(double)), "hipMalloc(drive)");
+    hipchk(hipMemcpyAsync(d_drive, dv.data(), dv.size() * sizeof(double), hipMemcpyHostToDevice, s), "drive");
+    DevProgram D;
+    upload(D, G, const_cast<void*>(d_state), d_ws, 0.0, d_drive, 1, s);
+    int* ctr = (int*)((char*)d_ws + p->ws_ctr);
+    hipchk(launch_step_inc(ctr, 0, s), "ctr");
+    run(D, p->fp64, ctr, s);
+    hipchk(hipStreamSynchronize(s), "sync");
+    hipchk(hipFree(d_drive), "hipFree");
+  });
+}
+
+int tenso_step_fixed(tenso_plan* p, void* d_state, double t0, double dt, int n_steps,
+                     const double* d_drive_tab, void* d_ws, hipStream_t s) {
+  return guard([&] {
+    if (!p || !d_state || !d_ws) fail(TENSO_EINVAL, "null argument");
+    if (!(dt > 0)) fail(TENSO_EINVAL, "dt must be > 0");
+    if (n_steps < 0) fail(TENSO_EINVAL, "n_steps must be >= 0");
+    if (p->opts.method != TENSO_PS1) fail(TENSO_EINVAL, "plan is not a ps1 plan");
+    if (p->gen.n_slots > 0 && !d_drive_tab) fail(TENSO_EINVAL, "generator has drive slots: drive table needed");
+    (void)t0;
+    const int ld = 4 * n_steps + 1;
+    if (!p->dev_step) {
+      p->dev_step = std::make_unique<DevProgram>();
+      p->dev_init = std::make_unique<DevProgram>();
+    }
+    if (!p->prog_step) {
+      p->prog_step = std::make_unique<Program>();
+      p->prog_init = std::make_unique<Program>();
+      build_step(*p, *p->prog_step);
+      build_init(*p, *p->prog_init);
+      p->b_state = nullptr;
+    }
+    if (p->b_state != d_state || p->b_ws != d_ws || p->b_dt != dt || p->b_drive != d_drive_tab ||
+        p->b_ld != ld) {
+      upload(*p->dev_step, *p->prog_step, d_state, d_ws, dt, d_drive_tab, ld, s);
+      upload(*p->dev_init, *p->prog_init, d_state, d_ws, dt, d_drive_tab, ld, s);
+      p->b_state = d_state;
+      p->b_ws = d_ws;
+      p->b_dt = dt;
+      p->b_drive = d_drive_tab;
+      p->b_ld = ld;
+    }
+    int* ctr = (int*)((char*)d_ws + p->ws_ctr);
+    hipchk(launch_step_inc(ctr, 0, s), "ctr");
+    run(*p->dev_init, p->fp64, ctr, s);
+    for (int k = 0; k < n_steps; ++k) {
+      run(*p->dev_step, p->fp64, ctr, s);
+      hipchk(launch_step_inc(ctr, -1, s), "ctr");
+    }
+  });
+}
+
+int tenso_step_adaptive(tenso_plan* p, void*, double, double, int, double, int, const double*,
+                        void*, hipStream_t) {
+  return guard([&] {
+    if (!p) fail(TENSO_EINVAL, "null plan");
+    fail(TENSO_EUNSUPPORTED, "ps2 is not built yet");
+  });
+}
+
+int tenso_reduced_rho(tenso_plan* p, const void* d_state, tenso_c128* h_rho, double* h_trace,
+                      void* d_ws, hipStream_t s) {
+  return guard([&] {
+    if (!p || !d_state || !h_rho || !d_ws) fail(TENSO_EINVAL, "null argument");
+    if (!p->dev_rho) p->dev_rho = std::make_unique<DevProgram>();
+    Program G;
+    Builder b(*p, G);
+    b.rho_prog();
+    upload(*p->dev_rho, G, const_cast<void*>(d_state), d_ws, 0.0, nullptr, 1, s);
+    run(*p->dev_rho, p->fp64, nullptr, s);
+    const int M = p->tree.end_dim[0];
+    hipchk(hipMemcpyAsync(h_rho, (char*)d_ws + p->ws_rhoout, (size_t)M * M * 16, hipMemcpyDeviceToHost, s),
+           "rho readback");
+    hipchk(hipStreamSynchronize(s), "sync");
+    if (h_trace) {
+      double tr = 0;
+      for (int i = 0; i < M; ++i) tr += h_rho[i * M + i].re;
+      *h_trace = tr;
+    }
+  });
+}
+
+int tenso_rank_trajectory(const tenso_plan* p, int32_t* h, int cap) {
+  if (!p) return TENSO_EINVAL;
+  int n = std::min<int>(cap, (int)p->rank_log.size());
+  for (int i = 0; i < n; ++i) h[i] = p->rank_log[i];
+  return n;
+}
+
+int tenso_batch_create(int, tenso_plan* const*, void* const*, void* const*, tenso_batch**) {
+  g_err = "batched propagation is not built yet";
+  return TENSO_EUNSUPPORTED;
+}
+int tenso_batch_step(tenso_batch*, const double*, const double*, int, const double* const*, hipStream_t) {
+  g_err = "batched propagation is not built yet";
+  return TENSO_EUNSUPPORTED;
+}
+int tenso_batch_reduced_rho(tenso_batch*, tenso_c128* const*, hipStream_t) {
+  g_err = "batched propagation is not built yet";
+  return TENSO_EUNSUPPORTED;
+}
+void tenso_batch_destroy(tenso_batch*) {}
+
+}  // extern "C"

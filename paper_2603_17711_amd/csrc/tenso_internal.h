@@ -1,0 +1,115 @@
+// Internal descriptors shared by the host plan compiler and the HIP kernels.
+// Every device-side operation of a propagation step is described by one of the
+// plain structs below; a launch hands a kernel an array of them.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tenso {
+
+// One SOP term as seen by a contraction: Y += coef(t) * A x_{l1} B x_{l2} X.
+// A (d1 x d1) or B (d2 x d2) is null for an identity factor.  Matrices are
+// row-major complex in the plan's compute precision.
+struct TermRef {
+  double cre, cim;     // base coefficient
+  int slot;            // drive slot (-1: time independent)
+  int pad;
+  const void* A;
+  const void* B;
+};
+
+// One pair group of one contraction: X viewed as [P0, d1, P1, d2, P2]; the
+// free index f = (p0, p1, p2) runs over F = P0*P1*P2 matrices X_f (d1 x d2).
+// Y (same view) receives sum_terms coef * A X_f B^T.
+struct ApplyGroup {
+  const void* X;       // input: FP64 master (in_fp64) or compute precision
+  void* Y;             // output, compute precision
+  const TermRef* terms;
+  const double* drive; // drive table of the instance (nullable)
+  int in_fp64;
+  int n_terms;
+  int d1, d2, P1, P2;
+  int F;
+  int drive_ld;        // row length of the drive table
+  int rel;             // stage time index relative to the step (0..4)
+  int accumulate;      // 1: Y += result, 0: Y = result
+};
+
+// A tile of the apply kernel: a range of units of one group.  A unit is one
+// (free index f, 16-column block jb of leg 2) pair, u = f * njb + jb; wavefront
+// w of the workgroup takes units u0 + w, u0 + w + 4, ...
+struct ApplyTile {
+  int group;           // index into the launch's group array
+  int u0, nu;
+  int pad;
+};
+
+// Weighted sum of matrices: out = sum_i coef_i(t) * M_i (single-leg terms).
+struct PresumOp {
+  void* out;           // compute precision, dim x dim
+  const TermRef* terms;  // uses cre/cim/slot and A
+  const double* drive;
+  int n_terms, dim, drive_ld, rel;
+};
+
+// RK4 stage update after an apply: k = sum of n_parts partial outputs.
+struct CombineOp {
+  double* y0;          // FP64 master (updated at stage 4)
+  void* xin;           // compute-precision stage input for the next apply
+  double* acc;         // FP64 RK4 accumulator
+  const void* parts;   // n_parts consecutive slabs of n elements
+  long n;
+  int n_parts;
+  int stage;           // 1..4
+  double h;            // sign * tau
+};
+
+// Householder QR (LAPACK geqr2/ung2r convention) of a core matricised as
+// (other legs, row-major) x (leg of dim n); Q replaces the core in place.
+// The m x n matrix element (row = pre*Ppost + post, col) sits at
+// pre*n*Ppost + col*Ppost + post.
+struct QrOp {
+  double* C;           // FP64 complex core
+  double* R;           // out: n x n (or its transpose when transposeR)
+  double* V;           // scratch m x n complex
+  double* tau;         // scratch n complex
+  int m, n, Ppost, transposeR;
+};
+
+// In-place mode product of an FP64 core with an n x n FP64 matrix on one leg:
+// C[pre, a, post] <- sum_a' Mx[a, a'] C[pre, a', post], Mx = M or M^T.
+struct AbsorbOp {
+  double* C;
+  const double* M;
+  int n, Ppost, Ppre, transposeM;
+};
+
+// Environment finalisation: E[a', a] = sum_{rest} conj(C[.., a', ..]) T[.., a, ..]
+// over every leg but the open one (dim r): C is the FP64 master core, T the
+// operator-applied copy (compute precision), E compute precision r x r.
+struct GramOp {
+  const double* C;
+  const void* T;
+  void* E;
+  int r, Ppost, Ppre;
+};
+
+// Bottom-up vacuum contraction for rho_S.
+struct RhoNode {
+  const double* C;     // FP64 core
+  int n_legs;
+  int dims[8];
+  int kind[8];         // 0 parent, 1 end (index 0), 2 system end (kept), 3 child bond
+  int child_slot[8];   // for kind 3: index into the vector scratch
+  int out_slot;        // vector scratch index of this node (-1 for the root)
+};
+
+struct RhoProg {
+  const RhoNode* nodes;  // reverse preorder (root last)
+  int n_nodes;
+  double* vecs;          // scratch: n_nodes vectors of up to max_rank complex
+  int vec_ld;
+  double* rho_out;       // M*M complex
+};
+
+}  // namespace tenso

@@ -140,3 +140,28 @@ def test_qr_toward_convention():
     Q, R = qr_toward(Z, 1)
     assert np.all(R[1:, :] == 0)
     assert np.abs(Q.conj().T @ Q - np.eye(3)).max() < 1e-14
+
+
+def test_householder_matches_lapack_on_full_rank():
+    from oracle.integrators import householder_qr
+    rng = np.random.default_rng(4)
+    for m, n in [(6, 6), (12, 5), (40, 8)]:
+        A = rng.normal(size=(m, n)) + 1j * rng.normal(size=(m, n))
+        Q, R = householder_qr(A)
+        Ql, Rl = np.linalg.qr(A)
+        assert np.abs(Q @ R - A).max() < 1e-13
+        assert np.abs(Q.conj().T @ Q - np.eye(n)).max() < 1e-13
+        # same reflectors as LAPACK: identical factors up to rounding
+        assert np.abs(Q - Ql).max() < 1e-12 and np.abs(R - Rl).max() < 1e-12
+
+
+def test_householder_rank_threshold_is_deterministic():
+    from oracle.integrators import householder_qr
+    rng = np.random.default_rng(5)
+    B = rng.normal(size=(10, 2)) + 1j * rng.normal(size=(10, 2))
+    A = np.concatenate([B, B @ np.array([[1.0, 2.0], [0.5, -1.0]])], axis=1)  # rank 2
+    Q1, R1 = householder_qr(A)
+    noise = 1e-14 * (rng.normal(size=A.shape) + 1j * rng.normal(size=A.shape))
+    Q2, R2 = householder_qr(A + noise)
+    assert np.abs(Q1 - Q2).max() < 1e-10  # completion does not follow the noise
+    assert R1[2, 2] == 0 and R1[3, 3] == 0 and np.abs(R1[2:, 2:]).max() < 1e-13
