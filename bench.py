@@ -1,0 +1,146 @@
+"""Benchmark: TTN-HEOM steps/sec on one MI355X (mixed precision) vs the FP64
+GPU path, with the SOP-contraction kernel's roofline and the FP64 CPU oracle
+timed on a bounded sample.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c1|c0]
+
+Prints ONE JSON line (see the keys below).  Inputs are seeded and synthetic
+(workloads.py); the state is resident in HBM before the timed region starts.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "TTN-HEOM steps/sec at trace-dist<=1e-6, mixed/batched vs FP64; % MFMA peak"
+PEAK_FP32_MFMA = 157.3  # TFLOP/s, MI355X dense FP32 matrix
+PEAK_FP64_MFMA = 78.6
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c1", choices=["c0", "c1"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU comparison")
+    return ap.parse_args()
+
+
+def instance(name, n):
+    import workloads
+    if name == "c0":
+        return workloads.config0(n_steps=n), "spin-boson K=3 N=10 train R=8 ps1 (dt 0.01)"
+    return workloads.config1(n_steps=n), "7-site exciton K=28 N=8 binary R=16 ps1 (dt 0.1 fs)"
+
+
+def timed_run(inst, precision, steps, warmup):
+    import torch
+    from paper_2603_17711_amd import api
+    plan = api.build_instance(inst, precision=precision)
+    if warmup:
+        plan.step(warmup, inst.dt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.step(steps, inst.dt, t0=warmup * inst.dt)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return plan, t1 - t0
+
+
+def kernel_roofline(inst, precision, steps):
+    """Average duration and algorithmic work of the SOP-contraction kernel,
+    from HIP events recorded on the launching stream."""
+    import ctypes as C
+    import torch
+    from paper_2603_17711_amd import api
+    from paper_2603_17711_amd._lib import check, lib
+    plan = api.build_instance(inst, precision=precision)
+    plan.step(1, inst.dt)
+    torch.cuda.synchronize()
+    check(lib().tenso_profile(1))
+    plan.step(steps, inst.dt)
+    torch.cuda.synchronize()
+    ms, n, fl, by = C.c_double(), C.c_int64(), C.c_double(), C.c_double()
+    check(lib().tenso_profile_stats(C.byref(ms), C.byref(n), C.byref(fl), C.byref(by)))
+    check(lib().tenso_profile(0))
+    return ms.value, n.value, fl.value, by.value
+
+
+def cpu_baseline(inst, n_sample):
+    """The FP64 oracle on the host, single BLAS thread, n_sample steps."""
+    from threadpoolctl import threadpool_limits
+    from oracle.run import propagate
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        _, rhos, _, _ = propagate(inst, n_steps=n_sample, every=1)
+        t1 = time.perf_counter()
+    return n_sample / (t1 - t0), rhos
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    torch.cuda.set_device(0)
+    from paper_2603_17711_amd import api
+
+    inst, wname = instance(a.workload, a.steps + a.warmup)
+    plan, dt_mixed = timed_run(inst, api.FP32, a.steps, a.warmup)
+    value = a.steps / dt_mixed
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "steps/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(1e3 * dt_mixed / a.steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64 contractions (fp32 MFMA), f64 master/QR", "data": "synthetic",
+        "config": {"workload": wname, "instances": 1, "precision": "mixed"},
+    }
+    if not a.no_fp64:
+        _, dt64 = timed_run(inst, api.FP64, max(1, a.steps // 2), 2)
+        v64 = max(1, a.steps // 2) / dt64
+        out["fp64_gpu_value"] = round(v64, 3)
+        out["speedup_vs_fp64_gpu"] = round(value / v64, 3)
+    prof_steps = max(1, min(a.steps, 20))
+    ms, n, fl, by = kernel_roofline(inst, api.FP32, prof_steps)
+    avg_ms = ms / max(1, n)
+    achieved = fl / max(1, n) / (avg_ms * 1e-3) / 1e12
+    out["roofline"] = {
+        "kernel": "k_apply<float> (SOP contraction, MFMA 16x16x4 f32)",
+        "bound": "mfma", "achieved": round(achieved, 4), "peak": PEAK_FP32_MFMA,
+        "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MFMA, 6), "traffic": None,
+        "avg_launch_us": round(1e3 * avg_ms, 3), "launches": int(n),
+        "algorithmic_flops_per_launch": fl / max(1, n),
+        "algorithmic_bytes_per_launch": by / max(1, n),
+        "apply_share_of_step": round(ms / prof_steps / (1e3 * dt_mixed / a.steps), 4),
+    }
+    if not a.no_cpu:
+        n_sample = 3 if a.workload == "c1" else 400
+        cinst, _ = instance(a.workload, n_sample)
+        v_cpu, rhos_cpu = cpu_baseline(cinst, n_sample)
+        out["cpu_baseline"] = {
+            "value": round(v_cpu, 4), "unit": "steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_sample} steps of the same workload, FP64 NumPy oracle, 1 BLAS thread",
+        }
+        # accuracy of the mixed path on the sample horizon
+        from oracle.ttn import trace_distance
+        p2 = api.build_instance(cinst, precision=api.FP32)
+        dmax = 0.0
+        for k in range(1, n_sample + 1):
+            p2.step(1, cinst.dt, t0=(k - 1) * cinst.dt)
+            if k % 10 == 0 or k == n_sample:
+                dmax = max(dmax, trace_distance(p2.rho(), rhos_cpu[k]))
+        out["trace_distance_vs_oracle"] = {"value": dmax, "steps": n_sample}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -174,6 +174,16 @@ int tenso_reduced_rho(tenso_plan* p, const void* d_state, tenso_c128* h_rho, dou
  * returns the number of entries (at most cap) or a negative error. */
 int tenso_rank_trajectory(const tenso_plan* p, int32_t* h_ranks, int cap);
 
+/* ---- measurement ---------------------------------------------------------
+ * tenso_profile(1) starts recording HIP events on the launching stream around
+ * every launch of the SOP-contraction (apply) kernel, together with its
+ * algorithmic work (8 flops per complex multiply-add, no padding; bytes = input
+ * read + output written + operand matrices); tenso_profile(0) stops and clears.
+ * tenso_profile_stats synchronises on the recorded events and returns the
+ * summed kernel time, launch count, flops and bytes.  Process-wide state. */
+int tenso_profile(int enable);
+int tenso_profile_stats(double* total_ms, int64_t* launches, double* flops, double* bytes);
+
 /* ---- batched fixed-rank propagation --------------------------------------
  * Many independent ps1 plans (uneven trees, ranks, dims) advance together:
  * one launch per phase serves every instance, and the whole step sequence is

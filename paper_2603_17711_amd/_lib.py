@@ -53,6 +53,8 @@ SIGS = {
                                       P, P, P]),
     "tenso_reduced_rho": (C.c_int, [P, P, C128P, DP, P, P]),
     "tenso_rank_trajectory": (C.c_int, [P, I32P, C.c_int]),
+    "tenso_profile": (C.c_int, [C.c_int]),
+    "tenso_profile_stats": (C.c_int, [DP, C.POINTER(C.c_int64), DP, DP]),
     "tenso_batch_create": (C.c_int, [C.c_int, C.POINTER(P), C.POINTER(P), C.POINTER(P), C.POINTER(P)]),
     "tenso_batch_step": (C.c_int, [P, DP, DP, C.c_int, C.POINTER(P), P]),
     "tenso_batch_reduced_rho": (C.c_int, [P, C.POINTER(C128P), P]),

@@ -199,6 +199,8 @@ struct LaunchRec {
   int first, count;    // descriptors
   int tfirst, tcount;  // tiles
   size_t lds;
+  double flops = 0;    // algorithmic flops of an apply launch (8 per complex MAC)
+  double bytes = 0;    // algorithmic HBM bytes of an apply launch
 };
 enum { LK_APPLY, LK_PRESUM, LK_COMBINE, LK_QR, LK_ABSORB, LK_GRAM, LK_RHO };
 
@@ -566,10 +568,32 @@ static void layout(tenso_plan& P) {
 struct Builder {
   tenso_plan& P;
   Program& G;
-  Builder(tenso_plan& p, Program& g) : P(p), G(g) {}
+  tenso_plan& P_;
+  Builder(tenso_plan& p, Program& g) : P(p), G(g), P_(p) {}
 
   void launch(int kind, int in_fp64, int first, int count, int tfirst, int tcount, size_t lds = 0) {
-    G.launches.push_back({kind, in_fp64, first, count, tfirst, tcount, lds});
+    LaunchRec L{kind, in_fp64, first, count, tfirst, tcount, lds};
+    if (kind == LK_APPLY) {
+      // useful work (no padding): pair term F*d1*d2*(d1+d2) complex MACs,
+      // one-sided terms F*d1*d1*d2 or F*d1*d2*d2; bytes: input read, output
+      // written, operand matrices read once per group
+      for (int gi = first; gi < first + count; ++gi) {
+        const ApplyGroup& g = G.groups[gi];
+        const double F = g.F, d1 = g.d1, d2 = g.d2, P = F * d1 * d2;
+        const double esz = in_fp64 ? 16.0 : (double)P_.tsz;
+        L.bytes += P * esz + P * P_.tsz;
+        const int t0 = (int)(((uint64_t)g.terms) & OFF_MASK);
+        for (int m = t0; m < t0 + g.n_terms; ++m) {
+          const TermRef& t = G.terms[m];
+          if (t.A && t.B) L.flops += 8.0 * F * d1 * d2 * (d1 + d2);
+          else if (t.A) L.flops += 8.0 * F * d1 * d1 * d2;
+          else L.flops += 8.0 * F * d1 * d2 * d2;
+          if (t.A) L.bytes += d1 * d1 * P_.tsz;
+          if (t.B) L.bytes += d2 * d2 * P_.tsz;
+        }
+      }
+    }
+    G.launches.push_back(L);
   }
 
   void* core(int s) { return tagp(TAG_STATE, P.core_off[s]); }
@@ -1075,12 +1099,41 @@ static void upload(DevProgram& D, const Program& G0, void* state, void* ws, doub
   D.launches = G.launches;
 }
 
+// Optional timing of the apply kernel (the SOP contraction): HIP events on
+// the caller's stream around every apply launch, with its algorithmic work.
+struct Prof {
+  bool on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  std::vector<std::pair<double, double>> work;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  hipEvent_t get() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      hipchk(hipEventCreate(&e), "hipEventCreate");
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+};
+static Prof g_prof;
+
 static void run(const DevProgram& D, int fp64, const int* ctr, hipStream_t s) {
   char* b = D.arena;
   for (const auto& L : D.launches) {
     hipError_t e = hipSuccess;
     switch (L.kind) {
       case LK_APPLY:
+        if (g_prof.on) {
+          hipEvent_t e0 = g_prof.get(), e1 = g_prof.get();
+          hipchk(hipEventRecord(e0, s), "hipEventRecord");
+          e = launch_apply(fp64, L.in_fp64, (const ApplyGroup*)(b + D.o_groups) + L.first,
+                           (const ApplyTile*)(b + D.o_atiles) + L.tfirst, L.tcount, ctr, s);
+          hipchk(hipEventRecord(e1, s), "hipEventRecord");
+          g_prof.ev.push_back({e0, e1});
+          g_prof.work.push_back({L.flops, L.bytes});
+          break;
+        }
         e = launch_apply(fp64, L.in_fp64, (const ApplyGroup*)(b + D.o_groups) + L.first,
                          (const ApplyTile*)(b + D.o_atiles) + L.tfirst, L.tcount, ctr, s);
         break;
@@ -1497,6 +1550,33 @@ int tenso_rank_trajectory(const tenso_plan* p, int32_t* h, int cap) {
   int n = std::min<int>(cap, (int)p->rank_log.size());
   for (int i = 0; i < n; ++i) h[i] = p->rank_log[i];
   return n;
+}
+
+int tenso_profile(int enable) {
+  return guard([&] {
+    g_prof.on = enable != 0;
+    g_prof.ev.clear();
+    g_prof.work.clear();
+    g_prof.used = 0;
+  });
+}
+
+int tenso_profile_stats(double* total_ms, int64_t* launches, double* flops, double* bytes) {
+  return guard([&] {
+    double ms = 0, fl = 0, by = 0;
+    for (size_t i = 0; i < g_prof.ev.size(); ++i) {
+      hipchk(hipEventSynchronize(g_prof.ev[i].second), "hipEventSynchronize");
+      float t = 0;
+      hipchk(hipEventElapsedTime(&t, g_prof.ev[i].first, g_prof.ev[i].second), "hipEventElapsedTime");
+      ms += t;
+      fl += g_prof.work[i].first;
+      by += g_prof.work[i].second;
+    }
+    if (total_ms) *total_ms = ms;
+    if (launches) *launches = (int64_t)g_prof.ev.size();
+    if (flops) *flops = fl;
+    if (bytes) *bytes = by;
+  });
 }
 
 int tenso_batch_create(int, tenso_plan* const*, void* const*, void* const*, tenso_batch**) {
