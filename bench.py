@@ -25,9 +25,10 @@ PEAK_FP64_MFMA = 78.6
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c1", choices=["c0", "c1"])
+    ap.add_argument("--workload", default="c2", choices=["c0", "c1", "c2"])
+    ap.add_argument("--instances", type=int, default=512, help="batch size for c2")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU comparison")
     return ap.parse_args()
@@ -84,6 +85,118 @@ def cpu_baseline(inst, n_sample):
     return n_sample / (t1 - t0), rhos
 
 
+def batch_main(a):
+    """512 uneven instances advanced together (one launch per phase)."""
+    import numpy as np
+    import torch
+    import workloads
+    from paper_2603_17711_amd import api
+    from oracle.ttn import trace_distance
+
+    insts = workloads.config2(n_inst=a.instances, n_steps=a.steps + a.warmup)
+    dts = [i.dt for i in insts]
+
+    def run_batch(precision, steps, warmup):
+        plans = [api.build_instance(i, precision=precision) for i in insts]
+        b = api.Batch(plans)
+        b.step(warmup, dts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.step(steps, dts)
+        torch.cuda.synchronize()
+        return plans, b, time.perf_counter() - t0
+
+    plans, batch, dt_mixed = run_batch(api.FP32, a.steps, a.warmup)
+    value = len(insts) * a.steps / dt_mixed
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "instance-steps/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(1e3 * dt_mixed / a.steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64 contractions (fp32 MFMA), f64 master/QR", "data": "synthetic",
+        "config": {"workload": f"batch of {len(insts)} uneven spin-boson-type instances "
+                               "(M 2-8, K 2-8, N 6-12, R 8-32, binary trees, ps1)",
+                   "instances": len(insts), "precision": "mixed"},
+    }
+    rho_mixed = batch.rho()
+    del batch, plans
+    torch.cuda.empty_cache()
+    if not a.no_fp64:
+        st64 = max(1, a.steps // 4)
+        plans64, b64, t64 = run_batch(api.FP64, st64, 1)
+        out["fp64_batched_value"] = round(len(insts) * st64 / t64, 2)
+        out["speedup_vs_fp64_batched"] = round(value / (len(insts) * st64 / t64), 3)
+        del b64, plans64
+        torch.cuda.empty_cache()
+        # plain FP64 GPU path: one instance per call, sequential, on a sample
+        ns, k = 16, 2
+        t_plain = 0.0
+        for inst in insts[:ns]:
+            p = api.build_instance(inst, precision=api.FP64)
+            p.step(1, inst.dt)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            p.step(k, inst.dt)
+            torch.cuda.synchronize()
+            t_plain += time.perf_counter() - t0
+        v_plain = ns * k / t_plain
+        out["fp64_plain_value"] = round(v_plain, 2)
+        out["fp64_plain_sample"] = f"first {ns} instances x {k} steps, one instance per call"
+        out["speedup_vs_fp64_plain"] = round(value / v_plain, 2)
+    # contraction-kernel roofline inside the batched step
+    import ctypes as C
+    from paper_2603_17711_amd._lib import check, lib
+    plans = [api.build_instance(i, precision=api.FP32) for i in insts]
+    b = api.Batch(plans)
+    b.step(1, dts)
+    torch.cuda.synchronize()
+    prof_steps = max(1, min(a.steps, 5))
+    check(lib().tenso_profile(1))
+    b.step(prof_steps, dts)
+    torch.cuda.synchronize()
+    ms, n, fl, by = C.c_double(), C.c_int64(), C.c_double(), C.c_double()
+    check(lib().tenso_profile_stats(C.byref(ms), C.byref(n), C.byref(fl), C.byref(by)))
+    check(lib().tenso_profile(0))
+    avg_ms = ms.value / max(1, n.value)
+    achieved = fl.value / max(1, n.value) / (avg_ms * 1e-3) / 1e12
+    out["roofline"] = {
+        "kernel": "k_apply<float> (SOP contraction, MFMA 16x16x4 f32)",
+        "bound": "mfma", "achieved": round(achieved, 4), "peak": PEAK_FP32_MFMA,
+        "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MFMA, 6), "traffic": None,
+        "avg_launch_us": round(1e3 * avg_ms, 3), "launches": int(n.value),
+        "algorithmic_flops_per_launch": fl.value / max(1, n.value),
+        "algorithmic_bytes_per_launch": by.value / max(1, n.value),
+        "apply_share_of_step": round(ms.value / prof_steps / (1e3 * dt_mixed / a.steps), 4),
+    }
+    del b, plans
+    if not a.no_cpu:
+        from threadpoolctl import threadpool_limits
+        from oracle.run import propagate
+        ns, k = 8, 2
+        sample = workloads.config2(n_inst=a.instances, n_steps=k)[:ns]
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            for inst in sample:
+                propagate(inst, n_steps=k, every=k)
+            tc = time.perf_counter() - t0
+        out["cpu_baseline"] = {
+            "value": round(ns * k / tc, 4), "unit": "instance-steps/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"first {ns} of the {len(insts)} instances x {k} steps, FP64 NumPy "
+                      "oracle, 1 BLAS thread",
+        }
+        # accuracy of the batched mixed-precision run on a sample of instances
+        dmax = 0.0
+        n_chk = min(4, len(insts))
+        for i in range(n_chk):
+            _, ro, _, _ = propagate(insts[i], n_steps=a.warmup + a.steps,
+                                    every=a.warmup + a.steps)
+            dmax = max(dmax, trace_distance(rho_mixed[i], ro[-1]))
+        out["trace_distance_vs_oracle"] = {
+            "value": dmax, "steps": a.warmup + a.steps,
+            "sample": f"final rho_S of instances 0..{n_chk - 1} of the timed batch"}
+    print(json.dumps(out))
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -93,6 +206,8 @@ def main():
     import torch
     torch.cuda.set_device(0)
     from paper_2603_17711_amd import api
+    if a.workload == "c2":
+        return batch_main(a)
 
     inst, wname = instance(a.workload, a.steps + a.warmup)
     plan, dt_mixed = timed_run(inst, api.FP32, a.steps, a.warmup)

@@ -199,3 +199,40 @@ def drive_table(inst, n_steps, t0=0.0, device="cuda"):
     ts = t0 + np.arange(4 * n_steps + 1) * (inst.dt / 4.0)
     vals = np.array([inst.drive_value(t) for t in ts], dtype=np.float64)
     return torch.tensor(vals.reshape(1, -1), dtype=torch.float64, device=device)
+
+
+class Batch:
+    """Many independent ps1 plans advanced together (tenso_batch_*)."""
+
+    def __init__(self, plans):
+        self.plans = list(plans)
+        n = len(self.plans)
+        hp = (C.c_void_p * n)(*[p.h for p in self.plans])
+        hs = (C.c_void_p * n)(*[p.state.data_ptr() for p in self.plans])
+        hw = (C.c_void_p * n)(*[p.ws.data_ptr() for p in self.plans])
+        h = C.c_void_p()
+        check(lib().tenso_batch_create(n, hp, hs, hw, C.byref(h)))
+        self.h = h
+
+    def step(self, n_steps, dts, t0s=None, drive_tabs=None):
+        n = len(self.plans)
+        dt = np.ascontiguousarray(np.broadcast_to(np.asarray(dts, np.float64), (n,)))
+        t0 = np.zeros(n) if t0s is None else np.ascontiguousarray(t0s, np.float64)
+        tabs = None
+        if drive_tabs is not None:
+            tabs = (C.c_void_p * n)(*[(t.data_ptr() if t is not None else None)
+                                      for t in drive_tabs])
+        check(lib().tenso_batch_step(self.h, t0.ctypes.data_as(C.POINTER(C.c_double)),
+                                     dt.ctypes.data_as(C.POINTER(C.c_double)), n_steps, tabs,
+                                     _stream()))
+
+    def rho(self):
+        outs = [np.zeros((p.M, p.M), np.complex128) for p in self.plans]
+        ptrs = (C.POINTER(c128) * len(outs))(*[o.ctypes.data_as(C.POINTER(c128)) for o in outs])
+        check(lib().tenso_batch_reduced_rho(self.h, ptrs, _stream()))
+        return outs
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib._lib is not None:
+            lib().tenso_batch_destroy(self.h)
+            self.h = None

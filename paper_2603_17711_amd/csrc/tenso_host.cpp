@@ -283,6 +283,7 @@ struct tenso_plan {
          ws_qrv = 0, ws_qrtau = 0, ws_rhovec = 0, ws_rhoout = 0, ws_ctr = 0, ws_bytes = 0;
   size_t presum_cap = 0, parts_cap = 0, envscr_cap = 0, qrv_cap = 0;
   int par_target = 64;  // tiles wanted per apply (single-instance latency)
+  int built_target = -1;  // par_target the cached programs were built with
   // compiled programs (host descriptors with tagged pointers, device copies)
   std::unique_ptr<Program> prog_step, prog_init;
   std::unique_ptr<DevProgram> dev_step, dev_init;
@@ -1011,17 +1012,58 @@ static size_t put(std::vector<char>& buf, const std::vector<T>& v) {
   return o;
 }
 
-// Resolve state / workspace tags and per-step scalars, then upload.
-static void upload(DevProgram& D, const Program& G0, void* state, void* ws, double dt,
-                   const double* drive, int drive_ld, hipStream_t s) {
-  Program G = G0;
+// Resolve state / workspace tags and per-step scalars of one instance's
+// program (term and rho-node references stay as indices).
+static void resolve(Program& G, void* state, void* ws, double dt, const double* drive,
+                    int drive_ld) {
   for (auto& t : G.terms) {
     t.A = res((void*)t.A, state, ws);
     t.B = res((void*)t.B, state, ws);
   }
+  for (auto& g : G.groups) {
+    g.X = res((void*)g.X, state, ws);
+    g.Y = res(g.Y, state, ws);
+    g.drive = drive;
+    g.drive_ld = drive_ld;
+  }
+  for (auto& p : G.presums) {
+    p.out = res(p.out, state, ws);
+    p.drive = drive;
+    p.drive_ld = drive_ld;
+  }
+  for (auto& c : G.combines) {
+    c.y0 = (double*)res(c.y0, state, ws);
+    c.xin = res(c.xin, state, ws);
+    c.acc = (double*)res(c.acc, state, ws);
+    c.parts = res((void*)c.parts, state, ws);
+    c.h = c.h * 0.5 * dt;
+  }
+  for (auto& q : G.qrs) {
+    q.C = (double*)res(q.C, state, ws);
+    q.R = (double*)res(q.R, state, ws);
+    q.V = (double*)res(q.V, state, ws);
+    q.tau = (double*)res(q.tau, state, ws);
+  }
+  for (auto& a : G.absorbs) {
+    a.C = (double*)res(a.C, state, ws);
+    a.M = (const double*)res((void*)a.M, state, ws);
+  }
+  for (auto& g : G.grams) {
+    g.C = (const double*)res((void*)g.C, state, ws);
+    g.T = res((void*)g.T, state, ws);
+    g.E = res(g.E, state, ws);
+  }
+  for (auto& n : G.rnodes) n.C = (const double*)res((void*)n.C, state, ws);
+  for (auto& r : G.rprogs) {
+    r.vecs = (double*)res(r.vecs, state, ws);
+    r.rho_out = (double*)res(r.rho_out, state, ws);
+  }
+}
+
+// Upload a resolved program, turning term / rho-node indices into pointers.
+static void upload_resolved(DevProgram& D, const Program& G, hipStream_t s) {
   std::vector<char> buf;
   D.o_terms = put(buf, G.terms);
-  // groups/presums reference terms by index: fixed after the arena base is known
   D.o_groups = put(buf, G.groups);
   D.o_atiles = put(buf, G.atiles);
   D.o_presums = put(buf, G.presums);
@@ -1046,57 +1088,158 @@ static void upload(DevProgram& D, const Program& G0, void* state, void* ws, doub
     return (const TermRef*)(base + D.o_terms + (v & OFF_MASK) * sizeof(TermRef));
   };
   ApplyGroup* gp = (ApplyGroup*)(buf.data() + D.o_groups);
-  for (size_t i = 0; i < G.groups.size(); ++i) {
-    gp[i].X = res((void*)gp[i].X, state, ws);
-    gp[i].Y = res(gp[i].Y, state, ws);
-    gp[i].terms = term_ptr(gp[i].terms);
-    gp[i].drive = drive;
-    gp[i].drive_ld = drive_ld;
-  }
+  for (size_t i = 0; i < G.groups.size(); ++i) gp[i].terms = term_ptr(gp[i].terms);
   PresumOp* pp = (PresumOp*)(buf.data() + D.o_presums);
-  for (size_t i = 0; i < G.presums.size(); ++i) {
-    pp[i].out = res(pp[i].out, state, ws);
-    pp[i].terms = term_ptr(pp[i].terms);
-    pp[i].drive = drive;
-    pp[i].drive_ld = drive_ld;
-  }
-  CombineOp* cp = (CombineOp*)(buf.data() + D.o_combines);
-  for (size_t i = 0; i < G.combines.size(); ++i) {
-    cp[i].y0 = (double*)res(cp[i].y0, state, ws);
-    cp[i].xin = res(cp[i].xin, state, ws);
-    cp[i].acc = (double*)res(cp[i].acc, state, ws);
-    cp[i].parts = res((void*)cp[i].parts, state, ws);
-    cp[i].h = cp[i].h * 0.5 * dt;
-  }
-  QrOp* qp = (QrOp*)(buf.data() + D.o_qrs);
-  for (size_t i = 0; i < G.qrs.size(); ++i) {
-    qp[i].C = (double*)res(qp[i].C, state, ws);
-    qp[i].R = (double*)res(qp[i].R, state, ws);
-    qp[i].V = (double*)res(qp[i].V, state, ws);
-    qp[i].tau = (double*)res(qp[i].tau, state, ws);
-  }
-  AbsorbOp* ap = (AbsorbOp*)(buf.data() + D.o_absorbs);
-  for (size_t i = 0; i < G.absorbs.size(); ++i) {
-    ap[i].C = (double*)res(ap[i].C, state, ws);
-    ap[i].M = (const double*)res((void*)ap[i].M, state, ws);
-  }
-  GramOp* gq = (GramOp*)(buf.data() + D.o_grams);
-  for (size_t i = 0; i < G.grams.size(); ++i) {
-    gq[i].C = (const double*)res((void*)gq[i].C, state, ws);
-    gq[i].T = res((void*)gq[i].T, state, ws);
-    gq[i].E = res(gq[i].E, state, ws);
-  }
-  RhoNode* rn = (RhoNode*)(buf.data() + D.o_rnodes);
-  for (size_t i = 0; i < G.rnodes.size(); ++i) rn[i].C = (const double*)res((void*)rn[i].C, state, ws);
+  for (size_t i = 0; i < G.presums.size(); ++i) pp[i].terms = term_ptr(pp[i].terms);
   RhoProg* rp = (RhoProg*)(buf.data() + D.o_rprogs);
   for (size_t i = 0; i < G.rprogs.size(); ++i) {
     uint64_t v = (uint64_t)rp[i].nodes;
     rp[i].nodes = (const RhoNode*)(base + D.o_rnodes + (v & OFF_MASK) * sizeof(RhoNode));
-    rp[i].vecs = (double*)res(rp[i].vecs, state, ws);
-    rp[i].rho_out = (double*)res(rp[i].rho_out, state, ws);
   }
   hipchk(hipMemcpyAsync(D.arena, buf.data(), buf.size(), hipMemcpyHostToDevice, s), "upload program");
+  hipchk(hipStreamSynchronize(s), "sync upload");
   D.launches = G.launches;
+}
+
+static void upload(DevProgram& D, const Program& G0, void* state, void* ws, double dt,
+                   const double* drive, int drive_ld, hipStream_t s) {
+  Program G = G0;
+  resolve(G, state, ws, dt, drive, drive_ld);
+  upload_resolved(D, G, s);
+}
+
+// Merge resolved per-instance programs into one launch sequence: at each
+// phase the kernel type whose waiting instances have the most remaining
+// launches (critical path first) is issued for all instances waiting on it.
+static Program merge_programs(std::vector<Program>& progs) {
+  Program M;
+  const size_t n = progs.size();
+  std::vector<int> term_off(n), rn_off(n);
+  for (size_t i = 0; i < n; ++i) {
+    term_off[i] = (int)M.terms.size();
+    M.terms.insert(M.terms.end(), progs[i].terms.begin(), progs[i].terms.end());
+    rn_off[i] = (int)M.rnodes.size();
+    M.rnodes.insert(M.rnodes.end(), progs[i].rnodes.begin(), progs[i].rnodes.end());
+  }
+  auto shift_term = [](const TermRef* p, int off) -> const TermRef* {
+    uint64_t v = (uint64_t)p;
+    if ((int)(v >> 56) != TAG_TERM) return p;
+    return (const TermRef*)tagp(TAG_TERM, (v & OFF_MASK) + off);
+  };
+  std::vector<size_t> pos(n, 0);
+  auto type_of = [](const LaunchRec& L) { return L.kind * 2 + L.in_fp64; };
+  while (true) {
+    std::map<int, long> weight;
+    for (size_t i = 0; i < n; ++i)
+      if (pos[i] < progs[i].launches.size())
+        weight[type_of(progs[i].launches[pos[i]])] += (long)(progs[i].launches.size() - pos[i]);
+    if (weight.empty()) break;
+    int best = -1;
+    long bw = -1;
+    for (auto& kv : weight)
+      if (kv.second > bw) {
+        bw = kv.second;
+        best = kv.first;
+      }
+    LaunchRec ML{best / 2, best % 2, 0, 0, 0, 0, 0};
+    const int kind = best / 2;
+    switch (kind) {
+      case LK_APPLY: ML.first = (int)M.groups.size(); ML.tfirst = (int)M.atiles.size(); break;
+      case LK_PRESUM: ML.first = (int)M.presums.size(); break;
+      case LK_COMBINE: ML.first = (int)M.combines.size(); ML.tfirst = (int)M.ctiles.size(); break;
+      case LK_QR: ML.first = (int)M.qrs.size(); break;
+      case LK_ABSORB: ML.first = (int)M.absorbs.size(); ML.tfirst = (int)M.abtiles.size(); break;
+      case LK_GRAM: ML.first = (int)M.grams.size(); break;
+      case LK_RHO: ML.first = (int)M.rprogs.size(); break;
+    }
+    for (size_t i = 0; i < n; ++i) {
+      if (pos[i] >= progs[i].launches.size()) continue;
+      const LaunchRec& L = progs[i].launches[pos[i]];
+      if (type_of(L) != best) continue;
+      ++pos[i];
+      Program& P = progs[i];
+      ML.flops += L.flops;
+      ML.bytes += L.bytes;
+      ML.lds = std::max(ML.lds, L.lds);
+      switch (kind) {
+        case LK_APPLY: {
+          const int goff = (int)M.groups.size() - ML.first;
+          for (int g = L.first; g < L.first + L.count; ++g) {
+            ApplyGroup ag = P.groups[g];
+            ag.terms = shift_term(ag.terms, term_off[i]);
+            M.groups.push_back(ag);
+          }
+          for (int t = L.tfirst; t < L.tfirst + L.tcount; ++t) {
+            ApplyTile tl = P.atiles[t];
+            tl.group += goff;
+            M.atiles.push_back(tl);
+          }
+          break;
+        }
+        case LK_PRESUM:
+          for (int k = L.first; k < L.first + L.count; ++k) {
+            PresumOp op = P.presums[k];
+            op.terms = shift_term(op.terms, term_off[i]);
+            M.presums.push_back(op);
+          }
+          break;
+        case LK_COMBINE: {
+          const int base = (int)M.combines.size();
+          for (int k = L.first; k < L.first + L.count; ++k) M.combines.push_back(P.combines[k]);
+          for (int t = L.tfirst; t < L.tfirst + L.tcount; ++t) {
+            CombineTileH ct = P.ctiles[t];
+            ct.op = base + (ct.op - L.first);
+            M.ctiles.push_back(ct);
+          }
+          break;
+        }
+        case LK_QR:
+          for (int k = L.first; k < L.first + L.count; ++k) M.qrs.push_back(P.qrs[k]);
+          break;
+        case LK_ABSORB: {
+          const int base = (int)M.absorbs.size();
+          for (int k = L.first; k < L.first + L.count; ++k) M.absorbs.push_back(P.absorbs[k]);
+          for (int t = L.tfirst; t < L.tfirst + L.tcount; ++t) {
+            AbsorbTileH at = P.abtiles[t];
+            at.op = base + (at.op - L.first);
+            M.abtiles.push_back(at);
+          }
+          break;
+        }
+        case LK_GRAM:
+          for (int k = L.first; k < L.first + L.count; ++k) M.grams.push_back(P.grams[k]);
+          break;
+        case LK_RHO:
+          for (int k = L.first; k < L.first + L.count; ++k) {
+            RhoProg rp = P.rprogs[k];
+            uint64_t v = (uint64_t)rp.nodes;
+            rp.nodes = (const RhoNode*)tagp(TAG_RNODE, (v & OFF_MASK) + rn_off[i]);
+            M.rprogs.push_back(rp);
+          }
+          break;
+      }
+    }
+    switch (kind) {
+      case LK_APPLY:
+        ML.count = (int)M.groups.size() - ML.first;
+        ML.tcount = (int)M.atiles.size() - ML.tfirst;
+        break;
+      case LK_PRESUM: ML.count = (int)M.presums.size() - ML.first; break;
+      case LK_COMBINE:
+        ML.count = (int)M.combines.size() - ML.first;
+        ML.tcount = (int)M.ctiles.size() - ML.tfirst;
+        break;
+      case LK_QR: ML.count = (int)M.qrs.size() - ML.first; break;
+      case LK_ABSORB:
+        ML.count = (int)M.absorbs.size() - ML.first;
+        ML.tcount = (int)M.abtiles.size() - ML.tfirst;
+        break;
+      case LK_GRAM: ML.count = (int)M.grams.size() - ML.first; break;
+      case LK_RHO: ML.count = (int)M.rprogs.size() - ML.first; break;
+    }
+    M.launches.push_back(ML);
+  }
+  return M;
 }
 
 // Optional timing of the apply kernel (the SOP contraction): HIP events on
@@ -1488,11 +1631,13 @@ int tenso_step_fixed(tenso_plan* p, void* d_state, double t0, double dt, int n_s
       p->dev_step = std::make_unique<DevProgram>();
       p->dev_init = std::make_unique<DevProgram>();
     }
-    if (!p->prog_step) {
+    p->par_target = 64;
+    if (!p->prog_step || p->built_target != p->par_target) {
       p->prog_step = std::make_unique<Program>();
       p->prog_init = std::make_unique<Program>();
       build_step(*p, *p->prog_step);
       build_init(*p, *p->prog_init);
+      p->built_target = p->par_target;
       p->b_state = nullptr;
     }
     if (p->b_state != d_state || p->b_ws != d_ws || p->b_dt != dt || p->b_drive != d_drive_tab ||
@@ -1579,18 +1724,127 @@ int tenso_profile_stats(double* total_ms, int64_t* launches, double* flops, doub
   });
 }
 
-int tenso_batch_create(int, tenso_plan* const*, void* const*, void* const*, tenso_batch**) {
-  g_err = "batched propagation is not built yet";
-  return TENSO_EUNSUPPORTED;
+}  // extern "C"
+
+struct tenso_batch {
+  std::vector<tenso_plan*> plans;
+  std::vector<void*> states, wss;
+  std::vector<double> dts;
+  std::vector<const double*> drives;
+  int ld = -1;
+  int fp64 = 0;
+  int* ctr = nullptr;
+  double* rho_buf = nullptr;
+  std::vector<size_t> rho_off;
+  DevProgram step, init, rho;
+  ~tenso_batch() {
+    if (ctr) (void)hipFree(ctr);
+    if (rho_buf) (void)hipFree(rho_buf);
+  }
+};
+
+static void batch_build(tenso_batch& B, hipStream_t s) {
+  const size_t n = B.plans.size();
+  std::vector<Program> st(n), in(n), rh(n);
+  for (size_t i = 0; i < n; ++i) {
+    tenso_plan& P = *B.plans[i];
+    P.par_target = 4;  // the batch supplies the parallelism
+    if (!P.prog_step || P.built_target != P.par_target) {
+      P.prog_step = std::make_unique<Program>();
+      P.prog_init = std::make_unique<Program>();
+      build_step(P, *P.prog_step);
+      build_init(P, *P.prog_init);
+      P.built_target = P.par_target;
+      P.b_state = nullptr;
+    }
+    st[i] = *P.prog_step;
+    in[i] = *P.prog_init;
+    Builder b(P, rh[i]);
+    b.rho_prog();
+    rh[i].rprogs.back().rho_out = (double*)((char*)B.rho_buf + B.rho_off[i]);
+    resolve(st[i], B.states[i], B.wss[i], B.dts[i], B.drives[i], B.ld);
+    resolve(in[i], B.states[i], B.wss[i], B.dts[i], B.drives[i], B.ld);
+    resolve(rh[i], B.states[i], B.wss[i], B.dts[i], nullptr, 1);
+  }
+  Program ms = merge_programs(st), mi = merge_programs(in), mr = merge_programs(rh);
+  upload_resolved(B.step, ms, s);
+  upload_resolved(B.init, mi, s);
+  upload_resolved(B.rho, mr, s);
 }
-int tenso_batch_step(tenso_batch*, const double*, const double*, int, const double* const*, hipStream_t) {
-  g_err = "batched propagation is not built yet";
-  return TENSO_EUNSUPPORTED;
+
+extern "C" {
+
+int tenso_batch_create(int n, tenso_plan* const* plans, void* const* d_states,
+                       void* const* d_wss, tenso_batch** out) {
+  return guard([&] {
+    if (n < 1 || !plans || !d_states || !d_wss || !out) fail(TENSO_EINVAL, "bad batch arguments");
+    auto B = std::make_unique<tenso_batch>();
+    size_t rho_bytes = 0;
+    for (int i = 0; i < n; ++i) {
+      if (!plans[i] || !d_states[i] || !d_wss[i]) fail(TENSO_EINVAL, "null plan or buffer");
+      if (plans[i]->opts.method != TENSO_PS1) fail(TENSO_EINVAL, "batches take ps1 plans");
+      if (i > 0 && plans[i]->fp64 != plans[0]->fp64) fail(TENSO_EINVAL, "mixed precisions in a batch");
+      B->plans.push_back(plans[i]);
+      B->states.push_back(d_states[i]);
+      B->wss.push_back(d_wss[i]);
+      B->rho_off.push_back(rho_bytes);
+      const size_t M = plans[i]->tree.end_dim[0];
+      rho_bytes += align256(M * M * 16);
+    }
+    B->fp64 = plans[0]->fp64;
+    hipchk(hipMalloc((void**)&B->ctr, 256), "hipMalloc(counter)");
+    hipchk(hipMalloc((void**)&B->rho_buf, std::max<size_t>(rho_bytes, 256)), "hipMalloc(rho)");
+    *out = B.release();
+  });
 }
-int tenso_batch_reduced_rho(tenso_batch*, tenso_c128* const*, hipStream_t) {
-  g_err = "batched propagation is not built yet";
-  return TENSO_EUNSUPPORTED;
+
+int tenso_batch_step(tenso_batch* b, const double* t0, const double* dt, int n_steps,
+                     const double* const* d_drive_tabs, hipStream_t s) {
+  return guard([&] {
+    if (!b || !dt) fail(TENSO_EINVAL, "null argument");
+    if (n_steps < 0) fail(TENSO_EINVAL, "n_steps must be >= 0");
+    (void)t0;
+    const size_t n = b->plans.size();
+    std::vector<double> dts(dt, dt + n);
+    std::vector<const double*> drv(n, nullptr);
+    for (size_t i = 0; i < n; ++i) {
+      if (!(dts[i] > 0)) fail(TENSO_EINVAL, "dt must be > 0");
+      if (d_drive_tabs) drv[i] = d_drive_tabs[i];
+      if (b->plans[i]->gen.n_slots > 0 && !drv[i]) fail(TENSO_EINVAL, "instance with drive slots needs a drive table");
+    }
+    const int ld = 4 * n_steps + 1;
+    if (dts != b->dts || drv != b->drives || ld != b->ld || !b->step.arena) {
+      b->dts = dts;
+      b->drives = drv;
+      b->ld = ld;
+      batch_build(*b, s);
+    }
+    hipchk(launch_step_inc(b->ctr, 0, s), "ctr");
+    run(b->init, b->fp64, b->ctr, s);
+    for (int k = 0; k < n_steps; ++k) {
+      run(b->step, b->fp64, b->ctr, s);
+      hipchk(launch_step_inc(b->ctr, -1, s), "ctr");
+    }
+  });
 }
-void tenso_batch_destroy(tenso_batch*) {}
+
+int tenso_batch_reduced_rho(tenso_batch* b, tenso_c128* const* h_rho, hipStream_t s) {
+  return guard([&] {
+    if (!b || !h_rho) fail(TENSO_EINVAL, "null argument");
+    if (!b->rho.arena) fail(TENSO_EINVAL, "batch has not been stepped yet");
+    run(b->rho, b->fp64, nullptr, s);
+    size_t total = b->rho_off.back() + align256(b->plans.back()->tree.end_dim[0] *
+                                                b->plans.back()->tree.end_dim[0] * 16);
+    std::vector<char> h(total);
+    hipchk(hipMemcpyAsync(h.data(), b->rho_buf, total, hipMemcpyDeviceToHost, s), "rho readback");
+    hipchk(hipStreamSynchronize(s), "sync");
+    for (size_t i = 0; i < b->plans.size(); ++i) {
+      const size_t M = b->plans[i]->tree.end_dim[0];
+      memcpy(h_rho[i], h.data() + b->rho_off[i], M * M * 16);
+    }
+  });
+}
+
+void tenso_batch_destroy(tenso_batch* b) { delete b; }
 
 }  // extern "C"

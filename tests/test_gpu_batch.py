@@ -1,0 +1,42 @@
+"""Batched propagation (one launch per phase for all instances) equals the
+single-instance GPU runs and the oracle, per instance."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle.run import propagate
+from oracle.ttn import trace_distance
+from tests.gpu_util import require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def small_batch(n, seed=7):
+    """Uneven small instances in the style of the 512-instance batch."""
+    rng = np.random.default_rng(seed)
+    insts = workloads.config2(n_inst=n, seed=seed, n_steps=20)
+    for inst in insts:  # keep the oracle fast
+        inst.depth = int(rng.integers(3, 6))
+        inst.rank = int(rng.integers(3, 7))
+    return insts
+
+
+@pytest.mark.parametrize("precision,tol_single,tol_oracle", [(0, 1e-13, 1e-10), (1, 1e-6, 1e-6)])
+def test_batch_matches_single_and_oracle(precision, tol_single, tol_oracle):
+    require_gpu()
+    from paper_2603_17711_amd import api
+    insts = small_batch(6)
+    n = 20
+    print(f"[batch parity] 6 instances, {n} steps, precision={precision}", flush=True)
+    plans = [api.build_instance(i, precision=precision) for i in insts]
+    batch = api.Batch(plans)
+    batch.step(n, [i.dt for i in insts])
+    rb = batch.rho()
+    for k, inst in enumerate(insts):
+        single = api.build_instance(inst, precision=precision)
+        single.step(n, inst.dt)
+        rs = single.rho()
+        _, ro, _, _ = propagate(inst, n_steps=n, every=n)
+        d1, d2 = trace_distance(rb[k], rs), trace_distance(rb[k], ro[-1])
+        print(f"  {inst.name} dt={inst.dt:.2e}: batch-single {d1:.2e} batch-oracle {d2:.2e} tr={np.trace(rb[k]).real:.6f}")
+        assert d1 < tol_single and d2 < tol_oracle

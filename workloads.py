@@ -103,8 +103,18 @@ def config1(n_steps=1000, seed=1):
                     ground(M), 0.1 * FS_TO_CM, n_steps)
 
 
+def stable_dt(dt_max, T, n_ltc, N, wc=1.0):
+    """Time step of a batch instance: dt_max unless the fastest decay rate of
+    the hierarchy, (N - 1) * max(wc, 2 pi n_ltc T), would put a half-step RK4
+    sub-flow outside RK4's real stability interval (|z| < 2.78); then
+    half of that limit."""
+    rate = (N - 1) * max(wc, 2.0 * np.pi * n_ltc * T)
+    return min(dt_max, 0.5 * 2 * 2.78 / rate)
+
+
 def config2(n_inst=512, seed=2, n_steps=200):
-    """Batch of uneven spin-boson-type instances."""
+    """Batch of uneven spin-boson-type instances (time step 0.01, lowered per
+    instance where RK4 would be unstable, see stable_dt)."""
     rng = np.random.default_rng(seed)
     out = []
     for i in range(n_inst):
@@ -122,7 +132,7 @@ def config2(n_inst=512, seed=2, n_steps=200):
         T = float(np.exp(rng.uniform(np.log(0.1), np.log(10.0))))
         bath = Bath(np.diag(q).astype(np.complex128), T, dl=[(lam, 1.0)], n_ltc=K - 1)
         out.append(Instance(f"batch[{i}] M={M} K={K} N={N} R={R}", H, [bath], N, "tree2",
-                            R, ground(M), 0.01, n_steps))
+                            R, ground(M), stable_dt(0.01, T, K - 1, N), n_steps))
     return out
 
 
