@@ -23,7 +23,7 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 template <typename T> struct MT;
 template <> struct MT<float> {
   typedef v4f v4;
-  static constexpr int NT = 8;  // accumulator tiles per wavefront
+  static constexpr int NT = 4;  // accumulator tiles per wavefront
   __device__ static inline v4 mma(float a, float b, v4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
@@ -67,9 +67,11 @@ __device__ inline void coef_at(const TermRef& t, const double* drive, int ld, in
 template <typename T>
 __device__ inline void cmma(typename MT<T>::v4& cr, typename MT<T>::v4& ci, T ar, T ai, T br,
                             T bi) {
+  // the two products into the same accumulator are issued apart so that the
+  // dependent MFMAs interleave with the independent ones
   cr = MT<T>::mma(ar, br, cr);
-  cr = MT<T>::mma(-ai, bi, cr);
   ci = MT<T>::mma(ar, bi, ci);
+  cr = MT<T>::mma(-ai, bi, cr);
   ci = MT<T>::mma(ai, br, ci);
 }
 
@@ -101,15 +103,31 @@ __device__ inline void load_scaled(const T* M, int d, int row, int kk, double cr
   }
 }
 
-// Accumulator tile T_idx (compile-time) belongs to local unit T_idx / nib and
-// row block T_idx % nib; a wavefront holds n_my units of nib row blocks each.
+// LDS layout of one apply tile (T elements; complex values interleaved):
+//   X : nfl x D1 x (D2 + 1)     the tile's input slices X_f, zero padded
+//   A : D1 x (D1 + 1)           coefficient-scaled operand of the current term
+//   B : D2 x (D2 + 1)
+//   Z : 4 wavefronts x D1 x 16  per-wave X_f B^T of one unit
+// with D = 16 * ceil(d / 16).  Every MFMA operand is then one LDS vector load
+// without bounds checks.
+__host__ __device__ inline long apply_lds_elems(int nfl, int d1, int d2, int) {
+  const long D1 = 16 * ((d1 + 15) / 16), D2 = 16 * ((d2 + 15) / 16);
+  return 2 * (nfl * D1 * (D2 + 1) + D1 * (D1 + 1) + D2 * (D2 + 1) + 4 * D1 * 16);
+}
+
+template <typename T> struct V2;
+template <> struct V2<float> { typedef float2 t; };
+template <> struct V2<double> { typedef double2 t; };
+
 template <typename T, typename Tin>
-__global__ void __launch_bounds__(256) k_apply(const ApplyGroup* __restrict__ groups,
+__global__ void __launch_bounds__(256, 2) k_apply(const ApplyGroup* __restrict__ groups,
                                                const ApplyTile* __restrict__ tiles,
                                                const int* __restrict__ step_ctr) {
   typedef typename MT<T>::v4 v4;
+  typedef typename V2<T>::t c2;
   constexpr int NT = MT<T>::NT;
   extern __shared__ char smem_raw[];
+  c2* smem = reinterpret_cast<c2*>(smem_raw);
   const ApplyTile tile = tiles[blockIdx.x];
   const ApplyGroup& G = groups[tile.group];
   const int lane = threadIdx.x & 63;
@@ -118,18 +136,40 @@ __global__ void __launch_bounds__(256) k_apply(const ApplyGroup* __restrict__ gr
   const int g = lane >> 4;   // K sub-index (0..3)
   const int d1 = G.d1, d2 = G.d2;
   const int nib = (d1 + 15) >> 4, njb = (d2 + 15) >> 4;
+  const int D1 = 16 * nib, D2 = 16 * njb;
+  const int xs1 = D2 + 1, as1 = D1 + 1, bs1 = D2 + 1;  // padded row strides
   const int nq1 = (d2 + 3) >> 2;  // K steps of X_f B^T
   const int nq2 = (d1 + 3) >> 2;  // K steps of A Z
   const long sb = G.P2;
   const long sa = (long)G.P1 * d2 * G.P2;
   const int step = step_ctr ? *step_ctr : 0;
   const int jdrv = 4 * step + G.rel;
-  T* zr = reinterpret_cast<T*>(smem_raw) + (size_t)wave * (2 * 64 * 16);
-  T* zi = zr + 64 * 16;
+  const int f_first = tile.u0 / njb;
+  const int nfl = (tile.u0 + tile.nu - 1) / njb - f_first + 1;
+  c2* xs = smem;
+  c2* as = xs + (long)nfl * D1 * xs1;
+  c2* bs = as + (long)D1 * as1;
+  c2* zs = bs + (long)D2 * bs1 + (long)wave * D1 * 16;
+
+  // stage the tile's input slices (zero padded, compute precision)
+  for (long e = threadIdx.x; e < (long)nfl * D1 * D2; e += 256) {
+    const int fl = (int)(e / ((long)D1 * D2));
+    const int rem = (int)(e % ((long)D1 * D2));
+    const int a = rem / D2, bcol = rem % D2;
+    c2 v;
+    v.x = 0;
+    v.y = 0;
+    if (a < d1 && bcol < d2) {
+      const UnitGeo ug = unit_geo(G, (f_first + fl) * njb, njb, 0);
+      const cpx<T> x = ldc<Tin, T>(G.X, ug.base + a * sa + bcol * sb);
+      v.x = x.re;
+      v.y = x.im;
+    }
+    xs[((long)fl * D1 + a) * xs1 + bcol] = v;
+  }
 
   int n_my = tile.nu > wave ? (tile.nu - wave + 3) / 4 : 0;
   if (n_my * nib > NT) n_my = NT / nib;
-  if (n_my == 0) return;
   v4 yr[NT], yi[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
@@ -143,9 +183,42 @@ __global__ void __launch_bounds__(256) k_apply(const ApplyGroup* __restrict__ gr
     coef_at(tr, G.drive, G.drive_ld, jdrv, cr, ci);
     const T* Am = reinterpret_cast<const T*>(tr.A);
     const T* Bm = reinterpret_cast<const T*>(tr.B);
+    __syncthreads();  // previous term's operands are no longer read
+    if (Am) {  // A carries the coefficient
+      for (int e = threadIdx.x; e < D1 * D1; e += 256) {
+        const int i = e / D1, j = e % D1;
+        c2 v;
+        v.x = 0;
+        v.y = 0;
+        if (i < d1 && j < d1) {
+          const double a0 = Am[2 * (i * d1 + j)], a1 = Am[2 * (i * d1 + j) + 1];
+          v.x = (T)(a0 * cr - a1 * ci);
+          v.y = (T)(a0 * ci + a1 * cr);
+        }
+        as[i * as1 + j] = v;
+      }
+    }
+    if (Bm) {  // B carries it only for one-sided B terms
+      const double br0 = Am ? 1.0 : cr, bi0 = Am ? 0.0 : ci;
+      for (int e = threadIdx.x; e < D2 * D2; e += 256) {
+        const int i = e / D2, j = e % D2;
+        c2 v;
+        v.x = 0;
+        v.y = 0;
+        if (i < d2 && j < d2) {
+          const double b0 = Bm[2 * (i * d2 + j)], b1 = Bm[2 * (i * d2 + j) + 1];
+          v.x = (T)(b0 * br0 - b1 * bi0);
+          v.y = (T)(b0 * bi0 + b1 * br0);
+        }
+        bs[i * bs1 + j] = v;
+      }
+    }
+    __syncthreads();
     for (int uu = 0; uu < n_my; ++uu) {
-      const UnitGeo ug = unit_geo(G, tile.u0 + wave + 4 * uu, njb, c);
-      const int col = ug.col;
+      const int u = tile.u0 + wave + 4 * uu;
+      const int fl = u / njb - f_first, jb = u % njb;
+      const c2* xf = xs + (long)fl * D1 * xs1;
+      const int col = 16 * jb + c;
       const int t_lo = uu * nib;
       if (Am && Bm) {
         v4 zra[NT], zia[NT];
@@ -156,18 +229,12 @@ __global__ void __launch_bounds__(256) k_apply(const ApplyGroup* __restrict__ gr
         }
         for (int q = 0; q < nq1; ++q) {
           const int kk = 4 * q + g;
-          T br = 0, bi = 0;
-          if (col < d2 && kk < d2) {
-            br = Bm[2 * ((long)col * d2 + kk)];
-            bi = Bm[2 * ((long)col * d2 + kk) + 1];
-          }
+          const c2 bv = bs[col * bs1 + kk];
 #pragma unroll
           for (int t = 0; t < NT; ++t) {
             if (t < nib) {
-              const int row = 16 * t + c;
-              cpx<T> x{0, 0};
-              if (row < d1 && kk < d2) x = ldc<Tin, T>(G.X, ug.base + row * sa + kk * sb);
-              cmma<T>(zra[t], zia[t], x.re, x.im, br, bi);
+              const c2 xv = xf[(16 * t + c) * xs1 + kk];
+              cmma<T>(zra[t], zia[t], xv.x, xv.y, bv.x, bv.y);
             }
           }
         }
@@ -176,8 +243,10 @@ __global__ void __launch_bounds__(256) k_apply(const ApplyGroup* __restrict__ gr
           if (t < nib) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-              zr[(16 * t + MT<T>::drow(g, r)) * 16 + c] = zra[t][r];
-              zi[(16 * t + MT<T>::drow(g, r)) * 16 + c] = zia[t][r];
+              c2 v;
+              v.x = zra[t][r];
+              v.y = zia[t][r];
+              zs[(16 * t + MT<T>::drow(g, r)) * 16 + c] = v;
             }
           }
         }
@@ -186,13 +255,12 @@ __global__ void __launch_bounds__(256) k_apply(const ApplyGroup* __restrict__ gr
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         for (int q = 0; q < nq2; ++q) {
           const int kk = 4 * q + g;
-          const T zbr = zr[kk * 16 + c], zbi = zi[kk * 16 + c];
+          const c2 zv = zs[kk * 16 + c];
 #pragma unroll
           for (int ti = 0; ti < NT; ++ti) {
             if (ti >= t_lo && ti < t_lo + nib) {
-              T ar, ai;
-              load_scaled<T>(Am, d1, 16 * (ti - t_lo) + c, kk, cr, ci, ar, ai);
-              cmma<T>(yr[ti], yi[ti], ar, ai, zbr, zbi);
+              const c2 av = as[(16 * (ti - t_lo) + c) * as1 + kk];
+              cmma<T>(yr[ti], yi[ti], av.x, av.y, zv.x, zv.y);
             }
           }
         }
@@ -202,29 +270,24 @@ __global__ void __launch_bounds__(256) k_apply(const ApplyGroup* __restrict__ gr
       } else if (Am) {
         for (int q = 0; q < nq2; ++q) {
           const int kk = 4 * q + g;
-          cpx<T> x{0, 0};
-          if (kk < d1 && col < d2) x = ldc<Tin, T>(G.X, ug.base + kk * sa + col * sb);
+          const c2 xv = xf[kk * xs1 + col];
 #pragma unroll
           for (int ti = 0; ti < NT; ++ti) {
             if (ti >= t_lo && ti < t_lo + nib) {
-              T ar, ai;
-              load_scaled<T>(Am, d1, 16 * (ti - t_lo) + c, kk, cr, ci, ar, ai);
-              cmma<T>(yr[ti], yi[ti], ar, ai, x.re, x.im);
+              const c2 av = as[(16 * (ti - t_lo) + c) * as1 + kk];
+              cmma<T>(yr[ti], yi[ti], av.x, av.y, xv.x, xv.y);
             }
           }
         }
       } else if (Bm) {
         for (int q = 0; q < nq1; ++q) {
           const int kk = 4 * q + g;
-          T br, bi;
-          load_scaled<T>(Bm, d2, col, kk, cr, ci, br, bi);
+          const c2 bv = bs[col * bs1 + kk];
 #pragma unroll
           for (int ti = 0; ti < NT; ++ti) {
             if (ti >= t_lo && ti < t_lo + nib) {
-              const int row = 16 * (ti - t_lo) + c;
-              cpx<T> x{0, 0};
-              if (row < d1 && kk < d2) x = ldc<Tin, T>(G.X, ug.base + row * sa + kk * sb);
-              cmma<T>(yr[ti], yi[ti], x.re, x.im, br, bi);
+              const c2 xv = xf[(16 * (ti - t_lo) + c) * xs1 + kk];
+              cmma<T>(yr[ti], yi[ti], xv.x, xv.y, bv.x, bv.y);
             }
           }
         }
@@ -553,29 +616,103 @@ __global__ void __launch_bounds__(256) k_absorb(const AbsorbOp* __restrict__ ops
 }
 
 // ---------------------------------------------------------------------------
-// gram: E[a', a] = sum conj(C[pre, a', post]) T[pre, a, post]
+// gram: E[a', a] = sum_k conj(C[pre, a', post]) T[pre, a, post],  k = (pre, post)
 // ---------------------------------------------------------------------------
+// One workgroup per environment matrix.  Work items = (16x16 output tile,
+// K part); with fewer than four tiles K is split across wavefronts and the
+// partial tiles are summed in LDS.
 template <typename T>
 __global__ void __launch_bounds__(256) k_gram(const GramOp* __restrict__ ops) {
+  typedef typename MT<T>::v4 v4;
   const GramOp op = ops[blockIdx.x];
   const int r = op.r;
   const long K = (long)op.Ppre * op.Ppost;
   const T* Tm = reinterpret_cast<const T*>(op.T);
   T* E = reinterpret_cast<T*>(op.E);
-  for (int e = threadIdx.x; e < r * r; e += blockDim.x) {
-    const int ap = e / r, a = e % r;
-    T sr = 0, si = 0;
-    for (long kk = 0; kk < K; ++kk) {
-      const long pre = kk / op.Ppost, post = kk % op.Ppost;
-      const long o1 = pre * r * op.Ppost + (long)ap * op.Ppost + post;
-      const long o2 = pre * r * op.Ppost + (long)a * op.Ppost + post;
-      const T cr = (T)op.C[2 * o1], ci = (T)op.C[2 * o1 + 1];
-      const T tr = Tm[2 * o2], ti = Tm[2 * o2 + 1];
-      sr += cr * tr + ci * ti;
-      si += cr * ti - ci * tr;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c = lane & 15, g = lane >> 4;
+  const int nb = (r + 15) >> 4, nt = nb * nb;
+  const int kparts = nt >= 4 ? 1 : 4 / nt;
+  const int n_items = nt * kparts;
+  const long kchunk = (K + kparts - 1) / kparts;
+  __shared__ T red[2][4][256];
+  v4 accr[4], acci[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    accr[j] = v4{0, 0, 0, 0};
+    acci[j] = v4{0, 0, 0, 0};
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int item = wave + 4 * j;
+    if (item < n_items) {
+      const int tile = item % nt, kp = item / nt;
+      const int ti = tile / nb, tj = tile % nb;
+      const int arow = 16 * ti + c, bcol = 16 * tj + c;
+      const long k0 = kp * kchunk, k1 = k0 + kchunk < K ? k0 + kchunk : K;
+      for (long kb = k0; kb < k1; kb += 4) {
+        const long k = kb + g;
+        T ar = 0, ai = 0, br = 0, bi = 0;
+        if (k < k1) {
+          const long pre = k / op.Ppost, post = k % op.Ppost;
+          const long base = pre * r * op.Ppost + post;
+          if (arow < r) {
+            const long o = base + (long)arow * op.Ppost;
+            ar = (T)op.C[2 * o];
+            ai = -(T)op.C[2 * o + 1];  // conj(C)
+          }
+          if (bcol < r) {
+            const long o = base + (long)bcol * op.Ppost;
+            br = Tm[2 * o];
+            bi = Tm[2 * o + 1];
+          }
+        }
+        cmma<T>(accr[j], acci[j], ar, ai, br, bi);
+      }
     }
-    E[2 * e] = sr;
-    E[2 * e + 1] = si;
+  }
+  if (kparts == 1) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int item = wave + 4 * j;
+      if (item < n_items) {
+        const int ti = item / nb, tj = item % nb;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int row = 16 * ti + MT<T>::drow(g, q), col = 16 * tj + c;
+          if (row < r && col < r) {
+            E[2 * ((long)row * r + col)] = accr[j][q];
+            E[2 * ((long)row * r + col) + 1] = acci[j][q];
+          }
+        }
+      }
+    }
+    return;
+  }
+  // nt < 4: each wave holds one partial of some tile in accr[0]
+  const int item = wave;
+  const int tile = item % nt, kp = item / nt;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    red[0][wave][MT<T>::drow(g, q) * 16 + c] = accr[0][q];
+    red[1][wave][MT<T>::drow(g, q) * 16 + c] = acci[0][q];
+  }
+  __syncthreads();
+  (void)tile;
+  (void)kp;
+  for (int e = threadIdx.x; e < nt * 256; e += 256) {
+    const int t = e / 256, w = e % 256;
+    T sr = 0, si = 0;
+    for (int p = 0; p < kparts; ++p) {
+      sr += red[0][t + p * nt][w];
+      si += red[1][t + p * nt][w];
+    }
+    const int ti = t / nb, tj = t % nb;
+    const int row = 16 * ti + w / 16, col = 16 * tj + w % 16;
+    if (row < r && col < r) {
+      E[2 * ((long)row * r + col)] = sr;
+      E[2 * ((long)row * r + col) + 1] = si;
+    }
   }
 }
 
@@ -647,10 +784,24 @@ __global__ void k_step_inc(int* ctr, int value) {
 // ---------------------------------------------------------------------------
 // launchers (host)
 // ---------------------------------------------------------------------------
+size_t apply_lds_bytes(int fp64, int nfl, int d1, int d2, int with_ab) {
+  return (size_t)apply_lds_elems(nfl, d1, d2, with_ab) * (fp64 ? sizeof(double) : sizeof(float));
+}
+
 hipError_t launch_apply(int fp64, int in_fp64, const ApplyGroup* groups, const ApplyTile* tiles,
-                        int n_tiles, const int* step_ctr, hipStream_t s) {
+                        int n_tiles, const int* step_ctr, size_t lds, hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
-  const size_t lds = fp64 ? 4 * 2 * 64 * 16 * sizeof(double) : 4 * 2 * 64 * 16 * sizeof(float);
+  static bool attr_set = false;
+  if (!attr_set) {
+    const int cap = 160 * 1024;
+    (void)hipFuncSetAttribute((const void*)k_apply<float, float>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, cap);
+    (void)hipFuncSetAttribute((const void*)k_apply<float, double>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, cap);
+    (void)hipFuncSetAttribute((const void*)k_apply<double, double>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, cap);
+    attr_set = true;
+  }
   if (fp64) {
     if (in_fp64)
       hipLaunchKernelGGL((k_apply<double, double>), dim3(n_tiles), dim3(256), lds, s, groups, tiles, step_ctr);

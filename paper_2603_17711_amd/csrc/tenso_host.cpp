@@ -18,7 +18,8 @@
 
 namespace tenso {
 hipError_t launch_apply(int fp64, int in_fp64, const ApplyGroup* groups, const ApplyTile* tiles,
-                        int n_tiles, const int* step_ctr, hipStream_t s);
+                        int n_tiles, const int* step_ctr, size_t lds, hipStream_t s);
+size_t apply_lds_bytes(int fp64, int nfl, int d1, int d2, int with_ab);
 hipError_t launch_presum(int fp64, const PresumOp* ops, int n, const int* step_ctr, hipStream_t s);
 hipError_t launch_combine(int fp64, const CombineOp* ops, const void* tiles, int n_tiles,
                           hipStream_t s);
@@ -575,6 +576,15 @@ struct Builder {
   void launch(int kind, int in_fp64, int first, int count, int tfirst, int tcount, size_t lds = 0) {
     LaunchRec L{kind, in_fp64, first, count, tfirst, tcount, lds};
     if (kind == LK_APPLY) {
+      size_t mx = 0;
+      for (int t = tfirst; t < tfirst + tcount; ++t) {
+        const ApplyTile& tl = G.atiles[t];
+        const ApplyGroup& g = G.groups[first + tl.group];
+        const int njb = (g.d2 + 15) / 16;
+        const int nfl = (tl.u0 + tl.nu - 1) / njb - tl.u0 / njb + 1;
+        mx = std::max(mx, apply_lds_bytes(P_.fp64, nfl, g.d1, g.d2, tl.pad));
+      }
+      L.lds = mx;
       // useful work (no padding): pair term F*d1*d2*(d1+d2) complex MACs,
       // one-sided terms F*d1*d1*d2 or F*d1*d2*d2; bytes: input read, output
       // written, operand matrices read once per group
@@ -615,22 +625,39 @@ struct Builder {
     return tr;
   }
 
-  // tiles for one group of units, each tile <= 4*uw units
-  void add_tiles(int gi, int d1, int d2, long F, int target) {
+  // Padded MFMA work (flops) of one unit (f, 16-column block) for one term.
+  static double unit_work(int d1, int d2) {
+    const int D1 = 16 * ((d1 + 15) / 16);
+    const int k1 = 4 * ((d2 + 3) / 4), k2 = 4 * ((d1 + 3) / 4);
+    return 8.0 * 16 * D1 * (k1 + k2);
+  }
+
+  // Tiles for one group of units: about `tile_work` flops per tile (at most
+  // 4*uw units), at least `target` tiles, and the tile's input slices and
+  // operand matrices within the LDS budget.
+  void add_tiles(int gi, int d1, int d2, long F, int target, int n_terms) {
     const int nib = (d1 + 15) / 16, njb = (d2 + 15) / 16;
-    const int NT = P.fp64 ? 4 : 8;
-    if (nib > NT || d1 > 64) fail(TENSO_EUNSUPPORTED, "leg dimension above 64 in the apply kernel");
-    long units = F * njb;
-    int uw = (int)std::max<long>(1, std::min<long>(NT / nib, (units + 4L * target - 1) / (4L * target)));
-    long per = 4L * uw;
+    const int NT = 4;  // accumulator tiles per wavefront in the kernel
+    const size_t budget = 160 * 1024;
+    if (nib > NT || d1 > 64 || d2 > 64 || apply_lds_bytes(P.fp64, 1, d1, d2, 1) > budget)
+      fail(TENSO_EUNSUPPORTED, "leg dimensions too large for the apply kernel in this precision");
+    const long units = F * njb;
+    const double per_unit = unit_work(d1, d2) * std::max(1, n_terms);
+    long want = std::max<long>(target, (long)std::ceil(units * per_unit / kTileWork));
+    long per = std::max<long>(1, (units + want - 1) / want);
+    per = std::min<long>(per, 4L * (NT / nib));
+    while (per > 1 && apply_lds_bytes(P.fp64, (int)((per + njb - 1) / njb + 1), d1, d2, 1) > budget)
+      per /= 2;
     for (long u = 0; u < units; u += per) {
       ApplyTile tl{};
       tl.group = gi;
       tl.u0 = (int)u;
       tl.nu = (int)std::min<long>(per, units - u);
+      tl.pad = 1;
       G.atiles.push_back(tl);
     }
   }
+  static constexpr double kTileWork = 16e6;
 
   // Emit apply launches of recipe R on input X -> parts (chunked), with the
   // presum launch in front.  Returns the number of partial slabs written.
@@ -694,12 +721,17 @@ struct Builder {
       const int d1 = R.dims[g.l1], d2 = R.dims[g.l2];
       const long F = Pn / ((long)d1 * d2);
       const long units = F * ((d2 + 15) / 16);
-      // chunks over terms so that the launch has about `target` tiles
+      // Term chunks (each with its own partial output): when even 4-unit
+      // tiles would exceed the tile work, or the launch wants more tiles
+      // than the units allow.
       int nchunk = 1;
-      if (target > 1) {
-        long tiles_one = (units + 3) / 4;
-        nchunk = (int)std::min<long>(8, std::max<long>(1, (long)target / std::max<long>(1, tiles_one * (long)R.groups.size())));
-        nchunk = std::min<int>(nchunk, std::max<int>(1, (int)trs.size() / 4));
+      {
+        const double w_all = (double)units * unit_work(d1, d2) * (double)trs.size();
+        const long tiles_units = std::max<long>(1, (units + 3) / 4);
+        long want = std::max<long>((long)std::ceil(w_all / kTileWork),
+                                   target > 1 ? (long)target / (long)R.groups.size() : 1);
+        nchunk = (int)std::min<long>(8, std::max<long>(1, (want + tiles_units - 1) / tiles_units));
+        nchunk = std::min<int>(nchunk, std::max<int>(1, (int)trs.size() / 2));
       }
       size_t per = (trs.size() + nchunk - 1) / nchunk;
       for (int ch = 0; ch < nchunk; ++ch) {
@@ -722,7 +754,9 @@ struct Builder {
         ag.rel = rel;
         ag.accumulate = 0;
         G.groups.push_back(ag);
-        add_tiles((int)G.groups.size() - 1 - gfirst, d1, d2, F, target > 1 ? std::max(1, target / (nchunk * (int)R.groups.size())) : 1);
+        add_tiles((int)G.groups.size() - 1 - gfirst, d1, d2, F,
+                  target > 1 ? std::max(1, target / (nchunk * (int)R.groups.size())) : 1,
+                  (int)(b - a));
       }
     }
     if ((size_t)part * Pn > P.parts_cap) fail(TENSO_EINVAL, "parts capacity exceeded");
@@ -867,7 +901,7 @@ struct Builder {
     ag.F = (int)(Pn / ((long)ag.d1 * ag.d2));
     ag.rel = 0;
     G.groups.push_back(ag);
-    add_tiles((int)G.groups.size() - 1 - gfirst, ag.d1, ag.d2, ag.F, std::max(1, P.par_target / 8));
+    add_tiles((int)G.groups.size() - 1 - gfirst, ag.d1, ag.d2, ag.F, std::max(1, P.par_target / 8), 1);
   }
 
   void emit_qr(int node, int leg, int transposeR) {
@@ -1271,14 +1305,14 @@ static void run(const DevProgram& D, int fp64, const int* ctr, hipStream_t s) {
           hipEvent_t e0 = g_prof.get(), e1 = g_prof.get();
           hipchk(hipEventRecord(e0, s), "hipEventRecord");
           e = launch_apply(fp64, L.in_fp64, (const ApplyGroup*)(b + D.o_groups) + L.first,
-                           (const ApplyTile*)(b + D.o_atiles) + L.tfirst, L.tcount, ctr, s);
+                           (const ApplyTile*)(b + D.o_atiles) + L.tfirst, L.tcount, ctr, L.lds, s);
           hipchk(hipEventRecord(e1, s), "hipEventRecord");
           g_prof.ev.push_back({e0, e1});
           g_prof.work.push_back({L.flops, L.bytes});
           break;
         }
         e = launch_apply(fp64, L.in_fp64, (const ApplyGroup*)(b + D.o_groups) + L.first,
-                         (const ApplyTile*)(b + D.o_atiles) + L.tfirst, L.tcount, ctr, s);
+                         (const ApplyTile*)(b + D.o_atiles) + L.tfirst, L.tcount, ctr, L.lds, s);
         break;
       case LK_PRESUM:
         e = launch_presum(fp64, (const PresumOp*)(b + D.o_presums) + L.first, L.count, ctr, s);
