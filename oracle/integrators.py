@@ -21,9 +21,16 @@ Readings (documented):
   norm are treated as exact zeros, which fixes the orthonormal completion of
   rank-deficient cores (the truncated-rank result depends on it).  When a matricisation has fewer rows than the bond
   dimension the QR move lowers the bond dimension to the row count (exact).
-* ps2 truncation: keep the smallest r' with
-  sqrt(sum_{i>=r'} s_i^2) <= eps * sqrt(sum s_i^2), then 1 <= r' <= max_rank;
-  if the singular value after the cut equals the last one kept, keep it too.
+* ps2 truncation: r_eps = the smallest r with sqrt(sum_{i>=r} s_i^2) <=
+  eps * sqrt(sum s_i^2); keep r' = min(max_rank, available, r_eps + 1)
+  directions (the extra direction is room for the rank to grow, in the
+  spirit of TENSO's ps2_ratio that reincorporates part of the discarded
+  spectrum).  ps2 starts from the padded initial state at rank 2: with
+  rank-1 bonds every two-site tensor of a tree whose inner nodes carry no
+  physical leg has a side of dimension 1 and no bond could ever grow.
+  Directions beyond the singular vectors with s_i > 1e-10 s_1 are completed
+  by projecting e_0, e_1, ... onto the orthogonal complement of the kept
+  singular subspace (deterministic, independent of the vectors' phases).
 
 Pins (tests): at full rank both sweeps equal exact dense propagation up to the
 RK4 error; results do not depend on the tree shape at full rank; ps2 with
@@ -47,6 +54,9 @@ def rk4(F, y, t0, tau):
 
 
 QR_RANK_TOL = 1e-10
+SVD_ZERO_TOL = 1e-10   # singular values below this fraction of the largest are zero
+PS2_GROW = 1           # directions kept beyond the rank needed for eps (room to grow)
+PS2_INIT_RANK = 2      # ps2 starts from the padded initial state at this rank
 
 
 def householder_qr(A, tol=QR_RANK_TOL):
@@ -187,20 +197,42 @@ class Propagator:
 
     # -- ps2 ----------------------------------------------------------------
     @staticmethod
-    def truncation_rank(s, eps, max_rank):
+    def truncation_rank(s, eps, max_rank, avail, grow=PS2_GROW):
+        """r_eps = smallest r with sqrt(sum_{i>=r} s_i^2) <= eps * sqrt(sum s_i^2);
+        keep r' = min(max_rank, avail, r_eps + grow)."""
         s = np.asarray(s, dtype=np.float64)
-        tot = np.sqrt(np.sum(s * s))
+        tot2 = float(np.sum(s * s))
         n = len(s)
-        r = n
-        for k in range(1, n + 1):
-            tail = np.sqrt(np.sum(s[k:] * s[k:]))
-            if tail <= eps * tot:
-                r = k
+        r_eps = n
+        tail2 = tot2
+        for k in range(0, n + 1):
+            tail2 = float(np.sum(s[k:] * s[k:]))
+            if tail2 <= eps * eps * tot2:
+                r_eps = k
                 break
-        r = max(1, min(r, max_rank, n))
-        while r < min(max_rank, n) and s[r] == s[r - 1]:
-            r += 1
-        return r
+        r_eps = max(1, r_eps)
+        return max(1, min(max_rank, avail, r_eps + grow))
+
+    @staticmethod
+    def complete_isometry(U, r):
+        """Columns U (n x k, orthonormal) completed to n x r: the unit vectors
+        e_0, e_1, ... are projected onto the orthogonal complement of span(U)
+        and orthonormalised in order (twice-repeated Gram-Schmidt), skipping
+        residuals with norm below 0.5.  Depends on span(U) only."""
+        n, k = U.shape
+        Q = [U[:, j] for j in range(k)]
+        j = 0
+        while len(Q) < r and j < n:
+            v = np.zeros(n, dtype=np.complex128)
+            v[j] = 1.0
+            for _ in range(2):
+                for q in Q:
+                    v = v - q * np.vdot(q, v)
+            nv = np.linalg.norm(v)
+            if nv > 0.5:
+                Q.append(v / nv)
+            j += 1
+        return np.stack(Q, axis=1)
 
     def _edge(self, s, c, t0, tau, eps, max_rank, center_to_child):
         tr, C = self.tree, self.C
@@ -213,12 +245,16 @@ class Propagator:
         rows = int(np.prod(shp[:ns]))
         mat = Th.reshape(rows, -1)
         U, S, Vh = np.linalg.svd(mat, full_matrices=False)
-        r = self.truncation_rank(S, eps, max_rank)
-        U, S, Vh = U[:, :r], S[:r], Vh[:r]
+        r = self.truncation_rank(S, eps, max_rank, min(mat.shape))
+        k = int(np.sum(S > SVD_ZERO_TOL * S[0])) if S[0] > 0 else 0
+        k = min(k, r)
         if center_to_child:
-            Cs, Cc = U, S[:, None] * Vh
+            Cs = self.complete_isometry(U[:, :k], r)      # rows x r isometry
+            Cc = Cs.conj().T @ mat                          # projection
         else:
-            Cs, Cc = U * S[None, :], Vh
+            W = self.complete_isometry(Vh[:k].conj().T, r)  # cols x r isometry
+            Cc = W.conj().T
+            Cs = mat @ W
         C[s] = np.moveaxis(Cs.reshape(shp[:ns] + (r,)), -1, i)
         C[c] = Cc.reshape((r,) + shp[ns:])
         self._set_rank(c, r)

@@ -21,7 +21,8 @@ def build(inst, rank=None):
     K = len(dims) - 2
     R = inst.rank if rank is None else rank
     if inst.method == "ps2":
-        R = 1
+        from .integrators import PS2_INIT_RANK
+        R = PS2_INIT_RANK
     if inst.tree == "train":
         tree = train_tree(inst.M, dims[2:], R)
     else:

@@ -53,7 +53,7 @@ def test_ps2_eps0_equals_dense():
     n = 50
     ref = dense_propagate(terms, dims, RHO0, 0.01, n, every=n)[-1]
     base = nary_tree(2, [5] * 3, 2, 1)
-    tree = Tree(base.parent, base.end_node, base.end_dims, max_rank=1)
+    tree = Tree(base.parent, base.end_node, base.end_dims, max_rank=2)
     P = Propagator(tree, terms, initial_state(tree, RHO0))
     for s in range(n):
         ranks = P.step_ps2(s * 0.01, 0.01, 0.0, 1000)
