@@ -161,6 +161,23 @@ class Plan:
         check(lib().tenso_step_fixed(self.h, C.c_void_p(self.state.data_ptr()), t0, dt, n_steps,
                                      ptr, C.c_void_p(self.ws.data_ptr()), _stream()))
 
+    def step_adaptive(self, n_steps, dt, eps, max_rank, t0=0.0, drive_tab=None):
+        ptr = C.c_void_p(drive_tab.data_ptr()) if drive_tab is not None else None
+        check(lib().tenso_step_adaptive(self.h, C.c_void_p(self.state.data_ptr()), t0, dt,
+                                        n_steps, eps, max_rank, ptr,
+                                        C.c_void_p(self.ws.data_ptr()), _stream()))
+
+    def rank_log(self, cap=100000):
+        out = np.zeros(cap, np.int32)
+        n = check(lib().tenso_rank_trajectory(self.h, out.ctypes.data_as(C.POINTER(C.c_int32)), cap))
+        return out[:n].tolist()
+
+    def ranks(self):
+        out = np.zeros(self.n_nodes, np.int32)
+        check(lib().tenso_state_export(self.h, C.c_void_p(self.state.data_ptr()), None,
+                                       out.ctypes.data_as(C.POINTER(C.c_int32)), _stream()))
+        return out
+
     def rho(self):
         M = self.M
         out = np.zeros((M, M), np.complex128)
@@ -177,7 +194,8 @@ class Plan:
 
 
 def build_instance(inst, precision=FP32, rank=None, device="cuda"):
-    """Tree + generator + plan for a workloads.Instance (ps1)."""
+    """Tree + generator + plan for a workloads.Instance (ps1, or ps2 when
+    inst.method == "ps2": `rank` is then the rank cap)."""
     drive_ops = [] if inst.drive is None else [inst.drive[0]]
     table, dims = heom_table(inst.H, inst.baths, inst.depth, drive_ops)
     R = inst.rank if rank is None else rank
@@ -186,7 +204,8 @@ def build_instance(inst, precision=FP32, rank=None, device="cuda"):
     else:
         tree = Tree.nary(inst.M, dims, int(inst.tree[4:]), R)
     gen = Generator(tree, table)
-    plan = Plan(tree, gen, precision=precision, method=PS1, device=device)
+    method = PS2 if inst.method == "ps2" else PS1
+    plan = Plan(tree, gen, precision=precision, method=method, max_rank=R, device=device)
     plan.init_state(inst.rho0)
     return plan
 

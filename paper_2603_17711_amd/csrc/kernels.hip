@@ -13,6 +13,7 @@
 // rho    : bottom-up vacuum contraction for rho_S = <0|Omega>.
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <algorithm>
 #include "tenso_internal.h"
 
 namespace tenso {
@@ -777,6 +778,333 @@ __global__ void __launch_bounds__(256) k_rho(const RhoProg* __restrict__ progs) 
   }
 }
 
+// ---------------------------------------------------------------------------
+// ps2: merge, Gram eigen-decomposition, split (FP64, single workgroup)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_merge(const MergeOp* __restrict__ ops) {
+  const MergeOp op = ops[blockIdx.y];
+  const z2* S = reinterpret_cast<const z2*>(op.Cs);
+  const z2* Cc = reinterpret_cast<const z2*>(op.Cc);
+  z2* Th = reinterpret_cast<z2*>(op.Theta);
+  const long n = (long)op.rows * op.cols;
+  for (long e = blockIdx.x * 256L + threadIdx.x; e < n; e += 256L * gridDim.x) {
+    const int row = (int)(e / op.cols), col = (int)(e % op.cols);
+    const int pre = row / op.Ppost, post = row % op.Ppost;
+    double sr = 0, si = 0;
+    for (int a = 0; a < op.r; ++a) {
+      const z2 x = S[(long)pre * op.r * op.Ppost + (long)a * op.Ppost + post];
+      const z2 y = Cc[(long)a * op.cols + col];
+      sr += x.r * y.r - x.i * y.i;
+      si += x.r * y.i + x.i * y.r;
+    }
+    Th[e] = z2{sr, si};
+  }
+}
+
+// Cyclic Jacobi on the n x n Hermitian Gram matrix held in LDS (n <= 64),
+// parallel rounds of the circle-method pairing.
+__global__ void __launch_bounds__(256) k_eig(const EigOp* __restrict__ ops) {
+  const EigOp op = ops[blockIdx.x];
+  const int n = op.side == 0 ? op.rows : op.cols;
+  const int m = op.side == 0 ? op.cols : op.rows;
+  const z2* Th = reinterpret_cast<const z2*>(op.Theta);
+  __shared__ z2 G[64 * 64];
+  __shared__ z2 U[64 * 64];
+  __shared__ double rot[32][4];  // c, s, cos(phi), sin(phi)
+  __shared__ int pr[32][2];
+  __shared__ double offmax, diagmax;
+  const int tid = threadIdx.x;
+  // Gram: side 0: G[i][j] = sum_c Th[i][c] conj(Th[j][c]); side 1: sum_r conj(Th[r][i]) Th[r][j]
+  for (int e = tid; e < n * n; e += 256) {
+    const int i = e / n, j = e % n;
+    double sr = 0, si = 0;
+    for (int q = 0; q < m; ++q) {
+      z2 x, y;
+      if (op.side == 0) {
+        x = Th[(long)i * op.cols + q];
+        y = Th[(long)j * op.cols + q];
+        sr += x.r * y.r + x.i * y.i;  // x * conj(y)
+        si += x.i * y.r - x.r * y.i;
+      } else {
+        x = Th[(long)q * op.cols + i];
+        y = Th[(long)q * op.cols + j];
+        sr += x.r * y.r + x.i * y.i;  // conj(x) * y
+        si += x.r * y.i - x.i * y.r;
+      }
+    }
+    G[i * 64 + j] = z2{sr, si};
+    U[i * 64 + j] = z2{i == j ? 1.0 : 0.0, 0.0};
+  }
+  __syncthreads();
+  const int np = (n + 1) / 2;            // pairs per round (a dummy player when n is odd)
+  const int nplay = 2 * np;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    if (tid == 0) {
+      double om = 0, dm = 0;
+      for (int i = 0; i < n; ++i) {
+        dm = fmax(dm, fabs(G[i * 64 + i].r));
+        for (int j = i + 1; j < n; ++j) {
+          const z2 g = G[i * 64 + j];
+          om = fmax(om, sqrt(g.r * g.r + g.i * g.i));
+        }
+      }
+      offmax = om;
+      diagmax = dm;
+    }
+    __syncthreads();
+    if (offmax <= 1e-15 * diagmax || offmax == 0.0) break;
+    for (int round = 0; round < nplay - 1; ++round) {
+      if (tid < np) {
+        int p, q;
+        if (tid == 0) {
+          p = round;
+          q = nplay - 1;
+        } else {
+          p = (round + tid) % (nplay - 1);
+          q = (round - tid + (nplay - 1)) % (nplay - 1);
+        }
+        if (p > q) {
+          const int t = p;
+          p = q;
+          q = t;
+        }
+        pr[tid][0] = p;
+        pr[tid][1] = q;
+        double c = 1, sn = 0, cph = 1, sph = 0;
+        if (q < n) {
+          const z2 g = G[p * 64 + q];
+          const double h = sqrt(g.r * g.r + g.i * g.i);
+          if (h > 1e-300) {
+            const double a = G[p * 64 + p].r, b = G[q * 64 + q].r;
+            const double zeta = (b - a) / (2.0 * h);
+            const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            c = 1.0 / sqrt(1.0 + t * t);
+            sn = t * c;
+            cph = g.r / h;
+            sph = g.i / h;
+          }
+        }
+        rot[tid][0] = c;
+        rot[tid][1] = sn;
+        rot[tid][2] = cph;
+        rot[tid][3] = sph;
+      }
+      __syncthreads();
+      // columns: G <- G J and U <- U J, J = [[c, s], [-s e^{-i phi}, c e^{-i phi}]]
+      for (int e = tid; e < np * n; e += 256) {
+        const int k = e / n, row = e % n;
+        const int p = pr[k][0], q = pr[k][1];
+        if (q >= n) continue;
+        const double c = rot[k][0], sn = rot[k][1], cph = rot[k][2], sph = rot[k][3];
+        const z2 emi{cph, -sph};  // e^{-i phi}
+        for (int w = 0; w < 2; ++w) {
+          z2* A = w == 0 ? G : U;
+          const z2 xp = A[row * 64 + p], xq = A[row * 64 + q];
+          const z2 xq_e = zmul(xq, emi);
+          A[row * 64 + p] = z2{c * xp.r - sn * xq_e.r, c * xp.i - sn * xq_e.i};
+          A[row * 64 + q] = z2{sn * xp.r + c * xq_e.r, sn * xp.i + c * xq_e.i};
+        }
+      }
+      __syncthreads();
+      // rows: G <- J^H G
+      for (int e = tid; e < np * n; e += 256) {
+        const int k = e / n, col = e % n;
+        const int p = pr[k][0], q = pr[k][1];
+        if (q >= n) continue;
+        const double c = rot[k][0], sn = rot[k][1], cph = rot[k][2], sph = rot[k][3];
+        const z2 epi{cph, sph};  // e^{i phi}
+        const z2 xp = G[p * 64 + col], xq = G[q * 64 + col];
+        const z2 xq_e = zmul(xq, epi);
+        G[p * 64 + col] = z2{c * xp.r - sn * xq_e.r, c * xp.i - sn * xq_e.i};
+        G[q * 64 + col] = z2{sn * xp.r + c * xq_e.r, sn * xp.i + c * xq_e.i};
+      }
+      __syncthreads();
+    }
+  }
+  // descending order: rank of each eigenvalue (ties by index)
+  for (int j = tid; j < n; j += 256) {
+    const double lj = G[j * 64 + j].r;
+    int rank = 0;
+    for (int i = 0; i < n; ++i) {
+      const double li = G[i * 64 + i].r;
+      if (li > lj || (li == lj && i < j)) ++rank;
+    }
+    op.evals[rank] = lj;
+    for (int row = 0; row < n; ++row) {
+      const z2 v = U[row * 64 + j];
+      op.evecs[2 * ((long)row * n + rank)] = v.r;
+      op.evecs[2 * ((long)row * n + rank) + 1] = v.i;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_split(const SplitOp* __restrict__ ops) {
+  const SplitOp op = ops[blockIdx.x];
+  const z2* Th = reinterpret_cast<const z2*>(op.Theta);
+  const z2* E = reinterpret_cast<const z2*>(op.evecs);
+  z2* W = reinterpret_cast<z2*>(op.W);
+  const int n = op.side == 0 ? op.rows : op.cols;       // spectral side
+  const int miso = op.iso == 0 ? op.rows : op.cols;     // isometry side
+  const int k = op.k, rp = op.rp;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ double red[2][4];
+  __shared__ double sh_norm;
+  // first k columns of W: spectral vectors on the isometry side
+  for (long e = tid; e < (long)miso * k; e += 256) {
+    const int i = (int)(e / k), j = (int)(e % k);
+    z2 v;
+    if (op.side == op.iso) {
+      v = E[(long)i * n + j];
+    } else {
+      // map through Theta: other side vector = Theta^(H) u_j / sigma_j
+      const double sig = sqrt(fmax(op.evals[j], 0.0));
+      double sr = 0, si = 0;
+      if (op.iso == 1) {  // spectral on rows: w_j = Theta^H u_j / s_j (cols)
+        for (int r = 0; r < op.rows; ++r) {
+          const z2 t = Th[(long)r * op.cols + i];
+          const z2 u = E[(long)r * n + j];
+          sr += t.r * u.r + t.i * u.i;  // conj(t) * u
+          si += t.r * u.i - t.i * u.r;
+        }
+      } else {  // spectral on cols: w_j = Theta v_j / s_j (rows)
+        for (int c = 0; c < op.cols; ++c) {
+          const z2 t = Th[(long)i * op.cols + c];
+          const z2 u = E[(long)c * n + j];
+          sr += t.r * u.r - t.i * u.i;
+          si += t.r * u.i + t.i * u.r;
+        }
+      }
+      v = z2{sr / sig, si / sig};
+    }
+    W[(long)i * rp + j] = v;
+  }
+  __syncthreads();
+  // re-orthonormalise the mapped columns (only needed when mapped through Theta)
+  if (op.side != op.iso) {
+    for (int j = 0; j < k; ++j) {
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int q = 0; q < j; ++q) {
+          double dr = 0, di = 0;
+          for (int i = lane; i < miso; i += 64) {
+            const z2 a = W[(long)i * rp + q], b = W[(long)i * rp + j];
+            dr += a.r * b.r + a.i * b.i;
+            di += a.r * b.i - a.i * b.r;
+          }
+          dr = wave_sum(dr);
+          di = wave_sum(di);
+          __syncthreads();
+          if (wave == 0)
+            for (int i = lane; i < miso; i += 64) {
+              const z2 a = W[(long)i * rp + q];
+              W[(long)i * rp + j].r -= a.r * dr - a.i * di;
+              W[(long)i * rp + j].i -= a.r * di + a.i * dr;
+            }
+          __syncthreads();
+        }
+      }
+      double s2 = 0;
+      for (int i = tid; i < miso; i += 256) {
+        const z2 b = W[(long)i * rp + j];
+        s2 += b.r * b.r + b.i * b.i;
+      }
+      s2 = wave_sum(s2);
+      if (lane == 0) red[0][wave] = s2;
+      __syncthreads();
+      if (tid == 0) sh_norm = sqrt(red[0][0] + red[0][1] + red[0][2] + red[0][3]);
+      __syncthreads();
+      for (int i = tid; i < miso; i += 256) {
+        W[(long)i * rp + j].r /= sh_norm;
+        W[(long)i * rp + j].i /= sh_norm;
+      }
+      __syncthreads();
+    }
+  }
+  // completion: unit vectors e_0, e_1, ... projected out of span(W[:, :j]),
+  // twice, accepted when the residual norm exceeds 0.5
+  int j = k;
+  for (int cand = 0; cand < miso && j < rp; ++cand) {
+    for (int i = tid; i < miso; i += 256) W[(long)i * rp + j] = z2{i == cand ? 1.0 : 0.0, 0.0};
+    __syncthreads();
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int q = 0; q < j; ++q) {
+        double dr = 0, di = 0;
+        for (int i = lane; i < miso; i += 64) {
+          const z2 a = W[(long)i * rp + q], b = W[(long)i * rp + j];
+          dr += a.r * b.r + a.i * b.i;
+          di += a.r * b.i - a.i * b.r;
+        }
+        dr = wave_sum(dr);
+        di = wave_sum(di);
+        __syncthreads();
+        if (wave == 0)
+          for (int i = lane; i < miso; i += 64) {
+            const z2 a = W[(long)i * rp + q];
+            W[(long)i * rp + j].r -= a.r * dr - a.i * di;
+            W[(long)i * rp + j].i -= a.r * di + a.i * dr;
+          }
+        __syncthreads();
+      }
+    }
+    double s2 = 0;
+    for (int i = tid; i < miso; i += 256) {
+      const z2 b = W[(long)i * rp + j];
+      s2 += b.r * b.r + b.i * b.i;
+    }
+    s2 = wave_sum(s2);
+    if (lane == 0) red[1][wave] = s2;
+    __syncthreads();
+    if (tid == 0) sh_norm = sqrt(red[1][0] + red[1][1] + red[1][2] + red[1][3]);
+    __syncthreads();
+    if (sh_norm > 0.5) {
+      for (int i = tid; i < miso; i += 256) {
+        W[(long)i * rp + j].r /= sh_norm;
+        W[(long)i * rp + j].i /= sh_norm;
+      }
+      ++j;
+    }
+    __syncthreads();
+  }
+  // new cores
+  z2* Cs = reinterpret_cast<z2*>(op.Cs);
+  z2* Cc = reinterpret_cast<z2*>(op.Cc);
+  auto cs_at = [&](int row, int a) -> long {
+    const int pre = row / op.Ppost_s, post = row % op.Ppost_s;
+    return (long)pre * rp * op.Ppost_s + (long)a * op.Ppost_s + post;
+  };
+  if (op.iso == 0) {
+    for (long e = tid; e < (long)op.rows * rp; e += 256) {
+      const int row = (int)(e / rp), a = (int)(e % rp);
+      Cs[cs_at(row, a)] = W[(long)row * rp + a];
+    }
+    for (long e = tid; e < (long)rp * op.cols; e += 256) {  // Cc = W^H Theta
+      const int a = (int)(e / op.cols), col = (int)(e % op.cols);
+      double sr = 0, si = 0;
+      for (int row = 0; row < op.rows; ++row) {
+        const z2 w = W[(long)row * rp + a], t = Th[(long)row * op.cols + col];
+        sr += w.r * t.r + w.i * t.i;
+        si += w.r * t.i - w.i * t.r;
+      }
+      Cc[e] = z2{sr, si};
+    }
+  } else {
+    for (long e = tid; e < (long)rp * op.cols; e += 256) {  // Cc = W^H
+      const int a = (int)(e / op.cols), col = (int)(e % op.cols);
+      const z2 w = W[(long)col * rp + a];
+      Cc[e] = z2{w.r, -w.i};
+    }
+    for (long e = tid; e < (long)op.rows * rp; e += 256) {  // Cs = Theta W
+      const int row = (int)(e / rp), a = (int)(e % rp);
+      double sr = 0, si = 0;
+      for (int col = 0; col < op.cols; ++col) {
+        const z2 t = Th[(long)row * op.cols + col], w = W[(long)col * rp + a];
+        sr += t.r * w.r - t.i * w.i;
+        si += t.r * w.i + t.i * w.r;
+      }
+      Cs[cs_at(row, a)] = z2{sr, si};
+    }
+  }
+}
+
 __global__ void k_step_inc(int* ctr, int value) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *ctr = value < 0 ? *ctr + 1 : value;
 }
@@ -861,6 +1189,20 @@ hipError_t launch_rho(const RhoProg* progs, int n, hipStream_t s) {
 
 hipError_t launch_step_inc(int* ctr, int value, hipStream_t s) {
   hipLaunchKernelGGL(k_step_inc, dim3(1), dim3(64), 0, s, ctr, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_merge(const MergeOp* op, long n, hipStream_t s) {
+  int blocks = (int)std::min<long>(1024, (n + 255) / 256);
+  hipLaunchKernelGGL(k_merge, dim3(blocks, 1), dim3(256), 0, s, op);
+  return hipGetLastError();
+}
+hipError_t launch_eig(const EigOp* op, hipStream_t s) {
+  hipLaunchKernelGGL(k_eig, dim3(1), dim3(256), 0, s, op);
+  return hipGetLastError();
+}
+hipError_t launch_split(const SplitOp* op, hipStream_t s) {
+  hipLaunchKernelGGL(k_split, dim3(1), dim3(256), 0, s, op);
   return hipGetLastError();
 }
 

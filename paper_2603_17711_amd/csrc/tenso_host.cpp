@@ -20,6 +20,9 @@ namespace tenso {
 hipError_t launch_apply(int fp64, int in_fp64, const ApplyGroup* groups, const ApplyTile* tiles,
                         int n_tiles, const int* step_ctr, size_t lds, hipStream_t s);
 size_t apply_lds_bytes(int fp64, int nfl, int d1, int d2, int with_ab);
+hipError_t launch_merge(const MergeOp* op, long n, hipStream_t s);
+hipError_t launch_eig(const EigOp* op, hipStream_t s);
+hipError_t launch_split(const SplitOp* op, hipStream_t s);
 hipError_t launch_presum(int fp64, const PresumOp* ops, int n, const int* step_ctr, hipStream_t s);
 hipError_t launch_combine(int fp64, const CombineOp* ops, const void* tiles, int n_tiles,
                           hipStream_t s);
@@ -262,9 +265,11 @@ struct Recipe {  // effective generator on one tensor (node core, bond or edge)
 };
 
 struct tenso_plan {
-  tenso_tree tree;
+  tenso_tree tree;   // current ranks
+  tenso_tree cap;    // capacity ranks (sizes every buffer; = tree for ps1)
   tenso_gen gen;
   tenso_plan_opts opts;
+  std::vector<int> slot_r;  // env slot stride (capacity rank) per node
   int fp64 = 0;
   size_t tsz = 8;  // bytes per complex in compute precision
   int max_dim = 1;
@@ -283,6 +288,8 @@ struct tenso_plan {
   size_t ws_presum = 0, ws_xin = 0, ws_acc = 0, ws_parts = 0, ws_envscr = 0, ws_bond = 0,
          ws_qrv = 0, ws_qrtau = 0, ws_rhovec = 0, ws_rhoout = 0, ws_ctr = 0, ws_bytes = 0;
   size_t presum_cap = 0, parts_cap = 0, envscr_cap = 0, qrv_cap = 0;
+  size_t ws_theta = 0, ws_evals = 0, ws_evecs = 0, ws_W = 0, theta_cap = 0, W_cap = 0;
+  void* opbuf = nullptr;  // device scratch for single-op descriptors (ps2)
   int par_target = 64;  // tiles wanted per apply (single-instance latency)
   int built_target = -1;  // par_target the cached programs were built with
   // compiled programs (host descriptors with tagged pointers, device copies)
@@ -300,6 +307,7 @@ struct tenso_plan {
 
   ~tenso_plan() {
     if (cbuf) (void)hipFree(cbuf);
+    if (opbuf) (void)hipFree(opbuf);
   }
 };
 
@@ -475,6 +483,23 @@ static Recipe bond_recipe(const tenso_plan& P, int c) {
   return R;
 }
 
+static Recipe edge_recipe(const tenso_plan& P, int s, int c) {
+  const tenso_tree& t = P.tree;
+  const int i = t.leg_of_child(s, c);
+  std::vector<std::pair<int, Leg>> legs;
+  std::vector<int> dims;
+  for (int j = 0; j < (int)t.legs[s].size(); ++j)
+    if (j != i) {
+      legs.push_back({s, t.legs[s][j]});
+      dims.push_back(t.leg_dim(s, t.legs[s][j]));
+    }
+  for (int j = 1; j < (int)t.legs[c].size(); ++j) {
+    legs.push_back({c, t.legs[c][j]});
+    dims.push_back(t.leg_dim(c, t.legs[c][j]));
+  }
+  return make_recipe(P, legs, dims);
+}
+
 // -- layouts ------------------------------------------------------------------
 static long prod(const std::vector<int>& d, int a, int b) {
   long p = 1;
@@ -487,11 +512,11 @@ static void* oref_ptr(const tenso_plan& P, const ORef& o) {
     case 1:
       return (char*)P.cbuf + (P.fp64 ? P.mat_off64[o.idx] : P.mat_off32[o.idx]);
     case 2: {
-      size_t r = P.tree.rank[o.node];
+      size_t r = P.slot_r[o.node];
       return tagp(TAG_WS, P.envd_off[o.node] + (size_t)o.idx * r * r * P.tsz);
     }
     case 3: {
-      size_t r = P.tree.rank[o.node];
+      size_t r = P.slot_r[o.node];
       return tagp(TAG_WS, P.envu_off[o.node] + (size_t)o.idx * r * r * P.tsz);
     }
   }
@@ -499,7 +524,12 @@ static void* oref_ptr(const tenso_plan& P, const ORef& o) {
 }
 
 static void layout(tenso_plan& P) {
+  // every size below is taken at the capacity ranks
+  tenso_tree cur = P.tree;
+  P.tree = P.cap;
   const tenso_tree& t = P.tree;
+  P.slot_r.assign(t.n, 1);
+  for (int c = 1; c < t.n; ++c) P.slot_r[c] = t.rank[c];
   P.core_off.assign(t.n, 0);
   size_t off = 0;
   long maxP = 1;
@@ -513,26 +543,36 @@ static void layout(tenso_plan& P) {
   for (int c = 1; c < t.n; ++c) maxr = std::max(maxr, t.rank[c]);
   for (int e = 0; e < t.n_ends; ++e) P.max_dim = std::max(P.max_dim, t.end_dim[e]);
   P.max_dim = std::max(P.max_dim, maxr);
-  // capacities
-  size_t presum = 0, parts = 0, envscr = 0, qrv = 0;
-  for (int s = 0; s < t.n; ++s) {
-    Recipe R = node_recipe(P, s);
+  size_t presum = 0, parts = 0, envscr = 0, qrv = 0, theta = 0, wcap = 0;
+  auto recipe_caps = [&](const Recipe& R, long n) {
     size_t ps = 0;
     for (auto& g : R.groups) {
       if (!g.sa.empty()) ps += (size_t)R.dims[g.l1] * R.dims[g.l1];
       if (!g.sb.empty()) ps += (size_t)R.dims[g.l2] * R.dims[g.l2];
     }
     presum = std::max(presum, ps);
-    // parts: groups x chunks (chunks <= 8)
-    parts = std::max(parts, (size_t)R.groups.size() * 8 * t.size(s));
+    parts = std::max(parts, (size_t)R.groups.size() * 8 * (size_t)n);
+  };
+  for (int s = 0; s < t.n; ++s) {
+    recipe_caps(node_recipe(P, s), t.size(s));
     if (s > 0) {
       envscr = std::max(envscr, P.dkeys[s].size() * (size_t)t.size(s));
       envscr = std::max(envscr, P.ukeys[s].size() * (size_t)t.size(t.parent[s]));
       size_t r = t.rank[s];
-      qrv = std::max(qrv, (size_t)t.size(s));                 // QR toward parent
-      qrv = std::max(qrv, (size_t)t.size(t.parent[s]));       // QR toward child
+      qrv = std::max(qrv, (size_t)t.size(s));
+      qrv = std::max(qrv, (size_t)t.size(t.parent[s]));
       presum = std::max(presum, 2 * r * r);
       parts = std::max(parts, 8 * r * r);
+      if (P.opts.method == TENSO_PS2) {
+        const int p = t.parent[s];
+        const long rows = t.size(p) / t.rank[s], cols = t.size(s) / t.rank[s];
+        if (std::min(rows, cols) > 64)
+          fail(TENSO_EUNSUPPORTED, "ps2 edge whose smaller side exceeds 64 at the rank cap");
+        theta = std::max(theta, (size_t)(rows * cols));
+        wcap = std::max(wcap, (size_t)std::max(rows, cols) * (size_t)maxr);
+        recipe_caps(edge_recipe(P, p, s), rows * cols);
+        maxP = std::max<long>(maxP, rows * cols);
+      }
     }
   }
   size_t w = 0;
@@ -552,6 +592,8 @@ static void layout(tenso_plan& P) {
   P.parts_cap = parts;
   P.envscr_cap = envscr;
   P.qrv_cap = qrv;
+  P.theta_cap = theta;
+  P.W_cap = wcap;
   P.ws_presum = take(std::max<size_t>(1, presum) * P.tsz);
   P.ws_xin = take((size_t)maxP * P.tsz);
   P.ws_acc = take((size_t)maxP * 16);
@@ -563,7 +605,14 @@ static void layout(tenso_plan& P) {
   P.ws_rhovec = take((size_t)t.n * maxr * 16);
   P.ws_rhoout = take((size_t)t.end_dim[0] * t.end_dim[0] * 16);
   P.ws_ctr = take(64);
+  if (P.opts.method == TENSO_PS2) {
+    P.ws_theta = take(std::max<size_t>(1, theta) * 16);
+    P.ws_evals = take(64 * 8);
+    P.ws_evecs = take(64 * 64 * 16);
+    P.ws_W = take(std::max<size_t>(1, wcap) * 16);
+  }
   P.ws_bytes = w;
+  P.tree = cur;
 }
 
 // -- program building ---------------------------------------------------------
@@ -820,7 +869,7 @@ struct Builder {
       GramOp go{};
       go.C = (const double*)core(x);
       go.T = ws(P.ws_envscr + k * Pn * P.tsz);
-      go.E = ws(P.envd_off[x] + k * (size_t)t.rank[x] * t.rank[x] * P.tsz);
+      go.E = ws(P.envd_off[x] + k * (size_t)P.slot_r[x] * P.slot_r[x] * P.tsz);
       go.r = t.rank[x];
       go.Ppre = 1;
       go.Ppost = (int)(Pn / t.rank[x]);
@@ -854,7 +903,7 @@ struct Builder {
       GramOp go{};
       go.C = (const double*)core(p);
       go.T = ws(P.ws_envscr + k * Pn * P.tsz);
-      go.E = ws(P.envu_off[x] + k * (size_t)t.rank[x] * t.rank[x] * P.tsz);
+      go.E = ws(P.envu_off[x] + k * (size_t)P.slot_r[x] * P.slot_r[x] * P.tsz);
       go.r = t.rank[x];
       go.Ppre = (int)prod(dims, 0, open);
       go.Ppost = (int)prod(dims, open + 1, (int)dims.size());
@@ -1020,7 +1069,7 @@ struct Builder {
     rp.n_nodes = t.n;
     rp.vecs = (double*)ws(P.ws_rhovec);
     int maxr = 1;
-    for (int c = 1; c < t.n; ++c) maxr = std::max(maxr, t.rank[c]);
+    for (int c = 1; c < t.n; ++c) maxr = std::max(maxr, P.slot_r[c]);
     rp.vec_ld = maxr;
     rp.rho_out = (double*)ws(P.ws_rhoout);
     G.rprogs.push_back(rp);
@@ -1363,6 +1412,159 @@ static void build_init(tenso_plan& P, Program& G) {
 }
 
 // ---------------------------------------------------------------------------
+// ps2: host-driven two-site sweep (ranks decided on the host per edge)
+// ---------------------------------------------------------------------------
+struct Ps2Exec {
+  tenso_plan& P;
+  void* state;
+  void* ws;
+  double dt;
+  const double* drive;
+  int ld;
+  hipStream_t s;
+  int max_rank;
+  double eps;
+  int* ctr = nullptr;
+  DevProgram D;
+
+  void exec(const Program& G) {
+    upload(D, G, state, ws, dt, drive, ld, s);
+    run(D, P.fp64, ctr, s);
+  }
+  char* wsb(size_t off) { return (char*)ws + off; }
+  double* core(int x) { return (double*)((char*)state + P.core_off[x]); }
+
+  void env_down(int x) {
+    Program G;
+    Builder b(P, G);
+    b.emit_env_down(x);
+    exec(G);
+  }
+  void env_up(int x) {
+    Program G;
+    Builder b(P, G);
+    b.emit_env_up(x);
+    exec(G);
+  }
+  void node_bwd(int x, int half) {
+    Program G;
+    Builder b(P, G);
+    b.emit_rk4(node_recipe(P, x), b.core(x), P.tree.size(x), -1.0, half);
+    exec(G);
+  }
+  // QR of core `a` toward leg `la`, R absorbed into core `b` on leg `lb`
+  void move(int a, int la, int b_, int lb) {
+    Program G;
+    Builder b(P, G);
+    b.emit_qr(a, la, 0);
+    b.emit_absorb(b_, lb, 0);
+    exec(G);
+  }
+  template <class T>
+  const T* put_op(const T& op, size_t slot) {
+    char* dst = (char*)P.opbuf + slot * 512;
+    hipchk(hipMemcpyAsync(dst, &op, sizeof(T), hipMemcpyHostToDevice, s), "op upload");
+    return (const T*)dst;
+  }
+
+  void edge(int sn, int c, int half, bool center_to_child) {
+    tenso_tree& t = P.tree;
+    const int i = t.leg_of_child(sn, c);
+    const int r = t.rank[c];
+    const std::vector<int> ds = t.shape(sn);
+    const long rows = t.size(sn) / r, cols = t.size(c) / r;
+    long ppost = 1;
+    for (int j = i + 1; j < (int)ds.size(); ++j) ppost *= ds[j];
+    double* theta = (double*)wsb(P.ws_theta);
+    MergeOp mo{core(sn), core(c), theta, (int)rows, (int)cols, r, (int)ppost};
+    hipchk(launch_merge(put_op(mo, 0), rows * cols, s), "merge");
+    {
+      Program G;
+      Builder b(P, G);
+      b.emit_rk4(edge_recipe(P, sn, c), b.ws(P.ws_theta), rows * cols, +1.0, half);
+      exec(G);
+    }
+    const int side = rows <= cols ? 0 : 1;
+    const int n = (int)std::min(rows, cols);
+    EigOp eo{theta, (int)rows, (int)cols, side, (double*)wsb(P.ws_evals), (double*)wsb(P.ws_evecs)};
+    hipchk(launch_eig(put_op(eo, 1), s), "eig");
+    std::vector<double> lam(n);
+    hipchk(hipMemcpyAsync(lam.data(), wsb(P.ws_evals), n * sizeof(double), hipMemcpyDeviceToHost, s),
+           "evals");
+    hipchk(hipStreamSynchronize(s), "sync");
+    // truncation: singular values s_i = sqrt(max(lambda_i, 0)), descending
+    std::vector<double> sv(n);
+    double tot2 = 0;
+    for (int j = 0; j < n; ++j) {
+      sv[j] = std::sqrt(std::max(lam[j], 0.0));
+      tot2 += sv[j] * sv[j];
+    }
+    int r_eps = n;
+    for (int k = 0; k <= n; ++k) {
+      double tail2 = 0;
+      for (int j = k; j < n; ++j) tail2 += sv[j] * sv[j];
+      if (tail2 <= eps * eps * tot2) {
+        r_eps = k;
+        break;
+      }
+    }
+    r_eps = std::max(1, r_eps);
+    const int cap_r = P.cap.rank[c];
+    const int rp = std::max(1, std::min({max_rank, cap_r, n, r_eps + 1}));
+    int k = 0;
+    if (sv[0] > 0)
+      for (int j = 0; j < n; ++j) k += sv[j] > 1e-10 * sv[0] ? 1 : 0;
+    k = std::min(k, rp);
+    // the ranks of the new cores must stay within the capacity layout
+    t.rank[c] = rp;
+    const std::vector<int> ds2 = t.shape(sn);
+    long ppost2 = 1;
+    for (int j = i + 1; j < (int)ds2.size(); ++j) ppost2 *= ds2[j];
+    SplitOp so{theta, (double*)wsb(P.ws_evecs), (double*)wsb(P.ws_evals), (int)rows, (int)cols,
+               side, center_to_child ? 0 : 1, k, rp, (double*)wsb(P.ws_W), core(sn), core(c),
+               (int)ppost2};
+    if ((size_t)std::max(rows, cols) * rp > P.W_cap) fail(TENSO_ENOMEM, "ps2 split scratch");
+    hipchk(launch_split(put_op(so, 2), s), "split");
+    P.rank_log.push_back(rp);
+  }
+
+  void W(int sn, int half) {
+    tenso_tree& t = P.tree;
+    const std::vector<int> kids = t.children[sn];
+    for (size_t idx = 0; idx < kids.size(); ++idx) {
+      const int c = kids[idx];
+      const int i = t.leg_of_child(sn, c);
+      edge(sn, c, half, true);
+      env_up(c);
+      if (!t.children[c].empty()) {
+        node_bwd(c, half);
+        W(c, half);
+      }
+      move(c, 0, sn, i);
+      env_down(c);
+      if (idx + 1 < kids.size()) node_bwd(sn, half);
+    }
+  }
+  void Wstar(int sn, int half) {
+    tenso_tree& t = P.tree;
+    const std::vector<int> kids = t.children[sn];
+    for (int idx = (int)kids.size() - 1; idx >= 0; --idx) {
+      const int c = kids[idx];
+      const int i = t.leg_of_child(sn, c);
+      if (idx + 1 < (int)kids.size()) node_bwd(sn, half);
+      move(sn, i, c, 0);
+      env_up(c);
+      if (!t.children[c].empty()) {
+        Wstar(c, half);
+        node_bwd(c, half);
+      }
+      edge(sn, c, half, false);
+      env_down(c);
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
 // host-side state helpers
 // ---------------------------------------------------------------------------
 static std::vector<cd> initial_cores(const tenso_plan& P, const tenso_c128* rho) {
@@ -1516,7 +1718,6 @@ int tenso_plan_create(const tenso_tree* t, const tenso_gen* g, const tenso_plan_
     if (!t || !g || !o || !out) fail(TENSO_EINVAL, "null argument");
     if (o->precision != TENSO_FP64 && o->precision != TENSO_FP32) fail(TENSO_EINVAL, "bad precision");
     if (o->method != TENSO_PS1 && o->method != TENSO_PS2) fail(TENSO_EINVAL, "bad method");
-    if (o->method == TENSO_PS2) fail(TENSO_EUNSUPPORTED, "ps2 plans are not built yet");
     if (g->n_ends != t->n_ends || g->end_dim != t->end_dim) fail(TENSO_EINVAL, "generator built for another tree");
     auto P = std::make_unique<tenso_plan>();
     P->tree = *t;
@@ -1524,6 +1725,14 @@ int tenso_plan_create(const tenso_tree* t, const tenso_gen* g, const tenso_plan_
     P->opts = *o;
     P->fp64 = o->precision == TENSO_FP64;
     P->tsz = P->fp64 ? 16 : 8;
+    P->cap = P->tree;
+    if (o->method == TENSO_PS2) {
+      if (o->max_rank < 2) fail(TENSO_EINVAL, "ps2 needs max_rank >= 2");
+      for (int c = 1; c < P->cap.n; ++c) P->cap.rank[c] = o->max_rank;
+      P->cap.clamp();
+      for (int c = 1; c < P->tree.n; ++c) P->tree.rank[c] = std::min(2, P->cap.rank[c]);
+      P->tree.clamp();
+    }
     analyse_slots(*P);
     // constant buffer: factor matrices in FP64 and FP32
     std::vector<char> cb;
@@ -1543,6 +1752,7 @@ int tenso_plan_create(const tenso_tree* t, const tenso_gen* g, const tenso_plan_
       P->mat_off32.push_back(o32);
     }
     hipchk(hipMalloc(&P->cbuf, std::max<size_t>(cb.size(), 256)), "hipMalloc(constants)");
+    hipchk(hipMalloc(&P->opbuf, 4096), "hipMalloc(op scratch)");
     if (!cb.empty()) hipchk(hipMemcpy(P->cbuf, cb.data(), cb.size(), hipMemcpyHostToDevice), "upload constants");
     layout(*P);
     // validate that every recipe compiles (throws EUNSUPPORTED otherwise)
@@ -1694,11 +1904,30 @@ int tenso_step_fixed(tenso_plan* p, void* d_state, double t0, double dt, int n_s
   });
 }
 
-int tenso_step_adaptive(tenso_plan* p, void*, double, double, int, double, int, const double*,
-                        void*, hipStream_t) {
+int tenso_step_adaptive(tenso_plan* p, void* d_state, double t0, double dt, int n_steps,
+                        double eps, int max_rank, const double* d_drive_tab, void* d_ws,
+                        hipStream_t s) {
   return guard([&] {
-    if (!p) fail(TENSO_EINVAL, "null plan");
-    fail(TENSO_EUNSUPPORTED, "ps2 is not built yet");
+    if (!p || !d_state || !d_ws) fail(TENSO_EINVAL, "null argument");
+    if (!(dt > 0)) fail(TENSO_EINVAL, "dt must be > 0");
+    if (n_steps < 0 || eps < 0) fail(TENSO_EINVAL, "bad n_steps or eps");
+    if (p->opts.method != TENSO_PS2) fail(TENSO_EINVAL, "plan is not a ps2 plan");
+    if (p->gen.n_slots > 0 && !d_drive_tab) fail(TENSO_EINVAL, "generator has drive slots: drive table needed");
+    (void)t0;
+    Ps2Exec X{*p, d_state, d_ws, dt, d_drive_tab, 4 * n_steps + 1, s, std::min(max_rank, p->opts.max_rank), eps};
+    X.ctr = (int*)((char*)d_ws + p->ws_ctr);
+    p->rank_log.clear();
+    {
+      Program G;
+      build_init(*p, G);
+      X.exec(G);
+    }
+    for (int k = 0; k < n_steps; ++k) {
+      hipchk(launch_step_inc(X.ctr, k, s), "ctr");
+      X.W(0, 0);
+      X.Wstar(0, 1);
+    }
+    hipchk(hipStreamSynchronize(s), "sync");
   });
 }
 

@@ -112,4 +112,39 @@ struct RhoProg {
   double* rho_out;       // M*M complex
 };
 
+// ps2 edge operations (FP64).  Theta is the merged two-site tensor stored as a
+// rows x cols row-major matrix: rows = the s-side legs in order (the legs of
+// core s except its leg toward c), cols = the c-side legs (core c except its
+// parent leg).
+struct MergeOp {           // Theta[row, col] = sum_a Cs[pre, a, post] Cc[a, col]
+  const double* Cs;
+  const double* Cc;
+  double* Theta;
+  int rows, cols, r, Ppost;  // row = pre * Ppost + post
+};
+
+// Hermitian eigen-decomposition (cyclic Jacobi, descending order) of the Gram
+// matrix of Theta on one side: side 0 -> Theta Theta^H (rows), 1 -> Theta^H Theta.
+struct EigOp {
+  const double* Theta;
+  int rows, cols, side;
+  double* evals;           // n eigenvalues, descending
+  double* evecs;           // n x n complex, column j = eigenvector j
+};
+
+// Split Theta into an isometry W (m_iso x r', first k columns from the
+// spectral basis, the rest completed by projecting unit vectors) and the
+// projected other core.  iso 0: W on the rows (new C_s), C_c = W^H Theta;
+// iso 1: W on the cols (new C_c = W^H as r' x cols), C_s = Theta W.
+struct SplitOp {
+  const double* Theta;
+  const double* evecs;
+  const double* evals;
+  int rows, cols, side, iso, k, rp;
+  double* W;               // scratch m_iso x rp complex
+  double* Cs;              // new core s: (rows x rp) scattered with leg i in place
+  double* Cc;              // new core c: rp x cols
+  int Ppost_s;             // product of s's legs after leg i (for the scatter)
+};
+
 }  // namespace tenso
