@@ -194,9 +194,40 @@ int tenso_batch_create(int n, tenso_plan* const* plans, void* const* d_states,
                        void* const* d_wss, tenso_batch** out);
 int tenso_batch_step(tenso_batch* b, const double* t0, const double* dt, int n_steps,
                      const double* const* d_drive_tabs, hipStream_t s);
+/* As tenso_batch_step, recording every instance's rho_S (Sec. II B) on the
+ * device before the first step and after every `every` steps into d_series:
+ * record j occupies bytes [j*B, (j+1)*B) with B from tenso_batch_record_bytes,
+ * instance i's M_i x M_i complex FP64 matrix at byte offset offsets[i] inside a
+ * record.  d_series must hold (n_steps/every + 1) records. */
+int tenso_batch_step_record(tenso_batch* b, const double* t0, const double* dt, int n_steps,
+                            int every, const double* const* d_drive_tabs, void* d_series,
+                            hipStream_t s);
+int tenso_batch_record_bytes(const tenso_batch* b, size_t* bytes_per_record, size_t* offsets);
+
 /* rho_S of every instance: h_rho[i] points to an M_i x M_i host array. */
 int tenso_batch_reduced_rho(tenso_batch* b, tenso_c128* const* h_rho, hipStream_t s);
 void tenso_batch_destroy(tenso_batch* b);
+
+/* ---- learned surrogate (a project addition; not in the paper) ------------
+ * Building blocks of a SiLU multilayer perceptron trained on trajectories of
+ * the batched solver.  Device FP32 buffers; GEMM operands are rounded to BF16
+ * and multiplied on BF16 MFMA with FP32 accumulation.
+ * tenso_mlp_gemm: C = beta*C + A*B with A(m,k) = A[m*sam + k*sak], B(k,n) =
+ *   B[k*sbk + n*sbn], C row-major (ldc); optional bias[n] added and, with
+ *   act = 1, SiLU(C) written to H (H = C copy when act = 0; H nullable).
+ * tenso_mlp_silu_bwd: dZ = dH * SiLU'(Z).   tenso_mlp_col_sum: column sums.
+ * tenso_mlp_mse: dY = 2(Y-T)/n and loss[0] += mean squared error (device).
+ * tenso_mlp_adam: one Adam update of n FP32 parameters (step count t >= 1).
+ * All are asynchronous on `s`; they return 0, -1 on bad sizes, -3 on a HIP
+ * launch error. */
+int tenso_mlp_gemm(int M, int N, int K, const float* A, long sam, long sak, const float* B, long sbk,
+                   long sbn, float* C, long ldc, float beta, const float* bias, int act, float* H,
+                   hipStream_t s);
+int tenso_mlp_silu_bwd(const float* dH, const float* Z, float* dZ, long n, hipStream_t s);
+int tenso_mlp_col_sum(const float* X, int rows, int cols, float* out, hipStream_t s);
+int tenso_mlp_mse(const float* Y, const float* T, long n, float* dY, float* loss, hipStream_t s);
+int tenso_mlp_adam(float* p, const float* g, float* m, float* v, long n, float lr, float b1,
+                   float b2, float eps, int t, hipStream_t s);
 
 #ifdef __cplusplus
 }

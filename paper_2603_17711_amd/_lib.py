@@ -59,6 +59,15 @@ SIGS = {
     "tenso_batch_step": (C.c_int, [P, DP, DP, C.c_int, C.POINTER(P), P]),
     "tenso_batch_reduced_rho": (C.c_int, [P, C.POINTER(C128P), P]),
     "tenso_batch_destroy": (None, [P]),
+    "tenso_batch_step_record": (C.c_int, [P, DP, DP, C.c_int, C.c_int, C.POINTER(P), P, P]),
+    "tenso_batch_record_bytes": (C.c_int, [P, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
+    "tenso_mlp_gemm": (C.c_int, [C.c_int, C.c_int, C.c_int, P, C.c_long, C.c_long, P, C.c_long,
+                                 C.c_long, P, C.c_long, C.c_float, P, C.c_int, P, P]),
+    "tenso_mlp_silu_bwd": (C.c_int, [P, P, P, C.c_long, P]),
+    "tenso_mlp_col_sum": (C.c_int, [P, C.c_int, C.c_int, P, P]),
+    "tenso_mlp_mse": (C.c_int, [P, P, C.c_long, P, P, P]),
+    "tenso_mlp_adam": (C.c_int, [P, P, P, P, C.c_long, C.c_float, C.c_float, C.c_float, C.c_float,
+                                 C.c_int, P]),
 }
 
 

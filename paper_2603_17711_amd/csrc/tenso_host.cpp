@@ -2091,6 +2091,59 @@ int tenso_batch_step(tenso_batch* b, const double* t0, const double* dt, int n_s
   });
 }
 
+int tenso_batch_step_record(tenso_batch* b, const double* t0, const double* dt, int n_steps,
+                            int every, const double* const* d_drive_tabs, void* d_series,
+                            hipStream_t s) {
+  return guard([&] {
+    if (!b || !dt || !d_series || every < 1) fail(TENSO_EINVAL, "bad arguments");
+    if (n_steps < 0) fail(TENSO_EINVAL, "n_steps must be >= 0");
+    (void)t0;
+    const size_t n = b->plans.size();
+    std::vector<double> dts(dt, dt + n);
+    std::vector<const double*> drv(n, nullptr);
+    for (size_t i = 0; i < n; ++i) {
+      if (!(dts[i] > 0)) fail(TENSO_EINVAL, "dt must be > 0");
+      if (d_drive_tabs) drv[i] = d_drive_tabs[i];
+      if (b->plans[i]->gen.n_slots > 0 && !drv[i]) fail(TENSO_EINVAL, "instance with drive slots needs a drive table");
+    }
+    const int ld = 4 * n_steps + 1;
+    if (dts != b->dts || drv != b->drives || ld != b->ld || !b->step.arena) {
+      b->dts = dts;
+      b->drives = drv;
+      b->ld = ld;
+      batch_build(*b, s);
+    }
+    const size_t rec = b->rho_off.back() + align256(b->plans.back()->tree.end_dim[0] *
+                                                    b->plans.back()->tree.end_dim[0] * 16);
+    hipchk(launch_step_inc(b->ctr, 0, s), "ctr");
+    run(b->init, b->fp64, b->ctr, s);
+    int r = 0;
+    run(b->rho, b->fp64, nullptr, s);
+    hipchk(hipMemcpyAsync((char*)d_series + (size_t)r++ * rec, b->rho_buf, rec,
+                          hipMemcpyDeviceToDevice, s), "record");
+    for (int k = 0; k < n_steps; ++k) {
+      run(b->step, b->fp64, b->ctr, s);
+      hipchk(launch_step_inc(b->ctr, -1, s), "ctr");
+      if ((k + 1) % every == 0) {
+        run(b->rho, b->fp64, nullptr, s);
+        hipchk(hipMemcpyAsync((char*)d_series + (size_t)r++ * rec, b->rho_buf, rec,
+                              hipMemcpyDeviceToDevice, s), "record");
+      }
+    }
+  });
+}
+
+int tenso_batch_record_bytes(const tenso_batch* b, size_t* bytes_per_record, size_t* offsets) {
+  return guard([&] {
+    if (!b) fail(TENSO_EINVAL, "null batch");
+    if (bytes_per_record)
+      *bytes_per_record = b->rho_off.back() + align256(b->plans.back()->tree.end_dim[0] *
+                                                       b->plans.back()->tree.end_dim[0] * 16);
+    if (offsets)
+      for (size_t i = 0; i < b->rho_off.size(); ++i) offsets[i] = b->rho_off[i];
+  });
+}
+
 int tenso_batch_reduced_rho(tenso_batch* b, tenso_c128* const* h_rho, hipStream_t s) {
   return guard([&] {
     if (!b || !h_rho) fail(TENSO_EINVAL, "null argument");

@@ -1,0 +1,40 @@
+"""Surrogate network kernels vs the FP64 oracle MLP (forward and gradients).
+GEMM operands are BF16 on MFMA with FP32 accumulation, hence ~1e-2 relative."""
+import numpy as np
+import pytest
+
+from oracle.mlp import forward as o_forward
+from oracle.mlp import loss_and_grads
+from tests.gpu_util import require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def test_mlp_forward_and_gradients_match_fp64_oracle():
+    require_gpu()
+    import torch
+    from paper_2603_17711_amd import surrogate
+    print("[mlp parity] 91-256-256-4, batch 64", flush=True)
+    model = surrogate.MLP(seed=3)
+    rng = np.random.default_rng(0)
+    X = rng.normal(size=(64, 91)).astype(np.float32)
+    T = rng.normal(size=(64, 4)).astype(np.float32)
+    params = [(W.double().cpu().numpy(), b.double().cpu().numpy())
+              for W, b in zip(model.W, model.b)]
+    y_ref, _ = o_forward(params, X.astype(np.float64))
+    loss_ref, g_ref = loss_and_grads(params, X.astype(np.float64), T.astype(np.float64))
+    Xd, Td = torch.tensor(X, device="cuda"), torch.tensor(T, device="cuda")
+    y, cache = model.forward(Xd)
+    loss, dY = model.loss_grad(y, Td)
+    grads = model.backward(cache, dY)
+    y = y.cpu().numpy()
+    rel = lambda a, b: np.abs(a - b).max() / np.abs(b).max()
+    print(f"  forward rel err {rel(y, y_ref):.2e}, loss {loss.item():.6f} vs {loss_ref:.6f}")
+    assert rel(y, y_ref) < 2e-2
+    assert abs(loss.item() - loss_ref) < 2e-2 * loss_ref
+    L = len(params)
+    for l in range(L):
+        gw, gb = grads[l].cpu().numpy(), grads[L + l].cpu().numpy()
+        ew, eb = rel(gw, g_ref[l][0]), rel(gb, g_ref[l][1])
+        print(f"  layer {l}: dW rel {ew:.2e}, db rel {eb:.2e}")
+        assert ew < 3e-2 and eb < 3e-2
