@@ -18,6 +18,30 @@
 
 namespace tenso {
 
+// Pointers read from op descriptors in memory are generic: the compiler would
+// access them with FLAT instructions, whose completion is counted together
+// with LDS traffic, so every wait for an LDS result would also wait for all
+// outstanding HBM loads.  Every such pointer refers to device global memory;
+// gmem() gives it the global address space, and accesses through it become
+// global loads/stores.
+// (The host compilation pass, which only parses device code, sees plain
+// pointers.)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define TENSO_GLOBAL __attribute__((address_space(1)))
+#else
+#define TENSO_GLOBAL
+#endif
+template <class T>
+using gp = TENSO_GLOBAL T*;
+template <class T>
+__device__ inline gp<T> gmem(T* p) {
+  return (gp<T>)p;
+}
+template <class T>
+__device__ inline gp<const T> gmem(const T* p) {
+  return (gp<const T>)p;
+}
+
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef double v4d __attribute__((ext_vector_type(4)));
 
@@ -408,21 +432,150 @@ __device__ inline z2 zconjmul(z2 a, z2 b) {  // conj(a) * b
   return z2{a.r * b.r + a.i * b.i, a.r * b.i - a.i * b.r};
 }
 
-__device__ inline double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+// One DPP move of a double across lanes (both 32-bit halves, same pattern).
+template <int CTRL>
+__device__ inline double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp((int)b, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(b >> 32), (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-__global__ void __launch_bounds__(256) k_qr(const QrOp* __restrict__ ops) {
-  const QrOp op = ops[blockIdx.x];
+__device__ inline double readlane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the 64 lanes of a wavefront, returned to every lane; all lanes
+// must be active.  Within each row of 16 lanes: swap neighbours, swap pairs
+// (quad permutes), mirror halves of 8, mirror the row; each exchange pairs
+// two partial sums, so every lane of a row ends with the row sum.  The four
+// row sums are then read as scalars and added.
+__device__ inline double wave_sum(double v) {
+  v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_d<0x141>(v);  // row_half_mirror
+  v += dpp_d<0x140>(v);  // row_mirror
+  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+}
+
+// Quotient n / d for 0 <= n < 2^31 and 1 <= d <= 2^12 through a
+// double-precision reciprocal: the product is within 2^-21 of n / d, so one
+// correction step gives the exact quotient.
+__device__ inline int qr_div(int n, int d, double dinv) {
+  int q = (int)((double)n * dinv);
+  const int r = n - q * d;
+  if (r >= d) ++q;
+  else if (r < 0) --q;
+  return q;
+}
+
+// Blocked form of the Householder QR (LAPACK zgeqrf / zungqr structure), for
+// m <= QR_MAX_M.  Panels of pb <= QR_PB columns are factored with the
+// unblocked algorithm, and the columns right of a panel (and later the Q
+// columns) are updated once per panel with the compact WY form
+// H_p ... H_{p+pb-1} = I - V T V^H.  Reflectors, taus and the rank rule are
+// those of the column-by-column algorithm; only the rounding order of the
+// updates differs.
+//   Thread t owns rows p + t + 256 j of each panel and keeps them in
+// registers.  Panel column jj needs one block reduction, of |x|^2 and of the
+// raw products x^H a_c for the later panel columns (then
+// v^H a_c = a_c[jj] + conj(1 / (alpha - beta)) x^H a_c); every thread derives
+// beta, tau and the scale from the same sums and updates its own rows: one
+// barrier per column.  The Gram products of the reflectors (for T) come from
+// the same registers.
+//   Column updates: the explicit reflectors go to LDS; one wavefront per
+// column holds the column's rows in registers (QR_RPL per lane), forms
+// w = V^H x with a wave reduction and writes x - V (S w).
+constexpr int QR_PB = 4;                 // panel width
+constexpr int QR_RPL = 16;               // rows per lane of a column update
+constexpr int QR_RPT = 4;                // panel rows per thread
+constexpr int QR_MAX_M = 64 * QR_RPL;    // 1024 = 256 * QR_RPT
+constexpr int QR_NPAIR = QR_PB * (QR_PB - 1) / 2;
+
+// x <- (I - V S V^H) x for one column, x[r] at X[off[q]] for r = q * 64 + lane
+// (rows past mp - 1 are clamped to mp - 1 in off); V explicit (unit
+// diagonal, zeros above) in LDS with leading dimension mp; S is QR_PB x
+// QR_PB in LDS, zero outside pb x pb; the result is scaled by ph.
+__device__ inline void qr_apply_col(const z2* __restrict__ Lv, int mp, int pb,
+                                    const z2* __restrict__ S, gp<z2> __restrict__ X,
+                                    const int* off, z2 ph, int lane) {
+  // reflectors i >= pb read column pb - 1; S has zero rows and columns there
+  int ci[QR_PB];
+#pragma unroll
+  for (int i = 0; i < QR_PB; ++i) ci[i] = (i < pb ? i : pb - 1) * mp;
+  z2 xs[QR_RPL];
+#pragma unroll
+  for (int q = 0; q < QR_RPL; ++q) xs[q] = X[off[q]];
+  double w[2 * QR_PB];
+#pragma unroll
+  for (int i = 0; i < 2 * QR_PB; ++i) w[i] = 0;
+#pragma unroll
+  for (int q = 0; q < QR_RPL; ++q) {
+    const int r = q * 64 + lane;
+    if (r >= mp) xs[q] = z2{0.0, 0.0};  // clamped duplicate: no contribution
+    const int rc = r < mp ? r : mp - 1;
+    z2 vv[QR_PB];
+#pragma unroll
+    for (int i = 0; i < QR_PB; ++i) vv[i] = Lv[ci[i] + rc];
+#pragma unroll
+    for (int i = 0; i < QR_PB; ++i) {  // w_i += conj(v_i) x
+      w[2 * i] = fma(vv[i].r, xs[q].r, fma(vv[i].i, xs[q].i, w[2 * i]));
+      w[2 * i + 1] = fma(vv[i].r, xs[q].i, fma(-vv[i].i, xs[q].r, w[2 * i + 1]));
+    }
+    // keep the scheduler from hoisting every reflector load of the column
+    // (they would not fit in registers)
+    if (q % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int i = 0; i < 2 * QR_PB; ++i) w[i] = wave_sum(w[i]);
+  // u = S w (w is the same in every lane): lane 2 i + h forms the real
+  // (h = 0) or imaginary (h = 1) part of u_i, then all lanes read it
+  double uc = 0;
+  {
+    const int ui = (lane >> 1) & (QR_PB - 1), uh = lane & 1;
+#pragma unroll
+    for (int l = 0; l < QR_PB; ++l) {
+      const z2 t = S[ui * QR_PB + l];
+      uc = uh ? fma(t.r, w[2 * l + 1], fma(t.i, w[2 * l], uc))
+              : fma(t.r, w[2 * l], fma(-t.i, w[2 * l + 1], uc));
+    }
+  }
+  double u[2 * QR_PB];
+#pragma unroll
+  for (int e = 0; e < 2 * QR_PB; ++e) u[e] = readlane_d(uc, e);
+#pragma unroll
+  for (int q = 0; q < QR_RPL; ++q) {
+    const int r = q * 64 + lane;
+    if (r < mp) {
+      z2 vv[QR_PB];
+#pragma unroll
+      for (int i = 0; i < QR_PB; ++i) vv[i] = Lv[ci[i] + r];
+      double ar = xs[q].r, ai = xs[q].i;
+#pragma unroll
+      for (int i = 0; i < QR_PB; ++i) {  // x -= v_i u_i
+        ar = fma(-vv[i].r, u[2 * i], fma(vv[i].i, u[2 * i + 1], ar));
+        ai = fma(-vv[i].r, u[2 * i + 1], fma(-vv[i].i, u[2 * i], ai));
+      }
+      X[off[q]] = zmul(z2{ar, ai}, ph);
+    }
+    if (q % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// Column-by-column form, all in global memory: used for matrices too tall
+// for the LDS panel of the blocked form.
+__device__ void qr_unblocked(const QrOp& op) {
   const int m = op.m, n = op.n, k = m < n ? m : n;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   __shared__ double red[8];  // [0..3] column norms, [4..7] Frobenius norm
   __shared__ double sh_tau[2], sh_scale[2], sh_beta[2];
   __shared__ int sh_skip;
-  z2* V = reinterpret_cast<z2*>(op.V);  // column-major m x n
-  z2* tau = reinterpret_cast<z2*>(op.tau);
-  z2* C = reinterpret_cast<z2*>(op.C);
+  const gp<z2> V = gmem(reinterpret_cast<z2*>(op.V));  // column-major m x n
+  const gp<z2> tau = gmem(reinterpret_cast<z2*>(op.tau));
+  const gp<z2> C = gmem(reinterpret_cast<z2*>(op.C));
   auto cidx = [&](int row, int col) -> long {
     const int pre = row / op.Ppost, post = row % op.Ppost;
     return (long)pre * n * op.Ppost + (long)col * op.Ppost + post;
@@ -511,7 +664,7 @@ __global__ void __launch_bounds__(256) k_qr(const QrOp* __restrict__ ops) {
     __syncthreads();
   }
   // R (n x n upper; rows >= k zero) into op.R, before Q overwrites V
-  z2* R = reinterpret_cast<z2*>(op.R);
+  const gp<z2> R = gmem(reinterpret_cast<z2*>(op.R));
   for (int e = tid; e < n * n; e += 256) {
     const int i = e / n, col = e % n;
     z2 v = (i <= col && i < k) ? V[(long)col * m + i] : z2{0, 0};
@@ -573,6 +726,291 @@ __global__ void __launch_bounds__(256) k_qr(const QrOp* __restrict__ ops) {
     const int row = e % m, col = e / m;
     z2 q = col < nq ? zmul(V[(long)col * m + row], z2{ph[2 * col], ph[2 * col + 1]}) : z2{0, 0};
     C[cidx(row, col)] = q;
+  }
+}
+
+
+__global__ void __launch_bounds__(256, 2) k_qr(const QrOp* __restrict__ ops) {
+  const QrOp op = ops[blockIdx.x];
+  if (op.m > QR_MAX_M) {
+    qr_unblocked(op);
+    return;
+  }
+  const int m = op.m, n = op.n, k = m < n ? m : n;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int NRED = 2 * QR_PB + 2 * QR_NPAIR;  // per-wave partial sums
+  __shared__ double red[2][4][NRED];              // double-buffered
+  __shared__ z2 rowjj[2][QR_PB];                  // row jj of the panel, copied by its owner
+  __shared__ z2 S[QR_PB * QR_PB];                 // T^H (factoring) or T (forming Q)
+  __shared__ z2 tauL[64];
+  __shared__ double ph[2 * 64];
+  extern __shared__ char smem_raw[];
+  z2* __restrict__ L = reinterpret_cast<z2*>(smem_raw);  // explicit panel, (m - p) x pb
+  const gp<z2> __restrict__ V = gmem(reinterpret_cast<z2*>(op.V));  // column-major m x n
+  const gp<z2> __restrict__ C = gmem(reinterpret_cast<z2*>(op.C));
+  const gp<z2> __restrict__ R = gmem(reinterpret_cast<z2*>(op.R));
+  const int ppost = op.Ppost;
+  const int cstride = n * ppost;
+  const double pinv = 1.0 / ppost;
+  auto crow = [=](int row) -> int {
+    const int q = qr_div(row, ppost, pinv);
+    return q * cstride + (row - q * ppost);
+  };
+
+  // C -> V and the Frobenius norm
+  double fro = 0;
+  for (int row = tid; row < m; row += 256) {
+    const int cb = crow(row);
+    for (int c0 = 0; c0 < n; c0 += 8) {
+      z2 t[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) t[u] = c0 + u < n ? C[cb + (c0 + u) * ppost] : z2{0.0, 0.0};
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (c0 + u < n) {
+          V[(c0 + u) * m + row] = t[u];
+          fro += t[u].r * t[u].r + t[u].i * t[u].i;
+        }
+    }
+  }
+  fro = wave_sum(fro);
+  if (lane == 0) red[0][wave][0] = fro;
+  __syncthreads();
+  // residual columns at or below this squared norm count as exact zeros
+  const double thr2 =
+      QR_RANK_TOL * QR_RANK_TOL * (red[0][0][0] + red[0][1][0] + red[0][2][0] + red[0][3][0]);
+  const int nbk = (k + QR_PB - 1) / QR_PB;
+  int par = 1;
+
+  for (int st = 0; st < 2 * nbk; ++st) {
+    const bool fact = st < nbk;
+    const int bk = fact ? st : 2 * nbk - 1 - st;
+    const int p = bk * QR_PB, pb = min(QR_PB, k - p), mp = m - p;
+    if (st == nbk) {
+      // phases that make diag(R) real non-negative; R with its rows rephased
+      if (tid < n) {
+        const z2 dd = tid < k ? V[tid * m + tid] : z2{0.0, 0.0};
+        const double a = sqrt(dd.r * dd.r + dd.i * dd.i);
+        ph[2 * tid] = a > 0 ? dd.r / a : 1.0;
+        ph[2 * tid + 1] = a > 0 ? dd.i / a : 0.0;
+      }
+      __syncthreads();
+      for (int e = tid; e < n * n; e += 256) {
+        const int i = e / n, c = e % n;
+        const z2 v = (i <= c && i < k) ? zmul(z2{ph[2 * i], -ph[2 * i + 1]}, V[c * m + i])
+                                       : z2{0.0, 0.0};
+        if (op.transposeR) R[c * n + i] = v;
+        else R[i * n + c] = v;
+      }
+      // Q starts as the first k unit columns
+      for (int row = tid; row < m; row += 256) {
+        const int cb = crow(row);
+        for (int c = 0; c < k; ++c) C[cb + c * ppost] = z2{row == c ? 1.0 : 0.0, 0.0};
+      }
+    }
+    // own panel rows (relative row tid + 256 j) into registers
+    z2 P[QR_RPT][QR_PB];
+#pragma unroll
+    for (int j = 0; j < QR_RPT; ++j) {
+      const int row = tid + 256 * j;
+#pragma unroll
+      for (int c = 0; c < QR_PB; ++c)
+        P[j][c] = row < mp && c < pb ? V[(p + c) * m + p + row] : z2{0.0, 0.0};
+    }
+    if (fact) {
+#pragma unroll
+      for (int jj = 0; jj < QR_PB; ++jj) {
+        if (jj >= pb) break;
+        double d[2 * QR_PB];  // slot 0: |x|^2; slots 2c, 2c+1: x^H a_c for c > jj
+#pragma unroll
+        for (int c = 0; c < 2 * QR_PB; ++c) d[c] = 0;
+#pragma unroll
+        for (int j = 0; j < QR_RPT; ++j) {
+          if (tid + 256 * j <= jj) continue;  // rows past mp hold zeros
+          const z2 x = P[j][jj];
+          d[0] = fma(x.r, x.r, fma(x.i, x.i, d[0]));
+#pragma unroll
+          for (int c = jj + 1; c < QR_PB; ++c) {
+            d[2 * c] = fma(x.r, P[j][c].r, fma(x.i, P[j][c].i, d[2 * c]));
+            d[2 * c + 1] = fma(x.r, P[j][c].i, fma(-x.i, P[j][c].r, d[2 * c + 1]));
+          }
+        }
+        d[0] = wave_sum(d[0]);
+#pragma unroll
+        for (int c = jj + 1; c < QR_PB; ++c) {
+          d[2 * c] = wave_sum(d[2 * c]);
+          d[2 * c + 1] = wave_sum(d[2 * c + 1]);
+        }
+        // row jj before this column's update; its owner (thread jj) updates
+        // it after the barrier while the others still read it
+        if (tid == jj) {
+#pragma unroll
+          for (int c = jj; c < QR_PB; ++c) rowjj[par][c] = P[0][c];
+        }
+        if (lane == 0) {
+          red[par][wave][0] = d[0];
+#pragma unroll
+          for (int c = jj + 1; c < QR_PB; ++c) {
+            red[par][wave][2 * c] = d[2 * c];
+            red[par][wave][2 * c + 1] = d[2 * c + 1];
+          }
+        }
+        __syncthreads();
+        const double xn2 = red[par][0][0] + red[par][1][0] + red[par][2][0] + red[par][3][0];
+        const z2 alpha = rowjj[par][jj];
+        z2 t{0.0, 0.0};
+        if (alpha.r * alpha.r + alpha.i * alpha.i + xn2 <= thr2) {
+          // numerically zero residual: identity reflector, zero column
+#pragma unroll
+          for (int j = 0; j < QR_RPT; ++j)
+            if (tid + 256 * j >= jj) P[j][jj] = z2{0.0, 0.0};
+        } else if (!(xn2 == 0.0 && alpha.i == 0.0)) {
+          const double nrm = sqrt(alpha.r * alpha.r + alpha.i * alpha.i + xn2);
+          // beta = -sign(Re alpha) * nrm (LAPACK zlarfg; a zero counts as positive)
+          const double beta = alpha.r >= 0.0 ? -nrm : nrm;
+          t = z2{(beta - alpha.r) / beta, -alpha.i / beta};
+          const double dr = alpha.r - beta, di = alpha.i;
+          const double den = dr * dr + di * di;
+          const z2 sc{dr / den, -di / den};  // 1 / (alpha - beta)
+          const z2 ct{t.r, -t.i};
+          z2 f[QR_PB];
+#pragma unroll
+          for (int c = jj + 1; c < QR_PB; ++c) {
+            const z2 D{red[par][0][2 * c] + red[par][1][2 * c] + red[par][2][2 * c] + red[par][3][2 * c],
+                       red[par][0][2 * c + 1] + red[par][1][2 * c + 1] + red[par][2][2 * c + 1] +
+                           red[par][3][2 * c + 1]};
+            const z2 cd = zmul(z2{sc.r, -sc.i}, D);
+            const z2 a0 = rowjj[par][c];
+            f[c] = zmul(ct, z2{a0.r + cd.r, a0.i + cd.i});
+          }
+#pragma unroll
+          for (int j = 0; j < QR_RPT; ++j) {
+            const int row = tid + 256 * j;
+            if (row < jj) continue;
+            const z2 v = row == jj ? z2{1.0, 0.0} : zmul(P[j][jj], sc);
+#pragma unroll
+            for (int c = jj + 1; c < QR_PB; ++c) {
+              P[j][c].r = fma(-f[c].r, v.r, fma(f[c].i, v.i, P[j][c].r));
+              P[j][c].i = fma(-f[c].r, v.i, fma(-f[c].i, v.r, P[j][c].i));
+            }
+            P[j][jj] = row == jj ? z2{beta, 0.0} : v;
+          }
+        }
+        if (tid == 0) {
+          tauL[p + jj] = t;
+          gmem(reinterpret_cast<z2*>(op.tau))[p + jj] = t;
+        }
+        par ^= 1;
+      }
+      // factored panel (R entries and reflectors) back to V
+#pragma unroll
+      for (int j = 0; j < QR_RPT; ++j) {
+        const int row = tid + 256 * j;
+        if (row < mp) {
+#pragma unroll
+          for (int c = 0; c < QR_PB; ++c)
+            if (c < pb) V[(p + c) * m + p + row] = P[j][c];
+        }
+      }
+    }
+    const int c0 = fact ? p + pb : p, c1 = fact ? n : k;
+    if (c0 < c1) {
+      // explicit reflectors: unit diagonal, zeros above; to LDS for the
+      // column updates, and their Gram products y_ij = v_i^H v_j (i < j)
+      double g[2 * QR_NPAIR];
+#pragma unroll
+      for (int e = 0; e < 2 * QR_NPAIR; ++e) g[e] = 0;
+#pragma unroll
+      for (int j = 0; j < QR_RPT; ++j) {
+        const int row = tid + 256 * j;
+#pragma unroll
+        for (int c = 0; c < QR_PB; ++c) {
+          if (row == c) P[j][c] = z2{1.0, 0.0};
+          else if (row < c) P[j][c] = z2{0.0, 0.0};
+        }
+        if (row < mp) {
+#pragma unroll
+          for (int c = 0; c < QR_PB; ++c)
+            if (c < pb) L[c * mp + row] = P[j][c];
+        }
+        int e = 0;
+#pragma unroll
+        for (int jc = 1; jc < QR_PB; ++jc)
+#pragma unroll
+          for (int ic = 0; ic < jc; ++ic, ++e) {
+            g[2 * e] = fma(P[j][ic].r, P[j][jc].r, fma(P[j][ic].i, P[j][jc].i, g[2 * e]));
+            g[2 * e + 1] = fma(P[j][ic].r, P[j][jc].i, fma(-P[j][ic].i, P[j][jc].r, g[2 * e + 1]));
+          }
+      }
+#pragma unroll
+      for (int e = 0; e < 2 * QR_NPAIR; ++e) g[e] = wave_sum(g[e]);
+      if (lane == 0) {
+#pragma unroll
+        for (int e = 0; e < 2 * QR_NPAIR; ++e) red[par][wave][2 * QR_PB + e] = g[e];
+      }
+      __syncthreads();
+      if (tid == 0) {
+        // T (forward column-wise): T[j][j] = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] y[0:j, j]
+        z2 T[QR_PB][QR_PB];
+#pragma unroll
+        for (int i = 0; i < QR_PB; ++i)
+#pragma unroll
+          for (int j = 0; j < QR_PB; ++j) T[i][j] = z2{0.0, 0.0};
+        int e0 = 0;
+#pragma unroll
+        for (int j = 0; j < QR_PB; ++j) {
+          if (j < pb) {
+            const z2 tj = tauL[p + j];
+            z2 y[QR_PB];
+#pragma unroll
+            for (int l = 0; l < j; ++l) {
+              const int o = 2 * QR_PB + 2 * (e0 + l);
+              y[l] = z2{red[par][0][o] + red[par][1][o] + red[par][2][o] + red[par][3][o],
+                        red[par][0][o + 1] + red[par][1][o + 1] + red[par][2][o + 1] + red[par][3][o + 1]};
+            }
+#pragma unroll
+            for (int i = 0; i < j; ++i) {
+              double sr = 0, si = 0;
+#pragma unroll
+              for (int l = i; l < j; ++l) {
+                const z2 pr = zmul(T[i][l], y[l]);
+                sr += pr.r;
+                si += pr.i;
+              }
+              const z2 pr = zmul(tj, z2{sr, si});
+              T[i][j] = z2{-pr.r, -pr.i};
+            }
+            T[j][j] = tj;
+          }
+          e0 += j;
+        }
+        // the factor applied: T^H while factoring (H^H is applied), T while forming Q
+#pragma unroll
+        for (int i = 0; i < QR_PB; ++i)
+#pragma unroll
+          for (int l = 0; l < QR_PB; ++l)
+            S[i * QR_PB + l] = fact ? z2{T[l][i].r, -T[l][i].i} : T[i][l];
+      }
+      par ^= 1;
+      __syncthreads();
+      // V (column-major) is addressed like C with a row period of m
+      const gp<z2> X = fact ? V : C;
+      const int xp = fact ? m : ppost, xcs = fact ? 0 : cstride;
+      const double xpinv = 1.0 / xp;
+      int off[QR_RPL];
+#pragma unroll
+      for (int q = 0; q < QR_RPL; ++q) {
+        const int r = q * 64 + lane, row = p + (r < mp ? r : mp - 1);
+        const int qq = qr_div(row, xp, xpinv);
+        off[q] = qq * xcs + (row - qq * xp);
+      }
+      const bool last = !fact && bk == 0;  // the final Q update also applies the phases
+      for (int cc = c0 + wave; cc < c1; cc += 4) {
+        const z2 phc = last ? z2{ph[2 * cc], ph[2 * cc + 1]} : z2{1.0, 0.0};
+        qr_apply_col(L, mp, pb, S, X + cc * xp, off, phc, lane);
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -1162,7 +1600,13 @@ hipError_t launch_combine(int fp64, const CombineOp* ops, const void* tiles, int
 
 hipError_t launch_qr(const QrOp* ops, int n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_qr, dim3(n), dim3(256), 0, s, ops);
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void*)k_qr, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              QR_MAX_M * QR_PB * 16);
+    attr = true;
+  }
+  hipLaunchKernelGGL(k_qr, dim3(n), dim3(256), QR_MAX_M * QR_PB * 16, s, ops);
   return hipGetLastError();
 }
 
