@@ -144,6 +144,123 @@ template <typename T> struct V2;
 template <> struct V2<float> { typedef float2 t; };
 template <> struct V2<double> { typedef double2 t; };
 
+// One unit of the apply tile for one term, with NIB 16-row tiles of leg 1
+// accumulated into tiles TLO .. TLO + NIB - 1 of the wavefront:
+// Y += A_t (X_f B^T)[:, col block] (two-sided), A_t X_f[:, col block]
+// (A only) or X_f B^T (B only).  Operands of k-step q + 1 are read from LDS
+// before the MFMAs of step q are issued, so LDS latency overlaps the matrix
+// cores.  (NIB and TLO are compile-time so that every register array is
+// indexed statically.)
+template <typename T, int NIB, int TLO, typename C2>
+__device__ inline void apply_unit(int kind, const C2* xf, const C2* as, const C2* bs, C2* zs,
+                                  int col, int c, int g, int nq1, int nq2, int xs1, int as1,
+                                  int bs1, typename MT<T>::v4 (&yr)[MT<T>::NT],
+                                  typename MT<T>::v4 (&yi)[MT<T>::NT]) {
+  typedef typename MT<T>::v4 v4;
+  if (kind == 3) {  // two-sided: Z = X_f B^T (16-column block), then Y += A Z
+    v4 zr[NIB], zi[NIB];
+#pragma unroll
+    for (int t = 0; t < NIB; ++t) {
+      zr[t] = v4{0, 0, 0, 0};
+      zi[t] = v4{0, 0, 0, 0};
+    }
+    C2 bc = bs[col * bs1 + g], xc[NIB];
+#pragma unroll
+    for (int t = 0; t < NIB; ++t) xc[t] = xf[(16 * t + c) * xs1 + g];
+    for (int q = 0; q < nq1; ++q) {
+      C2 bn = bc, xn[NIB];
+#pragma unroll
+      for (int t = 0; t < NIB; ++t) xn[t] = xc[t];
+      if (q + 1 < nq1) {
+        const int kk = 4 * (q + 1) + g;
+        bn = bs[col * bs1 + kk];
+#pragma unroll
+        for (int t = 0; t < NIB; ++t) xn[t] = xf[(16 * t + c) * xs1 + kk];
+      }
+#pragma unroll
+      for (int t = 0; t < NIB; ++t) cmma<T>(zr[t], zi[t], xc[t].x, xc[t].y, bc.x, bc.y);
+      bc = bn;
+#pragma unroll
+      for (int t = 0; t < NIB; ++t) xc[t] = xn[t];
+    }
+#pragma unroll
+    for (int t = 0; t < NIB; ++t) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        C2 v;
+        v.x = zr[t][r];
+        v.y = zi[t][r];
+        zs[(16 * t + MT<T>::drow(g, r)) * 16 + c] = v;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    C2 zc = zs[g * 16 + c], ac[NIB];
+#pragma unroll
+    for (int t = 0; t < NIB; ++t) ac[t] = as[(16 * t + c) * as1 + g];
+    for (int q = 0; q < nq2; ++q) {
+      C2 zn = zc, an[NIB];
+#pragma unroll
+      for (int t = 0; t < NIB; ++t) an[t] = ac[t];
+      if (q + 1 < nq2) {
+        const int kk = 4 * (q + 1) + g;
+        zn = zs[kk * 16 + c];
+#pragma unroll
+        for (int t = 0; t < NIB; ++t) an[t] = as[(16 * t + c) * as1 + kk];
+      }
+#pragma unroll
+      for (int t = 0; t < NIB; ++t) cmma<T>(yr[TLO + t], yi[TLO + t], ac[t].x, ac[t].y, zc.x, zc.y);
+      zc = zn;
+#pragma unroll
+      for (int t = 0; t < NIB; ++t) ac[t] = an[t];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else if (kind == 1) {  // A only: Y += A X_f[:, col block]
+    C2 xc = xf[g * xs1 + col], ac[NIB];
+#pragma unroll
+    for (int t = 0; t < NIB; ++t) ac[t] = as[(16 * t + c) * as1 + g];
+    for (int q = 0; q < nq2; ++q) {
+      C2 xn = xc, an[NIB];
+#pragma unroll
+      for (int t = 0; t < NIB; ++t) an[t] = ac[t];
+      if (q + 1 < nq2) {
+        const int kk = 4 * (q + 1) + g;
+        xn = xf[kk * xs1 + col];
+#pragma unroll
+        for (int t = 0; t < NIB; ++t) an[t] = as[(16 * t + c) * as1 + kk];
+      }
+#pragma unroll
+      for (int t = 0; t < NIB; ++t) cmma<T>(yr[TLO + t], yi[TLO + t], ac[t].x, ac[t].y, xc.x, xc.y);
+      xc = xn;
+#pragma unroll
+      for (int t = 0; t < NIB; ++t) ac[t] = an[t];
+    }
+  } else if (kind == 2) {  // B only: Y += X_f B^T (16-column block)
+    C2 bc = bs[col * bs1 + g], xc[NIB];
+#pragma unroll
+    for (int t = 0; t < NIB; ++t) xc[t] = xf[(16 * t + c) * xs1 + g];
+    for (int q = 0; q < nq1; ++q) {
+      C2 bn = bc, xn[NIB];
+#pragma unroll
+      for (int t = 0; t < NIB; ++t) xn[t] = xc[t];
+      if (q + 1 < nq1) {
+        const int kk = 4 * (q + 1) + g;
+        bn = bs[col * bs1 + kk];
+#pragma unroll
+        for (int t = 0; t < NIB; ++t) xn[t] = xf[(16 * t + c) * xs1 + kk];
+      }
+#pragma unroll
+      for (int t = 0; t < NIB; ++t) cmma<T>(yr[TLO + t], yi[TLO + t], xc[t].x, xc[t].y, bc.x, bc.y);
+      bc = bn;
+#pragma unroll
+      for (int t = 0; t < NIB; ++t) xc[t] = xn[t];
+    }
+  }
+}
+
 template <typename T, typename Tin>
 __global__ void __launch_bounds__(256, 2) k_apply(const ApplyGroup* __restrict__ groups,
                                                const ApplyTile* __restrict__ tiles,
@@ -177,9 +294,9 @@ __global__ void __launch_bounds__(256, 2) k_apply(const ApplyGroup* __restrict__
   c2* zs = bs + (long)D2 * bs1 + (long)wave * D1 * 16;
 
   // stage the tile's input slices (zero padded, compute precision)
-  for (long e = threadIdx.x; e < (long)nfl * D1 * D2; e += 256) {
-    const int fl = (int)(e / ((long)D1 * D2));
-    const int rem = (int)(e % ((long)D1 * D2));
+  for (int e = threadIdx.x; e < nfl * D1 * D2; e += 256) {
+    const int fl = e / (D1 * D2);
+    const int rem = e - fl * (D1 * D2);
     const int a = rem / D2, bcol = rem % D2;
     c2 v;
     v.x = 0;
@@ -239,84 +356,26 @@ __global__ void __launch_bounds__(256, 2) k_apply(const ApplyGroup* __restrict__
       }
     }
     __syncthreads();
+    const int kind = (Am ? 1 : 0) | (Bm ? 2 : 0);
     for (int uu = 0; uu < n_my; ++uu) {
       const int u = tile.u0 + wave + 4 * uu;
       const int fl = u / njb - f_first, jb = u % njb;
       const c2* xf = xs + (long)fl * D1 * xs1;
       const int col = 16 * jb + c;
       const int t_lo = uu * nib;
-      if (Am && Bm) {
-        v4 zra[NT], zia[NT];
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-          zra[t] = v4{0, 0, 0, 0};
-          zia[t] = v4{0, 0, 0, 0};
-        }
-        for (int q = 0; q < nq1; ++q) {
-          const int kk = 4 * q + g;
-          const c2 bv = bs[col * bs1 + kk];
-#pragma unroll
-          for (int t = 0; t < NT; ++t) {
-            if (t < nib) {
-              const c2 xv = xf[(16 * t + c) * xs1 + kk];
-              cmma<T>(zra[t], zia[t], xv.x, xv.y, bv.x, bv.y);
-            }
-          }
-        }
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-          if (t < nib) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              c2 v;
-              v.x = zra[t][r];
-              v.y = zia[t][r];
-              zs[(16 * t + MT<T>::drow(g, r)) * 16 + c] = v;
-            }
-          }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        for (int q = 0; q < nq2; ++q) {
-          const int kk = 4 * q + g;
-          const c2 zv = zs[kk * 16 + c];
-#pragma unroll
-          for (int ti = 0; ti < NT; ++ti) {
-            if (ti >= t_lo && ti < t_lo + nib) {
-              const c2 av = as[(16 * (ti - t_lo) + c) * as1 + kk];
-              cmma<T>(yr[ti], yi[ti], av.x, av.y, zv.x, zv.y);
-            }
-          }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      } else if (Am) {
-        for (int q = 0; q < nq2; ++q) {
-          const int kk = 4 * q + g;
-          const c2 xv = xf[kk * xs1 + col];
-#pragma unroll
-          for (int ti = 0; ti < NT; ++ti) {
-            if (ti >= t_lo && ti < t_lo + nib) {
-              const c2 av = as[(16 * (ti - t_lo) + c) * as1 + kk];
-              cmma<T>(yr[ti], yi[ti], av.x, av.y, xv.x, xv.y);
-            }
-          }
-        }
-      } else if (Bm) {
-        for (int q = 0; q < nq1; ++q) {
-          const int kk = 4 * q + g;
-          const c2 bv = bs[col * bs1 + kk];
-#pragma unroll
-          for (int ti = 0; ti < NT; ++ti) {
-            if (ti >= t_lo && ti < t_lo + nib) {
-              const c2 xv = xf[(16 * (ti - t_lo) + c) * xs1 + kk];
-              cmma<T>(yr[ti], yi[ti], xv.x, xv.y, bv.x, bv.y);
-            }
-          }
-        }
+#define TENSO_UNIT(NIB, TLO) \
+  apply_unit<T, NIB, TLO>(kind, xf, as, bs, zs, col, c, g, nq1, nq2, xs1, as1, bs1, yr, yi)
+      switch (4 * nib + t_lo) {
+        case 4: TENSO_UNIT(1, 0); break;
+        case 5: TENSO_UNIT(1, 1); break;
+        case 6: TENSO_UNIT(1, 2); break;
+        case 7: TENSO_UNIT(1, 3); break;
+        case 8: TENSO_UNIT(2, 0); break;
+        case 10: TENSO_UNIT(2, 2); break;
+        case 12: TENSO_UNIT(3, 0); break;
+        default: TENSO_UNIT(4, 0); break;
       }
+#undef TENSO_UNIT
     }
   }
   T* Y = reinterpret_cast<T*>(G.Y);
