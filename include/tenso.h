@@ -121,6 +121,16 @@ int tenso_plan_create(const tenso_tree* t, const tenso_gen* g, const tenso_plan_
                       tenso_plan** out);
 void tenso_plan_destroy(tenso_plan* p);
 
+/* Step execution switches (no device work).
+ * tenso_plan_set_graph: enable (default) or disable replaying tenso_step_fixed
+ * steps from a captured HIP graph; disabled, every step launches its kernels
+ * one by one (results are identical either way).
+ * tenso_plan_set_tile_work: flops per apply-kernel tile (default 16e6; range
+ * [1e5, 1e9], EINVAL outside); takes effect at the next build of the plan's
+ * programs, i.e. the next step call. */
+int tenso_plan_set_graph(tenso_plan* p, int enable);
+int tenso_plan_set_tile_work(tenso_plan* p, double flops);
+
 /* Device bytes the caller must provide: the state (FP64 master cores) and the
  * workspace (operand copies, environments, stage buffers, QR scratch). */
 int tenso_plan_sizes(const tenso_plan* p, size_t* state_bytes, size_t* workspace_bytes);
@@ -207,6 +217,25 @@ int tenso_batch_record_bytes(const tenso_batch* b, size_t* bytes_per_record, siz
 /* rho_S of every instance: h_rho[i] points to an M_i x M_i host array. */
 int tenso_batch_reduced_rho(tenso_batch* b, tenso_c128* const* h_rho, hipStream_t s);
 void tenso_batch_destroy(tenso_batch* b);
+
+/* Graph replay of batched steps on (default) or off; results are identical. */
+int tenso_batch_set_graph(tenso_batch* b, int enable);
+
+/* Bytes of a buffer that holds every instance's state (each 256-byte aligned). */
+int tenso_batch_state_bytes(const tenso_batch* b, size_t* bytes);
+
+/* Autotuner: times trial_steps batched steps (programs built and graph
+ * captured first, then timed on the stream with HIP events) for each apply
+ * tile size in {4e6, 8e6, 16e6, 32e6, 64e6} flops and keeps the fastest on
+ * every plan of the batch; *tile_work_out receives it.  The instance states
+ * are saved to d_backup (caller-owned device buffer of at least
+ * tenso_batch_state_bytes bytes; ENOMEM if smaller) and restored after every
+ * trial, so on return they are bit-identical to those on entry.  dt and
+ * d_drive_tabs are as for tenso_batch_step with n_steps = trial_steps.
+ * Synchronises the stream. */
+int tenso_batch_autotune(tenso_batch* b, const double* dt, int trial_steps,
+                         const double* const* d_drive_tabs, void* d_backup, size_t backup_bytes,
+                         double* tile_work_out, hipStream_t s);
 
 /* ---- learned surrogate (a project addition; not in the paper) ------------
  * Building blocks of a SiLU multilayer perceptron trained on trajectories of

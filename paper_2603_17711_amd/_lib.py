@@ -42,6 +42,8 @@ SIGS = {
     "tenso_gen_destroy": (None, [P]),
     "tenso_plan_create": (C.c_int, [P, P, C.POINTER(PlanOpts), C.POINTER(P)]),
     "tenso_plan_destroy": (None, [P]),
+    "tenso_plan_set_graph": (C.c_int, [P, C.c_int]),
+    "tenso_plan_set_tile_work": (C.c_int, [P, C.c_double]),
     "tenso_plan_sizes": (C.c_int, [P, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
     "tenso_plan_shapes": (C.c_int, [P, I32P, I32P]),
     "tenso_state_init": (C.c_int, [P, C128P, P, P]),
@@ -59,6 +61,9 @@ SIGS = {
     "tenso_batch_step": (C.c_int, [P, DP, DP, C.c_int, C.POINTER(P), P]),
     "tenso_batch_reduced_rho": (C.c_int, [P, C.POINTER(C128P), P]),
     "tenso_batch_destroy": (None, [P]),
+    "tenso_batch_set_graph": (C.c_int, [P, C.c_int]),
+    "tenso_batch_state_bytes": (C.c_int, [P, C.POINTER(C.c_size_t)]),
+    "tenso_batch_autotune": (C.c_int, [P, DP, C.c_int, C.POINTER(P), P, C.c_size_t, DP, P]),
     "tenso_batch_step_record": (C.c_int, [P, DP, DP, C.c_int, C.c_int, C.POINTER(P), P, P]),
     "tenso_batch_record_bytes": (C.c_int, [P, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
     "tenso_mlp_gemm": (C.c_int, [C.c_int, C.c_int, C.c_int, P, C.c_long, C.c_long, P, C.c_long,

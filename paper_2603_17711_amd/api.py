@@ -161,6 +161,14 @@ class Plan:
         check(lib().tenso_step_fixed(self.h, C.c_void_p(self.state.data_ptr()), t0, dt, n_steps,
                                      ptr, C.c_void_p(self.ws.data_ptr()), _stream()))
 
+    def set_graph(self, enable):
+        """Replay steps from a captured HIP graph (default) or launch eagerly."""
+        check(lib().tenso_plan_set_graph(self.h, int(bool(enable))))
+
+    def set_tile_work(self, flops):
+        """Flops per apply-kernel tile (default 16e6)."""
+        check(lib().tenso_plan_set_tile_work(self.h, float(flops)))
+
     def step_adaptive(self, n_steps, dt, eps, max_rank, t0=0.0, drive_tab=None):
         ptr = C.c_void_p(drive_tab.data_ptr()) if drive_tab is not None else None
         check(lib().tenso_step_adaptive(self.h, C.c_void_p(self.state.data_ptr()), t0, dt,
@@ -244,6 +252,29 @@ class Batch:
         check(lib().tenso_batch_step(self.h, t0.ctypes.data_as(C.POINTER(C.c_double)),
                                      dt.ctypes.data_as(C.POINTER(C.c_double)), n_steps, tabs,
                                      _stream()))
+
+    def set_graph(self, enable):
+        """Replay batched steps from a captured HIP graph (default) or launch eagerly."""
+        check(lib().tenso_batch_set_graph(self.h, int(bool(enable))))
+
+    def autotune(self, dts, trial_steps=2, drive_tabs=None):
+        """Pick the fastest apply tile size for this batch (states are restored
+        exactly); returns it in flops."""
+        import torch
+        n = len(self.plans)
+        dt = np.ascontiguousarray(np.broadcast_to(np.asarray(dts, np.float64), (n,)))
+        nb = C.c_size_t()
+        check(lib().tenso_batch_state_bytes(self.h, C.byref(nb)))
+        backup = torch.empty(int(nb.value), dtype=torch.uint8, device=self.plans[0].state.device)
+        tabs = None
+        if drive_tabs is not None:
+            tabs = (C.c_void_p * n)(*[(t.data_ptr() if t is not None else None)
+                                      for t in drive_tabs])
+        out = C.c_double()
+        check(lib().tenso_batch_autotune(self.h, dt.ctypes.data_as(C.POINTER(C.c_double)),
+                                         int(trial_steps), tabs, C.c_void_p(backup.data_ptr()),
+                                         int(nb.value), C.byref(out), _stream()))
+        return float(out.value)
 
     def rho(self):
         outs = [np.zeros((p.M, p.M), np.complex128) for p in self.plans]

@@ -264,6 +264,27 @@ struct Recipe {  // effective generator on one tensor (node core, bond or edge)
   std::vector<G> groups;
 };
 
+// One step of a compiled program (its launches plus the step-counter
+// advance) captured as a HIP graph, so that a step costs one graph launch
+// instead of hundreds of kernel launches.  Capture happens on a private
+// stream (the caller's may be the null stream, which cannot capture); the
+// graph is launched on the caller's stream.  The captured launches hold
+// device addresses bound at capture time: any re-upload of the program
+// resets the graph.
+struct StepGraph {
+  bool enabled = true;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap = nullptr;
+  void reset() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    exec = nullptr;
+  }
+  ~StepGraph() {
+    reset();
+    if (cap) (void)hipStreamDestroy(cap);
+  }
+};
+
 struct tenso_plan {
   tenso_tree tree;   // current ranks
   tenso_tree cap;    // capacity ranks (sizes every buffer; = tree for ps1)
@@ -292,6 +313,8 @@ struct tenso_plan {
   void* opbuf = nullptr;  // device scratch for single-op descriptors (ps2)
   int par_target = 64;  // tiles wanted per apply (single-instance latency)
   int built_target = -1;  // par_target the cached programs were built with
+  double tile_work = 16e6;        // flops per apply tile
+  double built_tile_work = -1;    // tile_work the cached programs were built with
   // compiled programs (host descriptors with tagged pointers, device copies)
   std::unique_ptr<Program> prog_step, prog_init;
   std::unique_ptr<DevProgram> dev_step, dev_init;
@@ -304,6 +327,7 @@ struct tenso_plan {
   const double* b_drive = nullptr;
   int b_ld = -1;
   std::vector<int32_t> rank_log;
+  StepGraph graph;  // captured step program (replayed per step)
 
   ~tenso_plan() {
     if (cbuf) (void)hipFree(cbuf);
@@ -692,7 +716,7 @@ struct Builder {
       fail(TENSO_EUNSUPPORTED, "leg dimensions too large for the apply kernel in this precision");
     const long units = F * njb;
     const double per_unit = unit_work(d1, d2) * std::max(1, n_terms);
-    long want = std::max<long>(target, (long)std::ceil(units * per_unit / kTileWork));
+    long want = std::max<long>(target, (long)std::ceil(units * per_unit / P.tile_work));
     long per = std::max<long>(1, (units + want - 1) / want);
     per = std::min<long>(per, 4L * (NT / nib));
     while (per > 1 && apply_lds_bytes(P.fp64, (int)((per + njb - 1) / njb + 1), d1, d2, 1) > budget)
@@ -706,7 +730,6 @@ struct Builder {
       G.atiles.push_back(tl);
     }
   }
-  static constexpr double kTileWork = 16e6;
 
   // Emit apply launches of recipe R on input X -> parts (chunked), with the
   // presum launch in front.  Returns the number of partial slabs written.
@@ -777,7 +800,7 @@ struct Builder {
       {
         const double w_all = (double)units * unit_work(d1, d2) * (double)trs.size();
         const long tiles_units = std::max<long>(1, (units + 3) / 4);
-        long want = std::max<long>((long)std::ceil(w_all / kTileWork),
+        long want = std::max<long>((long)std::ceil(w_all / P.tile_work),
                                    target > 1 ? (long)target / (long)R.groups.size() : 1);
         nchunk = (int)std::min<long>(8, std::max<long>(1, (want + tiles_units - 1) / tiles_units));
         nchunk = std::min<int>(nchunk, std::max<int>(1, (int)trs.size() / 2));
@@ -1388,6 +1411,43 @@ static void run(const DevProgram& D, int fp64, const int* ctr, hipStream_t s) {
   }
 }
 
+// Capture one step (program launches, then the step-counter advance).
+static void capture_step(StepGraph& G, const DevProgram& D, int fp64, int* ctr) {
+  if (!G.cap) hipchk(hipStreamCreateWithFlags(&G.cap, hipStreamNonBlocking), "hipStreamCreate");
+  hipGraph_t g = nullptr;
+  hipchk(hipStreamBeginCapture(G.cap, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+  try {
+    run(D, fp64, ctr, G.cap);
+    hipchk(launch_step_inc(ctr, -1, G.cap), "ctr");
+  } catch (...) {
+    (void)hipStreamEndCapture(G.cap, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  hipchk(hipStreamEndCapture(G.cap, &g), "hipStreamEndCapture");
+  const hipError_t e = hipGraphInstantiate(&G.exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  hipchk(e, "hipGraphInstantiate");
+}
+
+// n_steps steps of program D: graph replays when enabled (the first step of
+// a fresh binding runs eagerly, which also performs the kernels' one-time
+// attribute setup outside any capture), eager launches otherwise or while
+// the apply kernels are being timed.
+static void step_loop(StepGraph& G, const DevProgram& D, int fp64, int* ctr, int n_steps,
+                      hipStream_t s) {
+  const bool use = G.enabled && !g_prof.on;
+  for (int k = 0; k < n_steps; ++k) {
+    if (use && G.exec) {
+      hipchk(hipGraphLaunch(G.exec, s), "hipGraphLaunch");
+      continue;
+    }
+    run(D, fp64, ctr, s);
+    hipchk(launch_step_inc(ctr, -1, s), "ctr");
+    if (use) capture_step(G, D, fp64, ctr);
+  }
+}
+
 // Tile group indices are relative to the first group of their launch.
 static void fix_tile_groups(Program& G) {
   for (auto& L : G.launches) {
@@ -1763,6 +1823,22 @@ int tenso_plan_create(const tenso_tree* t, const tenso_gen* g, const tenso_plan_
 
 void tenso_plan_destroy(tenso_plan* p) { delete p; }
 
+int tenso_plan_set_graph(tenso_plan* p, int enable) {
+  return guard([&] {
+    if (!p) fail(TENSO_EINVAL, "null plan");
+    p->graph.enabled = enable != 0;
+    p->graph.reset();
+  });
+}
+
+int tenso_plan_set_tile_work(tenso_plan* p, double flops) {
+  return guard([&] {
+    if (!p) fail(TENSO_EINVAL, "null plan");
+    if (!(flops >= 1e5 && flops <= 1e9)) fail(TENSO_EINVAL, "tile work outside [1e5, 1e9] flops");
+    p->tile_work = flops;
+  });
+}
+
 int tenso_plan_sizes(const tenso_plan* p, size_t* sb, size_t* wb) {
   return guard([&] {
     if (!p) fail(TENSO_EINVAL, "null plan");
@@ -1876,18 +1952,20 @@ int tenso_step_fixed(tenso_plan* p, void* d_state, double t0, double dt, int n_s
       p->dev_init = std::make_unique<DevProgram>();
     }
     p->par_target = 64;
-    if (!p->prog_step || p->built_target != p->par_target) {
+    if (!p->prog_step || p->built_target != p->par_target || p->built_tile_work != p->tile_work) {
       p->prog_step = std::make_unique<Program>();
       p->prog_init = std::make_unique<Program>();
       build_step(*p, *p->prog_step);
       build_init(*p, *p->prog_init);
       p->built_target = p->par_target;
+      p->built_tile_work = p->tile_work;
       p->b_state = nullptr;
     }
     if (p->b_state != d_state || p->b_ws != d_ws || p->b_dt != dt || p->b_drive != d_drive_tab ||
         p->b_ld != ld) {
       upload(*p->dev_step, *p->prog_step, d_state, d_ws, dt, d_drive_tab, ld, s);
       upload(*p->dev_init, *p->prog_init, d_state, d_ws, dt, d_drive_tab, ld, s);
+      p->graph.reset();
       p->b_state = d_state;
       p->b_ws = d_ws;
       p->b_dt = dt;
@@ -1897,10 +1975,7 @@ int tenso_step_fixed(tenso_plan* p, void* d_state, double t0, double dt, int n_s
     int* ctr = (int*)((char*)d_ws + p->ws_ctr);
     hipchk(launch_step_inc(ctr, 0, s), "ctr");
     run(*p->dev_init, p->fp64, ctr, s);
-    for (int k = 0; k < n_steps; ++k) {
-      run(*p->dev_step, p->fp64, ctr, s);
-      hipchk(launch_step_inc(ctr, -1, s), "ctr");
-    }
+    step_loop(p->graph, *p->dev_step, p->fp64, ctr, n_steps, s);
   });
 }
 
@@ -2000,6 +2075,7 @@ struct tenso_batch {
   double* rho_buf = nullptr;
   std::vector<size_t> rho_off;
   DevProgram step, init, rho;
+  StepGraph graph;
   ~tenso_batch() {
     if (ctr) (void)hipFree(ctr);
     if (rho_buf) (void)hipFree(rho_buf);
@@ -2012,12 +2088,13 @@ static void batch_build(tenso_batch& B, hipStream_t s) {
   for (size_t i = 0; i < n; ++i) {
     tenso_plan& P = *B.plans[i];
     P.par_target = 4;  // the batch supplies the parallelism
-    if (!P.prog_step || P.built_target != P.par_target) {
+    if (!P.prog_step || P.built_target != P.par_target || P.built_tile_work != P.tile_work) {
       P.prog_step = std::make_unique<Program>();
       P.prog_init = std::make_unique<Program>();
       build_step(P, *P.prog_step);
       build_init(P, *P.prog_init);
       P.built_target = P.par_target;
+      P.built_tile_work = P.tile_work;
       P.b_state = nullptr;
     }
     st[i] = *P.prog_step;
@@ -2033,6 +2110,35 @@ static void batch_build(tenso_batch& B, hipStream_t s) {
   upload_resolved(B.step, ms, s);
   upload_resolved(B.init, mi, s);
   upload_resolved(B.rho, mr, s);
+  B.graph.reset();
+}
+
+// Check the batch arguments, (re)build the batch programs when the binding
+// changed, and advance every instance by n_steps.
+static void batch_advance(tenso_batch* b, const double* dt, int n_steps,
+                          const double* const* d_drive_tabs, hipStream_t s) {
+  if (!b || !dt) fail(TENSO_EINVAL, "null argument");
+  if (n_steps < 0) fail(TENSO_EINVAL, "n_steps must be >= 0");
+  const size_t n = b->plans.size();
+  std::vector<double> dts(dt, dt + n);
+  std::vector<const double*> drv(n, nullptr);
+  for (size_t i = 0; i < n; ++i) {
+    if (!(dts[i] > 0)) fail(TENSO_EINVAL, "dt must be > 0");
+    if (d_drive_tabs) drv[i] = d_drive_tabs[i];
+    if (b->plans[i]->gen.n_slots > 0 && !drv[i]) fail(TENSO_EINVAL, "instance with drive slots needs a drive table");
+  }
+  const int ld = 4 * n_steps + 1;
+  bool stale = false;
+  for (auto* P : b->plans) stale = stale || P->built_tile_work != P->tile_work;
+  if (stale || dts != b->dts || drv != b->drives || ld != b->ld || !b->step.arena) {
+    b->dts = dts;
+    b->drives = drv;
+    b->ld = ld;
+    batch_build(*b, s);
+  }
+  hipchk(launch_step_inc(b->ctr, 0, s), "ctr");
+  run(b->init, b->fp64, b->ctr, s);
+  step_loop(b->graph, b->step, b->fp64, b->ctr, n_steps, s);
 }
 
 extern "C" {
@@ -2064,30 +2170,8 @@ int tenso_batch_create(int n, tenso_plan* const* plans, void* const* d_states,
 int tenso_batch_step(tenso_batch* b, const double* t0, const double* dt, int n_steps,
                      const double* const* d_drive_tabs, hipStream_t s) {
   return guard([&] {
-    if (!b || !dt) fail(TENSO_EINVAL, "null argument");
-    if (n_steps < 0) fail(TENSO_EINVAL, "n_steps must be >= 0");
     (void)t0;
-    const size_t n = b->plans.size();
-    std::vector<double> dts(dt, dt + n);
-    std::vector<const double*> drv(n, nullptr);
-    for (size_t i = 0; i < n; ++i) {
-      if (!(dts[i] > 0)) fail(TENSO_EINVAL, "dt must be > 0");
-      if (d_drive_tabs) drv[i] = d_drive_tabs[i];
-      if (b->plans[i]->gen.n_slots > 0 && !drv[i]) fail(TENSO_EINVAL, "instance with drive slots needs a drive table");
-    }
-    const int ld = 4 * n_steps + 1;
-    if (dts != b->dts || drv != b->drives || ld != b->ld || !b->step.arena) {
-      b->dts = dts;
-      b->drives = drv;
-      b->ld = ld;
-      batch_build(*b, s);
-    }
-    hipchk(launch_step_inc(b->ctr, 0, s), "ctr");
-    run(b->init, b->fp64, b->ctr, s);
-    for (int k = 0; k < n_steps; ++k) {
-      run(b->step, b->fp64, b->ctr, s);
-      hipchk(launch_step_inc(b->ctr, -1, s), "ctr");
-    }
+    batch_advance(b, dt, n_steps, d_drive_tabs, s);
   });
 }
 
@@ -2107,7 +2191,9 @@ int tenso_batch_step_record(tenso_batch* b, const double* t0, const double* dt, 
       if (b->plans[i]->gen.n_slots > 0 && !drv[i]) fail(TENSO_EINVAL, "instance with drive slots needs a drive table");
     }
     const int ld = 4 * n_steps + 1;
-    if (dts != b->dts || drv != b->drives || ld != b->ld || !b->step.arena) {
+    bool stale = false;
+    for (auto* P : b->plans) stale = stale || P->built_tile_work != P->tile_work;
+    if (stale || dts != b->dts || drv != b->drives || ld != b->ld || !b->step.arena) {
       b->dts = dts;
       b->drives = drv;
       b->ld = ld;
@@ -2122,8 +2208,7 @@ int tenso_batch_step_record(tenso_batch* b, const double* t0, const double* dt, 
     hipchk(hipMemcpyAsync((char*)d_series + (size_t)r++ * rec, b->rho_buf, rec,
                           hipMemcpyDeviceToDevice, s), "record");
     for (int k = 0; k < n_steps; ++k) {
-      run(b->step, b->fp64, b->ctr, s);
-      hipchk(launch_step_inc(b->ctr, -1, s), "ctr");
+      step_loop(b->graph, b->step, b->fp64, b->ctr, 1, s);
       if ((k + 1) % every == 0) {
         run(b->rho, b->fp64, nullptr, s);
         hipchk(hipMemcpyAsync((char*)d_series + (size_t)r++ * rec, b->rho_buf, rec,
@@ -2158,6 +2243,82 @@ int tenso_batch_reduced_rho(tenso_batch* b, tenso_c128* const* h_rho, hipStream_
       const size_t M = b->plans[i]->tree.end_dim[0];
       memcpy(h_rho[i], h.data() + b->rho_off[i], M * M * 16);
     }
+  });
+}
+
+int tenso_batch_set_graph(tenso_batch* b, int enable) {
+  return guard([&] {
+    if (!b) fail(TENSO_EINVAL, "null batch");
+    b->graph.enabled = enable != 0;
+    b->graph.reset();
+  });
+}
+
+int tenso_batch_state_bytes(const tenso_batch* b, size_t* bytes) {
+  return guard([&] {
+    if (!b || !bytes) fail(TENSO_EINVAL, "null argument");
+    size_t tot = 0;
+    for (auto* P : b->plans) tot += align256(P->state_bytes);
+    *bytes = tot;
+  });
+}
+
+int tenso_batch_autotune(tenso_batch* b, const double* dt, int trial_steps,
+                         const double* const* d_drive_tabs, void* d_backup, size_t backup_bytes,
+                         double* tile_work_out, hipStream_t s) {
+  return guard([&] {
+    if (!b || !dt || !d_backup) fail(TENSO_EINVAL, "null argument");
+    if (trial_steps < 1) fail(TENSO_EINVAL, "trial_steps must be >= 1");
+    const size_t n = b->plans.size();
+    std::vector<size_t> off(n);
+    size_t tot = 0;
+    for (size_t i = 0; i < n; ++i) {
+      off[i] = tot;
+      tot += align256(b->plans[i]->state_bytes);
+    }
+    if (backup_bytes < tot) fail(TENSO_ENOMEM, "backup buffer smaller than the batch states");
+    auto copy_states = [&](bool save) {
+      for (size_t i = 0; i < n; ++i) {
+        char* bk = (char*)d_backup + off[i];
+        if (save)
+          hipchk(hipMemcpyAsync(bk, b->states[i], b->plans[i]->state_bytes, hipMemcpyDeviceToDevice, s), "save");
+        else
+          hipchk(hipMemcpyAsync(b->states[i], bk, b->plans[i]->state_bytes, hipMemcpyDeviceToDevice, s), "restore");
+      }
+    };
+    copy_states(true);
+    static const double cand[] = {4e6, 8e6, 16e6, 32e6, 64e6};
+    hipEvent_t e0, e1;
+    hipchk(hipEventCreate(&e0), "hipEventCreate");
+    hipchk(hipEventCreate(&e1), "hipEventCreate");
+    double best = -1, best_ms = 0;
+    try {
+      for (double w : cand) {
+        for (auto* P : b->plans) P->tile_work = w;
+        batch_advance(b, dt, trial_steps, d_drive_tabs, s);  // build, capture, warm up
+        copy_states(false);
+        hipchk(hipEventRecord(e0, s), "hipEventRecord");
+        batch_advance(b, dt, trial_steps, d_drive_tabs, s);
+        hipchk(hipEventRecord(e1, s), "hipEventRecord");
+        hipchk(hipEventSynchronize(e1), "hipEventSynchronize");
+        float ms = 0;
+        hipchk(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+        copy_states(false);
+        if (best < 0 || ms < best_ms) {
+          best = w;
+          best_ms = ms;
+        }
+      }
+    } catch (...) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    for (auto* P : b->plans) P->tile_work = best;
+    hipchk(hipStreamSynchronize(s), "sync");
+    if (tile_work_out) *tile_work_out = best;
   });
 }
 
