@@ -220,6 +220,7 @@ struct AbsorbTileH {
 
 struct Program {
   std::vector<TermRef> terms;
+  std::vector<double> credit;  // per term: generator terms it stands for (work accounting)
   std::vector<ApplyGroup> groups;
   std::vector<ApplyTile> atiles;
   std::vector<PresumOp> presums;
@@ -263,6 +264,48 @@ struct Recipe {  // effective generator on one tensor (node core, bond or edge)
   std::vector<int> dims;
   std::vector<G> groups;
 };
+
+// Term grouping: pair terms of a group that carry the same operator on one
+// leg satisfy sum_m c_m(t) A (x) B_m = A (x) (sum_m c_m(t) B_m), so each such
+// cluster costs one pair of products on a presummed operator.  The shared
+// side is the one with fewer distinct operators.
+struct PairCluster {
+  int shared_side;  // 0: operator on l1 shared, others on l2; 1: the reverse
+  ORef shared;
+  std::vector<std::pair<int, ORef>> others;  // (term, operator on the other leg)
+};
+
+static bool same_ref(const ORef& a, const ORef& b) {
+  return a.kind == b.kind && a.node == b.node && a.idx == b.idx;
+}
+
+static std::vector<PairCluster> cluster_pairs(const Recipe::G& g) {
+  auto distinct = [&](int side) {
+    std::vector<ORef> seen;
+    for (auto& pt : g.pair_terms) {
+      const ORef& o = side == 0 ? pt.second.first : pt.second.second;
+      bool found = false;
+      for (auto& x : seen) found = found || same_ref(x, o);
+      if (!found) seen.push_back(o);
+    }
+    return seen.size();
+  };
+  const int side = distinct(1) < distinct(0) ? 1 : 0;
+  std::vector<PairCluster> out;
+  for (auto& pt : g.pair_terms) {
+    const ORef& key = side == 0 ? pt.second.first : pt.second.second;
+    const ORef& oth = side == 0 ? pt.second.second : pt.second.first;
+    PairCluster* c = nullptr;
+    for (auto& x : out)
+      if (same_ref(x.shared, key)) c = &x;
+    if (!c) {
+      out.push_back({side, key, {}});
+      c = &out.back();
+    }
+    c->others.push_back({pt.first, oth});
+  }
+  return out;
+}
 
 // One step of a compiled program (its launches plus the step-counter
 // advance) captured as a HIP graph, so that a step costs one graph launch
@@ -573,6 +616,11 @@ static void layout(tenso_plan& P) {
     for (auto& g : R.groups) {
       if (!g.sa.empty()) ps += (size_t)R.dims[g.l1] * R.dims[g.l1];
       if (!g.sb.empty()) ps += (size_t)R.dims[g.l2] * R.dims[g.l2];
+      for (auto& c : cluster_pairs(g))
+        if (c.others.size() > 1) {
+          const size_t d = R.dims[c.shared_side == 0 ? g.l2 : g.l1];
+          ps += d * d;
+        }
     }
     presum = std::max(presum, ps);
     parts = std::max(parts, (size_t)R.groups.size() * 8 * (size_t)n);
@@ -587,6 +635,7 @@ static void layout(tenso_plan& P) {
       qrv = std::max(qrv, (size_t)t.size(t.parent[s]));
       presum = std::max(presum, 2 * r * r);
       parts = std::max(parts, 8 * r * r);
+      recipe_caps(bond_recipe(P, s), (long)r * r);
       if (P.opts.method == TENSO_PS2) {
         const int p = t.parent[s];
         const long rows = t.size(p) / t.rank[s], cols = t.size(s) / t.rank[s];
@@ -668,12 +717,15 @@ struct Builder {
         L.bytes += P * esz + P * P_.tsz;
         const int t0 = (int)(((uint64_t)g.terms) & OFF_MASK);
         for (int m = t0; m < t0 + g.n_terms; ++m) {
+          // credited per generator term the entry stands for (grouped and
+          // presummed terms count as the separate terms they replace)
           const TermRef& t = G.terms[m];
-          if (t.A && t.B) L.flops += 8.0 * F * d1 * d2 * (d1 + d2);
-          else if (t.A) L.flops += 8.0 * F * d1 * d1 * d2;
-          else L.flops += 8.0 * F * d1 * d2 * d2;
-          if (t.A) L.bytes += d1 * d1 * P_.tsz;
-          if (t.B) L.bytes += d2 * d2 * P_.tsz;
+          const double w = G.credit[m];
+          if (t.A && t.B) L.flops += w * 8.0 * F * d1 * d2 * (d1 + d2);
+          else if (t.A) L.flops += w * 8.0 * F * d1 * d1 * d2;
+          else L.flops += w * 8.0 * F * d1 * d2 * d2;
+          if (t.A) L.bytes += w * d1 * d1 * P_.tsz;
+          if (t.B) L.bytes += w * d2 * d2 * P_.tsz;
         }
       }
     }
@@ -683,8 +735,9 @@ struct Builder {
   void* core(int s) { return tagp(TAG_STATE, P.core_off[s]); }
   void* ws(size_t off) { return tagp(TAG_WS, off); }
 
-  int term_index(const TermRef& tr) {
+  int term_index(const TermRef& tr, double credit = 1.0) {
     G.terms.push_back(tr);
+    G.credit.push_back(credit);
     return (int)G.terms.size() - 1;
   }
 
@@ -762,6 +815,35 @@ struct Builder {
         if (presum_now) G.presums.push_back(op);
       }
     }
+    // grouped pair terms: presum of the non-shared operators of each cluster
+    std::vector<std::vector<void*>> cl_buf(R.groups.size());
+    std::vector<std::vector<PairCluster>> clusters(R.groups.size());
+    for (size_t gi = 0; gi < R.groups.size(); ++gi) {
+      auto& g = R.groups[gi];
+      clusters[gi] = cluster_pairs(g);
+      for (auto& c : clusters[gi]) {
+        if (c.others.size() < 2) {
+          cl_buf[gi].push_back(nullptr);
+          continue;
+        }
+        const int d = R.dims[c.shared_side == 0 ? g.l2 : g.l1];
+        void* out = ws(poff);
+        poff += (size_t)d * d * P.tsz;
+        cl_buf[gi].push_back(out);
+        PresumOp op{};
+        op.out = out;
+        int first = -1;
+        for (auto& o : c.others) {
+          int k = term_index(term_ref(o.first, oref_ptr(P, o.second), nullptr));
+          if (first < 0) first = k;
+        }
+        op.terms = (const TermRef*)tagp(TAG_TERM, first);
+        op.n_terms = (int)c.others.size();
+        op.dim = d;
+        op.rel = rel;
+        if (presum_now) G.presums.push_back(op);
+      }
+    }
     if (poff - P.ws_presum > P.presum_cap * P.tsz + 1) fail(TENSO_EINVAL, "presum capacity");
     int np = (int)G.presums.size() - pfirst;
     if (np) launch(LK_PRESUM, 0, pfirst, np, 0, 0);
@@ -774,14 +856,32 @@ struct Builder {
     for (size_t gi = 0; gi < R.groups.size(); ++gi) {
       auto& g = R.groups[gi];
       std::vector<TermRef> trs;
-      for (auto& pt : g.pair_terms)
-        trs.push_back(term_ref(pt.first, oref_ptr(P, pt.second.first), oref_ptr(P, pt.second.second)));
+      std::vector<double> trc;  // generator terms per entry
+      for (size_t ci = 0; ci < clusters[gi].size(); ++ci) {
+        const PairCluster& c = clusters[gi][ci];
+        if (!cl_buf[gi][ci]) {  // a cluster of one: the plain pair term
+          const auto& o = c.others[0];
+          void* sh = oref_ptr(P, c.shared);
+          void* ot = oref_ptr(P, o.second);
+          trs.push_back(c.shared_side == 0 ? term_ref(o.first, sh, ot) : term_ref(o.first, ot, sh));
+          trc.push_back(1.0);
+          continue;
+        }
+        TermRef tr{};
+        tr.cre = 1;
+        tr.slot = -1;
+        tr.A = c.shared_side == 0 ? oref_ptr(P, c.shared) : cl_buf[gi][ci];
+        tr.B = c.shared_side == 0 ? cl_buf[gi][ci] : oref_ptr(P, c.shared);
+        trs.push_back(tr);
+        trc.push_back((double)c.others.size());
+      }
       if (sa_buf[gi]) {
         TermRef tr{};
         tr.cre = 1;
         tr.slot = -1;
         tr.A = sa_buf[gi];
         trs.push_back(tr);
+        trc.push_back((double)g.sa.size());
       }
       if (sb_buf[gi]) {
         TermRef tr{};
@@ -789,6 +889,7 @@ struct Builder {
         tr.slot = -1;
         tr.B = sb_buf[gi];
         trs.push_back(tr);
+        trc.push_back((double)g.sb.size());
       }
       const int d1 = R.dims[g.l1], d2 = R.dims[g.l2];
       const long F = Pn / ((long)d1 * d2);
@@ -814,7 +915,10 @@ struct Builder {
         ag.Y = ws(P.ws_parts + (size_t)part * Pn * P.tsz);
         ++part;
         int first = (int)G.terms.size();
-        for (size_t i = a; i < b; ++i) G.terms.push_back(trs[i]);
+        for (size_t i = a; i < b; ++i) {
+          G.terms.push_back(trs[i]);
+          G.credit.push_back(trc[i]);
+        }
         ag.terms = (const TermRef*)tagp(TAG_TERM, first);
         ag.in_fp64 = in_fp64;
         ag.n_terms = (int)(b - a);
@@ -859,9 +963,10 @@ struct Builder {
     const int rel0 = half == 0 ? 0 : 2;
     const int rels[4] = {rel0, rel0 + 1, rel0 + 1, rel0 + 2};
     bool td = false;
-    for (auto& g : R.groups) {
+    for (auto& g : R.groups) {  // presummed coefficients that change within the sub-flow
       for (auto& s : g.sa) td |= P.gen.terms[s.first].slot >= 0;
       for (auto& s : g.sb) td |= P.gen.terms[s.first].slot >= 0;
+      for (auto& s : g.pair_terms) td |= P.gen.terms[s.first].slot >= 0;
     }
     for (int st = 1; st <= 4; ++st) {
       void* X = st == 1 ? y0 : ws(P.ws_xin);
