@@ -319,6 +319,30 @@ __global__ void __launch_bounds__(256, 2) k_apply(const ApplyGroup* __restrict__
     yi[t] = v4{0, 0, 0, 0};
   }
 
+  // write the wavefront's accumulators (its units of this tile) to Yb
+  auto store_out = [&](T* Yb) {
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti) {
+      if (ti < n_my * nib) {
+        const int uu = ti / nib, t = ti % nib;
+        const UnitGeo ug = unit_geo(G, tile.u0 + wave + 4 * uu, njb, c);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * t + MT<T>::drow(g, r);
+          if (row < d1 && ug.col < d2) {
+            const long o = 2 * (ug.base + row * sa + (long)ug.col * sb);
+            if (G.accumulate) {
+              Yb[o] += yr[ti][r];
+              Yb[o + 1] += yi[ti][r];
+            } else {
+              Yb[o] = yr[ti][r];
+              Yb[o + 1] = yi[ti][r];
+            }
+          }
+        }
+      }
+    }
+  };
   for (int m = 0; m < G.n_terms; ++m) {
     const TermRef tr = G.terms[m];
     double cr, ci;
@@ -377,29 +401,16 @@ __global__ void __launch_bounds__(256, 2) k_apply(const ApplyGroup* __restrict__
       }
 #undef TENSO_UNIT
     }
-  }
-  T* Y = reinterpret_cast<T*>(G.Y);
+    if (G.per_term_out) {  // this term's result goes to its own slab
+      store_out(reinterpret_cast<T*>(G.Y) + 2 * (long)G.F * d1 * d2 * m);
 #pragma unroll
-  for (int ti = 0; ti < NT; ++ti) {
-    if (ti < n_my * nib) {
-      const int uu = ti / nib, t = ti % nib;
-      const UnitGeo ug = unit_geo(G, tile.u0 + wave + 4 * uu, njb, c);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = 16 * t + MT<T>::drow(g, r);
-        if (row < d1 && ug.col < d2) {
-          const long o = 2 * (ug.base + row * sa + (long)ug.col * sb);
-          if (G.accumulate) {
-            Y[o] += yr[ti][r];
-            Y[o + 1] += yi[ti][r];
-          } else {
-            Y[o] = yr[ti][r];
-            Y[o + 1] = yi[ti][r];
-          }
-        }
+      for (int t = 0; t < NT; ++t) {
+        yr[t] = v4{0, 0, 0, 0};
+        yi[t] = v4{0, 0, 0, 0};
       }
     }
   }
+  if (!G.per_term_out) store_out(reinterpret_cast<T*>(G.Y));
 }
 
 // ---------------------------------------------------------------------------
@@ -412,20 +423,53 @@ __global__ void __launch_bounds__(256) k_presum(const PresumOp* __restrict__ ops
   const int step = step_ctr ? *step_ctr : 0;
   const int j = 4 * step + op.rel;
   const int n = op.dim * op.dim;
-  T* out = reinterpret_cast<T*>(op.out);
-  for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    double sr = 0, si = 0;
-    for (int m = 0; m < op.n_terms; ++m) {
-      const TermRef& t = op.terms[m];
-      double cr, ci;
-      coef_at(t, op.drive, op.drive_ld, j, cr, ci);
-      const T* M = reinterpret_cast<const T*>(t.A);
-      const double a = M[2 * e], b = M[2 * e + 1];
-      sr += a * cr - b * ci;
-      si += a * ci + b * cr;
+  const gp<T> out = gmem(reinterpret_cast<T*>(op.out));
+  const gp<const TermRef> terms = gmem(op.terms);
+  const gp<const double> drive = op.drive ? gmem(op.drive) : nullptr;
+  // term matrices and coefficients (drive factor included) staged once;
+  // the host keeps n_terms <= PRESUM_MAX_TERMS
+  __shared__ const T* mats[PRESUM_MAX_TERMS];
+  __shared__ double cfs[PRESUM_MAX_TERMS][2];
+  for (int m = threadIdx.x; m < op.n_terms; m += blockDim.x) {
+    const TermRef t = terms[m];
+    double cr = t.cre, ci = t.cim;
+    if (t.slot >= 0 && drive) {
+      const double f = drive[(long)t.slot * op.drive_ld + j];
+      cr *= f;
+      ci *= f;
     }
-    out[2 * e] = (T)sr;
-    out[2 * e + 1] = (T)si;
+    mats[m] = reinterpret_cast<const T*>(t.A);
+    cfs[m][0] = cr;
+    cfs[m][1] = ci;
+  }
+  __syncthreads();
+  const int nm = op.n_terms;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    double ar = 0, ai = 0;
+    int m = 0;
+    for (; m + 4 <= nm; m += 4) {  // four independent loads per batch
+      T v[4][2];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const gp<const T> M = gmem(mats[m + u]);
+        v[u][0] = M[2 * e];
+        v[u][1] = M[2 * e + 1];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double a = v[u][0], b = v[u][1];
+        ar += a * cfs[m + u][0] - b * cfs[m + u][1];
+        ai += a * cfs[m + u][1] + b * cfs[m + u][0];
+      }
+    }
+    for (; m < nm; ++m) {
+      const gp<const T> M = gmem(mats[m]);
+      const double a = M[2 * e], b = M[2 * e + 1];
+      ar += a * cfs[m][0] - b * cfs[m][1];
+      ai += a * cfs[m][1] + b * cfs[m][0];
+    }
+    out[2 * e] = (T)ar;
+    out[2 * e + 1] = (T)ai;
   }
 }
 
@@ -1119,14 +1163,33 @@ __global__ void __launch_bounds__(256) k_absorb(const AbsorbOp* __restrict__ ops
 // One workgroup per environment matrix.  Work items = (16x16 output tile,
 // K part); with fewer than four tiles K is split across wavefronts and the
 // partial tiles are summed in LDS.
+// Operands of one k-step of the Gram product for one accumulator tile:
+// conj(C)[arow, k] and T[bcol, k], k = pre * Ppost + post.
+template <typename T>
+struct GramOpnd {
+  T ar, ai, br, bi;
+};
+
+// Quotient n / d for 0 <= n < 2^31, d >= 1, through a double-precision
+// reciprocal and integer correction.
+__device__ inline long gram_div(long n, long d, double dinv) {
+  long q = (long)((double)n * dinv);
+  while (q * d > n) --q;
+  while ((q + 1) * d <= n) ++q;
+  return q;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_gram(const GramOp* __restrict__ ops) {
   typedef typename MT<T>::v4 v4;
   const GramOp op = ops[blockIdx.x];
   const int r = op.r;
   const long K = (long)op.Ppre * op.Ppost;
-  const T* Tm = reinterpret_cast<const T*>(op.T);
-  T* E = reinterpret_cast<T*>(op.E);
+  const long Ppost = op.Ppost;
+  const double pinv = 1.0 / (double)Ppost;
+  const gp<const T> Tm = gmem(reinterpret_cast<const T*>(op.T));
+  const gp<const double> Cm = gmem(op.C);
+  const gp<T> E = gmem(reinterpret_cast<T*>(op.E));
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int c = lane & 15, g = lane >> 4;
   const int nb = (r + 15) >> 4, nt = nb * nb;
@@ -1140,6 +1203,9 @@ __global__ void __launch_bounds__(256) k_gram(const GramOp* __restrict__ ops) {
     accr[j] = v4{0, 0, 0, 0};
     acci[j] = v4{0, 0, 0, 0};
   }
+  // KU k-steps per batch; the next batch is read while the current one is
+  // multiplied
+  constexpr int KU = 4;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int item = wave + 4 * j;
@@ -1148,24 +1214,35 @@ __global__ void __launch_bounds__(256) k_gram(const GramOp* __restrict__ ops) {
       const int ti = tile / nb, tj = tile % nb;
       const int arow = 16 * ti + c, bcol = 16 * tj + c;
       const long k0 = kp * kchunk, k1 = k0 + kchunk < K ? k0 + kchunk : K;
-      for (long kb = k0; kb < k1; kb += 4) {
-        const long k = kb + g;
-        T ar = 0, ai = 0, br = 0, bi = 0;
-        if (k < k1) {
-          const long pre = k / op.Ppost, post = k % op.Ppost;
-          const long base = pre * r * op.Ppost + post;
-          if (arow < r) {
-            const long o = base + (long)arow * op.Ppost;
-            ar = (T)op.C[2 * o];
-            ai = -(T)op.C[2 * o + 1];  // conj(C)
-          }
-          if (bcol < r) {
-            const long o = base + (long)bcol * op.Ppost;
-            br = Tm[2 * o];
-            bi = Tm[2 * o + 1];
+      auto load = [&](long kb, GramOpnd<T>(&o)[KU]) {
+#pragma unroll
+        for (int u = 0; u < KU; ++u) {
+          const long k = kb + 4 * u + g;
+          o[u] = GramOpnd<T>{0, 0, 0, 0};
+          if (k < k1) {
+            const long pre = gram_div(k, Ppost, pinv), post = k - pre * Ppost;
+            const long base = pre * r * Ppost + post;
+            if (arow < r) {
+              const long oa = base + (long)arow * Ppost;
+              o[u].ar = (T)Cm[2 * oa];
+              o[u].ai = -(T)Cm[2 * oa + 1];  // conj(C)
+            }
+            if (bcol < r) {
+              const long ob = base + (long)bcol * Ppost;
+              o[u].br = Tm[2 * ob];
+              o[u].bi = Tm[2 * ob + 1];
+            }
           }
         }
-        cmma<T>(accr[j], acci[j], ar, ai, br, bi);
+      };
+      GramOpnd<T> cur[KU], nxt[KU];
+      load(k0, cur);
+      for (long kb = k0; kb < k1; kb += 4 * KU) {
+        if (kb + 4 * KU < k1) load(kb + 4 * KU, nxt);
+#pragma unroll
+        for (int u = 0; u < KU; ++u) cmma<T>(accr[j], acci[j], cur[u].ar, cur[u].ai, cur[u].br, cur[u].bi);
+#pragma unroll
+        for (int u = 0; u < KU; ++u) cur[u] = nxt[u];
       }
     }
   }

@@ -761,7 +761,8 @@ struct Builder {
   // Tiles for one group of units: about `tile_work` flops per tile (at most
   // 4*uw units), at least `target` tiles, and the tile's input slices and
   // operand matrices within the LDS budget.
-  void add_tiles(int gi, int d1, int d2, long F, int target, int n_terms) {
+  // Units per tile for a group (see add_tiles).
+  long tile_units(int d1, int d2, long F, int target, int n_terms) {
     const int nib = (d1 + 15) / 16, njb = (d2 + 15) / 16;
     const int NT = 4;  // accumulator tiles per wavefront in the kernel
     const size_t budget = 160 * 1024;
@@ -774,6 +775,13 @@ struct Builder {
     per = std::min<long>(per, 4L * (NT / nib));
     while (per > 1 && apply_lds_bytes(P.fp64, (int)((per + njb - 1) / njb + 1), d1, d2, 1) > budget)
       per /= 2;
+    return per;
+  }
+
+  void add_tiles(int gi, int d1, int d2, long F, int target, int n_terms) {
+    const int njb = (d2 + 15) / 16;
+    const long units = F * njb;
+    const long per = tile_units(d1, d2, F, target, n_terms);
     for (long u = 0; u < units; u += per) {
       ApplyTile tl{};
       tl.group = gi;
@@ -812,6 +820,7 @@ struct Builder {
         op.n_terms = (int)lst.size();
         op.dim = d;
         op.rel = rel;
+        if (op.n_terms > PRESUM_MAX_TERMS) fail(TENSO_EUNSUPPORTED, "more than 512 terms in one presum");
         if (presum_now) G.presums.push_back(op);
       }
     }
@@ -841,6 +850,7 @@ struct Builder {
         op.n_terms = (int)c.others.size();
         op.dim = d;
         op.rel = rel;
+        if (op.n_terms > PRESUM_MAX_TERMS) fail(TENSO_EUNSUPPORTED, "more than 512 terms in one presum");
         if (presum_now) G.presums.push_back(op);
       }
     }
@@ -981,6 +991,7 @@ struct Builder {
     const std::vector<int> dims = t.shape(x);
     const long Pn = t.size(x);
     int gfirst = (int)G.groups.size(), tfirst = (int)G.atiles.size();
+    std::vector<std::vector<std::pair<int, ORef>>> nzs;
     for (size_t k = 0; k < P.dkeys[x].size(); ++k) {
       const Key& key = P.dkeys[x][k];
       std::vector<std::pair<int, ORef>> nz;
@@ -988,15 +999,16 @@ struct Builder {
         ORef o = leg_ref_for_key(P, x, t.legs[x][i], key);
         if (o.kind) nz.push_back({i, o});
       }
-      add_env_group(dims, Pn, 0, nz, k, x, gfirst);
+      nzs.push_back(nz);
     }
+    const std::vector<size_t> slab = add_env_groups(dims, Pn, 0, nzs, x, gfirst);
     launch(LK_APPLY, 1, gfirst, (int)G.groups.size() - gfirst, tfirst,
            (int)G.atiles.size() - tfirst);
     int qf = (int)G.grams.size();
     for (size_t k = 0; k < P.dkeys[x].size(); ++k) {
       GramOp go{};
       go.C = (const double*)core(x);
-      go.T = ws(P.ws_envscr + k * Pn * P.tsz);
+      go.T = ws(P.ws_envscr + slab[k] * Pn * P.tsz);
       go.E = ws(P.envd_off[x] + k * (size_t)P.slot_r[x] * P.slot_r[x] * P.tsz);
       go.r = t.rank[x];
       go.Ppre = 1;
@@ -1014,6 +1026,7 @@ struct Builder {
     const long Pn = t.size(p);
     const int open = t.leg_of_child(p, x);
     int gfirst = (int)G.groups.size(), tfirst = (int)G.atiles.size();
+    std::vector<std::vector<std::pair<int, ORef>>> nzs;
     for (size_t k = 0; k < P.ukeys[x].size(); ++k) {
       const Key& key = P.ukeys[x][k];
       std::vector<std::pair<int, ORef>> nz;
@@ -1022,15 +1035,16 @@ struct Builder {
         ORef o = leg_ref_for_key(P, p, t.legs[p][i], key);
         if (o.kind) nz.push_back({i, o});
       }
-      add_env_group(dims, Pn, open, nz, k, p, gfirst);
+      nzs.push_back(nz);
     }
+    const std::vector<size_t> slab = add_env_groups(dims, Pn, open, nzs, p, gfirst);
     launch(LK_APPLY, 1, gfirst, (int)G.groups.size() - gfirst, tfirst,
            (int)G.atiles.size() - tfirst);
     int qf = (int)G.grams.size();
     for (size_t k = 0; k < P.ukeys[x].size(); ++k) {
       GramOp go{};
       go.C = (const double*)core(p);
-      go.T = ws(P.ws_envscr + k * Pn * P.tsz);
+      go.T = ws(P.ws_envscr + slab[k] * Pn * P.tsz);
       go.E = ws(P.envu_off[x] + k * (size_t)P.slot_r[x] * P.slot_r[x] * P.tsz);
       go.r = t.rank[x];
       go.Ppre = (int)prod(dims, 0, open);
@@ -1040,45 +1054,91 @@ struct Builder {
     launch(LK_GRAM, 0, qf, (int)G.grams.size() - qf, 0, 0);
   }
 
-  // one env slot = one group with a single unit-coefficient term on core `node`
-  void add_env_group(const std::vector<int>& dims, long Pn, int open,
-                     const std::vector<std::pair<int, ORef>>& nz, size_t k, int node, int gfirst) {
-    if (nz.empty() || nz.size() > 2)
-      fail(TENSO_EUNSUPPORTED, "environment operator acts on more than two legs");
-    int l1, l2;
-    void *A = nullptr, *B = nullptr;
-    if (nz.size() == 2) {
-      l1 = nz[0].first;
-      l2 = nz[1].first;
-      A = oref_ptr(P, nz[0].second);
-      B = oref_ptr(P, nz[1].second);
-    } else {
-      int l = nz[0].first, other = open;
-      l1 = std::min(l, other);
-      l2 = std::max(l, other);
-      if (l1 == l) A = oref_ptr(P, nz[0].second);
-      else B = oref_ptr(P, nz[0].second);
+  // Environment operators on core `node` (one per env slot k, acting on one
+  // or two of its legs besides `open`): slots with the same leg pair share
+  // one apply group whose terms each write their own result slab, so the
+  // core is staged once per tile for all of them.  Returns the scratch slab
+  // of every slot (slabs of a group are consecutive).
+  std::vector<size_t> add_env_groups(const std::vector<int>& dims, long Pn, int open,
+                                     const std::vector<std::vector<std::pair<int, ORef>>>& nzs,
+                                     int node, int gfirst) {
+    struct Item {
+      int l1, l2;
+      void *A, *B;
+    };
+    std::vector<Item> items;
+    for (auto& nz : nzs) {
+      if (nz.empty() || nz.size() > 2)
+        fail(TENSO_EUNSUPPORTED, "environment operator acts on more than two legs");
+      Item it{};
+      if (nz.size() == 2) {
+        it.l1 = nz[0].first;
+        it.l2 = nz[1].first;
+        it.A = oref_ptr(P, nz[0].second);
+        it.B = oref_ptr(P, nz[1].second);
+      } else {
+        const int l = nz[0].first;
+        it.l1 = std::min(l, open);
+        it.l2 = std::max(l, open);
+        if (it.l1 == l) it.A = oref_ptr(P, nz[0].second);
+        else it.B = oref_ptr(P, nz[0].second);
+      }
+      items.push_back(it);
     }
-    TermRef tr{};
-    tr.cre = 1;
-    tr.slot = -1;
-    tr.A = A;
-    tr.B = B;
-    int ti = term_index(tr);
-    ApplyGroup ag{};
-    ag.X = core(node);
-    ag.Y = ws(P.ws_envscr + k * Pn * P.tsz);
-    ag.terms = (const TermRef*)tagp(TAG_TERM, ti);
-    ag.in_fp64 = 1;
-    ag.n_terms = 1;
-    ag.d1 = dims[l1];
-    ag.d2 = dims[l2];
-    ag.P1 = (int)prod(dims, l1 + 1, l2);
-    ag.P2 = (int)prod(dims, l2 + 1, (int)dims.size());
-    ag.F = (int)(Pn / ((long)ag.d1 * ag.d2));
-    ag.rel = 0;
-    G.groups.push_back(ag);
-    add_tiles((int)G.groups.size() - 1 - gfirst, ag.d1, ag.d2, ag.F, std::max(1, P.par_target / 8), 1);
+    std::vector<size_t> slab(items.size());
+    std::vector<bool> done(items.size(), false);
+    size_t next = 0;
+    const int target = std::max(1, P.par_target / 8);
+    for (size_t k0 = 0; k0 < items.size(); ++k0) {
+      if (done[k0]) continue;
+      const int l1 = items[k0].l1, l2 = items[k0].l2;
+      std::vector<size_t> ks;
+      for (size_t k = k0; k < items.size(); ++k) {
+        if (done[k] || items[k].l1 != l1 || items[k].l2 != l2) continue;
+        done[k] = true;
+        ks.push_back(k);
+      }
+      const int d1 = dims[l1], d2 = dims[l2];
+      const long F = Pn / ((long)d1 * d2);
+      // term chunks (separate groups) while one chunk would give fewer tiles
+      // than the plan's parallelism target
+      const long units = F * ((d2 + 15) / 16);
+      const long per = tile_units(d1, d2, F, target, (int)ks.size());
+      const long tiles_all = (units + per - 1) / per;
+      const int nchunk = (int)std::min<long>((long)ks.size(),
+                                             std::max<long>(1, (P.par_target + tiles_all - 1) / tiles_all));
+      const size_t cper = (ks.size() + nchunk - 1) / nchunk;
+      for (size_t a = 0; a < ks.size(); a += cper) {
+        const size_t b = std::min(ks.size(), a + cper);
+        const size_t s0 = next;
+        const int first = (int)G.terms.size();
+        for (size_t i = a; i < b; ++i) {
+          slab[ks[i]] = next++;
+          TermRef tr{};
+          tr.cre = 1;
+          tr.slot = -1;
+          tr.A = items[ks[i]].A;
+          tr.B = items[ks[i]].B;
+          term_index(tr);
+        }
+        ApplyGroup ag{};
+        ag.X = core(node);
+        ag.Y = ws(P.ws_envscr + s0 * Pn * P.tsz);
+        ag.terms = (const TermRef*)tagp(TAG_TERM, first);
+        ag.in_fp64 = 1;
+        ag.n_terms = (int)(b - a);
+        ag.per_term_out = 1;
+        ag.d1 = d1;
+        ag.d2 = d2;
+        ag.P1 = (int)prod(dims, l1 + 1, l2);
+        ag.P2 = (int)prod(dims, l2 + 1, (int)dims.size());
+        ag.F = (int)F;
+        ag.rel = 0;
+        G.groups.push_back(ag);
+        add_tiles((int)G.groups.size() - 1 - gfirst, d1, d2, F, target, ag.n_terms);
+      }
+    }
+    return slab;
   }
 
   void emit_qr(int node, int leg, int transposeR) {

@@ -33,6 +33,8 @@ struct ApplyGroup {
   int drive_ld;        // row length of the drive table
   int rel;             // stage time index relative to the step (0..4)
   int accumulate;      // 1: Y += result, 0: Y = result
+  int per_term_out;    // 1: term m writes its own result to Y + m * F*d1*d2 (no sum)
+  int pad_;
 };
 
 // A tile of the apply kernel: a range of units of one group.  A unit is one
@@ -45,6 +47,9 @@ struct ApplyTile {
 };
 
 // Weighted sum of matrices: out = sum_i coef_i(t) * M_i (single-leg terms).
+// Largest number of terms one presum sums (its descriptors are staged in LDS).
+constexpr int PRESUM_MAX_TERMS = 512;
+
 struct PresumOp {
   void* out;           // compute precision, dim x dim
   const TermRef* terms;  // uses cre/cim/slot and A
