@@ -125,9 +125,10 @@ void tenso_plan_destroy(tenso_plan* p);
  * tenso_plan_set_graph: enable (default) or disable replaying tenso_step_fixed
  * steps from a captured HIP graph; disabled, every step launches its kernels
  * one by one (results are identical either way).
- * tenso_plan_set_tile_work: flops per apply-kernel tile (default 16e6; range
- * [1e5, 1e9], EINVAL outside); takes effect at the next build of the plan's
- * programs, i.e. the next step call. */
+ * tenso_plan_set_tile_work: flops per apply-kernel tile (default 16e6 for a
+ * plan stepped alone, 64e6 inside a batch unless set here; range [1e5, 1e9],
+ * EINVAL outside); takes effect at the next build of the plan's programs,
+ * i.e. the next step call. */
 int tenso_plan_set_graph(tenso_plan* p, int enable);
 int tenso_plan_set_tile_work(tenso_plan* p, double flops);
 

@@ -357,6 +357,7 @@ struct tenso_plan {
   int par_target = 64;  // tiles wanted per apply (single-instance latency)
   int built_target = -1;  // par_target the cached programs were built with
   double tile_work = 16e6;        // flops per apply tile
+  bool tile_work_set = false;     // set by the caller (else batches use their default)
   double built_tile_work = -1;    // tile_work the cached programs were built with
   // compiled programs (host descriptors with tagged pointers, device copies)
   std::unique_ptr<Program> prog_step, prog_init;
@@ -2001,6 +2002,7 @@ int tenso_plan_set_tile_work(tenso_plan* p, double flops) {
     if (!p) fail(TENSO_EINVAL, "null plan");
     if (!(flops >= 1e5 && flops <= 1e9)) fail(TENSO_EINVAL, "tile work outside [1e5, 1e9] flops");
     p->tile_work = flops;
+    p->tile_work_set = true;
   });
 }
 
@@ -2253,6 +2255,9 @@ static void batch_build(tenso_batch& B, hipStream_t s) {
   for (size_t i = 0; i < n; ++i) {
     tenso_plan& P = *B.plans[i];
     P.par_target = 4;  // the batch supplies the parallelism
+    // larger tiles in batches: fewer stagings of each term's operands (the
+    // tile-size autotuner settles on this value for a 512-instance batch)
+    if (!P.tile_work_set) P.tile_work = 64e6;
     if (!P.prog_step || P.built_target != P.par_target || P.built_tile_work != P.tile_work) {
       P.prog_step = std::make_unique<Program>();
       P.prog_init = std::make_unique<Program>();
@@ -2459,7 +2464,10 @@ int tenso_batch_autotune(tenso_batch* b, const double* dt, int trial_steps,
     double best = -1, best_ms = 0;
     try {
       for (double w : cand) {
-        for (auto* P : b->plans) P->tile_work = w;
+        for (auto* P : b->plans) {
+          P->tile_work = w;
+          P->tile_work_set = true;
+        }
         batch_advance(b, dt, trial_steps, d_drive_tabs, s);  // build, capture, warm up
         copy_states(false);
         hipchk(hipEventRecord(e0, s), "hipEventRecord");
