@@ -1179,10 +1179,110 @@ __device__ inline long gram_div(long n, long d, double dinv) {
   return q;
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) k_gram(const GramOp* __restrict__ ops) {
+// Workgroups are dealt to the 8 XCDs (each with its own L2) in turn by
+// block index.  Consecutive ops of a launch usually read the same core, so
+// block b runs op (b % 8) * per + b / 8: a run of `per` consecutive ops stays
+// on one XCD and shares its L2.  The grid has 8 * per blocks; blocks past
+// the last op exit.
+constexpr int N_XCD = 8;
+__device__ inline int xcd_op(int b, int n) {
+  const int per = (n + N_XCD - 1) / N_XCD;
+  return (b % N_XCD) * per + b / N_XCD;
+}
+
+// Gram product for r <= 32 (NB = 1 or 2 row tiles): K is split across the
+// four wavefronts, each accumulating every output tile over its quarter (the
+// operand rows of a k-step are loaded once and serve NB x NB tiles); the
+// partials are summed through LDS.
+template <typename T, int NB>
+__device__ void gram_small(const GramOp& op, long K, long Ppost, double pinv, gp<const double> Cm,
+                           gp<const T> Tm, gp<T> E, T* red /* [4][NB*NB][2][256] */) {
   typedef typename MT<T>::v4 v4;
-  const GramOp op = ops[blockIdx.x];
+  const int r = op.r;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c = lane & 15, g = lane >> 4;
+  constexpr int KU = 4;
+  const long kq = 16 * ((K + 63) / 64);  // multiple of 4 * KU
+  const long k0 = wave * kq, k1 = k0 + kq < K ? k0 + kq : K;
+  v4 accr[NB * NB], acci[NB * NB];
+#pragma unroll
+  for (int t = 0; t < NB * NB; ++t) {
+    accr[t] = v4{0, 0, 0, 0};
+    acci[t] = v4{0, 0, 0, 0};
+  }
+  struct Opnd {
+    T ar[NB], ai[NB], br[NB], bi[NB];
+  };
+  auto load = [&](long kb, Opnd (&o)[KU]) {
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+      const long k = kb + 4 * u + g;
+#pragma unroll
+      for (int t = 0; t < NB; ++t) o[u].ar[t] = o[u].ai[t] = o[u].br[t] = o[u].bi[t] = 0;
+      if (k < k1) {
+        const long pre = gram_div(k, Ppost, pinv), post = k - pre * Ppost;
+        const long base = pre * r * Ppost + post;
+#pragma unroll
+        for (int t = 0; t < NB; ++t) {
+          const int row = 16 * t + c;
+          if (row < r) {
+            const long o2 = base + (long)row * Ppost;
+            o[u].ar[t] = (T)Cm[2 * o2];
+            o[u].ai[t] = -(T)Cm[2 * o2 + 1];  // conj(C)
+            o[u].br[t] = Tm[2 * o2];
+            o[u].bi[t] = Tm[2 * o2 + 1];
+          }
+        }
+      }
+    }
+  };
+  Opnd cur[KU], nxt[KU];
+  if (k0 < k1) load(k0, cur);
+  for (long kb = k0; kb < k1; kb += 4 * KU) {
+    if (kb + 4 * KU < k1) load(kb + 4 * KU, nxt);
+#pragma unroll
+    for (int u = 0; u < KU; ++u)
+#pragma unroll
+      for (int ti = 0; ti < NB; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < NB; ++tj)
+          cmma<T>(accr[ti * NB + tj], acci[ti * NB + tj], cur[u].ar[ti], cur[u].ai[ti], cur[u].br[tj],
+                  cur[u].bi[tj]);
+#pragma unroll
+    for (int u = 0; u < KU; ++u) cur[u] = nxt[u];
+  }
+#pragma unroll
+  for (int t = 0; t < NB * NB; ++t)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = MT<T>::drow(g, q) * 16 + c;
+      red[((wave * NB * NB + t) * 2 + 0) * 256 + e] = accr[t][q];
+      red[((wave * NB * NB + t) * 2 + 1) * 256 + e] = acci[t][q];
+    }
+  __syncthreads();
+  for (int e = threadIdx.x; e < NB * NB * 256; e += 256) {
+    const int t = e / 256, w = e % 256;
+    T sr = 0, si = 0;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      sr += red[((p * NB * NB + t) * 2 + 0) * 256 + w];
+      si += red[((p * NB * NB + t) * 2 + 1) * 256 + w];
+    }
+    const int ti = t / NB, tj = t % NB;
+    const int row = 16 * ti + w / 16, col = 16 * tj + w % 16;
+    if (row < r && col < r) {
+      E[2 * ((long)row * r + col)] = sr;
+      E[2 * ((long)row * r + col) + 1] = si;
+    }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_gram(const GramOp* __restrict__ ops, int n_ops) {
+  typedef typename MT<T>::v4 v4;
+  const int oi = xcd_op(blockIdx.x, n_ops);
+  if (oi >= n_ops) return;
+  const GramOp op = ops[oi];
   const int r = op.r;
   const long K = (long)op.Ppre * op.Ppost;
   const long Ppost = op.Ppost;
@@ -1190,6 +1290,12 @@ __global__ void __launch_bounds__(256) k_gram(const GramOp* __restrict__ ops) {
   const gp<const T> Tm = gmem(reinterpret_cast<const T*>(op.T));
   const gp<const double> Cm = gmem(op.C);
   const gp<T> E = gmem(reinterpret_cast<T*>(op.E));
+  if (r <= 32) {  // uniform per block
+    __shared__ T red_small[4 * 4 * 2 * 256];
+    if (r <= 16) gram_small<T, 1>(op, K, Ppost, pinv, Cm, Tm, E, red_small);
+    else gram_small<T, 2>(op, K, Ppost, pinv, Cm, Tm, E, red_small);
+    return;
+  }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int c = lane & 15, g = lane >> 4;
   const int nb = (r + 15) >> 4, nt = nb * nb;
@@ -1756,8 +1862,9 @@ hipError_t launch_absorb(const AbsorbOp* ops, const void* tiles, int n_tiles, si
 
 hipError_t launch_gram(int fp64, const GramOp* ops, int n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  if (fp64) hipLaunchKernelGGL(k_gram<double>, dim3(n), dim3(256), 0, s, ops);
-  else hipLaunchKernelGGL(k_gram<float>, dim3(n), dim3(256), 0, s, ops);
+  const int blocks = N_XCD * ((n + N_XCD - 1) / N_XCD);
+  if (fp64) hipLaunchKernelGGL(k_gram<double>, dim3(blocks), dim3(256), 0, s, ops, n);
+  else hipLaunchKernelGGL(k_gram<float>, dim3(blocks), dim3(256), 0, s, ops, n);
   return hipGetLastError();
 }
 
