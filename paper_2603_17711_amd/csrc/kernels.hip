@@ -582,7 +582,7 @@ __device__ inline int qr_div(int n, int d, double dinv) {
 // H_p ... H_{p+pb-1} = I - V T V^H.  Reflectors, taus and the rank rule are
 // those of the column-by-column algorithm; only the rounding order of the
 // updates differs.
-//   Thread t owns rows p + t + 256 j of each panel and keeps them in
+//   Thread t owns rows p + t + QR_NT j of each panel and keeps them in
 // registers.  Panel column jj needs one block reduction, of |x|^2 and of the
 // raw products x^H a_c for the later panel columns (then
 // v^H a_c = a_c[jj] + conj(1 / (alpha - beta)) x^H a_c); every thread derives
@@ -592,10 +592,12 @@ __device__ inline int qr_div(int n, int d, double dinv) {
 //   Column updates: the explicit reflectors go to LDS; one wavefront per
 // column holds the column's rows in registers (QR_RPL per lane), forms
 // w = V^H x with a wave reduction and writes x - V (S w).
+constexpr int QR_NT = 512;               // threads per QR (8 wavefronts)
+constexpr int QR_NW = QR_NT / 64;
 constexpr int QR_PB = 4;                 // panel width
 constexpr int QR_RPL = 16;               // rows per lane of a column update
-constexpr int QR_RPT = 4;                // panel rows per thread
-constexpr int QR_MAX_M = 64 * QR_RPL;    // 1024 = 256 * QR_RPT
+constexpr int QR_RPT = 2;                // panel rows per thread
+constexpr int QR_MAX_M = 64 * QR_RPL;    // 1024 = QR_NT * QR_RPT
 constexpr int QR_NPAIR = QR_PB * (QR_PB - 1) / 2;
 
 // x <- (I - V S V^H) x for one column, x[r] at X[off[q]] for r = q * 64 + lane
@@ -673,7 +675,7 @@ __device__ inline void qr_apply_col(const z2* __restrict__ Lv, int mp, int pb,
 __device__ void qr_unblocked(const QrOp& op) {
   const int m = op.m, n = op.n, k = m < n ? m : n;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  __shared__ double red[8];  // [0..3] column norms, [4..7] Frobenius norm
+  __shared__ double red[2 * QR_NW];  // [0, NW) column norms, [NW, 2 NW) Frobenius norm
   __shared__ double sh_tau[2], sh_scale[2], sh_beta[2];
   __shared__ int sh_skip;
   const gp<z2> V = gmem(reinterpret_cast<z2*>(op.V));  // column-major m x n
@@ -684,21 +686,23 @@ __device__ void qr_unblocked(const QrOp& op) {
     return (long)pre * n * op.Ppost + (long)col * op.Ppost + post;
   };
   double fro = 0;
-  for (long e = tid; e < (long)m * n; e += 256) {
+  for (long e = tid; e < (long)m * n; e += QR_NT) {
     const int row = e % m, col = e / m;
     const z2 v = C[cidx(row, col)];
     V[e] = v;
     fro += v.r * v.r + v.i * v.i;
   }
   fro = wave_sum(fro);
-  if (lane == 0) red[4 + wave] = fro;
+  if (lane == 0) red[QR_NW + wave] = fro;
   __syncthreads();
   // residual columns at or below this squared norm count as exact zeros
-  const double thr2 = QR_RANK_TOL * QR_RANK_TOL * (red[4] + red[5] + red[6] + red[7]);
+  double fsum = 0;
+  for (int w = 0; w < QR_NW; ++w) fsum += red[QR_NW + w];
+  const double thr2 = QR_RANK_TOL * QR_RANK_TOL * fsum;
   for (int j = 0; j < k; ++j) {
     // xnorm of V[j+1:m, j]
     double s = 0;
-    for (int i = j + 1 + tid; i < m; i += 256) {
+    for (int i = j + 1 + tid; i < m; i += QR_NT) {
       z2 v = V[(long)j * m + i];
       s += v.r * v.r + v.i * v.i;
     }
@@ -706,7 +710,8 @@ __device__ void qr_unblocked(const QrOp& op) {
     if (lane == 0) red[wave] = s;
     __syncthreads();
     if (tid == 0) {
-      const double xn2 = red[0] + red[1] + red[2] + red[3];
+      double xn2 = 0;
+      for (int w = 0; w < QR_NW; ++w) xn2 += red[w];
       const z2 alpha = V[(long)j * m + j];
       if (alpha.r * alpha.r + alpha.i * alpha.i + xn2 <= thr2) {
         sh_skip = 2;  // numerically zero residual: identity reflector, zero column
@@ -735,16 +740,16 @@ __device__ void qr_unblocked(const QrOp& op) {
     }
     __syncthreads();
     if (sh_skip == 2) {
-      for (int i = j + tid; i < m; i += 256) V[(long)j * m + i] = z2{0, 0};
+      for (int i = j + tid; i < m; i += QR_NT) V[(long)j * m + i] = z2{0, 0};
     }
     if (!sh_skip) {
       const z2 sc{sh_scale[0], sh_scale[1]};
-      for (int i = j + 1 + tid; i < m; i += 256) V[(long)j * m + i] = zmul(V[(long)j * m + i], sc);
+      for (int i = j + 1 + tid; i < m; i += QR_NT) V[(long)j * m + i] = zmul(V[(long)j * m + i], sc);
       if (tid == 0) V[(long)j * m + j] = z2{sh_beta[0], 0.0};
       __syncthreads();
       // apply H^H = I - conj(tau) v v^H to columns j+1..n-1
       const z2 ct{sh_tau[0], -sh_tau[1]};
-      for (int col = j + 1 + wave; col < n; col += 4) {
+      for (int col = j + 1 + wave; col < n; col += QR_NW) {
         double wr = 0, wi = 0;
         for (int i = j + lane; i < m; i += 64) {
           const z2 v = i == j ? z2{1.0, 0.0} : V[(long)j * m + i];
@@ -768,7 +773,7 @@ __device__ void qr_unblocked(const QrOp& op) {
   }
   // R (n x n upper; rows >= k zero) into op.R, before Q overwrites V
   const gp<z2> R = gmem(reinterpret_cast<z2*>(op.R));
-  for (int e = tid; e < n * n; e += 256) {
+  for (int e = tid; e < n * n; e += QR_NT) {
     const int i = e / n, col = e % n;
     z2 v = (i <= col && i < k) ? V[(long)col * m + i] : z2{0, 0};
     if (op.transposeR) R[(long)col * n + i] = v;
@@ -780,7 +785,7 @@ __device__ void qr_unblocked(const QrOp& op) {
   for (int i = k - 1; i >= 0; --i) {
     const z2 t = tau[i];
     if (i < nq - 1) {
-      for (int col = i + 1 + wave; col < nq; col += 4) {
+      for (int col = i + 1 + wave; col < nq; col += QR_NW) {
         double wr = 0, wi = 0;
         for (int r = i + lane; r < m; r += 64) {
           const z2 v = r == i ? z2{1.0, 0.0} : V[(long)i * m + r];
@@ -800,13 +805,13 @@ __device__ void qr_unblocked(const QrOp& op) {
       }
     }
     __syncthreads();
-    for (int r = i + 1 + tid; r < m; r += 256) {
+    for (int r = i + 1 + tid; r < m; r += QR_NT) {
       const z2 v = V[(long)i * m + r];
       const z2 p = zmul(t, v);
       V[(long)i * m + r] = z2{-p.r, -p.i};
     }
     if (tid == 0) V[(long)i * m + i] = z2{1.0 - t.r, -t.i};
-    for (int r = tid; r < i; r += 256) V[(long)i * m + r] = z2{0, 0};
+    for (int r = tid; r < i; r += QR_NT) V[(long)i * m + r] = z2{0, 0};
     __syncthreads();
   }
   // phases: make diag(R) real non-negative
@@ -819,13 +824,13 @@ __device__ void qr_unblocked(const QrOp& op) {
     ph[2 * j + 1] = a > 0 ? d.i / a : 0.0;
   }
   __syncthreads();
-  for (int e = tid; e < n * n; e += 256) {
+  for (int e = tid; e < n * n; e += QR_NT) {
     const int i = e / n, col = e % n;
     const z2 cph{ph[2 * i], -ph[2 * i + 1]};
     const long o = op.transposeR ? (long)col * n + i : (long)i * n + col;
     R[o] = zmul(cph, R[o]);
   }
-  for (long e = tid; e < (long)m * n; e += 256) {
+  for (long e = tid; e < (long)m * n; e += QR_NT) {
     const int row = e % m, col = e / m;
     z2 q = col < nq ? zmul(V[(long)col * m + row], z2{ph[2 * col], ph[2 * col + 1]}) : z2{0, 0};
     C[cidx(row, col)] = q;
@@ -833,7 +838,7 @@ __device__ void qr_unblocked(const QrOp& op) {
 }
 
 
-__global__ void __launch_bounds__(256, 2) k_qr(const QrOp* __restrict__ ops) {
+__global__ void __launch_bounds__(QR_NT) k_qr(const QrOp* __restrict__ ops) {
   const QrOp op = ops[blockIdx.x];
   if (op.m > QR_MAX_M) {
     qr_unblocked(op);
@@ -842,7 +847,7 @@ __global__ void __launch_bounds__(256, 2) k_qr(const QrOp* __restrict__ ops) {
   const int m = op.m, n = op.n, k = m < n ? m : n;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   constexpr int NRED = 2 * QR_PB + 2 * QR_NPAIR;  // per-wave partial sums
-  __shared__ double red[2][4][NRED];              // double-buffered
+  __shared__ double red[2][QR_NW][NRED];          // double-buffered
   __shared__ z2 rowjj[2][QR_PB];                  // row jj of the panel, copied by its owner
   __shared__ z2 S[QR_PB * QR_PB];                 // T^H (factoring) or T (forming Q)
   __shared__ z2 tauL[64];
@@ -862,7 +867,7 @@ __global__ void __launch_bounds__(256, 2) k_qr(const QrOp* __restrict__ ops) {
 
   // C -> V and the Frobenius norm
   double fro = 0;
-  for (int row = tid; row < m; row += 256) {
+  for (int row = tid; row < m; row += QR_NT) {
     const int cb = crow(row);
     for (int c0 = 0; c0 < n; c0 += 8) {
       z2 t[8];
@@ -880,8 +885,9 @@ __global__ void __launch_bounds__(256, 2) k_qr(const QrOp* __restrict__ ops) {
   if (lane == 0) red[0][wave][0] = fro;
   __syncthreads();
   // residual columns at or below this squared norm count as exact zeros
-  const double thr2 =
-      QR_RANK_TOL * QR_RANK_TOL * (red[0][0][0] + red[0][1][0] + red[0][2][0] + red[0][3][0]);
+  double fsum = 0;
+  for (int w = 0; w < QR_NW; ++w) fsum += red[0][w][0];
+  const double thr2 = QR_RANK_TOL * QR_RANK_TOL * fsum;
   const int nbk = (k + QR_PB - 1) / QR_PB;
   int par = 1;
 
@@ -898,7 +904,7 @@ __global__ void __launch_bounds__(256, 2) k_qr(const QrOp* __restrict__ ops) {
         ph[2 * tid + 1] = a > 0 ? dd.i / a : 0.0;
       }
       __syncthreads();
-      for (int e = tid; e < n * n; e += 256) {
+      for (int e = tid; e < n * n; e += QR_NT) {
         const int i = e / n, c = e % n;
         const z2 v = (i <= c && i < k) ? zmul(z2{ph[2 * i], -ph[2 * i + 1]}, V[c * m + i])
                                        : z2{0.0, 0.0};
@@ -906,16 +912,16 @@ __global__ void __launch_bounds__(256, 2) k_qr(const QrOp* __restrict__ ops) {
         else R[i * n + c] = v;
       }
       // Q starts as the first k unit columns
-      for (int row = tid; row < m; row += 256) {
+      for (int row = tid; row < m; row += QR_NT) {
         const int cb = crow(row);
         for (int c = 0; c < k; ++c) C[cb + c * ppost] = z2{row == c ? 1.0 : 0.0, 0.0};
       }
     }
-    // own panel rows (relative row tid + 256 j) into registers
+    // own panel rows (relative row tid + QR_NT j) into registers
     z2 P[QR_RPT][QR_PB];
 #pragma unroll
     for (int j = 0; j < QR_RPT; ++j) {
-      const int row = tid + 256 * j;
+      const int row = tid + QR_NT * j;
 #pragma unroll
       for (int c = 0; c < QR_PB; ++c)
         P[j][c] = row < mp && c < pb ? V[(p + c) * m + p + row] : z2{0.0, 0.0};
@@ -929,7 +935,7 @@ __global__ void __launch_bounds__(256, 2) k_qr(const QrOp* __restrict__ ops) {
         for (int c = 0; c < 2 * QR_PB; ++c) d[c] = 0;
 #pragma unroll
         for (int j = 0; j < QR_RPT; ++j) {
-          if (tid + 256 * j <= jj) continue;  // rows past mp hold zeros
+          if (tid + QR_NT * j <= jj) continue;  // rows past mp hold zeros
           const z2 x = P[j][jj];
           d[0] = fma(x.r, x.r, fma(x.i, x.i, d[0]));
 #pragma unroll
@@ -959,14 +965,15 @@ __global__ void __launch_bounds__(256, 2) k_qr(const QrOp* __restrict__ ops) {
           }
         }
         __syncthreads();
-        const double xn2 = red[par][0][0] + red[par][1][0] + red[par][2][0] + red[par][3][0];
+        double xn2 = 0;
+        for (int w = 0; w < QR_NW; ++w) xn2 += red[par][w][0];
         const z2 alpha = rowjj[par][jj];
         z2 t{0.0, 0.0};
         if (alpha.r * alpha.r + alpha.i * alpha.i + xn2 <= thr2) {
           // numerically zero residual: identity reflector, zero column
 #pragma unroll
           for (int j = 0; j < QR_RPT; ++j)
-            if (tid + 256 * j >= jj) P[j][jj] = z2{0.0, 0.0};
+            if (tid + QR_NT * j >= jj) P[j][jj] = z2{0.0, 0.0};
         } else if (!(xn2 == 0.0 && alpha.i == 0.0)) {
           const double nrm = sqrt(alpha.r * alpha.r + alpha.i * alpha.i + xn2);
           // beta = -sign(Re alpha) * nrm (LAPACK zlarfg; a zero counts as positive)
@@ -979,16 +986,18 @@ __global__ void __launch_bounds__(256, 2) k_qr(const QrOp* __restrict__ ops) {
           z2 f[QR_PB];
 #pragma unroll
           for (int c = jj + 1; c < QR_PB; ++c) {
-            const z2 D{red[par][0][2 * c] + red[par][1][2 * c] + red[par][2][2 * c] + red[par][3][2 * c],
-                       red[par][0][2 * c + 1] + red[par][1][2 * c + 1] + red[par][2][2 * c + 1] +
-                           red[par][3][2 * c + 1]};
+            z2 D{0.0, 0.0};
+            for (int w = 0; w < QR_NW; ++w) {
+              D.r += red[par][w][2 * c];
+              D.i += red[par][w][2 * c + 1];
+            }
             const z2 cd = zmul(z2{sc.r, -sc.i}, D);
             const z2 a0 = rowjj[par][c];
             f[c] = zmul(ct, z2{a0.r + cd.r, a0.i + cd.i});
           }
 #pragma unroll
           for (int j = 0; j < QR_RPT; ++j) {
-            const int row = tid + 256 * j;
+            const int row = tid + QR_NT * j;
             if (row < jj) continue;
             const z2 v = row == jj ? z2{1.0, 0.0} : zmul(P[j][jj], sc);
 #pragma unroll
@@ -1008,7 +1017,7 @@ __global__ void __launch_bounds__(256, 2) k_qr(const QrOp* __restrict__ ops) {
       // factored panel (R entries and reflectors) back to V
 #pragma unroll
       for (int j = 0; j < QR_RPT; ++j) {
-        const int row = tid + 256 * j;
+        const int row = tid + QR_NT * j;
         if (row < mp) {
 #pragma unroll
           for (int c = 0; c < QR_PB; ++c)
@@ -1025,7 +1034,7 @@ __global__ void __launch_bounds__(256, 2) k_qr(const QrOp* __restrict__ ops) {
       for (int e = 0; e < 2 * QR_NPAIR; ++e) g[e] = 0;
 #pragma unroll
       for (int j = 0; j < QR_RPT; ++j) {
-        const int row = tid + 256 * j;
+        const int row = tid + QR_NT * j;
 #pragma unroll
         for (int c = 0; c < QR_PB; ++c) {
           if (row == c) P[j][c] = z2{1.0, 0.0};
@@ -1068,8 +1077,11 @@ __global__ void __launch_bounds__(256, 2) k_qr(const QrOp* __restrict__ ops) {
 #pragma unroll
             for (int l = 0; l < j; ++l) {
               const int o = 2 * QR_PB + 2 * (e0 + l);
-              y[l] = z2{red[par][0][o] + red[par][1][o] + red[par][2][o] + red[par][3][o],
-                        red[par][0][o + 1] + red[par][1][o + 1] + red[par][2][o + 1] + red[par][3][o + 1]};
+              y[l] = z2{0.0, 0.0};
+              for (int w = 0; w < QR_NW; ++w) {
+                y[l].r += red[par][w][o];
+                y[l].i += red[par][w][o + 1];
+              }
             }
 #pragma unroll
             for (int i = 0; i < j; ++i) {
@@ -1108,7 +1120,7 @@ __global__ void __launch_bounds__(256, 2) k_qr(const QrOp* __restrict__ ops) {
         off[q] = qq * xcs + (row - qq * xp);
       }
       const bool last = !fact && bk == 0;  // the final Q update also applies the phases
-      for (int cc = c0 + wave; cc < c1; cc += 4) {
+      for (int cc = c0 + wave; cc < c1; cc += QR_NW) {
         const z2 phc = last ? z2{ph[2 * cc], ph[2 * cc + 1]} : z2{1.0, 0.0};
         qr_apply_col(L, mp, pb, S, X + cc * xp, off, phc, lane);
       }
@@ -1848,7 +1860,7 @@ hipError_t launch_qr(const QrOp* ops, int n, hipStream_t s) {
                               QR_MAX_M * QR_PB * 16);
     attr = true;
   }
-  hipLaunchKernelGGL(k_qr, dim3(n), dim3(256), QR_MAX_M * QR_PB * 16, s, ops);
+  hipLaunchKernelGGL(k_qr, dim3(n), dim3(QR_NT), QR_MAX_M * QR_PB * 16, s, ops);
   return hipGetLastError();
 }
 
