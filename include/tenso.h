@@ -222,6 +222,13 @@ void tenso_batch_destroy(tenso_batch* b);
 /* Graph replay of batched steps on (default) or off; results are identical. */
 int tenso_batch_set_graph(tenso_batch* b, int enable);
 
+/* Independent parts of a batched step (1..4, default 4; EINVAL outside):
+ * instances sorted by step work are cut into parts of about equal work, each
+ * part a phase-merged launch sequence of its own; in graph replay the parts
+ * are parallel branches of one graph (eager steps run them in turn).  Results
+ * are identical for every part count.  Takes effect at the next step call. */
+int tenso_batch_set_parts(tenso_batch* b, int n_parts);
+
 /* Bytes of a buffer that holds every instance's state (each 256-byte aligned). */
 int tenso_batch_state_bytes(const tenso_batch* b, size_t* bytes);
 

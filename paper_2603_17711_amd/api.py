@@ -257,6 +257,10 @@ class Batch:
         """Replay batched steps from a captured HIP graph (default) or launch eagerly."""
         check(lib().tenso_batch_set_graph(self.h, int(bool(enable))))
 
+    def set_parts(self, n_parts):
+        """Independent parts of a step (1..4), parallel branches of the step graph."""
+        check(lib().tenso_batch_set_parts(self.h, int(n_parts)))
+
     def autotune(self, dts, trial_steps=2, drive_tabs=None):
         """Pick the fastest apply tile size for this batch (states are restored
         exactly); returns it in flops."""

@@ -314,10 +314,15 @@ static std::vector<PairCluster> cluster_pairs(const Recipe::G& g) {
 // graph is launched on the caller's stream.  The captured launches hold
 // device addresses bound at capture time: any re-upload of the program
 // resets the graph.
+// A step may consist of several independent programs (parts of a batch):
+// they are captured as parallel branches (fork from the capture stream, one
+// side stream per further part, join before the counter advance).
 struct StepGraph {
   bool enabled = true;
   hipGraphExec_t exec = nullptr;
   hipStream_t cap = nullptr;
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> ev;  // [0] fork, [k] join of part k
   void reset() {
     if (exec) (void)hipGraphExecDestroy(exec);
     exec = nullptr;
@@ -325,6 +330,8 @@ struct StepGraph {
   ~StepGraph() {
     reset();
     if (cap) (void)hipStreamDestroy(cap);
+    for (auto x : side) (void)hipStreamDestroy(x);
+    for (auto e : ev) (void)hipEventDestroy(e);
   }
 };
 
@@ -1578,12 +1585,30 @@ static void run(const DevProgram& D, int fp64, const int* ctr, hipStream_t s) {
 }
 
 // Capture one step (program launches, then the step-counter advance).
-static void capture_step(StepGraph& G, const DevProgram& D, int fp64, int* ctr) {
+static void capture_step(StepGraph& G, const std::vector<const DevProgram*>& parts, int fp64,
+                         int* ctr) {
   if (!G.cap) hipchk(hipStreamCreateWithFlags(&G.cap, hipStreamNonBlocking), "hipStreamCreate");
+  while (G.side.size() + 1 < parts.size()) {
+    hipStream_t x;
+    hipchk(hipStreamCreateWithFlags(&x, hipStreamNonBlocking), "hipStreamCreate");
+    G.side.push_back(x);
+  }
+  while (G.ev.size() < parts.size()) {
+    hipEvent_t e;
+    hipchk(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+    G.ev.push_back(e);
+  }
   hipGraph_t g = nullptr;
   hipchk(hipStreamBeginCapture(G.cap, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
   try {
-    run(D, fp64, ctr, G.cap);
+    if (parts.size() > 1) hipchk(hipEventRecord(G.ev[0], G.cap), "fork");
+    for (size_t k = 1; k < parts.size(); ++k) {
+      hipchk(hipStreamWaitEvent(G.side[k - 1], G.ev[0], 0), "fork wait");
+      run(*parts[k], fp64, ctr, G.side[k - 1]);
+      hipchk(hipEventRecord(G.ev[k], G.side[k - 1]), "join");
+    }
+    run(*parts[0], fp64, ctr, G.cap);
+    for (size_t k = 1; k < parts.size(); ++k) hipchk(hipStreamWaitEvent(G.cap, G.ev[k], 0), "join wait");
     hipchk(launch_step_inc(ctr, -1, G.cap), "ctr");
   } catch (...) {
     (void)hipStreamEndCapture(G.cap, &g);
@@ -1600,17 +1625,17 @@ static void capture_step(StepGraph& G, const DevProgram& D, int fp64, int* ctr) 
 // a fresh binding runs eagerly, which also performs the kernels' one-time
 // attribute setup outside any capture), eager launches otherwise or while
 // the apply kernels are being timed.
-static void step_loop(StepGraph& G, const DevProgram& D, int fp64, int* ctr, int n_steps,
-                      hipStream_t s) {
+static void step_loop(StepGraph& G, const std::vector<const DevProgram*>& parts, int fp64,
+                      int* ctr, int n_steps, hipStream_t s) {
   const bool use = G.enabled && !g_prof.on;
   for (int k = 0; k < n_steps; ++k) {
     if (use && G.exec) {
       hipchk(hipGraphLaunch(G.exec, s), "hipGraphLaunch");
       continue;
     }
-    run(D, fp64, ctr, s);
+    for (auto* D : parts) run(*D, fp64, ctr, s);  // eager: parts one after another
     hipchk(launch_step_inc(ctr, -1, s), "ctr");
-    if (use) capture_step(G, D, fp64, ctr);
+    if (use) capture_step(G, parts, fp64, ctr);
   }
 }
 
@@ -2142,7 +2167,7 @@ int tenso_step_fixed(tenso_plan* p, void* d_state, double t0, double dt, int n_s
     int* ctr = (int*)((char*)d_ws + p->ws_ctr);
     hipchk(launch_step_inc(ctr, 0, s), "ctr");
     run(*p->dev_init, p->fp64, ctr, s);
-    step_loop(p->graph, *p->dev_step, p->fp64, ctr, n_steps, s);
+    step_loop(p->graph, {p->dev_step.get()}, p->fp64, ctr, n_steps, s);
   });
 }
 
@@ -2241,8 +2266,15 @@ struct tenso_batch {
   int* ctr = nullptr;
   double* rho_buf = nullptr;
   std::vector<size_t> rho_off;
-  DevProgram step, init, rho;
+  DevProgram init, rho;
+  std::vector<std::unique_ptr<DevProgram>> steps;  // independent parts of one step
+  int n_parts = 4;                                 // parts requested
   StepGraph graph;
+  std::vector<const DevProgram*> step_parts() const {
+    std::vector<const DevProgram*> v;
+    for (auto& d : steps) v.push_back(d.get());
+    return v;
+  }
   ~tenso_batch() {
     if (ctr) (void)hipFree(ctr);
     if (rho_buf) (void)hipFree(rho_buf);
@@ -2252,6 +2284,7 @@ struct tenso_batch {
 static void batch_build(tenso_batch& B, hipStream_t s) {
   const size_t n = B.plans.size();
   std::vector<Program> st(n), in(n), rh(n);
+  std::vector<double> cost(n, 0.0);
   for (size_t i = 0; i < n; ++i) {
     tenso_plan& P = *B.plans[i];
     P.par_target = 4;  // the batch supplies the parallelism
@@ -2269,6 +2302,7 @@ static void batch_build(tenso_batch& B, hipStream_t s) {
     }
     st[i] = *P.prog_step;
     in[i] = *P.prog_init;
+    for (auto& L : st[i].launches) cost[i] += L.flops;
     Builder b(P, rh[i]);
     b.rho_prog();
     rh[i].rprogs.back().rho_out = (double*)((char*)B.rho_buf + B.rho_off[i]);
@@ -2276,8 +2310,32 @@ static void batch_build(tenso_batch& B, hipStream_t s) {
     resolve(in[i], B.states[i], B.wss[i], B.dts[i], B.drives[i], B.ld);
     resolve(rh[i], B.states[i], B.wss[i], B.dts[i], nullptr, 1);
   }
-  Program ms = merge_programs(st), mi = merge_programs(in), mr = merge_programs(rh);
-  upload_resolved(B.step, ms, s);
+  // Parts of the step: instances sorted by their step's apply work and cut
+  // into runs of about equal total work, so the few largest instances (long
+  // QR chains, small launches) share a part and run beside the rest.
+  std::vector<size_t> order(n);
+  for (size_t i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+  double total = 0;
+  for (double c : cost) total += c;
+  const int S = (int)std::max<size_t>(1, std::min<size_t>((size_t)B.n_parts, n));
+  std::vector<std::vector<Program>> parts(S);
+  double acc = 0;
+  int k = 0;
+  for (size_t j = 0; j < n; ++j) {
+    const size_t i = order[j];
+    if (k + 1 < S && !parts[k].empty() && acc >= total * (k + 1) / S) ++k;
+    parts[k].push_back(std::move(st[i]));
+    acc += cost[i];
+  }
+  B.steps.clear();
+  for (auto& pv : parts) {
+    if (pv.empty()) continue;
+    Program mp = merge_programs(pv);
+    B.steps.push_back(std::make_unique<DevProgram>());
+    upload_resolved(*B.steps.back(), mp, s);
+  }
+  Program mi = merge_programs(in), mr = merge_programs(rh);
   upload_resolved(B.init, mi, s);
   upload_resolved(B.rho, mr, s);
   B.graph.reset();
@@ -2300,7 +2358,7 @@ static void batch_advance(tenso_batch* b, const double* dt, int n_steps,
   const int ld = 4 * n_steps + 1;
   bool stale = false;
   for (auto* P : b->plans) stale = stale || P->built_tile_work != P->tile_work;
-  if (stale || dts != b->dts || drv != b->drives || ld != b->ld || !b->step.arena) {
+  if (stale || dts != b->dts || drv != b->drives || ld != b->ld || b->steps.empty()) {
     b->dts = dts;
     b->drives = drv;
     b->ld = ld;
@@ -2308,7 +2366,7 @@ static void batch_advance(tenso_batch* b, const double* dt, int n_steps,
   }
   hipchk(launch_step_inc(b->ctr, 0, s), "ctr");
   run(b->init, b->fp64, b->ctr, s);
-  step_loop(b->graph, b->step, b->fp64, b->ctr, n_steps, s);
+  step_loop(b->graph, b->step_parts(), b->fp64, b->ctr, n_steps, s);
 }
 
 extern "C" {
@@ -2363,7 +2421,7 @@ int tenso_batch_step_record(tenso_batch* b, const double* t0, const double* dt, 
     const int ld = 4 * n_steps + 1;
     bool stale = false;
     for (auto* P : b->plans) stale = stale || P->built_tile_work != P->tile_work;
-    if (stale || dts != b->dts || drv != b->drives || ld != b->ld || !b->step.arena) {
+    if (stale || dts != b->dts || drv != b->drives || ld != b->ld || b->steps.empty()) {
       b->dts = dts;
       b->drives = drv;
       b->ld = ld;
@@ -2378,7 +2436,7 @@ int tenso_batch_step_record(tenso_batch* b, const double* t0, const double* dt, 
     hipchk(hipMemcpyAsync((char*)d_series + (size_t)r++ * rec, b->rho_buf, rec,
                           hipMemcpyDeviceToDevice, s), "record");
     for (int k = 0; k < n_steps; ++k) {
-      step_loop(b->graph, b->step, b->fp64, b->ctr, 1, s);
+      step_loop(b->graph, b->step_parts(), b->fp64, b->ctr, 1, s);
       if ((k + 1) % every == 0) {
         run(b->rho, b->fp64, nullptr, s);
         hipchk(hipMemcpyAsync((char*)d_series + (size_t)r++ * rec, b->rho_buf, rec,
@@ -2413,6 +2471,16 @@ int tenso_batch_reduced_rho(tenso_batch* b, tenso_c128* const* h_rho, hipStream_
       const size_t M = b->plans[i]->tree.end_dim[0];
       memcpy(h_rho[i], h.data() + b->rho_off[i], M * M * 16);
     }
+  });
+}
+
+int tenso_batch_set_parts(tenso_batch* b, int n_parts) {
+  return guard([&] {
+    if (!b) fail(TENSO_EINVAL, "null batch");
+    if (n_parts < 1 || n_parts > 4) fail(TENSO_EINVAL, "n_parts must be in [1, 4]");
+    b->n_parts = n_parts;
+    b->steps.clear();  // rebuilt at the next step call
+    b->graph.reset();
   });
 }
 

@@ -32,16 +32,18 @@ def _other_work():
     return float(y)
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_batch_graph_replay_matches_eager(precision):
+@pytest.mark.parametrize("precision,parts", [(0, 4), (1, 4), (1, 1)])
+def test_batch_graph_replay_matches_eager(precision, parts):
     require_gpu()
     import torch
     from paper_2603_17711_amd import api
-    insts = _instances(5)
-    print(f"[graph batch] 5 instances precision={precision}", flush=True)
+    insts = _instances(7)
+    print(f"[graph batch] 7 instances precision={precision} parts={parts}", flush=True)
     ga = api.Batch([api.build_instance(i, precision=precision) for i in insts])
+    ga.set_parts(parts)
     eb = api.Batch([api.build_instance(i, precision=precision) for i in insts])
     eb.set_graph(False)
+    eb.set_parts(1)
     dts = [i.dt for i in insts]
     for rnd in range(4):
         ga.step(3, dts)
