@@ -606,7 +606,7 @@ constexpr int QR_NPAIR = QR_PB * (QR_PB - 1) / 2;
 // QR_PB in LDS, zero outside pb x pb; the result is scaled by ph.
 __device__ inline void qr_apply_col(const z2* __restrict__ Lv, int mp, int pb,
                                     const z2* __restrict__ S, gp<z2> __restrict__ X,
-                                    const int* off, z2 ph, int lane) {
+                                    const int* off, z2 ph, int lane, double* tail) {
   // reflectors i >= pb read column pb - 1; S has zero rows and columns there
   int ci[QR_PB];
 #pragma unroll
@@ -651,6 +651,7 @@ __device__ inline void qr_apply_col(const z2* __restrict__ Lv, int mp, int pb,
   double u[2 * QR_PB];
 #pragma unroll
   for (int e = 0; e < 2 * QR_PB; ++e) u[e] = readlane_d(uc, e);
+  double t2 = 0;  // squared norm of the result below the panel's rows
 #pragma unroll
   for (int q = 0; q < QR_RPL; ++q) {
     const int r = q * 64 + lane;
@@ -664,9 +665,14 @@ __device__ inline void qr_apply_col(const z2* __restrict__ Lv, int mp, int pb,
         ar = fma(-vv[i].r, u[2 * i], fma(vv[i].i, u[2 * i + 1], ar));
         ai = fma(-vv[i].r, u[2 * i + 1], fma(-vv[i].i, u[2 * i], ai));
       }
+      if (r >= pb) t2 = fma(ar, ar, fma(ai, ai, t2));
       X[off[q]] = zmul(z2{ar, ai}, ph);
     }
     if (q % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+  }
+  if (tail) {
+    t2 = wave_sum(t2);
+    if (lane == 0) *tail = t2;
   }
 }
 
@@ -851,6 +857,7 @@ __global__ void __launch_bounds__(QR_NT) k_qr(const QrOp* __restrict__ ops) {
   __shared__ z2 rowjj[2][QR_PB];                  // row jj of the panel, copied by its owner
   __shared__ z2 S[QR_PB * QR_PB];                 // T^H (factoring) or T (forming Q)
   __shared__ z2 tauL[64];
+  __shared__ double tailn[64];  // per column: squared norm below the last factored panel
   __shared__ double ph[2 * 64];
   extern __shared__ char smem_raw[];
   z2* __restrict__ L = reinterpret_cast<z2*>(smem_raw);  // explicit panel, (m - p) x pb
@@ -889,10 +896,12 @@ __global__ void __launch_bounds__(QR_NT) k_qr(const QrOp* __restrict__ ops) {
   for (int w = 0; w < QR_NW; ++w) fsum += red[0][w][0];
   const double thr2 = QR_RANK_TOL * QR_RANK_TOL * fsum;
   const int nbk = (k + QR_PB - 1) / QR_PB;
+  int nbf = nbk;  // panels actually factored (fewer after an early exit)
   int par = 1;
 
   for (int st = 0; st < 2 * nbk; ++st) {
     const bool fact = st < nbk;
+    if (fact && st >= nbf) continue;  // past an early exit (uniform)
     const int bk = fact ? st : 2 * nbk - 1 - st;
     const int p = bk * QR_PB, pb = min(QR_PB, k - p), mp = m - p;
     if (st == nbk) {
@@ -916,6 +925,10 @@ __global__ void __launch_bounds__(QR_NT) k_qr(const QrOp* __restrict__ ops) {
         const int cb = crow(row);
         for (int c = 0; c < k; ++c) C[cb + c * ppost] = z2{row == c ? 1.0 : 0.0, 0.0};
       }
+    }
+    if (!fact && bk >= nbf) {  // identity reflectors (all tau zero): nothing to apply
+      __syncthreads();
+      continue;
     }
     // own panel rows (relative row tid + QR_NT j) into registers
     z2 P[QR_RPT][QR_PB];
@@ -1122,10 +1135,29 @@ __global__ void __launch_bounds__(QR_NT) k_qr(const QrOp* __restrict__ ops) {
       const bool last = !fact && bk == 0;  // the final Q update also applies the phases
       for (int cc = c0 + wave; cc < c1; cc += QR_NW) {
         const z2 phc = last ? z2{ph[2 * cc], ph[2 * cc + 1]} : z2{1.0, 0.0};
-        qr_apply_col(L, mp, pb, S, X + cc * xp, off, phc, lane);
+        qr_apply_col(L, mp, pb, S, X + cc * xp, off, phc, lane, fact ? tailn + cc : nullptr);
       }
     }
     __syncthreads();
+    if (fact && c0 < c1) {
+      // Early exit by the rank rule: if every remaining column's norm below
+      // this panel is at or under the threshold, each of them would in turn
+      // be found numerically zero (identity reflectors change nothing, and a
+      // column's norm from its diagonal down is at most its norm from here
+      // down).  Do that at once: zero each from its diagonal down, tau = 0.
+      double mx = 0;
+      for (int cc = c0; cc < c1; ++cc) mx = fmax(mx, tailn[cc]);
+      if (mx <= thr2) {
+        for (int cc = c0; cc < c1; ++cc)
+          for (int row = cc + tid; row < m; row += QR_NT) V[cc * m + row] = z2{0.0, 0.0};
+        if (tid >= c0 && tid < k) {
+          tauL[tid] = z2{0.0, 0.0};
+          gmem(reinterpret_cast<z2*>(op.tau))[tid] = z2{0.0, 0.0};
+        }
+        nbf = st + 1;
+        __syncthreads();
+      }
+    }
   }
 }
 
