@@ -118,3 +118,17 @@ def test_drive_zero_coupling_matches_von_neumann():
         errs.append(trace_distance(P.rho(), ref))
     assert errs[1] < 1e-5
     assert 3.0 < errs[0] / errs[1] < 5.0
+
+
+def test_depth_convergence_trend():
+    """A too-shallow hierarchy misses bath memory: with the dense generator
+    (no tree truncation) the distance to a deep reference falls with depth."""
+    n = 150
+    ref_terms, ref_dims = spin_boson(12)
+    ref = dense_propagate(ref_terms, ref_dims, RHO0, 0.02, n, every=n)[-1]
+    errs = []
+    for depth in (2, 4, 7):
+        terms, dims = spin_boson(depth)
+        errs.append(trace_distance(dense_propagate(terms, dims, RHO0, 0.02, n, every=n)[-1], ref))
+    assert errs[0] > errs[1] > errs[2]
+
