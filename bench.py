@@ -101,15 +101,27 @@ def batch_main(a):
 
     tile_work = {"w": None}
 
+    from paper_2603_17711_amd._lib import TensoError
+
+    def advance(b, n):
+        # instances whose RK4 step is unstable at their dt diverge; the library
+        # flags them with ENUMERIC after completing every step, and they are
+        # counted below, not dropped
+        try:
+            b.step(n, dts)
+        except TensoError as e:
+            if e.code != "ENUMERIC":
+                raise
+
     def run_batch(precision, steps, warmup, tune=False):
         plans = [api.build_instance(i, precision=precision) for i in insts]
         b = api.Batch(plans)
         if tune:  # untimed set-up: pick the apply tile size for this batch
             tile_work["w"] = b.autotune(dts, trial_steps=2)
-        b.step(warmup, dts)
+        advance(b, warmup)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        b.step(steps, dts)
+        advance(b, steps)
         torch.cuda.synchronize()
         return plans, b, time.perf_counter() - t0
 
@@ -127,6 +139,14 @@ def batch_main(a):
                    "tile_size": "autotuned" if tile_work["w"] else "default"},
     }
     rho_mixed = batch.rho()
+    nonfinite = [i for i, f in enumerate(batch.status()) if f]
+    trace_off = [i for i, r in enumerate(rho_mixed)
+                 if i not in nonfinite and abs(np.trace(r).real - 1.0) > 1e-3]
+    out["diverged_instances"] = {
+        "non_finite": len(nonfinite), "trace_off_by_1e-3": len(trace_off),
+        "indices": (nonfinite + trace_off)[:32],
+        "note": "RK4 at the instance's dt: unstable in the FP64 oracle as well, or (the "
+                "rest) unstable under FP32-level rounding; flagged, not dropped"}
     del batch, plans
     torch.cuda.empty_cache()
     if not a.no_fp64:
@@ -159,11 +179,11 @@ def batch_main(a):
         for p in plans:
             p.set_tile_work(tile_work["w"])
     b = api.Batch(plans)
-    b.step(1, dts)
+    advance(b, 1)
     torch.cuda.synchronize()
     prof_steps = max(1, min(a.steps, 5))
     check(lib().tenso_profile(1))
-    b.step(prof_steps, dts)
+    advance(b, prof_steps)
     torch.cuda.synchronize()
     ms, n, fl, by = C.c_double(), C.c_int64(), C.c_double(), C.c_double()
     check(lib().tenso_profile_stats(C.byref(ms), C.byref(n), C.byref(fl), C.byref(by)))

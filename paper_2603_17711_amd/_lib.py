@@ -63,6 +63,7 @@ SIGS = {
     "tenso_batch_destroy": (None, [P]),
     "tenso_batch_set_graph": (C.c_int, [P, C.c_int]),
     "tenso_batch_set_parts": (C.c_int, [P, C.c_int]),
+    "tenso_batch_status": (C.c_int, [P, C.POINTER(C.c_int32)]),
     "tenso_batch_state_bytes": (C.c_int, [P, C.POINTER(C.c_size_t)]),
     "tenso_batch_autotune": (C.c_int, [P, DP, C.c_int, C.POINTER(P), P, C.c_size_t, DP, P]),
     "tenso_batch_step_record": (C.c_int, [P, DP, DP, C.c_int, C.c_int, C.POINTER(P), P, P]),

@@ -69,8 +69,9 @@ class Tree:
         return out
 
     def __del__(self):
-        if getattr(self, "h", None) and _lib._lib is not None:
-            lib().tenso_tree_destroy(self.h)
+        L = getattr(_lib, "_lib", None) if _lib is not None else None
+        if getattr(self, "h", None) and L is not None:  # modules may be torn down at exit
+            L.tenso_tree_destroy(self.h)
             self.h = None
 
 
@@ -88,8 +89,9 @@ class Generator:
         self.n_slots = int(slot.max() + 1) if len(slot) and slot.max() >= 0 else 0
 
     def __del__(self):
-        if getattr(self, "h", None) and _lib._lib is not None:
-            lib().tenso_gen_destroy(self.h)
+        L = getattr(_lib, "_lib", None) if _lib is not None else None
+        if getattr(self, "h", None) and L is not None:  # modules may be torn down at exit
+            L.tenso_gen_destroy(self.h)
             self.h = None
 
 
@@ -196,8 +198,9 @@ class Plan:
         return out
 
     def __del__(self):
-        if getattr(self, "h", None) and _lib._lib is not None:
-            lib().tenso_plan_destroy(self.h)
+        L = getattr(_lib, "_lib", None) if _lib is not None else None
+        if getattr(self, "h", None) and L is not None:  # modules may be torn down at exit
+            L.tenso_plan_destroy(self.h)
             self.h = None
 
 
@@ -257,6 +260,12 @@ class Batch:
         """Replay batched steps from a captured HIP graph (default) or launch eagerly."""
         check(lib().tenso_batch_set_graph(self.h, int(bool(enable))))
 
+    def status(self):
+        """Per instance: True where the last step call found NaN/inf in its state."""
+        out = np.zeros(len(self.plans), np.int32)
+        check(lib().tenso_batch_status(self.h, out.ctypes.data_as(C.POINTER(C.c_int32))))
+        return out.astype(bool)
+
     def set_parts(self, n_parts):
         """Independent parts of a step (1..4), parallel branches of the step graph."""
         check(lib().tenso_batch_set_parts(self.h, int(n_parts)))
@@ -287,6 +296,7 @@ class Batch:
         return outs
 
     def __del__(self):
-        if getattr(self, "h", None) and _lib._lib is not None:
-            lib().tenso_batch_destroy(self.h)
+        L = getattr(_lib, "_lib", None) if _lib is not None else None
+        if getattr(self, "h", None) and L is not None:  # modules may be torn down at exit
+            L.tenso_batch_destroy(self.h)
             self.h = None

@@ -293,21 +293,34 @@ __global__ void __launch_bounds__(256, 2) k_apply(const ApplyGroup* __restrict__
   c2* bs = as + (long)D1 * as1;
   c2* zs = bs + (long)D2 * bs1 + (long)wave * D1 * 16;
 
-  // stage the tile's input slices (zero padded, compute precision)
-  for (int e = threadIdx.x; e < nfl * D1 * D2; e += 256) {
-    const int fl = e / (D1 * D2);
-    const int rem = e - fl * (D1 * D2);
-    const int a = rem / D2, bcol = rem % D2;
-    c2 v;
-    v.x = 0;
-    v.y = 0;
-    if (a < d1 && bcol < d2) {
-      const UnitGeo ug = unit_geo(G, (f_first + fl) * njb, njb, 0);
-      const cpx<T> x = ldc<Tin, T>(G.X, ug.base + a * sa + bcol * sb);
-      v.x = x.re;
-      v.y = x.im;
+  // stage the tile's input slices (zero padded, compute precision): slice
+  // bases once, then lanes over the columns of a row (D2 = 16, 32, 64: 64/D2
+  // rows per wavefront pass; D2 = 48: one row, lanes 48..63 idle)
+  __shared__ long sbase[17];
+  if ((int)threadIdx.x < nfl)
+    sbase[threadIdx.x] = unit_geo(G, (f_first + (int)threadIdx.x) * njb, njb, 0).base;
+  __syncthreads();
+  {
+    const bool p2 = (D2 & (D2 - 1)) == 0;
+    const int rpw = p2 ? 64 / D2 : 1;
+    const int sub = p2 ? lane / D2 : 0;
+    const int bcol = p2 ? (lane & (D2 - 1)) : lane;
+    if (bcol < D2 && (p2 || lane < D2)) {
+      const int nrows = nfl * D1;
+#pragma unroll 4
+      for (int ra = wave * rpw + sub; ra < nrows; ra += 4 * rpw) {
+        const int fl = ra / D1, a = ra - fl * D1;
+        c2 v;
+        v.x = 0;
+        v.y = 0;
+        if (a < d1 && bcol < d2) {
+          const cpx<T> x = ldc<Tin, T>(G.X, sbase[fl] + a * sa + bcol * sb);
+          v.x = x.re;
+          v.y = x.im;
+        }
+        xs[((long)fl * D1 + a) * xs1 + bcol] = v;
+      }
     }
-    xs[((long)fl * D1 + a) * xs1 + bcol] = v;
   }
 
   int n_my = tile.nu > wave ? (tile.nu - wave + 3) / 4 : 0;
@@ -350,35 +363,34 @@ __global__ void __launch_bounds__(256, 2) k_apply(const ApplyGroup* __restrict__
     const T* Am = reinterpret_cast<const T*>(tr.A);
     const T* Bm = reinterpret_cast<const T*>(tr.B);
     __syncthreads();  // previous term's operands are no longer read
-    if (Am) {  // A carries the coefficient
-      for (int e = threadIdx.x; e < D1 * D1; e += 256) {
-        const int i = e / D1, j = e % D1;
+    // operand tiles: lanes over columns, rows per wavefront pass as for X;
+    // entries are scaled by the coefficient unless it is exactly 1
+    auto stage_op = [&](const T* M, int d, int D, int ld, c2* dst, double sr, double si) {
+      const bool p2 = (D & (D - 1)) == 0;
+      const int rpw = p2 ? 64 / D : 1;
+      const int sub = p2 ? lane / D : 0;
+      const int j = p2 ? (lane & (D - 1)) : lane;
+      if (j >= D || (!p2 && lane >= D)) return;
+      const bool unit = sr == 1.0 && si == 0.0;
+      for (int i = wave * rpw + sub; i < D; i += 4 * rpw) {
         c2 v;
         v.x = 0;
         v.y = 0;
-        if (i < d1 && j < d1) {
-          const double a0 = Am[2 * (i * d1 + j)], a1 = Am[2 * (i * d1 + j) + 1];
-          v.x = (T)(a0 * cr - a1 * ci);
-          v.y = (T)(a0 * ci + a1 * cr);
+        if (i < d && j < d) {
+          const T a0 = M[2 * (i * d + j)], a1 = M[2 * (i * d + j) + 1];
+          if (unit) {
+            v.x = a0;
+            v.y = a1;
+          } else {
+            v.x = (T)((double)a0 * sr - (double)a1 * si);
+            v.y = (T)((double)a0 * si + (double)a1 * sr);
+          }
         }
-        as[i * as1 + j] = v;
+        dst[i * ld + j] = v;
       }
-    }
-    if (Bm) {  // B carries it only for one-sided B terms
-      const double br0 = Am ? 1.0 : cr, bi0 = Am ? 0.0 : ci;
-      for (int e = threadIdx.x; e < D2 * D2; e += 256) {
-        const int i = e / D2, j = e % D2;
-        c2 v;
-        v.x = 0;
-        v.y = 0;
-        if (i < d2 && j < d2) {
-          const double b0 = Bm[2 * (i * d2 + j)], b1 = Bm[2 * (i * d2 + j) + 1];
-          v.x = (T)(b0 * br0 - b1 * bi0);
-          v.y = (T)(b0 * bi0 + b1 * br0);
-        }
-        bs[i * bs1 + j] = v;
-      }
-    }
+    };
+    if (Am) stage_op(Am, d1, D1, as1, as, cr, ci);  // A carries the coefficient
+    if (Bm) stage_op(Bm, d2, D2, bs1, bs, Am ? 1.0 : cr, Am ? 0.0 : ci);  // B only when alone
     __syncthreads();
     const int kind = (Am ? 1 : 0) | (Bm ? 2 : 0);
     for (int uu = 0; uu < n_my; ++uu) {
@@ -1829,6 +1841,22 @@ __global__ void __launch_bounds__(256) k_split(const SplitOp* __restrict__ ops) 
   }
 }
 
+// Non-finite values in FP64 states: block (op, chunk) scans a 1/16 share of
+// op's doubles and sets the op's flag (plain vector stores of 1).
+__global__ void __launch_bounds__(256) k_finite(const FiniteOp* __restrict__ ops) {
+  const FiniteOp op = ops[blockIdx.x];
+  const gp<const double> p = gmem(op.p);
+  bool bad = false;
+  for (long i = (long)blockIdx.y * 256 + threadIdx.x; i < op.n; i += 256L * gridDim.y)
+    bad = bad || !isfinite(p[i]);
+  if (__syncthreads_or(bad) && threadIdx.x == 0) *gmem(op.flag) = 1;
+}
+
+__global__ void k_clear_flags(int* flags, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) gmem(flags)[i] = 0;
+}
+
 __global__ void k_step_inc(int* ctr, int value) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *ctr = value < 0 ? *ctr + 1 : value;
 }
@@ -1845,7 +1873,7 @@ hipError_t launch_apply(int fp64, int in_fp64, const ApplyGroup* groups, const A
   if (n_tiles <= 0) return hipSuccess;
   static bool attr_set = false;
   if (!attr_set) {
-    const int cap = 160 * 1024;
+    const int cap = kApplyLdsBudget;
     (void)hipFuncSetAttribute((const void*)k_apply<float, float>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, cap);
     (void)hipFuncSetAttribute((const void*)k_apply<float, double>,
@@ -1920,6 +1948,13 @@ hipError_t launch_rho(const RhoProg* progs, int n, hipStream_t s) {
 
 hipError_t launch_step_inc(int* ctr, int value, hipStream_t s) {
   hipLaunchKernelGGL(k_step_inc, dim3(1), dim3(64), 0, s, ctr, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_finite(const FiniteOp* ops, int n, int* flags, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_clear_flags, dim3((n + 255) / 256), dim3(256), 0, s, flags, n);
+  hipLaunchKernelGGL(k_finite, dim3(n, 16), dim3(256), 0, s, ops);
   return hipGetLastError();
 }
 

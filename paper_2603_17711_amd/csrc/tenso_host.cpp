@@ -32,6 +32,7 @@ hipError_t launch_absorb(const AbsorbOp* ops, const void* tiles, int n_tiles, si
 hipError_t launch_gram(int fp64, const GramOp* ops, int n, hipStream_t s);
 hipError_t launch_rho(const RhoProg* progs, int n, hipStream_t s);
 hipError_t launch_step_inc(int* ctr, int value, hipStream_t s);
+hipError_t launch_finite(const FiniteOp* ops, int n, int* flags, hipStream_t s);
 }  // namespace tenso
 
 using namespace tenso;
@@ -685,7 +686,7 @@ static void layout(tenso_plan& P) {
   P.ws_qrtau = take((size_t)P.max_dim * 16);
   P.ws_rhovec = take((size_t)t.n * maxr * 16);
   P.ws_rhoout = take((size_t)t.end_dim[0] * t.end_dim[0] * 16);
-  P.ws_ctr = take(64);
+  P.ws_ctr = take(256);  // step counter at 0, finiteness flag at 64, its descriptor at 128
   if (P.opts.method == TENSO_PS2) {
     P.ws_theta = take(std::max<size_t>(1, theta) * 16);
     P.ws_evals = take(64 * 8);
@@ -773,7 +774,7 @@ struct Builder {
   long tile_units(int d1, int d2, long F, int target, int n_terms) {
     const int nib = (d1 + 15) / 16, njb = (d2 + 15) / 16;
     const int NT = 4;  // accumulator tiles per wavefront in the kernel
-    const size_t budget = 160 * 1024;
+    const size_t budget = kApplyLdsBudget;
     if (nib > NT || d1 > 64 || d2 > 64 || apply_lds_bytes(P.fp64, 1, d1, d2, 1) > budget)
       fail(TENSO_EUNSUPPORTED, "leg dimensions too large for the apply kernel in this precision");
     const long units = F * njb;
@@ -1639,6 +1640,22 @@ static void step_loop(StepGraph& G, const std::vector<const DevProgram*>& parts,
   }
 }
 
+// Non-finite values in a plan's state after stepping: ENUMERIC.  One small
+// launch and a synchronisation per step call.
+static void check_plan_finite(tenso_plan* p, void* d_state, void* d_ws, hipStream_t s) {
+  char* base = (char*)d_ws + p->ws_ctr;
+  FiniteOp op{};
+  op.p = (const double*)d_state;
+  op.n = (long)(p->state_bytes / sizeof(double));
+  op.flag = (int*)(base + 64);
+  hipchk(hipMemcpyAsync(base + 128, &op, sizeof(op), hipMemcpyHostToDevice, s), "finite op");
+  hipchk(launch_finite((const FiniteOp*)(base + 128), 1, op.flag, s), "finite check");
+  int flag = 0;
+  hipchk(hipMemcpyAsync(&flag, op.flag, sizeof(int), hipMemcpyDeviceToHost, s), "finite flag");
+  hipchk(hipStreamSynchronize(s), "sync");
+  if (flag) fail(TENSO_ENUMERIC, "non-finite values in the state after stepping");
+}
+
 // Tile group indices are relative to the first group of their launch.
 static void fix_tile_groups(Program& G) {
   for (auto& L : G.launches) {
@@ -2168,6 +2185,7 @@ int tenso_step_fixed(tenso_plan* p, void* d_state, double t0, double dt, int n_s
     hipchk(launch_step_inc(ctr, 0, s), "ctr");
     run(*p->dev_init, p->fp64, ctr, s);
     step_loop(p->graph, {p->dev_step.get()}, p->fp64, ctr, n_steps, s);
+    check_plan_finite(p, d_state, d_ws, s);
   });
 }
 
@@ -2194,7 +2212,7 @@ int tenso_step_adaptive(tenso_plan* p, void* d_state, double t0, double dt, int 
       X.W(0, 0);
       X.Wstar(0, 1);
     }
-    hipchk(hipStreamSynchronize(s), "sync");
+    check_plan_finite(p, d_state, d_ws, s);
   });
 }
 
@@ -2267,6 +2285,9 @@ struct tenso_batch {
   double* rho_buf = nullptr;
   std::vector<size_t> rho_off;
   DevProgram init, rho;
+  FiniteOp* fin_ops = nullptr;      // per instance: its state, for the finiteness check
+  int* fin_flags = nullptr;
+  std::vector<int> last_flags;      // flags of the last step call
   std::vector<std::unique_ptr<DevProgram>> steps;  // independent parts of one step
   int n_parts = 4;                                 // parts requested
   StepGraph graph;
@@ -2276,6 +2297,8 @@ struct tenso_batch {
     return v;
   }
   ~tenso_batch() {
+    if (fin_ops) (void)hipFree(fin_ops);
+    if (fin_flags) (void)hipFree(fin_flags);
     if (ctr) (void)hipFree(ctr);
     if (rho_buf) (void)hipFree(rho_buf);
   }
@@ -2341,10 +2364,23 @@ static void batch_build(tenso_batch& B, hipStream_t s) {
   B.graph.reset();
 }
 
+// Non-finite values in any instance's state: ENUMERIC (flags kept for
+// tenso_batch_status).
+static void check_batch_finite(tenso_batch* b, hipStream_t s) {
+  const int n = (int)b->plans.size();
+  hipchk(launch_finite(b->fin_ops, n, b->fin_flags, s), "finite check");
+  b->last_flags.assign(n, 0);
+  hipchk(hipMemcpyAsync(b->last_flags.data(), b->fin_flags, n * sizeof(int), hipMemcpyDeviceToHost, s),
+         "finite flags");
+  hipchk(hipStreamSynchronize(s), "sync");
+  for (int i = 0; i < n; ++i)
+    if (b->last_flags[i]) fail(TENSO_ENUMERIC, "non-finite values in the state of a batch instance after stepping");
+}
+
 // Check the batch arguments, (re)build the batch programs when the binding
 // changed, and advance every instance by n_steps.
 static void batch_advance(tenso_batch* b, const double* dt, int n_steps,
-                          const double* const* d_drive_tabs, hipStream_t s) {
+                          const double* const* d_drive_tabs, hipStream_t s, bool check = true) {
   if (!b || !dt) fail(TENSO_EINVAL, "null argument");
   if (n_steps < 0) fail(TENSO_EINVAL, "n_steps must be >= 0");
   const size_t n = b->plans.size();
@@ -2367,6 +2403,7 @@ static void batch_advance(tenso_batch* b, const double* dt, int n_steps,
   hipchk(launch_step_inc(b->ctr, 0, s), "ctr");
   run(b->init, b->fp64, b->ctr, s);
   step_loop(b->graph, b->step_parts(), b->fp64, b->ctr, n_steps, s);
+  if (check) check_batch_finite(b, s);
 }
 
 extern "C" {
@@ -2390,6 +2427,17 @@ int tenso_batch_create(int n, tenso_plan* const* plans, void* const* d_states,
     }
     B->fp64 = plans[0]->fp64;
     hipchk(hipMalloc((void**)&B->ctr, 256), "hipMalloc(counter)");
+    {
+      std::vector<FiniteOp> ops(n);
+      for (int i = 0; i < n; ++i) {
+        ops[i].p = (const double*)d_states[i];
+        ops[i].n = (long)(plans[i]->state_bytes / sizeof(double));
+      }
+      hipchk(hipMalloc((void**)&B->fin_flags, std::max(1, n) * sizeof(int)), "hipMalloc(flags)");
+      for (int i = 0; i < n; ++i) ops[i].flag = B->fin_flags + i;
+      hipchk(hipMalloc((void**)&B->fin_ops, n * sizeof(FiniteOp)), "hipMalloc(finite ops)");
+      hipchk(hipMemcpy(B->fin_ops, ops.data(), n * sizeof(FiniteOp), hipMemcpyHostToDevice), "finite ops");
+    }
     hipchk(hipMalloc((void**)&B->rho_buf, std::max<size_t>(rho_bytes, 256)), "hipMalloc(rho)");
     *out = B.release();
   });
@@ -2443,6 +2491,7 @@ int tenso_batch_step_record(tenso_batch* b, const double* t0, const double* dt, 
                               hipMemcpyDeviceToDevice, s), "record");
       }
     }
+    check_batch_finite(b, s);
   });
 }
 
@@ -2471,6 +2520,14 @@ int tenso_batch_reduced_rho(tenso_batch* b, tenso_c128* const* h_rho, hipStream_
       const size_t M = b->plans[i]->tree.end_dim[0];
       memcpy(h_rho[i], h.data() + b->rho_off[i], M * M * 16);
     }
+  });
+}
+
+int tenso_batch_status(const tenso_batch* b, int32_t* flags) {
+  return guard([&] {
+    if (!b || !flags) fail(TENSO_EINVAL, "null argument");
+    for (size_t i = 0; i < b->plans.size(); ++i)
+      flags[i] = i < b->last_flags.size() ? b->last_flags[i] : 0;
   });
 }
 
@@ -2536,10 +2593,10 @@ int tenso_batch_autotune(tenso_batch* b, const double* dt, int trial_steps,
           P->tile_work = w;
           P->tile_work_set = true;
         }
-        batch_advance(b, dt, trial_steps, d_drive_tabs, s);  // build, capture, warm up
+        batch_advance(b, dt, trial_steps, d_drive_tabs, s, false);  // build, capture, warm up
         copy_states(false);
         hipchk(hipEventRecord(e0, s), "hipEventRecord");
-        batch_advance(b, dt, trial_steps, d_drive_tabs, s);
+        batch_advance(b, dt, trial_steps, d_drive_tabs, s, false);
         hipchk(hipEventRecord(e1, s), "hipEventRecord");
         hipchk(hipEventSynchronize(e1), "hipEventSynchronize");
         float ms = 0;
@@ -2551,6 +2608,8 @@ int tenso_batch_autotune(tenso_batch* b, const double* dt, int trial_steps,
         }
       }
     } catch (...) {
+      copy_states(false);  // the caller gets its states back even on failure
+      (void)hipStreamSynchronize(s);
       (void)hipEventDestroy(e0);
       (void)hipEventDestroy(e1);
       throw;

@@ -40,6 +40,10 @@ struct ApplyGroup {
 // A tile of the apply kernel: a range of units of one group.  A unit is one
 // (free index f, 16-column block jb of leg 2) pair, u = f * njb + jb; wavefront
 // w of the workgroup takes units u0 + w, u0 + w + 4, ...
+// Dynamic LDS available to one apply tile: the 160 KB of a CU less 1 KB
+// kept for the kernel's static LDS.
+constexpr int kApplyLdsBudget = 159 * 1024;
+
 struct ApplyTile {
   int group;           // index into the launch's group array
   int u0, nu;
@@ -47,6 +51,15 @@ struct ApplyTile {
 };
 
 // Weighted sum of matrices: out = sum_i coef_i(t) * M_i (single-leg terms).
+// Finiteness check of one FP64 state: *flag is set to 1 if any of its n
+// doubles is NaN or infinite (the caller clears the flags first).
+struct FiniteOp {
+  const double* p;
+  long n;
+  int* flag;
+  int pad_[2];
+};
+
 // Largest number of terms one presum sums (its descriptors are staged in LDS).
 constexpr int PRESUM_MAX_TERMS = 512;
 

@@ -17,3 +17,24 @@ def test_surrogate_pipeline_small():
     print("  ", {k: (round(v, 5) if isinstance(v, float) else v) for k, v in r.items()})
     assert r["train_mse_first_last"][1] < r["train_mse_first_last"][0]
     assert np.isfinite(r["max_feature_error"])
+
+
+def test_forced_monitor_trip_runs_the_ttn_fallback():
+    """A monitor that accepts nothing trips every trajectory at its first
+    prediction; the fallback must then hand back exactly the TTN-HEOM
+    trajectory from that point (same batched solver, same inputs)."""
+    require_gpu()
+    import workloads
+    from paper_2603_17711_amd import surrogate as S
+    print("[surrogate] forced trips on 4 trajectories x 400 steps", flush=True)
+    n_steps = 400
+    held = workloads.config4(workloads.HELDOUT_SEEDS[:4], n_steps)
+    rho, _ = S.generate(held, n_steps)
+    judge = S.features(rho)
+    n_rec = rho.shape[1]
+    model = S.MLP(seed=1)  # untrained: its output does not matter here
+    f, trip, _ = S.rollout(model, held, judge[:, :S.WINDOW], n_rec, tol=-1.0)
+    assert (trip == S.WINDOW).all(), trip
+    f, t_fb = S.fallback(held, trip, f, n_steps)
+    assert t_fb > 0
+    assert np.abs(f[:, S.WINDOW:] - judge[:, S.WINDOW:]).max() < 1e-12
