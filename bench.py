@@ -20,6 +20,7 @@ if ROOT not in sys.path:
 METRIC = "TTN-HEOM steps/sec at trace-dist<=1e-6, mixed/batched vs FP64; % MFMA peak"
 PEAK_FP32_MFMA = 157.3  # TFLOP/s, MI355X dense FP32 matrix
 PEAK_FP64_MFMA = 78.6
+COPY_PROBE_BYTES = 256 << 20
 
 
 def parse():
@@ -31,6 +32,9 @@ def parse():
     ap.add_argument("--instances", type=int, default=512, help="batch size for c2")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU comparison")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after the run, a plain 256 MiB streaming kernel (torch.neg) whose "
+                         "HBM counters calibrate FETCH_SIZE / WRITE_SIZE")
     ap.add_argument("--autotune", action="store_true",
                     help="c2: autotune the apply tile size before timing (default: the "
                          "batch default tile size)")
@@ -229,11 +233,27 @@ def batch_main(a):
     print(json.dumps(out))
 
 
+def copy_probe():
+    """Known-size streaming kernel: reads and writes COPY_PROBE_BYTES each."""
+    import torch
+    x = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        torch.neg(x, out=y)
+    torch.cuda.synchronize()
+
+
 def main():
     a = parse()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    run_main(a)
+    if a.copy_probe:
+        copy_probe()
+
+
+def run_main(a):
     import numpy as np
     import torch
     torch.cuda.set_device(0)

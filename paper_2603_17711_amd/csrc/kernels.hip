@@ -12,6 +12,7 @@
 // gram   : environment finalisation E = conj(C)_(open) T_(open)^T.
 // rho    : bottom-up vacuum contraction for rho_S = <0|Omega>.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <math.h>
 #include <algorithm>
 #include "tenso_internal.h"
@@ -611,18 +612,23 @@ constexpr int QR_RPL = 16;               // rows per lane of a column update
 constexpr int QR_RPT = 2;                // panel rows per thread
 constexpr int QR_MAX_M = 64 * QR_RPL;    // 1024 = QR_NT * QR_RPT
 constexpr int QR_NPAIR = QR_PB * (QR_PB - 1) / 2;
+static_assert(QR_MAX_M == kQrBlockedMaxM, "blocked QR height");
 
 // x <- (I - V S V^H) x for one column, x[r] at X[off[q]] for r = q * 64 + lane
 // (rows past mp - 1 are clamped to mp - 1 in off); V explicit (unit
-// diagonal, zeros above) in LDS with leading dimension mp; S is QR_PB x
-// QR_PB in LDS, zero outside pb x pb; the result is scaled by ph.
+// diagonal, zeros above) in LDS with leading dimension QR_MAX_M, finite
+// (zero) in rows >= mp and columns >= pb, so that every read is the lane's
+// base plus a constant offset; S is QR_PB x QR_PB in LDS, zero outside
+// pb x pb.
 __device__ inline void qr_apply_col(const z2* __restrict__ Lv, int mp, int pb,
                                     const z2* __restrict__ S, gp<z2> __restrict__ X,
-                                    const int* off, z2 ph, int lane, double* tail) {
-  // reflectors i >= pb read column pb - 1; S has zero rows and columns there
-  int ci[QR_PB];
-#pragma unroll
-  for (int i = 0; i < QR_PB; ++i) ci[i] = (i < pb ? i : pb - 1) * mp;
+                                    const int* off, int lane, double* tail) {
+  // 16-byte panel reads: one ds_read_b128 with a constant offset each
+  const double2* __restrict__ Ll = reinterpret_cast<const double2*>(Lv) + lane;
+  auto lv = [&](int i, int q) {
+    const double2 t = Ll[i * QR_MAX_M + q * 64];
+    return z2{t.x, t.y};
+  };
   z2 xs[QR_RPL];
 #pragma unroll
   for (int q = 0; q < QR_RPL; ++q) xs[q] = X[off[q]];
@@ -633,10 +639,9 @@ __device__ inline void qr_apply_col(const z2* __restrict__ Lv, int mp, int pb,
   for (int q = 0; q < QR_RPL; ++q) {
     const int r = q * 64 + lane;
     if (r >= mp) xs[q] = z2{0.0, 0.0};  // clamped duplicate: no contribution
-    const int rc = r < mp ? r : mp - 1;
     z2 vv[QR_PB];
 #pragma unroll
-    for (int i = 0; i < QR_PB; ++i) vv[i] = Lv[ci[i] + rc];
+    for (int i = 0; i < QR_PB; ++i) vv[i] = lv(i, q);
 #pragma unroll
     for (int i = 0; i < QR_PB; ++i) {  // w_i += conj(v_i) x
       w[2 * i] = fma(vv[i].r, xs[q].r, fma(vv[i].i, xs[q].i, w[2 * i]));
@@ -670,7 +675,7 @@ __device__ inline void qr_apply_col(const z2* __restrict__ Lv, int mp, int pb,
     if (r < mp) {
       z2 vv[QR_PB];
 #pragma unroll
-      for (int i = 0; i < QR_PB; ++i) vv[i] = Lv[ci[i] + r];
+      for (int i = 0; i < QR_PB; ++i) vv[i] = lv(i, q);
       double ar = xs[q].r, ai = xs[q].i;
 #pragma unroll
       for (int i = 0; i < QR_PB; ++i) {  // x -= v_i u_i
@@ -678,7 +683,7 @@ __device__ inline void qr_apply_col(const z2* __restrict__ Lv, int mp, int pb,
         ai = fma(-vv[i].r, u[2 * i + 1], fma(-vv[i].i, u[2 * i], ai));
       }
       if (r >= pb) t2 = fma(ar, ar, fma(ai, ai, t2));
-      X[off[q]] = zmul(z2{ar, ai}, ph);
+      X[off[q]] = z2{ar, ai};
     }
     if (q % 4 == 3) __builtin_amdgcn_sched_barrier(0);
   }
@@ -872,7 +877,7 @@ __global__ void __launch_bounds__(QR_NT) k_qr(const QrOp* __restrict__ ops) {
   __shared__ double tailn[64];  // per column: squared norm below the last factored panel
   __shared__ double ph[2 * 64];
   extern __shared__ char smem_raw[];
-  z2* __restrict__ L = reinterpret_cast<z2*>(smem_raw);  // explicit panel, (m - p) x pb
+  z2* __restrict__ L = reinterpret_cast<z2*>(smem_raw);  // explicit panel, QR_MAX_M x QR_PB
   const gp<z2> __restrict__ V = gmem(reinterpret_cast<z2*>(op.V));  // column-major m x n
   const gp<z2> __restrict__ C = gmem(reinterpret_cast<z2*>(op.C));
   const gp<z2> __restrict__ R = gmem(reinterpret_cast<z2*>(op.R));
@@ -884,18 +889,20 @@ __global__ void __launch_bounds__(QR_NT) k_qr(const QrOp* __restrict__ ops) {
     return q * cstride + (row - q * ppost);
   };
 
-  // C -> V and the Frobenius norm
+  // C -> V and the Frobenius norm (V may be C itself: a core whose QR leg is
+  // its slowest index is already column-major m x n)
+  const bool in_place = op.V == op.C;
   double fro = 0;
   for (int row = tid; row < m; row += QR_NT) {
     const int cb = crow(row);
-    for (int c0 = 0; c0 < n; c0 += 8) {
-      z2 t[8];
+    for (int c0 = 0; c0 < n; c0 += 16) {
+      z2 t[16];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) t[u] = c0 + u < n ? C[cb + (c0 + u) * ppost] : z2{0.0, 0.0};
+      for (int u = 0; u < 16; ++u) t[u] = c0 + u < n ? C[cb + (c0 + u) * ppost] : z2{0.0, 0.0};
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
+      for (int u = 0; u < 16; ++u)
         if (c0 + u < n) {
-          V[(c0 + u) * m + row] = t[u];
+          if (!in_place) V[(c0 + u) * m + row] = t[u];
           fro += t[u].r * t[u].r + t[u].i * t[u].i;
         }
     }
@@ -932,11 +939,12 @@ __global__ void __launch_bounds__(QR_NT) k_qr(const QrOp* __restrict__ ops) {
         if (op.transposeR) R[c * n + i] = v;
         else R[i * n + c] = v;
       }
-      // Q starts as the first k unit columns
-      for (int row = tid; row < m; row += QR_NT) {
-        const int cb = crow(row);
-        for (int c = 0; c < k; ++c) C[cb + c * ppost] = z2{row == c ? 1.0 : 0.0, 0.0};
-      }
+      // Q is formed in V (column-major): column c starts as the unit column
+      // e_c once its reflector has been read; the columns of the identity
+      // blocks (past an early exit) start so now, after R has been read out
+      __syncthreads();
+      for (int c = nbf * QR_PB; c < k; ++c)
+        for (int row = tid; row < m; row += QR_NT) V[c * m + row] = z2{row == c ? 1.0 : 0.0, 0.0};
     }
     if (!fact && bk >= nbf) {  // identity reflectors (all tau zero): nothing to apply
       __syncthreads();
@@ -1065,11 +1073,9 @@ __global__ void __launch_bounds__(QR_NT) k_qr(const QrOp* __restrict__ ops) {
           if (row == c) P[j][c] = z2{1.0, 0.0};
           else if (row < c) P[j][c] = z2{0.0, 0.0};
         }
-        if (row < mp) {
+        // every row and column of the LDS panel (zeros past mp and pb)
 #pragma unroll
-          for (int c = 0; c < QR_PB; ++c)
-            if (c < pb) L[c * mp + row] = P[j][c];
-        }
+        for (int c = 0; c < QR_PB; ++c) L[c * QR_MAX_M + row] = P[j][c];
         int e = 0;
 #pragma unroll
         for (int jc = 1; jc < QR_PB; ++jc)
@@ -1086,6 +1092,10 @@ __global__ void __launch_bounds__(QR_NT) k_qr(const QrOp* __restrict__ ops) {
         for (int e = 0; e < 2 * QR_NPAIR; ++e) red[par][wave][2 * QR_PB + e] = g[e];
       }
       __syncthreads();
+      if (!fact) {  // every thread holds its panel rows: the reflectors' columns become e_c
+        for (int c = p; c < p + pb; ++c)
+          for (int row = tid; row < m; row += QR_NT) V[c * m + row] = z2{row == c ? 1.0 : 0.0, 0.0};
+      }
       if (tid == 0) {
         // T (forward column-wise): T[j][j] = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] y[0:j, j]
         z2 T[QR_PB][QR_PB];
@@ -1133,22 +1143,15 @@ __global__ void __launch_bounds__(QR_NT) k_qr(const QrOp* __restrict__ ops) {
       }
       par ^= 1;
       __syncthreads();
-      // V (column-major) is addressed like C with a row period of m
-      const gp<z2> X = fact ? V : C;
-      const int xp = fact ? m : ppost, xcs = fact ? 0 : cstride;
-      const double xpinv = 1.0 / xp;
+      // columns of V (reflectors while factoring, Q while forming it)
       int off[QR_RPL];
 #pragma unroll
       for (int q = 0; q < QR_RPL; ++q) {
-        const int r = q * 64 + lane, row = p + (r < mp ? r : mp - 1);
-        const int qq = qr_div(row, xp, xpinv);
-        off[q] = qq * xcs + (row - qq * xp);
+        const int r = q * 64 + lane;
+        off[q] = p + (r < mp ? r : mp - 1);
       }
-      const bool last = !fact && bk == 0;  // the final Q update also applies the phases
-      for (int cc = c0 + wave; cc < c1; cc += QR_NW) {
-        const z2 phc = last ? z2{ph[2 * cc], ph[2 * cc + 1]} : z2{1.0, 0.0};
-        qr_apply_col(L, mp, pb, S, X + cc * xp, off, phc, lane, fact ? tailn + cc : nullptr);
-      }
+      for (int cc = c0 + wave; cc < c1; cc += QR_NW)
+        qr_apply_col(L, mp, pb, S, V + cc * m, off, lane, fact ? tailn + cc : nullptr);
     }
     __syncthreads();
     if (fact && c0 < c1) {
@@ -1168,6 +1171,20 @@ __global__ void __launch_bounds__(QR_NT) k_qr(const QrOp* __restrict__ ops) {
         }
         nbf = st + 1;
         __syncthreads();
+      }
+    }
+  }
+  // Q (the first k columns of V) into the core, with the phases of R
+  for (int row = tid; row < m; row += QR_NT) {
+    const int cb = crow(row);
+    for (int c0 = 0; c0 < k; c0 += 16) {
+      z2 t[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) t[u] = c0 + u < k ? V[(c0 + u) * m + row] : z2{0.0, 0.0};
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int c = c0 + u;
+        if (c < k) C[cb + c * ppost] = zmul(t[u], z2{ph[2 * c], ph[2 * c + 1]});
       }
     }
   }
@@ -1868,8 +1885,11 @@ size_t apply_lds_bytes(int fp64, int nfl, int d1, int d2, int with_ab) {
   return (size_t)apply_lds_elems(nfl, d1, d2, with_ab) * (fp64 ? sizeof(double) : sizeof(float));
 }
 
+// With t0/t1 given, the events are taken by the kernel's own dispatch (start
+// and end of its execution), not by separate stream markers.
 hipError_t launch_apply(int fp64, int in_fp64, const ApplyGroup* groups, const ApplyTile* tiles,
-                        int n_tiles, const int* step_ctr, size_t lds, hipStream_t s) {
+                        int n_tiles, const int* step_ctr, size_t lds, hipStream_t s,
+                        hipEvent_t t0, hipEvent_t t1) {
   if (n_tiles <= 0) return hipSuccess;
   static bool attr_set = false;
   if (!attr_set) {
@@ -1882,17 +1902,16 @@ hipError_t launch_apply(int fp64, int in_fp64, const ApplyGroup* groups, const A
                               hipFuncAttributeMaxDynamicSharedMemorySize, cap);
     attr_set = true;
   }
-  if (fp64) {
-    if (in_fp64)
-      hipLaunchKernelGGL((k_apply<double, double>), dim3(n_tiles), dim3(256), lds, s, groups, tiles, step_ctr);
+  auto go = [&](auto kern) {
+    if (t0 && t1)
+      hipExtLaunchKernelGGL(kern, dim3(n_tiles), dim3(256), (uint32_t)lds, s, t0, t1, 0, groups, tiles,
+                            step_ctr);
     else
-      hipLaunchKernelGGL((k_apply<double, double>), dim3(n_tiles), dim3(256), lds, s, groups, tiles, step_ctr);
-  } else {
-    if (in_fp64)
-      hipLaunchKernelGGL((k_apply<float, double>), dim3(n_tiles), dim3(256), lds, s, groups, tiles, step_ctr);
-    else
-      hipLaunchKernelGGL((k_apply<float, float>), dim3(n_tiles), dim3(256), lds, s, groups, tiles, step_ctr);
-  }
+      hipLaunchKernelGGL(kern, dim3(n_tiles), dim3(256), lds, s, groups, tiles, step_ctr);
+  };
+  if (fp64) go(k_apply<double, double>);
+  else if (in_fp64) go(k_apply<float, double>);
+  else go(k_apply<float, float>);
   return hipGetLastError();
 }
 

@@ -18,7 +18,8 @@
 
 namespace tenso {
 hipError_t launch_apply(int fp64, int in_fp64, const ApplyGroup* groups, const ApplyTile* tiles,
-                        int n_tiles, const int* step_ctr, size_t lds, hipStream_t s);
+                        int n_tiles, const int* step_ctr, size_t lds, hipStream_t s,
+                        hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 size_t apply_lds_bytes(int fp64, int nfl, int d1, int d2, int with_ab);
 hipError_t launch_merge(const MergeOp* op, long n, hipStream_t s);
 hipError_t launch_eig(const EigOp* op, hipStream_t s);
@@ -718,12 +719,13 @@ struct Builder {
       L.lds = mx;
       // useful work (no padding): pair term F*d1*d2*(d1+d2) complex MACs,
       // one-sided terms F*d1*d1*d2 or F*d1*d2*d2; bytes: input read, output
-      // written, operand matrices read once per group
+      // written (one slab per term for per-term outputs), operand matrices
+      // read once per group
       for (int gi = first; gi < first + count; ++gi) {
         const ApplyGroup& g = G.groups[gi];
         const double F = g.F, d1 = g.d1, d2 = g.d2, P = F * d1 * d2;
         const double esz = in_fp64 ? 16.0 : (double)P_.tsz;
-        L.bytes += P * esz + P * P_.tsz;
+        L.bytes += P * esz + P * P_.tsz * (g.per_term_out ? g.n_terms : 1);
         const int t0 = (int)(((uint64_t)g.terms) & OFF_MASK);
         for (int m = t0; m < t0 + g.n_terms; ++m) {
           // credited per generator term the entry stands for (grouped and
@@ -1162,6 +1164,8 @@ struct Builder {
     q.m = (int)(t.size(node) / d[leg]);
     q.Ppost = (int)prod(d, leg + 1, (int)d.size());
     q.transposeR = transposeR;
+    // the core is already column-major m x n: factor it in place
+    if (q.Ppost == q.m && q.m <= kQrBlockedMaxM) q.V = q.C;
     if (q.m < q.n) fail(TENSO_EUNSUPPORTED, "QR with fewer rows than columns");
     if (q.n > 64) fail(TENSO_EUNSUPPORTED, "QR of a bond wider than 64");
     int qi = (int)G.qrs.size();
@@ -1522,8 +1526,9 @@ static Program merge_programs(std::vector<Program>& progs) {
   return M;
 }
 
-// Optional timing of the apply kernel (the SOP contraction): HIP events on
-// the caller's stream around every apply launch, with its algorithmic work.
+// Optional timing of the apply kernel (the SOP contraction): HIP start/stop
+// events taken by every apply launch's own dispatch on the caller's stream,
+// with its algorithmic work.
 struct Prof {
   bool on = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
@@ -1549,10 +1554,9 @@ static void run(const DevProgram& D, int fp64, const int* ctr, hipStream_t s) {
       case LK_APPLY:
         if (g_prof.on) {
           hipEvent_t e0 = g_prof.get(), e1 = g_prof.get();
-          hipchk(hipEventRecord(e0, s), "hipEventRecord");
           e = launch_apply(fp64, L.in_fp64, (const ApplyGroup*)(b + D.o_groups) + L.first,
-                           (const ApplyTile*)(b + D.o_atiles) + L.tfirst, L.tcount, ctr, L.lds, s);
-          hipchk(hipEventRecord(e1, s), "hipEventRecord");
+                           (const ApplyTile*)(b + D.o_atiles) + L.tfirst, L.tcount, ctr, L.lds, s,
+                           e0, e1);
           g_prof.ev.push_back({e0, e1});
           g_prof.work.push_back({L.flops, L.bytes});
           break;

@@ -86,10 +86,14 @@ struct CombineOp {
 // (other legs, row-major) x (leg of dim n); Q replaces the core in place.
 // The m x n matrix element (row = pre*Ppost + post, col) sits at
 // pre*n*Ppost + col*Ppost + post.
+// Tallest QR factored by the blocked kernel (taller ones take the
+// column-by-column form, which needs V apart from C).
+constexpr int kQrBlockedMaxM = 1024;
+
 struct QrOp {
   double* C;           // FP64 complex core
   double* R;           // out: n x n (or its transpose when transposeR)
-  double* V;           // scratch m x n complex
+  double* V;           // scratch m x n complex (may be C when Ppost == m <= kQrBlockedMaxM)
   double* tau;         // scratch n complex
   int m, n, Ppost, transposeR;
 };
