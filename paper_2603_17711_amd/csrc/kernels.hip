@@ -49,7 +49,7 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 template <typename T> struct MT;
 template <> struct MT<float> {
   typedef v4f v4;
-  static constexpr int NT = 4;  // accumulator tiles per wavefront
+  static constexpr int NT = kApplyAccTiles;  // accumulator tiles per wavefront
   __device__ static inline v4 mma(float a, float b, v4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
@@ -58,7 +58,7 @@ template <> struct MT<float> {
 };
 template <> struct MT<double> {
   typedef v4d v4;
-  static constexpr int NT = 4;
+  static constexpr int NT = kApplyAccTiles;
   __device__ static inline v4 mma(double a, double b, v4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
@@ -138,7 +138,7 @@ __device__ inline void load_scaled(const T* M, int d, int row, int kk, double cr
 // without bounds checks.
 __host__ __device__ inline long apply_lds_elems(int nfl, int d1, int d2, int) {
   const long D1 = 16 * ((d1 + 15) / 16), D2 = 16 * ((d2 + 15) / 16);
-  return 2 * (nfl * D1 * (D2 + 1) + D1 * (D1 + 1) + D2 * (D2 + 1) + 4 * D1 * 16);
+  return 2 * (nfl * D1 * (D2 + 1) + D1 * (D1 + 1) + D2 * (D2 + 1) + kApplyWaves * D1 * 16);
 }
 
 template <typename T> struct V2;
@@ -263,7 +263,7 @@ __device__ inline void apply_unit(int kind, const C2* xf, const C2* as, const C2
 }
 
 template <typename T, typename Tin>
-__global__ void __launch_bounds__(256, 2) k_apply(const ApplyGroup* __restrict__ groups,
+__global__ void __launch_bounds__(64 * kApplyWaves) k_apply(const ApplyGroup* __restrict__ groups,
                                                const ApplyTile* __restrict__ tiles,
                                                const int* __restrict__ step_ctr) {
   typedef typename MT<T>::v4 v4;
@@ -297,7 +297,8 @@ __global__ void __launch_bounds__(256, 2) k_apply(const ApplyGroup* __restrict__
   // stage the tile's input slices (zero padded, compute precision): slice
   // bases once, then lanes over the columns of a row (D2 = 16, 32, 64: 64/D2
   // rows per wavefront pass; D2 = 48: one row, lanes 48..63 idle)
-  __shared__ long sbase[17];
+  constexpr int AW = kApplyWaves;
+  __shared__ long sbase[kApplyMaxUnits + 1];
   if ((int)threadIdx.x < nfl)
     sbase[threadIdx.x] = unit_geo(G, (f_first + (int)threadIdx.x) * njb, njb, 0).base;
   __syncthreads();
@@ -307,24 +308,41 @@ __global__ void __launch_bounds__(256, 2) k_apply(const ApplyGroup* __restrict__
     const int sub = p2 ? lane / D2 : 0;
     const int bcol = p2 ? (lane & (D2 - 1)) : lane;
     if (bcol < D2 && (p2 || lane < D2)) {
-      const int nrows = nfl * D1;
+      // rows (fl, a) in steps of AW * rpw
+      const int step = AW * rpw;
+      int fl = 0, a = wave * rpw + sub;
+      c2* dst = xs + (long)a * xs1 + bcol;
+      while (a >= D1) {  // the first row may already lie in a later slice
+        a -= D1;
+        ++fl;
+      }
+      long src = fl < nfl ? sbase[fl] + (long)bcol * sb : 0;
+      const bool colok = bcol < d2;
 #pragma unroll 4
-      for (int ra = wave * rpw + sub; ra < nrows; ra += 4 * rpw) {
-        const int fl = ra / D1, a = ra - fl * D1;
+      for (int ra = a; ra < nfl * D1; ra += step) {
         c2 v;
         v.x = 0;
         v.y = 0;
-        if (a < d1 && bcol < d2) {
-          const cpx<T> x = ldc<Tin, T>(G.X, sbase[fl] + a * sa + bcol * sb);
+        if (a < d1 && colok) {
+          const cpx<T> x = ldc<Tin, T>(G.X, src + a * sa);
           v.x = x.re;
           v.y = x.im;
         }
-        xs[((long)fl * D1 + a) * xs1 + bcol] = v;
+        *dst = v;
+        dst += (long)step * xs1;
+        a += step;
+        if (a >= D1) {
+          do {
+            a -= D1;
+            ++fl;
+          } while (a >= D1);
+          if (fl < nfl) src = sbase[fl] + (long)bcol * sb;
+        }
       }
     }
   }
 
-  int n_my = tile.nu > wave ? (tile.nu - wave + 3) / 4 : 0;
+  int n_my = tile.nu > wave ? (tile.nu - wave + AW - 1) / AW : 0;
   if (n_my * nib > NT) n_my = NT / nib;
   v4 yr[NT], yi[NT];
 #pragma unroll
@@ -339,7 +357,7 @@ __global__ void __launch_bounds__(256, 2) k_apply(const ApplyGroup* __restrict__
     for (int ti = 0; ti < NT; ++ti) {
       if (ti < n_my * nib) {
         const int uu = ti / nib, t = ti % nib;
-        const UnitGeo ug = unit_geo(G, tile.u0 + wave + 4 * uu, njb, c);
+        const UnitGeo ug = unit_geo(G, tile.u0 + wave + AW * uu, njb, c);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = 16 * t + MT<T>::drow(g, r);
@@ -372,19 +390,23 @@ __global__ void __launch_bounds__(256, 2) k_apply(const ApplyGroup* __restrict__
       const int sub = p2 ? lane / D : 0;
       const int j = p2 ? (lane & (D - 1)) : lane;
       if (j >= D || (!p2 && lane >= D)) return;
+      // the coefficient is applied in the compute precision (one rounding,
+      // as for the operand itself)
       const bool unit = sr == 1.0 && si == 0.0;
-      for (int i = wave * rpw + sub; i < D; i += 4 * rpw) {
+      const T sr_t = (T)sr, si_t = (T)si;
+      const bool jok = j < d;
+      for (int i = wave * rpw + sub; i < D; i += AW * rpw) {
         c2 v;
         v.x = 0;
         v.y = 0;
-        if (i < d && j < d) {
+        if (i < d && jok) {
           const T a0 = M[2 * (i * d + j)], a1 = M[2 * (i * d + j) + 1];
           if (unit) {
             v.x = a0;
             v.y = a1;
           } else {
-            v.x = (T)((double)a0 * sr - (double)a1 * si);
-            v.y = (T)((double)a0 * si + (double)a1 * sr);
+            v.x = a0 * sr_t - a1 * si_t;
+            v.y = a0 * si_t + a1 * sr_t;
           }
         }
         dst[i * ld + j] = v;
@@ -395,7 +417,7 @@ __global__ void __launch_bounds__(256, 2) k_apply(const ApplyGroup* __restrict__
     __syncthreads();
     const int kind = (Am ? 1 : 0) | (Bm ? 2 : 0);
     for (int uu = 0; uu < n_my; ++uu) {
-      const int u = tile.u0 + wave + 4 * uu;
+      const int u = tile.u0 + wave + AW * uu;
       const int fl = u / njb - f_first, jb = u % njb;
       const c2* xf = xs + (long)fl * D1 * xs1;
       const int col = 16 * jb + c;
@@ -1904,10 +1926,10 @@ hipError_t launch_apply(int fp64, int in_fp64, const ApplyGroup* groups, const A
   }
   auto go = [&](auto kern) {
     if (t0 && t1)
-      hipExtLaunchKernelGGL(kern, dim3(n_tiles), dim3(256), (uint32_t)lds, s, t0, t1, 0, groups, tiles,
+      hipExtLaunchKernelGGL(kern, dim3(n_tiles), dim3(64 * kApplyWaves), (uint32_t)lds, s, t0, t1, 0, groups, tiles,
                             step_ctr);
     else
-      hipLaunchKernelGGL(kern, dim3(n_tiles), dim3(256), lds, s, groups, tiles, step_ctr);
+      hipLaunchKernelGGL(kern, dim3(n_tiles), dim3(64 * kApplyWaves), lds, s, groups, tiles, step_ctr);
   };
   if (fp64) go(k_apply<double, double>);
   else if (in_fp64) go(k_apply<float, double>);

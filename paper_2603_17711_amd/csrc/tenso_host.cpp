@@ -770,12 +770,12 @@ struct Builder {
   }
 
   // Tiles for one group of units: about `tile_work` flops per tile (at most
-  // 4*uw units), at least `target` tiles, and the tile's input slices and
-  // operand matrices within the LDS budget.
+  // kApplyMaxUnits / nib units), at least `target` tiles, and the
+  // tile's input slices and operand matrices within the LDS budget.
   // Units per tile for a group (see add_tiles).
   long tile_units(int d1, int d2, long F, int target, int n_terms) {
     const int nib = (d1 + 15) / 16, njb = (d2 + 15) / 16;
-    const int NT = 4;  // accumulator tiles per wavefront in the kernel
+    const int NT = kApplyAccTiles;  // accumulator tiles per wavefront in the kernel
     const size_t budget = kApplyLdsBudget;
     if (nib > NT || d1 > 64 || d2 > 64 || apply_lds_bytes(P.fp64, 1, d1, d2, 1) > budget)
       fail(TENSO_EUNSUPPORTED, "leg dimensions too large for the apply kernel in this precision");
@@ -783,7 +783,7 @@ struct Builder {
     const double per_unit = unit_work(d1, d2) * std::max(1, n_terms);
     long want = std::max<long>(target, (long)std::ceil(units * per_unit / P.tile_work));
     long per = std::max<long>(1, (units + want - 1) / want);
-    per = std::min<long>(per, 4L * (NT / nib));
+    per = std::min<long>(per, (long)(kApplyMaxUnits / nib));
     while (per > 1 && apply_lds_bytes(P.fp64, (int)((per + njb - 1) / njb + 1), d1, d2, 1) > budget)
       per /= 2;
     return per;

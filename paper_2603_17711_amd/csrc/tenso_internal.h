@@ -37,9 +37,17 @@ struct ApplyGroup {
   int pad_;
 };
 
+// Wavefronts of an apply workgroup, accumulator tiles per wavefront, and the
+// most units of one tile (kApplyMaxUnits / nib for nib 16-row blocks of leg 1;
+// at most kApplyWaves * kApplyAccTiles / nib, the accumulators of a workgroup).
+constexpr int kApplyWaves = 4;
+constexpr int kApplyAccTiles = 4;
+constexpr int kApplyMaxUnits = 16;
+static_assert(kApplyMaxUnits <= kApplyWaves * kApplyAccTiles, "tile units");
+
 // A tile of the apply kernel: a range of units of one group.  A unit is one
 // (free index f, 16-column block jb of leg 2) pair, u = f * njb + jb; wavefront
-// w of the workgroup takes units u0 + w, u0 + w + 4, ...
+// w of the workgroup takes units u0 + w, u0 + w + kApplyWaves, ...
 // Dynamic LDS available to one apply tile: the 160 KB of a CU less 1 KB
 // kept for the kernel's static LDS.
 constexpr int kApplyLdsBudget = 159 * 1024;
