@@ -136,7 +136,7 @@ __device__ inline void load_scaled(const T* M, int d, int row, int kk, double cr
 //   Z : 4 wavefronts x D1 x 16  per-wave X_f B^T of one unit
 // with D = 16 * ceil(d / 16).  Every MFMA operand is then one LDS vector load
 // without bounds checks.
-__host__ __device__ inline long apply_lds_elems(int nfl, int d1, int d2, int) {
+__host__ __device__ inline long apply_lds_elems(int nfl, int d1, int d2) {
   const long D1 = 16 * ((d1 + 15) / 16), D2 = 16 * ((d2 + 15) / 16);
   return 2 * (nfl * D1 * (D2 + 1) + D1 * (D1 + 1) + D2 * (D2 + 1) + kApplyWaves * D1 * 16);
 }
@@ -145,81 +145,87 @@ template <typename T> struct V2;
 template <> struct V2<float> { typedef float2 t; };
 template <> struct V2<double> { typedef double2 t; };
 
-// One unit of the apply tile for one term, with NIB 16-row tiles of leg 1
-// accumulated into tiles TLO .. TLO + NIB - 1 of the wavefront:
-// Y += A_t (X_f B^T)[:, col block] (two-sided), A_t X_f[:, col block]
-// (A only) or X_f B^T (B only).  Operands of k-step q + 1 are read from LDS
-// before the MFMAs of step q are issued, so LDS latency overlaps the matrix
-// cores.  (NIB and TLO are compile-time so that every register array is
-// indexed statically.)
+// Units of the apply tile for one term, with NIB 16-row tiles of leg 1.
+// Operands of k-step q + 1 are read from LDS before the MFMAs of step q are
+// issued, so LDS latency overlaps the matrix cores.  (NIB and TLO are
+// compile-time so that every register array is indexed statically.)
+//   Two-sided terms, Y += A_t (X_f B^T)[:, col block], in two products per
+// unit: first Z = X_f B^T (16-column block) into the wavefront's slab zu ...
+template <typename T, int NIB, typename C2>
+__device__ inline void apply_z(const C2* xf, const C2* bs, C2* zu, int col, int c, int g, int nq1,
+                               int xs1, int bs1) {
+  typedef typename MT<T>::v4 v4;
+  v4 zr[NIB], zi[NIB];
+#pragma unroll
+  for (int t = 0; t < NIB; ++t) {
+    zr[t] = v4{0, 0, 0, 0};
+    zi[t] = v4{0, 0, 0, 0};
+  }
+  C2 bc = bs[col * bs1 + g], xc[NIB];
+#pragma unroll
+  for (int t = 0; t < NIB; ++t) xc[t] = xf[(16 * t + c) * xs1 + g];
+  for (int q = 0; q < nq1; ++q) {
+    C2 bn = bc, xn[NIB];
+#pragma unroll
+    for (int t = 0; t < NIB; ++t) xn[t] = xc[t];
+    if (q + 1 < nq1) {
+      const int kk = 4 * (q + 1) + g;
+      bn = bs[col * bs1 + kk];
+#pragma unroll
+      for (int t = 0; t < NIB; ++t) xn[t] = xf[(16 * t + c) * xs1 + kk];
+    }
+#pragma unroll
+    for (int t = 0; t < NIB; ++t) cmma<T>(zr[t], zi[t], xc[t].x, xc[t].y, bc.x, bc.y);
+    bc = bn;
+#pragma unroll
+    for (int t = 0; t < NIB; ++t) xc[t] = xn[t];
+  }
+#pragma unroll
+  for (int t = 0; t < NIB; ++t) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      C2 v;
+      v.x = zr[t][r];
+      v.y = zi[t][r];
+      zu[(16 * t + MT<T>::drow(g, r)) * 16 + c] = v;
+    }
+  }
+}
+
+// ... then Y += A Z_u into accumulator tiles TLO .. TLO + NIB - 1.
 template <typename T, int NIB, int TLO, typename C2>
-__device__ inline void apply_unit(int kind, const C2* xf, const C2* as, const C2* bs, C2* zs,
+__device__ inline void apply_az(const C2* as, const C2* zu, int c, int g, int nq2, int as1,
+                                typename MT<T>::v4 (&yr)[MT<T>::NT],
+                                typename MT<T>::v4 (&yi)[MT<T>::NT]) {
+  C2 zc = zu[g * 16 + c], ac[NIB];
+#pragma unroll
+  for (int t = 0; t < NIB; ++t) ac[t] = as[(16 * t + c) * as1 + g];
+  for (int q = 0; q < nq2; ++q) {
+    C2 zn = zc, an[NIB];
+#pragma unroll
+    for (int t = 0; t < NIB; ++t) an[t] = ac[t];
+    if (q + 1 < nq2) {
+      const int kk = 4 * (q + 1) + g;
+      zn = zu[kk * 16 + c];
+#pragma unroll
+      for (int t = 0; t < NIB; ++t) an[t] = as[(16 * t + c) * as1 + kk];
+    }
+#pragma unroll
+    for (int t = 0; t < NIB; ++t) cmma<T>(yr[TLO + t], yi[TLO + t], ac[t].x, ac[t].y, zc.x, zc.y);
+    zc = zn;
+#pragma unroll
+    for (int t = 0; t < NIB; ++t) ac[t] = an[t];
+  }
+}
+
+// One-sided terms, one unit at a time, into accumulator tiles TLO .. TLO +
+// NIB - 1: Y += A_t X_f[:, col block] (kind 1) or X_f B^T (kind 2).
+template <typename T, int NIB, int TLO, typename C2>
+__device__ inline void apply_unit(int kind, const C2* xf, const C2* as, const C2* bs,
                                   int col, int c, int g, int nq1, int nq2, int xs1, int as1,
                                   int bs1, typename MT<T>::v4 (&yr)[MT<T>::NT],
                                   typename MT<T>::v4 (&yi)[MT<T>::NT]) {
-  typedef typename MT<T>::v4 v4;
-  if (kind == 3) {  // two-sided: Z = X_f B^T (16-column block), then Y += A Z
-    v4 zr[NIB], zi[NIB];
-#pragma unroll
-    for (int t = 0; t < NIB; ++t) {
-      zr[t] = v4{0, 0, 0, 0};
-      zi[t] = v4{0, 0, 0, 0};
-    }
-    C2 bc = bs[col * bs1 + g], xc[NIB];
-#pragma unroll
-    for (int t = 0; t < NIB; ++t) xc[t] = xf[(16 * t + c) * xs1 + g];
-    for (int q = 0; q < nq1; ++q) {
-      C2 bn = bc, xn[NIB];
-#pragma unroll
-      for (int t = 0; t < NIB; ++t) xn[t] = xc[t];
-      if (q + 1 < nq1) {
-        const int kk = 4 * (q + 1) + g;
-        bn = bs[col * bs1 + kk];
-#pragma unroll
-        for (int t = 0; t < NIB; ++t) xn[t] = xf[(16 * t + c) * xs1 + kk];
-      }
-#pragma unroll
-      for (int t = 0; t < NIB; ++t) cmma<T>(zr[t], zi[t], xc[t].x, xc[t].y, bc.x, bc.y);
-      bc = bn;
-#pragma unroll
-      for (int t = 0; t < NIB; ++t) xc[t] = xn[t];
-    }
-#pragma unroll
-    for (int t = 0; t < NIB; ++t) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        C2 v;
-        v.x = zr[t][r];
-        v.y = zi[t][r];
-        zs[(16 * t + MT<T>::drow(g, r)) * 16 + c] = v;
-      }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    C2 zc = zs[g * 16 + c], ac[NIB];
-#pragma unroll
-    for (int t = 0; t < NIB; ++t) ac[t] = as[(16 * t + c) * as1 + g];
-    for (int q = 0; q < nq2; ++q) {
-      C2 zn = zc, an[NIB];
-#pragma unroll
-      for (int t = 0; t < NIB; ++t) an[t] = ac[t];
-      if (q + 1 < nq2) {
-        const int kk = 4 * (q + 1) + g;
-        zn = zs[kk * 16 + c];
-#pragma unroll
-        for (int t = 0; t < NIB; ++t) an[t] = as[(16 * t + c) * as1 + kk];
-      }
-#pragma unroll
-      for (int t = 0; t < NIB; ++t) cmma<T>(yr[TLO + t], yi[TLO + t], ac[t].x, ac[t].y, zc.x, zc.y);
-      zc = zn;
-#pragma unroll
-      for (int t = 0; t < NIB; ++t) ac[t] = an[t];
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  } else if (kind == 1) {  // A only: Y += A X_f[:, col block]
+  if (kind == 1) {  // A only: Y += A X_f[:, col block]
     C2 xc = xf[g * xs1 + col], ac[NIB];
 #pragma unroll
     for (int t = 0; t < NIB; ++t) ac[t] = as[(16 * t + c) * as1 + g];
@@ -416,25 +422,55 @@ __global__ void __launch_bounds__(64 * kApplyWaves) k_apply(const ApplyGroup* __
     if (Bm) stage_op(Bm, d2, D2, bs1, bs, Am ? 1.0 : cr, Am ? 0.0 : ci);  // B only when alone
     __syncthreads();
     const int kind = (Am ? 1 : 0) | (Bm ? 2 : 0);
-    for (int uu = 0; uu < n_my; ++uu) {
-      const int u = tile.u0 + wave + AW * uu;
-      const int fl = u / njb - f_first, jb = u % njb;
-      const c2* xf = xs + (long)fl * D1 * xs1;
-      const int col = 16 * jb + c;
-      const int t_lo = uu * nib;
-#define TENSO_UNIT(NIB, TLO) \
-  apply_unit<T, NIB, TLO>(kind, xf, as, bs, zs, col, c, g, nq1, nq2, xs1, as1, bs1, yr, yi)
-      switch (4 * nib + t_lo) {
-        case 4: TENSO_UNIT(1, 0); break;
-        case 5: TENSO_UNIT(1, 1); break;
-        case 6: TENSO_UNIT(1, 2); break;
-        case 7: TENSO_UNIT(1, 3); break;
-        case 8: TENSO_UNIT(2, 0); break;
-        case 10: TENSO_UNIT(2, 2); break;
-        case 12: TENSO_UNIT(3, 0); break;
-        default: TENSO_UNIT(4, 0); break;
+    if (kind == 3) {
+      // one unit at a time: X_f B^T into the wavefront's slab, then A times it
+      for (int uu = 0; uu < n_my; ++uu) {
+        const int u = tile.u0 + wave + AW * uu;
+        const int fl = u / njb - f_first, jb = u % njb;
+        const c2* xf = xs + (long)fl * D1 * xs1;
+        const int col = 16 * jb + c;
+#define TENSO_ZAZ(NIB, TLO)                                               \
+  apply_z<T, NIB>(xf, bs, zs, col, c, g, nq1, xs1, bs1);                  \
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");                  \
+  __builtin_amdgcn_wave_barrier();                                        \
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");                  \
+  apply_az<T, NIB, TLO>(as, zs, c, g, nq2, as1, yr, yi)
+        switch (4 * nib + uu * nib) {
+          case 4: TENSO_ZAZ(1, 0); break;
+          case 5: TENSO_ZAZ(1, 1); break;
+          case 6: TENSO_ZAZ(1, 2); break;
+          case 7: TENSO_ZAZ(1, 3); break;
+          case 8: TENSO_ZAZ(2, 0); break;
+          case 10: TENSO_ZAZ(2, 2); break;
+          case 12: TENSO_ZAZ(3, 0); break;
+          default: TENSO_ZAZ(4, 0); break;
+        }
+#undef TENSO_ZAZ
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
+    } else {
+      for (int uu = 0; uu < n_my; ++uu) {
+        const int u = tile.u0 + wave + AW * uu;
+        const int fl = u / njb - f_first, jb = u % njb;
+        const c2* xf = xs + (long)fl * D1 * xs1;
+        const int col = 16 * jb + c;
+        const int t_lo = uu * nib;
+#define TENSO_UNIT(NIB, TLO) \
+  apply_unit<T, NIB, TLO>(kind, xf, as, bs, col, c, g, nq1, nq2, xs1, as1, bs1, yr, yi)
+        switch (4 * nib + t_lo) {
+          case 4: TENSO_UNIT(1, 0); break;
+          case 5: TENSO_UNIT(1, 1); break;
+          case 6: TENSO_UNIT(1, 2); break;
+          case 7: TENSO_UNIT(1, 3); break;
+          case 8: TENSO_UNIT(2, 0); break;
+          case 10: TENSO_UNIT(2, 2); break;
+          case 12: TENSO_UNIT(3, 0); break;
+          default: TENSO_UNIT(4, 0); break;
+        }
 #undef TENSO_UNIT
+      }
     }
     if (G.per_term_out) {  // this term's result goes to its own slab
       store_out(reinterpret_cast<T*>(G.Y) + 2 * (long)G.F * d1 * d2 * m);
@@ -1903,8 +1939,8 @@ __global__ void k_step_inc(int* ctr, int value) {
 // ---------------------------------------------------------------------------
 // launchers (host)
 // ---------------------------------------------------------------------------
-size_t apply_lds_bytes(int fp64, int nfl, int d1, int d2, int with_ab) {
-  return (size_t)apply_lds_elems(nfl, d1, d2, with_ab) * (fp64 ? sizeof(double) : sizeof(float));
+size_t apply_lds_bytes(int fp64, int nfl, int d1, int d2) {
+  return (size_t)apply_lds_elems(nfl, d1, d2) * (fp64 ? sizeof(double) : sizeof(float));
 }
 
 // With t0/t1 given, the events are taken by the kernel's own dispatch (start

@@ -20,7 +20,7 @@ namespace tenso {
 hipError_t launch_apply(int fp64, int in_fp64, const ApplyGroup* groups, const ApplyTile* tiles,
                         int n_tiles, const int* step_ctr, size_t lds, hipStream_t s,
                         hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
-size_t apply_lds_bytes(int fp64, int nfl, int d1, int d2, int with_ab);
+size_t apply_lds_bytes(int fp64, int nfl, int d1, int d2);
 hipError_t launch_merge(const MergeOp* op, long n, hipStream_t s);
 hipError_t launch_eig(const EigOp* op, hipStream_t s);
 hipError_t launch_split(const SplitOp* op, hipStream_t s);
@@ -714,7 +714,7 @@ struct Builder {
         const ApplyGroup& g = G.groups[first + tl.group];
         const int njb = (g.d2 + 15) / 16;
         const int nfl = (tl.u0 + tl.nu - 1) / njb - tl.u0 / njb + 1;
-        mx = std::max(mx, apply_lds_bytes(P_.fp64, nfl, g.d1, g.d2, tl.pad));
+        mx = std::max(mx, apply_lds_bytes(P_.fp64, nfl, g.d1, g.d2));
       }
       L.lds = mx;
       // useful work (no padding): pair term F*d1*d2*(d1+d2) complex MACs,
@@ -777,14 +777,14 @@ struct Builder {
     const int nib = (d1 + 15) / 16, njb = (d2 + 15) / 16;
     const int NT = kApplyAccTiles;  // accumulator tiles per wavefront in the kernel
     const size_t budget = kApplyLdsBudget;
-    if (nib > NT || d1 > 64 || d2 > 64 || apply_lds_bytes(P.fp64, 1, d1, d2, 1) > budget)
+    if (nib > NT || d1 > 64 || d2 > 64 || apply_lds_bytes(P.fp64, 1, d1, d2) > budget)
       fail(TENSO_EUNSUPPORTED, "leg dimensions too large for the apply kernel in this precision");
     const long units = F * njb;
     const double per_unit = unit_work(d1, d2) * std::max(1, n_terms);
     long want = std::max<long>(target, (long)std::ceil(units * per_unit / P.tile_work));
     long per = std::max<long>(1, (units + want - 1) / want);
     per = std::min<long>(per, (long)(kApplyMaxUnits / nib));
-    while (per > 1 && apply_lds_bytes(P.fp64, (int)((per + njb - 1) / njb + 1), d1, d2, 1) > budget)
+    while (per > 1 && apply_lds_bytes(P.fp64, (int)((per + njb - 1) / njb + 1), d1, d2) > budget)
       per /= 2;
     return per;
   }
