@@ -2312,6 +2312,7 @@ static void batch_build(tenso_batch& B, hipStream_t s) {
   const size_t n = B.plans.size();
   std::vector<Program> st(n), in(n), rh(n);
   std::vector<double> cost(n, 0.0);
+  std::vector<size_t> chain(n, 0);  // launches of the instance's step program
   for (size_t i = 0; i < n; ++i) {
     tenso_plan& P = *B.plans[i];
     P.par_target = 4;  // the batch supplies the parallelism
@@ -2330,6 +2331,7 @@ static void batch_build(tenso_batch& B, hipStream_t s) {
     st[i] = *P.prog_step;
     in[i] = *P.prog_init;
     for (auto& L : st[i].launches) cost[i] += L.flops;
+    chain[i] = st[i].launches.size();
     Builder b(P, rh[i]);
     b.rho_prog();
     rh[i].rprogs.back().rho_out = (double*)((char*)B.rho_buf + B.rho_off[i]);
@@ -2337,12 +2339,15 @@ static void batch_build(tenso_batch& B, hipStream_t s) {
     resolve(in[i], B.states[i], B.wss[i], B.dts[i], B.drives[i], B.ld);
     resolve(rh[i], B.states[i], B.wss[i], B.dts[i], nullptr, 1);
   }
-  // Parts of the step: instances sorted by their step's apply work and cut
-  // into runs of about equal total work, so the few largest instances (long
-  // QR chains, small launches) share a part and run beside the rest.
+  // Parts of the step: instances sorted by the length of their step's launch
+  // chain (then by apply work) and cut into runs of about equal total work, so
+  // the deep trees share a part and the shallow ones run beside them on short
+  // chains.
   std::vector<size_t> order(n);
   for (size_t i = 0; i < n; ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+    return chain[a] != chain[b] ? chain[a] > chain[b] : cost[a] > cost[b];
+  });
   double total = 0;
   for (double c : cost) total += c;
   const int S = (int)std::max<size_t>(1, std::min<size_t>((size_t)B.n_parts, n));
