@@ -136,9 +136,13 @@ __device__ inline void load_scaled(const T* M, int d, int row, int kk, double cr
 //   Z : 4 wavefronts x D1 x 16  per-wave X_f B^T of one unit
 // with D = 16 * ceil(d / 16).  Every MFMA operand is then one LDS vector load
 // without bounds checks.
+// Row stride of a wavefront's X_f B^T slab in LDS (padded: rows 4 apart map
+// to different banks).
+constexpr int ZS1 = 17;
+
 __host__ __device__ inline long apply_lds_elems(int nfl, int d1, int d2) {
   const long D1 = 16 * ((d1 + 15) / 16), D2 = 16 * ((d2 + 15) / 16);
-  return 2 * (nfl * D1 * (D2 + 1) + D1 * (D1 + 1) + D2 * (D2 + 1) + kApplyWaves * D1 * 16);
+  return 2 * (nfl * D1 * (D2 + 1) + D1 * (D1 + 1) + D2 * (D2 + 1) + kApplyWaves * D1 * ZS1);
 }
 
 template <typename T> struct V2;
@@ -187,7 +191,7 @@ __device__ inline void apply_z(const C2* xf, const C2* bs, C2* zu, int col, int 
       C2 v;
       v.x = zr[t][r];
       v.y = zi[t][r];
-      zu[(16 * t + MT<T>::drow(g, r)) * 16 + c] = v;
+      zu[(16 * t + MT<T>::drow(g, r)) * ZS1 + c] = v;
     }
   }
 }
@@ -197,7 +201,7 @@ template <typename T, int NIB, int TLO, typename C2>
 __device__ inline void apply_az(const C2* as, const C2* zu, int c, int g, int nq2, int as1,
                                 typename MT<T>::v4 (&yr)[MT<T>::NT],
                                 typename MT<T>::v4 (&yi)[MT<T>::NT]) {
-  C2 zc = zu[g * 16 + c], ac[NIB];
+  C2 zc = zu[g * ZS1 + c], ac[NIB];
 #pragma unroll
   for (int t = 0; t < NIB; ++t) ac[t] = as[(16 * t + c) * as1 + g];
   for (int q = 0; q < nq2; ++q) {
@@ -206,7 +210,7 @@ __device__ inline void apply_az(const C2* as, const C2* zu, int c, int g, int nq
     for (int t = 0; t < NIB; ++t) an[t] = ac[t];
     if (q + 1 < nq2) {
       const int kk = 4 * (q + 1) + g;
-      zn = zu[kk * 16 + c];
+      zn = zu[kk * ZS1 + c];
 #pragma unroll
       for (int t = 0; t < NIB; ++t) an[t] = as[(16 * t + c) * as1 + kk];
     }
@@ -298,7 +302,7 @@ __global__ void __launch_bounds__(64 * kApplyWaves) k_apply(const ApplyGroup* __
   c2* xs = smem;
   c2* as = xs + (long)nfl * D1 * xs1;
   c2* bs = as + (long)D1 * as1;
-  c2* zs = bs + (long)D2 * bs1 + (long)wave * D1 * 16;
+  c2* zs = bs + (long)D2 * bs1 + (long)wave * D1 * ZS1;
 
   // stage the tile's input slices (zero padded, compute precision): slice
   // bases once, then lanes over the columns of a row (D2 = 16, 32, 64: 64/D2
