@@ -70,7 +70,7 @@ template <typename T> struct cpx { T re, im; };
 
 template <typename Tin, typename T>
 __device__ inline cpx<T> ldc(const void* base, long idx) {
-  const Tin* p = reinterpret_cast<const Tin*>(base) + 2 * idx;
+  const gp<const Tin> p = gmem(reinterpret_cast<const Tin*>(base)) + 2 * idx;
   return cpx<T>{(T)p[0], (T)p[1]};
 }
 
@@ -79,7 +79,7 @@ __device__ inline void coef_at(const TermRef& t, const double* drive, int ld, in
   cr = t.cre;
   ci = t.cim;
   if (t.slot >= 0 && drive) {
-    double f = drive[(long)t.slot * ld + j];
+    double f = gmem(drive)[(long)t.slot * ld + j];
     cr *= f;
     ci *= f;
   }
@@ -295,7 +295,7 @@ __global__ void __launch_bounds__(64 * kApplyWaves) k_apply(const ApplyGroup* __
   const int nq2 = (d1 + 3) >> 2;  // K steps of A Z
   const long sb = G.P2;
   const long sa = (long)G.P1 * d2 * G.P2;
-  const int step = step_ctr ? *step_ctr : 0;
+  const int step = step_ctr ? gmem(step_ctr)[0] : 0;
   const int jdrv = 4 * step + G.rel;
   const int f_first = tile.u0 / njb;
   const int nfl = (tile.u0 + tile.nu - 1) / njb - f_first + 1;
@@ -362,7 +362,7 @@ __global__ void __launch_bounds__(64 * kApplyWaves) k_apply(const ApplyGroup* __
   }
 
   // write the wavefront's accumulators (its units of this tile) to Yb
-  auto store_out = [&](T* Yb) {
+  auto store_out = [&](gp<T> Yb) {
 #pragma unroll
     for (int ti = 0; ti < NT; ++ti) {
       if (ti < n_my * nib) {
@@ -386,7 +386,7 @@ __global__ void __launch_bounds__(64 * kApplyWaves) k_apply(const ApplyGroup* __
     }
   };
   for (int m = 0; m < G.n_terms; ++m) {
-    const TermRef tr = G.terms[m];
+    const TermRef tr = gmem(G.terms)[m];
     double cr, ci;
     coef_at(tr, G.drive, G.drive_ld, jdrv, cr, ci);
     const T* Am = reinterpret_cast<const T*>(tr.A);
@@ -410,7 +410,8 @@ __global__ void __launch_bounds__(64 * kApplyWaves) k_apply(const ApplyGroup* __
         v.x = 0;
         v.y = 0;
         if (i < d && jok) {
-          const T a0 = M[2 * (i * d + j)], a1 = M[2 * (i * d + j) + 1];
+          const gp<const T> e = gmem(M) + 2 * (i * d + j);
+          const T a0 = e[0], a1 = e[1];
           if (unit) {
             v.x = a0;
             v.y = a1;
@@ -477,7 +478,7 @@ __global__ void __launch_bounds__(64 * kApplyWaves) k_apply(const ApplyGroup* __
       }
     }
     if (G.per_term_out) {  // this term's result goes to its own slab
-      store_out(reinterpret_cast<T*>(G.Y) + 2 * (long)G.F * d1 * d2 * m);
+      store_out(gmem(reinterpret_cast<T*>(G.Y)) + 2 * (long)G.F * d1 * d2 * m);
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         yr[t] = v4{0, 0, 0, 0};
@@ -485,7 +486,7 @@ __global__ void __launch_bounds__(64 * kApplyWaves) k_apply(const ApplyGroup* __
       }
     }
   }
-  if (!G.per_term_out) store_out(reinterpret_cast<T*>(G.Y));
+  if (!G.per_term_out) store_out(gmem(reinterpret_cast<T*>(G.Y)));
 }
 
 // ---------------------------------------------------------------------------
