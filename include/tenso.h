@@ -51,7 +51,7 @@ extern "C" {
 #define TENSO_ENOMEM       -2   /* workspace too small / size beyond the budget */
 #define TENSO_EHIP         -3   /* a HIP runtime error (message carries hipGetErrorString) */
 #define TENSO_ENUMERIC     -4   /* NaN or infinity in a state after stepping */
-#define TENSO_EUNSUPPORTED -5   /* valid input outside what this build implements */
+#define TENSO_EUNSUPPORTED -5   /* valid input outside what this library implements */
 
 typedef struct { double re, im; } tenso_c128;
 typedef struct tenso_tree tenso_tree;
