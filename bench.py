@@ -50,7 +50,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2", choices=["c0", "c1", "c2"])
+    ap.add_argument("--workload", default="c2", choices=["c0", "c1", "c2", "c3", "c4"],
+                    help="c2 (default): 512-instance ps1 batch; c0, c1: single ps1 instances; "
+                         "c3: ps2 on the structured-bath ternary tree; c4: the surrogate pipeline")
     ap.add_argument("--instances", type=int, default=512, help="batch size for c2")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU comparison")
@@ -279,6 +281,109 @@ def main():
         copy_probe()
 
 
+def ps2_main(a):
+    """Adaptive-rank (ps2) propagation of the structured-bath ternary tree at rank
+    cap 4, one instance."""
+    import ctypes as C
+    import numpy as np
+    import torch
+    import workloads
+    from paper_2603_17711_amd import api
+    from paper_2603_17711_amd._lib import check, lib
+    cap = 4
+    inst = workloads.config3(n_steps=a.steps + a.warmup)
+    wname = "structured bath K=24 N=10 ternary ps2 (eps 1e-6, rank cap 4, dt 0.01)"
+
+    def run(precision, steps, warmup, profile=False):
+        plan = api.build_instance(inst, precision=precision, rank=cap)
+        plan.step_adaptive(warmup, inst.dt, inst.eps, cap)
+        torch.cuda.synchronize()
+        if profile:
+            check(lib().tenso_profile(1))
+        t0 = time.perf_counter()
+        plan.step_adaptive(steps, inst.dt, inst.eps, cap, t0=warmup * inst.dt)
+        torch.cuda.synchronize()
+        return plan, time.perf_counter() - t0
+
+    plan, dt_mixed = run(api.FP32, a.steps, a.warmup)
+    value = a.steps / dt_mixed
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "steps/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(1e3 * dt_mixed / a.steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64 contractions (fp32 MFMA), f64 master/QR/eigen", "data": "synthetic",
+        "config": {"workload": wname, "instances": 1, "precision": "mixed",
+                   "max_rank_reached": int(max(plan.ranks()))},
+    }
+    if not a.no_fp64:
+        st = max(1, a.steps // 2)
+        _, dt64 = run(api.FP64, st, 1)
+        out["fp64_gpu_value"] = round(st / dt64, 3)
+        out["speedup_vs_fp64_gpu"] = round(value / (st / dt64), 3)
+    prof_steps = max(1, min(a.steps, 10))
+    _, _ = run(api.FP32, prof_steps, 1, profile=True)
+    ms, n, fl, by = C.c_double(), C.c_int64(), C.c_double(), C.c_double()
+    check(lib().tenso_profile_stats(C.byref(ms), C.byref(n), C.byref(fl), C.byref(by)))
+    check(lib().tenso_profile(0))
+    avg_ms = ms.value / max(1, n.value)
+    achieved = fl.value / max(1, n.value) / (avg_ms * 1e-3) / 1e12
+    out["roofline"] = {
+        "kernel": "k_apply<float> (SOP contraction, MFMA 16x16x4 f32)",
+        "bound": "mfma", "achieved": round(achieved, 4), "peak": PEAK_FP32_MFMA,
+        "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MFMA, 6), "traffic": None,
+        "avg_launch_us": round(1e3 * avg_ms, 3), "launches": int(n.value),
+        "algorithmic_flops_per_launch": fl.value / max(1, n.value),
+        "algorithmic_bytes_per_launch": by.value / max(1, n.value),
+    }
+    if not a.no_cpu:
+        from threadpoolctl import threadpool_limits
+        from oracle.run import propagate
+        from oracle.ttn import trace_distance
+        n_sample = 3
+        cinst = workloads.config3(n_steps=n_sample)
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            _, ro, _, _ = propagate(cinst, n_steps=n_sample, every=n_sample, max_rank=cap)
+            tc = time.perf_counter() - t0
+        out["cpu_baseline"] = {
+            "value": round(n_sample / tc, 4), "unit": "steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_sample} ps2 steps of the same workload, FP64 NumPy oracle, 1 BLAS thread"}
+        p2 = api.build_instance(cinst, precision=api.FP32, rank=cap)
+        p2.step_adaptive(n_sample, cinst.dt, cinst.eps, cap)
+        out["trace_distance_vs_oracle"] = {"value": trace_distance(p2.rho(), ro[-1]),
+                                           "steps": n_sample}
+    print(json.dumps(out))
+
+
+def surrogate_main(a):
+    """The surrogate pipeline (config 4) at a bounded size: TTN-HEOM trajectories
+    on training seeds, BF16 MLP training, monitored rollout on held-out seeds,
+    TTN fallback for tripped trajectories, judged against TTN-HEOM."""
+    from paper_2603_17711_amd import surrogate
+    n_train, n_held, n_steps, epochs = 512, 64, 1000, 10
+    res = surrogate.experiment(n_train, n_held, n_steps=n_steps, epochs=epochs, log=lambda *x: None)
+    value = n_held * n_steps / res["surrogate_s"]
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "trajectory-steps/s (surrogate)",
+        "n_gpus": 1, "steps": n_steps, "warmup": 0,
+        "ms_per_step": round(1e3 * res["surrogate_s"] / n_steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16 MLP (fp32 accumulate); c64/f64 TTN fallback", "data": "synthetic",
+        "config": {"workload": f"driven spin-boson surrogate: {n_train} training and {n_held} "
+                               f"held-out trajectories x {n_steps} steps, {epochs} epochs",
+                   "instances": n_held, "precision": "mixed"},
+        "ttn_batched_value": round(n_held * n_steps / res["ttn_heldout_s"], 2),
+        "gain_vs_ttn_batched": round(res["gain"], 3),
+        "monitor_trips": res["monitor_trips"],
+        "spot_checked": res["spot_checked"], "spot_trips": res["spot_trips"],
+        "max_feature_error_vs_ttn": res["max_feature_error"],
+        "median_feature_error_vs_ttn": res["median_feature_error"],
+        "train_s": round(res["train_s"], 3), "train_mse_first_last": res["train_mse_first_last"],
+        "roofline": None,
+    }
+    print(json.dumps(out))
+
+
 def run_main(a):
     import numpy as np
     import torch
@@ -286,6 +391,10 @@ def run_main(a):
     from paper_2603_17711_amd import api
     if a.workload == "c2":
         return batch_main(a)
+    if a.workload == "c3":
+        return ps2_main(a)
+    if a.workload == "c4":
+        return surrogate_main(a)
 
     inst, wname = instance(a.workload, a.steps + a.warmup)
     plan, dt_mixed = timed_run(inst, api.FP32, a.steps, a.warmup)
