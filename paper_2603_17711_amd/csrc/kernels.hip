@@ -1624,45 +1624,97 @@ __global__ void __launch_bounds__(256) k_eig(const EigOp* __restrict__ ops) {
   const int n = op.side == 0 ? op.rows : op.cols;
   const int m = op.side == 0 ? op.cols : op.rows;
   const z2* Th = reinterpret_cast<const z2*>(op.Theta);
-  __shared__ z2 G[64 * 64];
-  __shared__ z2 U[64 * 64];
+  // row stride 65: consecutive rows of a column fall in different LDS banks
+  constexpr int LD = 65;
+  __shared__ z2 G[64 * LD];
+  __shared__ z2 U[64 * LD];
   __shared__ double rot[32][4];  // c, s, cos(phi), sin(phi)
   __shared__ int pr[32][2];
   __shared__ double offmax, diagmax;
   const int tid = threadIdx.x;
-  // Gram: side 0: G[i][j] = sum_c Th[i][c] conj(Th[j][c]); side 1: sum_r conj(Th[r][i]) Th[r][j]
-  for (int e = tid; e < n * n; e += 256) {
-    const int i = e / n, j = e % n;
-    double sr = 0, si = 0;
-    for (int q = 0; q < m; ++q) {
-      z2 x, y;
+  // Gram: side 0: G[i][j] = sum_c Th[i][c] conj(Th[j][c]); side 1: sum_r conj(Th[r][i]) Th[r][j].
+  // Theta is staged 64 entries of the summed index at a time into U as
+  // S[q][i] (coalesced loads along whichever index is contiguous); each
+  // thread accumulates a 4x4 block of G (rows bi + 16a, cols bj + 16b), so
+  // every LDS read feeds four products.  Side 1 is the conjugate of the
+  // side-0 sum over S.
+  {
+    const gp<const z2> T = gmem(Th);
+    const int bi = tid >> 4, bj = tid & 15;
+    z2 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = z2{0.0, 0.0};
+    for (int q0 = 0; q0 < m; q0 += 64) {
+      const int kq = min(64, m - q0);
+      __syncthreads();
       if (op.side == 0) {
-        x = Th[(long)i * op.cols + q];
-        y = Th[(long)j * op.cols + q];
-        sr += x.r * y.r + x.i * y.i;  // x * conj(y)
-        si += x.i * y.r - x.r * y.i;
+        for (int e = tid; e < 64 * n; e += 256) {
+          const int i = e >> 6, qq = e & 63;
+          z2 v{0.0, 0.0};
+          if (qq < kq) v = T[(long)i * op.cols + q0 + qq];
+          U[qq * LD + i] = v;
+        }
       } else {
-        x = Th[(long)q * op.cols + i];
-        y = Th[(long)q * op.cols + j];
-        sr += x.r * y.r + x.i * y.i;  // conj(x) * y
-        si += x.r * y.i - x.i * y.r;
+        for (int e = tid; e < kq * n; e += 256) {
+          const int qq = e / n, i = e - qq * n;
+          U[qq * LD + i] = T[(long)(q0 + qq) * op.cols + i];
+        }
+      }
+      __syncthreads();
+      for (int qq = 0; qq < kq; ++qq) {
+        z2 x[4], y[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          x[a] = U[qq * LD + bi + 16 * a];
+          y[a] = U[qq * LD + bj + 16 * a];
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {  // x * conj(y)
+            acc[a][b].r += x[a].r * y[b].r + x[a].i * y[b].i;
+            acc[a][b].i += x[a].i * y[b].r - x[a].r * y[b].i;
+          }
       }
     }
-    G[i * 64 + j] = z2{sr, si};
-    U[i * 64 + j] = z2{i == j ? 1.0 : 0.0, 0.0};
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int i = bi + 16 * a, j = bj + 16 * b;
+        if (i < n && j < n)
+          G[i * LD + j] = z2{acc[a][b].r, op.side == 0 ? acc[a][b].i : -acc[a][b].i};
+      }
+    for (int e = tid; e < n * n; e += 256) {
+      const int i = e / n, j = e % n;
+      U[i * LD + j] = z2{i == j ? 1.0 : 0.0, 0.0};
+    }
   }
   __syncthreads();
   const int np = (n + 1) / 2;            // pairs per round (a dummy player when n is odd)
   const int nplay = 2 * np;
+  __shared__ double pmax[2][256];
   for (int sweep = 0; sweep < 40; ++sweep) {
+    {  // largest off-diagonal modulus and diagonal magnitude, all threads
+      double om = 0, dm = 0;
+      for (int e = tid; e < n * n; e += 256) {
+        const int i = e / n, j = e % n;
+        const z2 g = G[i * LD + j];
+        if (j > i) om = fmax(om, sqrt(g.r * g.r + g.i * g.i));
+        else if (j == i) dm = fmax(dm, fabs(g.r));
+      }
+      pmax[0][tid] = om;
+      pmax[1][tid] = dm;
+    }
+    __syncthreads();
     if (tid == 0) {
       double om = 0, dm = 0;
-      for (int i = 0; i < n; ++i) {
-        dm = fmax(dm, fabs(G[i * 64 + i].r));
-        for (int j = i + 1; j < n; ++j) {
-          const z2 g = G[i * 64 + j];
-          om = fmax(om, sqrt(g.r * g.r + g.i * g.i));
-        }
+      for (int t = 0; t < 256; ++t) {
+        om = fmax(om, pmax[0][t]);
+        dm = fmax(dm, pmax[1][t]);
       }
       offmax = om;
       diagmax = dm;
@@ -1688,10 +1740,10 @@ __global__ void __launch_bounds__(256) k_eig(const EigOp* __restrict__ ops) {
         pr[tid][1] = q;
         double c = 1, sn = 0, cph = 1, sph = 0;
         if (q < n) {
-          const z2 g = G[p * 64 + q];
+          const z2 g = G[p * LD + q];
           const double h = sqrt(g.r * g.r + g.i * g.i);
           if (h > 1e-300) {
-            const double a = G[p * 64 + p].r, b = G[q * 64 + q].r;
+            const double a = G[p * LD + p].r, b = G[q * LD + q].r;
             const double zeta = (b - a) / (2.0 * h);
             const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
             c = 1.0 / sqrt(1.0 + t * t);
@@ -1706,48 +1758,60 @@ __global__ void __launch_bounds__(256) k_eig(const EigOp* __restrict__ ops) {
         rot[tid][3] = sph;
       }
       __syncthreads();
-      // columns: G <- G J and U <- U J, J = [[c, s], [-s e^{-i phi}, c e^{-i phi}]]
+      // G <- J^H G J, J = [[c, s], [-s e^{-i phi}, c e^{-i phi}]] per pair, on
+      // the 2 x 2 blocks (rows of pair a, columns of pair b): columns first,
+      // then rows, as two separate passes would; every element is in one
+      // block.  The dummy pair of an odd n (q = n) rotates by the identity, so
+      // its block entries with index n are absent.
+      for (int e = tid; e < np * np; e += 256) {
+        const int a = e / np, b = e % np;
+        const int pa = pr[a][0], qa = pr[a][1], pb = pr[b][0], qb = pr[b][1];
+        const bool ra = qa < n, rb = qb < n;
+        const double ca = rot[a][0], sa = rot[a][1], cb = rot[b][0], sb = rot[b][1];
+        const z2 epa{rot[a][2], rot[a][3]};   // e^{i phi_a}
+        const z2 emb{rot[b][2], -rot[b][3]};  // e^{-i phi_b}
+        const z2 m00 = G[pa * LD + pb];
+        z2 m01{0.0, 0.0}, m10{0.0, 0.0}, m11{0.0, 0.0};
+        if (rb) m01 = G[pa * LD + qb];
+        if (ra) m10 = G[qa * LD + pb];
+        if (ra && rb) m11 = G[qa * LD + qb];
+        const z2 t01 = zmul(m01, emb), t11 = zmul(m11, emb);
+        const z2 n00{cb * m00.r - sb * t01.r, cb * m00.i - sb * t01.i};
+        const z2 n01{sb * m00.r + cb * t01.r, sb * m00.i + cb * t01.i};
+        const z2 n10{cb * m10.r - sb * t11.r, cb * m10.i - sb * t11.i};
+        const z2 n11{sb * m10.r + cb * t11.r, sb * m10.i + cb * t11.i};
+        const z2 u10 = zmul(n10, epa), u11 = zmul(n11, epa);
+        G[pa * LD + pb] = z2{ca * n00.r - sa * u10.r, ca * n00.i - sa * u10.i};
+        if (rb) G[pa * LD + qb] = z2{ca * n01.r - sa * u11.r, ca * n01.i - sa * u11.i};
+        if (ra) G[qa * LD + pb] = z2{sa * n00.r + ca * u10.r, sa * n00.i + ca * u10.i};
+        if (ra && rb) G[qa * LD + qb] = z2{sa * n01.r + ca * u11.r, sa * n01.i + ca * u11.i};
+      }
+      // U <- U J (columns)
       for (int e = tid; e < np * n; e += 256) {
         const int k = e / n, row = e % n;
         const int p = pr[k][0], q = pr[k][1];
         if (q >= n) continue;
         const double c = rot[k][0], sn = rot[k][1], cph = rot[k][2], sph = rot[k][3];
         const z2 emi{cph, -sph};  // e^{-i phi}
-        for (int w = 0; w < 2; ++w) {
-          z2* A = w == 0 ? G : U;
-          const z2 xp = A[row * 64 + p], xq = A[row * 64 + q];
-          const z2 xq_e = zmul(xq, emi);
-          A[row * 64 + p] = z2{c * xp.r - sn * xq_e.r, c * xp.i - sn * xq_e.i};
-          A[row * 64 + q] = z2{sn * xp.r + c * xq_e.r, sn * xp.i + c * xq_e.i};
-        }
-      }
-      __syncthreads();
-      // rows: G <- J^H G
-      for (int e = tid; e < np * n; e += 256) {
-        const int k = e / n, col = e % n;
-        const int p = pr[k][0], q = pr[k][1];
-        if (q >= n) continue;
-        const double c = rot[k][0], sn = rot[k][1], cph = rot[k][2], sph = rot[k][3];
-        const z2 epi{cph, sph};  // e^{i phi}
-        const z2 xp = G[p * 64 + col], xq = G[q * 64 + col];
-        const z2 xq_e = zmul(xq, epi);
-        G[p * 64 + col] = z2{c * xp.r - sn * xq_e.r, c * xp.i - sn * xq_e.i};
-        G[q * 64 + col] = z2{sn * xp.r + c * xq_e.r, sn * xp.i + c * xq_e.i};
+        const z2 xp = U[row * LD + p], xq = U[row * LD + q];
+        const z2 xq_e = zmul(xq, emi);
+        U[row * LD + p] = z2{c * xp.r - sn * xq_e.r, c * xp.i - sn * xq_e.i};
+        U[row * LD + q] = z2{sn * xp.r + c * xq_e.r, sn * xp.i + c * xq_e.i};
       }
       __syncthreads();
     }
   }
   // descending order: rank of each eigenvalue (ties by index)
   for (int j = tid; j < n; j += 256) {
-    const double lj = G[j * 64 + j].r;
+    const double lj = G[j * LD + j].r;
     int rank = 0;
     for (int i = 0; i < n; ++i) {
-      const double li = G[i * 64 + i].r;
+      const double li = G[i * LD + i].r;
       if (li > lj || (li == lj && i < j)) ++rank;
     }
     op.evals[rank] = lj;
     for (int row = 0; row < n; ++row) {
-      const z2 v = U[row * 64 + j];
+      const z2 v = U[row * LD + j];
       op.evecs[2 * ((long)row * n + rank)] = v.r;
       op.evecs[2 * ((long)row * n + rank) + 1] = v.i;
     }
