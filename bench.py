@@ -316,10 +316,10 @@ def ps2_main(a):
                    "max_rank_reached": int(max(plan.ranks()))},
     }
     if not a.no_fp64:
-        st = max(1, a.steps // 2)
-        _, dt64 = run(api.FP64, st, 1)
-        out["fp64_gpu_value"] = round(st / dt64, 3)
-        out["speedup_vs_fp64_gpu"] = round(value / (st / dt64), 3)
+        # the same steps as the mixed run: the cost of a ps2 step grows with the ranks
+        _, dt64 = run(api.FP64, a.steps, a.warmup)
+        out["fp64_gpu_value"] = round(a.steps / dt64, 3)
+        out["speedup_vs_fp64_gpu"] = round(value / (a.steps / dt64), 3)
     prof_steps = max(1, min(a.steps, 10))
     _, _ = run(api.FP32, prof_steps, 1, profile=True)
     ms, n, fl, by = C.c_double(), C.c_int64(), C.c_double(), C.c_double()

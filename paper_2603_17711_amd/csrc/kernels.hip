@@ -1618,62 +1618,65 @@ __global__ void __launch_bounds__(256) k_merge(const MergeOp* __restrict__ ops) 
 }
 
 // Cyclic Jacobi on the n x n Hermitian Gram matrix held in LDS (n <= 64),
-// parallel rounds of the circle-method pairing.
-__global__ void __launch_bounds__(256) k_eig(const EigOp* __restrict__ ops) {
+// parallel rounds of the circle-method pairing.  1024 lanes: in each round
+// lane (a, b) = (tid / 32, tid % 32) rotates the 2 x 2 block on the rows of
+// pair a and the columns of pair b, and two eigenvector entries; sixteen
+// waves per CU hide the LDS latency that a round otherwise waits on.
+constexpr int kEigThreads = 1024;
+__global__ void __launch_bounds__(kEigThreads) k_eig(const EigOp* __restrict__ ops) {
   const EigOp op = ops[blockIdx.x];
   const int n = op.side == 0 ? op.rows : op.cols;
   const int m = op.side == 0 ? op.cols : op.rows;
-  const z2* Th = reinterpret_cast<const z2*>(op.Theta);
   // row stride 65: consecutive rows of a column fall in different LDS banks
   constexpr int LD = 65;
   __shared__ z2 G[64 * LD];
   __shared__ z2 U[64 * LD];
   __shared__ double rot[32][4];  // c, s, cos(phi), sin(phi)
   __shared__ int pr[32][2];
-  __shared__ double offmax, diagmax;
+  __shared__ double pmax[2][kEigThreads / 64];
+  __shared__ int order[64];
   const int tid = threadIdx.x;
   // Gram: side 0: G[i][j] = sum_c Th[i][c] conj(Th[j][c]); side 1: sum_r conj(Th[r][i]) Th[r][j].
   // Theta is staged 64 entries of the summed index at a time into U as
-  // S[q][i] (coalesced loads along whichever index is contiguous); each
-  // thread accumulates a 4x4 block of G (rows bi + 16a, cols bj + 16b), so
-  // every LDS read feeds four products.  Side 1 is the conjugate of the
-  // side-0 sum over S.
+  // S[q][i] (coalesced loads along whichever index is contiguous); each lane
+  // accumulates a 2 x 2 block of G (rows bi + 32a, cols bj + 32b).  Side 1 is
+  // the conjugate of the side-0 sum over S.
   {
-    const gp<const z2> T = gmem(Th);
-    const int bi = tid >> 4, bj = tid & 15;
-    z2 acc[4][4];
+    const gp<const z2> T = gmem(reinterpret_cast<const z2*>(op.Theta));
+    const int bi = tid >> 5, bj = tid & 31;
+    z2 acc[2][2];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] = z2{0.0, 0.0};
+      for (int b = 0; b < 2; ++b) acc[a][b] = z2{0.0, 0.0};
     for (int q0 = 0; q0 < m; q0 += 64) {
       const int kq = min(64, m - q0);
       __syncthreads();
       if (op.side == 0) {
-        for (int e = tid; e < 64 * n; e += 256) {
+        for (int e = tid; e < 64 * n; e += kEigThreads) {
           const int i = e >> 6, qq = e & 63;
           z2 v{0.0, 0.0};
           if (qq < kq) v = T[(long)i * op.cols + q0 + qq];
           U[qq * LD + i] = v;
         }
       } else {
-        for (int e = tid; e < kq * n; e += 256) {
+        for (int e = tid; e < kq * n; e += kEigThreads) {
           const int qq = e / n, i = e - qq * n;
           U[qq * LD + i] = T[(long)(q0 + qq) * op.cols + i];
         }
       }
       __syncthreads();
       for (int qq = 0; qq < kq; ++qq) {
-        z2 x[4], y[4];
+        z2 x[2], y[2];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          x[a] = U[qq * LD + bi + 16 * a];
-          y[a] = U[qq * LD + bj + 16 * a];
+        for (int a = 0; a < 2; ++a) {
+          x[a] = U[qq * LD + bi + 32 * a];
+          y[a] = U[qq * LD + bj + 32 * a];
         }
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < 2; ++a)
 #pragma unroll
-          for (int b = 0; b < 4; ++b) {  // x * conj(y)
+          for (int b = 0; b < 2; ++b) {  // x * conj(y)
             acc[a][b].r += x[a].r * y[b].r + x[a].i * y[b].i;
             acc[a][b].i += x[a].i * y[b].r - x[a].r * y[b].i;
           }
@@ -1681,55 +1684,60 @@ __global__ void __launch_bounds__(256) k_eig(const EigOp* __restrict__ ops) {
     }
     __syncthreads();
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int i = bi + 16 * a, j = bj + 16 * b;
+      for (int b = 0; b < 2; ++b) {
+        const int i = bi + 32 * a, j = bj + 32 * b;
         if (i < n && j < n)
           G[i * LD + j] = z2{acc[a][b].r, op.side == 0 ? acc[a][b].i : -acc[a][b].i};
       }
-    for (int e = tid; e < n * n; e += 256) {
-      const int i = e / n, j = e % n;
+    for (int e = tid; e < n * n; e += kEigThreads) {
+      const int i = e / n, j = e - i * n;
       U[i * LD + j] = z2{i == j ? 1.0 : 0.0, 0.0};
     }
   }
   __syncthreads();
-  const int np = (n + 1) / 2;            // pairs per round (a dummy player when n is odd)
-  const int nplay = 2 * np;
-  __shared__ double pmax[2][256];
+  const int np = (n + 1) / 2;  // pairs per round (a dummy player when n is odd)
+  const int nr = 2 * np - 1;   // rounds per sweep; player nr stays in place
+  const int ba = tid >> 5, bb = tid & 31;
   for (int sweep = 0; sweep < 40; ++sweep) {
-    {  // largest off-diagonal modulus and diagonal magnitude, all threads
+    {  // largest off-diagonal modulus and diagonal magnitude
       double om = 0, dm = 0;
-      for (int e = tid; e < n * n; e += 256) {
-        const int i = e / n, j = e % n;
+      for (int e = tid; e < n * n; e += kEigThreads) {
+        const int i = e / n, j = e - i * n;
         const z2 g = G[i * LD + j];
         if (j > i) om = fmax(om, sqrt(g.r * g.r + g.i * g.i));
         else if (j == i) dm = fmax(dm, fabs(g.r));
       }
-      pmax[0][tid] = om;
-      pmax[1][tid] = dm;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      double om = 0, dm = 0;
-      for (int t = 0; t < 256; ++t) {
-        om = fmax(om, pmax[0][t]);
-        dm = fmax(dm, pmax[1][t]);
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        om = fmax(om, __shfl_xor(om, o));
+        dm = fmax(dm, __shfl_xor(dm, o));
       }
-      offmax = om;
-      diagmax = dm;
+      if ((tid & 63) == 0) {
+        pmax[0][tid >> 6] = om;
+        pmax[1][tid >> 6] = dm;
+      }
     }
     __syncthreads();
-    if (offmax <= 1e-15 * diagmax || offmax == 0.0) break;
-    for (int round = 0; round < nplay - 1; ++round) {
+    double offmax = 0, diagmax = 0;
+#pragma unroll
+    for (int w = 0; w < kEigThreads / 64; ++w) {
+      offmax = fmax(offmax, pmax[0][w]);
+      diagmax = fmax(diagmax, pmax[1][w]);
+    }
+    if (offmax <= 1e-15 * diagmax || offmax == 0.0) break;  // the same decision in every lane
+    for (int round = 0; round < nr; ++round) {
       if (tid < np) {
         int p, q;
         if (tid == 0) {
           p = round;
-          q = nplay - 1;
+          q = nr;
         } else {
-          p = (round + tid) % (nplay - 1);
-          q = (round - tid + (nplay - 1)) % (nplay - 1);
+          p = round + tid;
+          if (p >= nr) p -= nr;
+          q = round - tid;
+          if (q < 0) q += nr;
         }
         if (p > q) {
           const int t = p;
@@ -1759,17 +1767,16 @@ __global__ void __launch_bounds__(256) k_eig(const EigOp* __restrict__ ops) {
       }
       __syncthreads();
       // G <- J^H G J, J = [[c, s], [-s e^{-i phi}, c e^{-i phi}]] per pair, on
-      // the 2 x 2 blocks (rows of pair a, columns of pair b): columns first,
+      // the 2 x 2 block (rows of pair ba, columns of pair bb): columns first,
       // then rows, as two separate passes would; every element is in one
       // block.  The dummy pair of an odd n (q = n) rotates by the identity, so
       // its block entries with index n are absent.
-      for (int e = tid; e < np * np; e += 256) {
-        const int a = e / np, b = e % np;
-        const int pa = pr[a][0], qa = pr[a][1], pb = pr[b][0], qb = pr[b][1];
+      if (ba < np && bb < np) {
+        const int pa = pr[ba][0], qa = pr[ba][1], pb = pr[bb][0], qb = pr[bb][1];
         const bool ra = qa < n, rb = qb < n;
-        const double ca = rot[a][0], sa = rot[a][1], cb = rot[b][0], sb = rot[b][1];
-        const z2 epa{rot[a][2], rot[a][3]};   // e^{i phi_a}
-        const z2 emb{rot[b][2], -rot[b][3]};  // e^{-i phi_b}
+        const double ca = rot[ba][0], sa = rot[ba][1], cb = rot[bb][0], sb = rot[bb][1];
+        const z2 epa{rot[ba][2], rot[ba][3]};   // e^{i phi_a}
+        const z2 emb{rot[bb][2], -rot[bb][3]};  // e^{-i phi_b}
         const z2 m00 = G[pa * LD + pb];
         z2 m01{0.0, 0.0}, m10{0.0, 0.0}, m11{0.0, 0.0};
         if (rb) m01 = G[pa * LD + qb];
@@ -1786,35 +1793,42 @@ __global__ void __launch_bounds__(256) k_eig(const EigOp* __restrict__ ops) {
         if (ra) G[qa * LD + pb] = z2{sa * n00.r + ca * u10.r, sa * n00.i + ca * u10.i};
         if (ra && rb) G[qa * LD + qb] = z2{sa * n01.r + ca * u11.r, sa * n01.i + ca * u11.i};
       }
-      // U <- U J (columns)
-      for (int e = tid; e < np * n; e += 256) {
-        const int k = e / n, row = e % n;
-        const int p = pr[k][0], q = pr[k][1];
-        if (q >= n) continue;
-        const double c = rot[k][0], sn = rot[k][1], cph = rot[k][2], sph = rot[k][3];
-        const z2 emi{cph, -sph};  // e^{-i phi}
-        const z2 xp = U[row * LD + p], xq = U[row * LD + q];
-        const z2 xq_e = zmul(xq, emi);
-        U[row * LD + p] = z2{c * xp.r - sn * xq_e.r, c * xp.i - sn * xq_e.i};
-        U[row * LD + q] = z2{sn * xp.r + c * xq_e.r, sn * xp.i + c * xq_e.i};
+      // U <- U J (columns): entry (row, pair k), two per lane
+#pragma unroll
+      for (int it = 0; it < 2; ++it) {
+        const int e = tid + it * kEigThreads;
+        const int k = e >> 6, row = e & 63;
+        if (k < np && row < n) {
+          const int p = pr[k][0], q = pr[k][1];
+          if (q < n) {
+            const double c = rot[k][0], sn = rot[k][1];
+            const z2 emi{rot[k][2], -rot[k][3]};  // e^{-i phi}
+            const z2 xp = U[row * LD + p], xq = U[row * LD + q];
+            const z2 xq_e = zmul(xq, emi);
+            U[row * LD + p] = z2{c * xp.r - sn * xq_e.r, c * xp.i - sn * xq_e.i};
+            U[row * LD + q] = z2{sn * xp.r + c * xq_e.r, sn * xp.i + c * xq_e.i};
+          }
+        }
       }
       __syncthreads();
     }
   }
   // descending order: rank of each eigenvalue (ties by index)
-  for (int j = tid; j < n; j += 256) {
-    const double lj = G[j * LD + j].r;
+  if (tid < n) {
+    const double lj = G[tid * LD + tid].r;
     int rank = 0;
     for (int i = 0; i < n; ++i) {
       const double li = G[i * LD + i].r;
-      if (li > lj || (li == lj && i < j)) ++rank;
+      if (li > lj || (li == lj && i < tid)) ++rank;
     }
-    op.evals[rank] = lj;
-    for (int row = 0; row < n; ++row) {
-      const z2 v = U[row * LD + j];
-      op.evecs[2 * ((long)row * n + rank)] = v.r;
-      op.evecs[2 * ((long)row * n + rank) + 1] = v.i;
-    }
+    order[tid] = rank;
+    gmem(op.evals)[rank] = lj;
+  }
+  __syncthreads();
+  const gp<z2> ev = gmem(reinterpret_cast<z2*>(op.evecs));
+  for (int e = tid; e < n * n; e += kEigThreads) {
+    const int row = e / n, j = e - row * n;
+    ev[(long)row * n + order[j]] = U[row * LD + j];
   }
 }
 
@@ -2110,7 +2124,7 @@ hipError_t launch_merge(const MergeOp* op, long n, hipStream_t s) {
   return hipGetLastError();
 }
 hipError_t launch_eig(const EigOp* op, hipStream_t s) {
-  hipLaunchKernelGGL(k_eig, dim3(1), dim3(256), 0, s, op);
+  hipLaunchKernelGGL(k_eig, dim3(1), dim3(kEigThreads), 0, s, op);
   return hipGetLastError();
 }
 hipError_t launch_split(const SplitOp* op, hipStream_t s) {
