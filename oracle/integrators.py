@@ -34,9 +34,12 @@ Readings (documented):
 
 Pins (tests): at full rank both sweeps equal exact dense propagation up to the
 RK4 error; results do not depend on the tree shape at full rank; ps2 with
-eps = 0 and a large rank cap equals dense propagation.  Truncated-rank
-trajectories have no independent pin ("parity unpinned" beyond the trend
-tests in rank and depth).
+eps = 0 and a large rank cap equals dense propagation.  At truncated rank,
+a generator whose terms each act on one end keeps the exact solution
+(x)_e exp(t A_e) Omega(0) at the ranks of Omega(0), and both sweeps
+reproduce that closed form up to the RK4 error.  Truncated-rank
+trajectories of coupled generators (the HEOM workloads) have no independent
+pin ("parity unpinned" beyond the trend tests in rank and depth).
 """
 import numpy as np
 

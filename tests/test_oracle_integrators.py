@@ -7,17 +7,26 @@
 * gauge covariance: random unitaries inserted on saturated bonds leave the
   trajectory unchanged;
 * a time-dependent drive with zero bath coupling matches the 2x2 von Neumann
-  equation integrated to tight tolerance."""
+  equation integrated to tight tolerance;
+* truncated rank, exactness on the manifold: a generator whose terms each act
+  on one end only keeps the exact solution (x)_e exp(t A_e) Omega(0) at the
+  TTN ranks of Omega(0), so the tangent projection drops nothing and both
+  sweeps reproduce it at truncated rank up to RK4 error (a two-end term
+  breaks this, which shows the ranks really truncate).  A wrong sign of the
+  backward bond flow, or a skipped one, fails it by O(1)."""
 import copy
 
 import numpy as np
 import pytest
 from scipy.integrate import solve_ivp
+from scipy.linalg import expm
 
 from oracle.bath import bath_features
 from oracle.integrators import Propagator
-from oracle.sop import dense_propagate, heom_terms
-from oracle.ttn import Tree, initial_state, mode_product, nary_tree, trace_distance, train_tree
+from oracle.sop import dense_generator, dense_propagate, heom_terms
+from oracle.ttn import (Tree, contract_dense, initial_state, mode_product, nary_tree, trace_distance,
+                        train_tree)
+from tests.oracle_helpers import canonicalize_root, rand_cores
 
 SZ = np.diag([1.0, -1.0]).astype(complex)
 SX = np.array([[0, 1], [1, 0]], complex)
@@ -132,3 +141,80 @@ def test_depth_convergence_trend():
         errs.append(trace_distance(dense_propagate(terms, dims, RHO0, 0.02, n, every=n)[-1], ref))
     assert errs[0] > errs[1] > errs[2]
 
+
+
+def single_leg_terms(end_dims, rng, per_end=2):
+    """Random terms, each with one non-identity factor."""
+    terms = []
+    for e, d in enumerate(end_dims):
+        for _ in range(per_end):
+            X = (rng.normal(size=(d, d)) + 1j * rng.normal(size=(d, d))) / np.sqrt(d)
+            terms.append({'coef': 0.5 * (rng.normal() + 1j * rng.normal()), 'slot': -1,
+                          'factors': {e: X}})
+    return terms
+
+
+def closed_form_single_leg(end_dims, terms, om0, t):
+    """Omega(t) = (x)_e exp(t A_e) Omega(0), A_e the sum of the terms on end e."""
+    om = om0.copy()
+    for e, d in enumerate(end_dims):
+        A = np.zeros((d, d), complex)
+        for term in terms:
+            if e in term['factors']:
+                A += term['coef'] * term['factors'][e]
+        om = np.moveaxis(np.tensordot(expm(t * A), om, axes=([1], [e])), 0, e)
+    return om
+
+
+def random_canonical_state(tree, rng):
+    C = rand_cores(tree, rng)
+    canonicalize_root(tree, C)
+    C[0] = C[0] / np.linalg.norm(contract_dense(tree, C))
+    return C
+
+
+TRUNC_TREES = [("train", lambda: train_tree(2, [3, 3, 3], 2)),
+               ("binary", lambda: nary_tree(2, [3, 3, 3, 3], 2, 2)),
+               ("ternary", lambda: nary_tree(2, [3, 3, 3, 3], 3, 2))]
+
+
+@pytest.mark.parametrize("method", ["ps1", "ps2"])
+@pytest.mark.parametrize("name,mk", TRUNC_TREES)
+def test_truncated_rank_exact_for_single_leg_generators(name, mk, method):
+    rng = np.random.default_rng(21)
+    tree = mk()
+    full = nary_tree(2, [3] * (len(tree.end_dims) - 2), 2, 10 ** 6)
+    assert max(tree.rank) == 2 and max(full.rank) > 2
+    C = random_canonical_state(tree, rng)
+    terms = single_leg_terms(tree.end_dims, rng)
+    dt, n = 0.005, 40
+    ref = closed_form_single_leg(tree.end_dims, terms, contract_dense(tree, C), n * dt)
+    P = Propagator(tree, terms, C)
+    for s in range(n):
+        if method == "ps1":
+            P.step_ps1(s * dt, dt)
+        else:
+            P.step_ps2(s * dt, dt, 1e-12, 2)
+    assert max(tree.rank) == 2
+    err = np.linalg.norm(contract_dense(tree, P.C) - ref) / np.linalg.norm(ref)
+    assert err < 1e-8, err
+
+
+def test_truncated_rank_two_end_term_leaves_the_manifold():
+    """The control for the test above: one term coupling two ends makes the
+    rank-2 trajectory depart from the dense one by O(0.1)."""
+    rng = np.random.default_rng(21)
+    tree = nary_tree(2, [3, 3, 3, 3], 2, 2)
+    C = random_canonical_state(tree, rng)
+    terms = single_leg_terms(tree.end_dims, rng)
+    d0, d5 = tree.end_dims[0], tree.end_dims[5]
+    terms.append({'coef': 0.3, 'slot': -1,
+                  'factors': {0: rng.normal(size=(d0, d0)) + 0j, 5: rng.normal(size=(d5, d5)) + 0j}})
+    dt, n = 0.005, 40
+    om0 = contract_dense(tree, C)
+    ref = expm(n * dt * dense_generator(terms, tree.end_dims).toarray()) @ om0.reshape(-1)
+    P = Propagator(tree, terms, C)
+    for s in range(n):
+        P.step_ps1(s * dt, dt)
+    err = np.linalg.norm(contract_dense(tree, P.C).reshape(-1) - ref) / np.linalg.norm(ref)
+    assert err > 1e-3, err
