@@ -167,12 +167,15 @@ def batch_main(a):
                    "tile_size": "autotuned" if tile_work["w"] else "default"},
     }
     rho_mixed = batch.rho()
-    nonfinite = [i for i, f in enumerate(batch.status()) if f]
+    flagged = [i for i, f in enumerate(batch.status()) if f]
+    nonfinite = [i for i in flagged if not np.isfinite(rho_mixed[i]).all()]
+    grown = [i for i in flagged if i not in nonfinite]
     trace_off = [i for i, r in enumerate(rho_mixed)
-                 if i not in nonfinite and abs(np.trace(r).real - 1.0) > 1e-3]
+                 if i not in flagged and abs(np.trace(r).real - 1.0) > 1e-3]
     out["diverged_instances"] = {
-        "non_finite": len(nonfinite), "trace_off_by_1e-3": len(trace_off),
-        "indices": (nonfinite + trace_off)[:32],
+        "non_finite": len(nonfinite), "norm_grown_1e6": len(grown),
+        "trace_off_by_1e-3": len(trace_off),
+        "indices": (nonfinite + grown + trace_off)[:32],
         "note": "RK4 at the instance's dt: unstable in the FP64 oracle as well, or (the "
                 "rest) unstable under FP32-level rounding; flagged, not dropped"}
     del batch, plans

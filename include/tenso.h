@@ -50,7 +50,8 @@ extern "C" {
 #define TENSO_EINVAL       -1   /* malformed input (tree, dims, sizes, dt <= 0) */
 #define TENSO_ENOMEM       -2   /* workspace too small / size beyond the budget */
 #define TENSO_EHIP         -3   /* a HIP runtime error (message carries hipGetErrorString) */
-#define TENSO_ENUMERIC     -4   /* NaN or infinity in a state after stepping */
+#define TENSO_ENUMERIC     -4   /* NaN or infinity in a state after stepping, or its
+                                   norm grown more than 1e6-fold over the step call */
 #define TENSO_EUNSUPPORTED -5   /* valid input outside what this library implements */
 
 typedef struct { double re, im; } tenso_c128;
@@ -165,8 +166,10 @@ int tenso_apply_generator(tenso_plan* p, const void* d_state, int center, double
  * sweep over half a step, then its adjoint).  d_drive_tab (nullable when the
  * generator has no slots) holds f_slot at t0 + j*dt/4, j = 0..4*n_steps,
  * as [n_slots][4*n_steps+1] doubles on the device.  The state stays canonical
- * toward the root.  At the end the state is checked for NaN/infinity
- * (ENUMERIC), which synchronises `s` once per call. */
+ * toward the root.  At the end the state is checked for NaN/infinity and
+ * for a norm grown more than 1e6-fold over the call (both ENUMERIC; the norm
+ * is that of the root core, which carries it in a root-canonical state),
+ * which synchronises `s` once per call. */
 int tenso_step_fixed(tenso_plan* p, void* d_state, double t0, double dt, int n_steps,
                      const double* d_drive_tab, void* d_ws, hipStream_t s);
 
@@ -221,8 +224,9 @@ int tenso_batch_reduced_rho(tenso_batch* b, tenso_c128* const* h_rho, hipStream_
 void tenso_batch_destroy(tenso_batch* b);
 
 /* Per instance, 1 if its state held NaN or infinite values after the last
- * step call (which then returned TENSO_ENUMERIC), else 0; flags has n entries.
- * Host call, no device work. */
+ * step call, or its norm grew more than 1e6-fold over that call (the call then
+ * returned TENSO_ENUMERIC), else 0; flags has n entries.  Host call, no
+ * device work. */
 int tenso_batch_status(const tenso_batch* b, int32_t* flags);
 
 /* Graph replay of batched steps on (default) or off; results are identical. */

@@ -15,6 +15,7 @@
 
 #include "../../include/tenso.h"
 #include "tenso_internal.h"
+#include "checks.h"
 
 namespace tenso {
 hipError_t launch_apply(int fp64, int in_fp64, const ApplyGroup* groups, const ApplyTile* tiles,
@@ -687,7 +688,8 @@ static void layout(tenso_plan& P) {
   P.ws_qrtau = take((size_t)P.max_dim * 16);
   P.ws_rhovec = take((size_t)t.n * maxr * 16);
   P.ws_rhoout = take((size_t)t.end_dim[0] * t.end_dim[0] * 16);
-  P.ws_ctr = take(256);  // step counter at 0, finiteness flag at 64, its descriptor at 128
+  P.ws_ctr = take(256);  // step counter at 0, finiteness flag at 64, its descriptor at 128,
+                         // the root-norm descriptor at 160, norms before / after at 192 / 200
   if (P.opts.method == TENSO_PS2) {
     P.ws_theta = take(std::max<size_t>(1, theta) * 16);
     P.ws_evals = take(64 * 8);
@@ -1644,8 +1646,21 @@ static void step_loop(StepGraph& G, const std::vector<const DevProgram*>& parts,
   }
 }
 
-// Non-finite values in a plan's state after stepping: ENUMERIC.  One small
-// launch and a synchronisation per step call.
+// Norm of the plan's root core (the state's norm: the state is canonical
+// toward the root between step calls) into the workspace slot `slot` (0:
+// before the call, 1: after it).
+static void plan_root_norm(tenso_plan* p, void* d_state, void* d_ws, int slot, hipStream_t s) {
+  char* base = (char*)d_ws + p->ws_ctr;
+  NormOp op{};
+  op.p = (const double*)((const char*)d_state + p->core_off[0]);
+  op.n = 2 * p->tree.size(0);
+  hipchk(hipMemcpyAsync(base + 160, &op, sizeof(op), hipMemcpyHostToDevice, s), "norm op");
+  hipchk(launch_norms((const NormOp*)(base + 160), 1, (double*)(base + 192) + slot, s), "root norm");
+}
+
+// After stepping: non-finite values in the plan's state, or a norm grown by
+// more than kNormGrowthLimit over the call, are ENUMERIC.  Two small
+// launches and one synchronisation per step call.
 static void check_plan_finite(tenso_plan* p, void* d_state, void* d_ws, hipStream_t s) {
   char* base = (char*)d_ws + p->ws_ctr;
   FiniteOp op{};
@@ -1654,10 +1669,15 @@ static void check_plan_finite(tenso_plan* p, void* d_state, void* d_ws, hipStrea
   op.flag = (int*)(base + 64);
   hipchk(hipMemcpyAsync(base + 128, &op, sizeof(op), hipMemcpyHostToDevice, s), "finite op");
   hipchk(launch_finite((const FiniteOp*)(base + 128), 1, op.flag, s), "finite check");
+  plan_root_norm(p, d_state, d_ws, 1, s);
   int flag = 0;
+  double norms[2] = {0, 0};
   hipchk(hipMemcpyAsync(&flag, op.flag, sizeof(int), hipMemcpyDeviceToHost, s), "finite flag");
+  hipchk(hipMemcpyAsync(norms, base + 192, sizeof(norms), hipMemcpyDeviceToHost, s), "norms");
   hipchk(hipStreamSynchronize(s), "sync");
   if (flag) fail(TENSO_ENUMERIC, "non-finite values in the state after stepping");
+  if (norms[1] > kNormGrowthLimit * norms[0])
+    fail(TENSO_ENUMERIC, "state norm grew by more than a factor 1e6 over the step call");
 }
 
 // Tile group indices are relative to the first group of their launch.
@@ -2186,6 +2206,7 @@ int tenso_step_fixed(tenso_plan* p, void* d_state, double t0, double dt, int n_s
       p->b_ld = ld;
     }
     int* ctr = (int*)((char*)d_ws + p->ws_ctr);
+    plan_root_norm(p, d_state, d_ws, 0, s);
     hipchk(launch_step_inc(ctr, 0, s), "ctr");
     run(*p->dev_init, p->fp64, ctr, s);
     step_loop(p->graph, {p->dev_step.get()}, p->fp64, ctr, n_steps, s);
@@ -2206,6 +2227,7 @@ int tenso_step_adaptive(tenso_plan* p, void* d_state, double t0, double dt, int 
     Ps2Exec X{*p, d_state, d_ws, dt, d_drive_tab, 4 * n_steps + 1, s, std::min(max_rank, p->opts.max_rank), eps};
     X.ctr = (int*)((char*)d_ws + p->ws_ctr);
     p->rank_log.clear();
+    plan_root_norm(p, d_state, d_ws, 0, s);
     {
       Program G;
       build_init(*p, G);
@@ -2291,6 +2313,8 @@ struct tenso_batch {
   DevProgram init, rho;
   FiniteOp* fin_ops = nullptr;      // per instance: its state, for the finiteness check
   int* fin_flags = nullptr;
+  NormOp* norm_ops = nullptr;       // per instance: its root core, for the norm-growth check
+  double* norms = nullptr;          // n norms before the step call, then n after it
   std::vector<int> last_flags;      // flags of the last step call
   std::vector<std::unique_ptr<DevProgram>> steps;  // independent parts of one step
   int n_parts = 4;                                 // parts requested
@@ -2303,6 +2327,8 @@ struct tenso_batch {
   ~tenso_batch() {
     if (fin_ops) (void)hipFree(fin_ops);
     if (fin_flags) (void)hipFree(fin_flags);
+    if (norm_ops) (void)hipFree(norm_ops);
+    if (norms) (void)hipFree(norms);
     if (ctr) (void)hipFree(ctr);
     if (rho_buf) (void)hipFree(rho_buf);
   }
@@ -2373,17 +2399,34 @@ static void batch_build(tenso_batch& B, hipStream_t s) {
   B.graph.reset();
 }
 
-// Non-finite values in any instance's state: ENUMERIC (flags kept for
-// tenso_batch_status).
+// Root-core norms of every instance before a step call.
+static void batch_norms_before(tenso_batch* b, hipStream_t s) {
+  hipchk(launch_norms(b->norm_ops, (int)b->plans.size(), b->norms, s), "root norms");
+}
+
+// Non-finite values in any instance's state, or a norm grown by more than
+// kNormGrowthLimit over the call: ENUMERIC (flags kept for tenso_batch_status).
 static void check_batch_finite(tenso_batch* b, hipStream_t s) {
   const int n = (int)b->plans.size();
   hipchk(launch_finite(b->fin_ops, n, b->fin_flags, s), "finite check");
+  hipchk(launch_norms(b->norm_ops, n, b->norms + n, s), "root norms");
   b->last_flags.assign(n, 0);
+  std::vector<double> nb(2 * (size_t)n);
   hipchk(hipMemcpyAsync(b->last_flags.data(), b->fin_flags, n * sizeof(int), hipMemcpyDeviceToHost, s),
          "finite flags");
+  hipchk(hipMemcpyAsync(nb.data(), b->norms, 2 * (size_t)n * sizeof(double), hipMemcpyDeviceToHost, s),
+         "norms");
   hipchk(hipStreamSynchronize(s), "sync");
-  for (int i = 0; i < n; ++i)
-    if (b->last_flags[i]) fail(TENSO_ENUMERIC, "non-finite values in the state of a batch instance after stepping");
+  bool nonfinite = false, grown = false;
+  for (int i = 0; i < n; ++i) {
+    nonfinite = nonfinite || b->last_flags[i];
+    if (!b->last_flags[i] && nb[n + i] > kNormGrowthLimit * nb[i]) {
+      b->last_flags[i] = 1;
+      grown = true;
+    }
+  }
+  if (nonfinite) fail(TENSO_ENUMERIC, "non-finite values in the state of a batch instance after stepping");
+  if (grown) fail(TENSO_ENUMERIC, "the state norm of a batch instance grew by more than a factor 1e6 over the step call");
 }
 
 // Check the batch arguments, (re)build the batch programs when the binding
@@ -2409,6 +2452,7 @@ static void batch_advance(tenso_batch* b, const double* dt, int n_steps,
     b->ld = ld;
     batch_build(*b, s);
   }
+  if (check) batch_norms_before(b, s);
   hipchk(launch_step_inc(b->ctr, 0, s), "ctr");
   run(b->init, b->fp64, b->ctr, s);
   step_loop(b->graph, b->step_parts(), b->fp64, b->ctr, n_steps, s);
@@ -2446,6 +2490,14 @@ int tenso_batch_create(int n, tenso_plan* const* plans, void* const* d_states,
       for (int i = 0; i < n; ++i) ops[i].flag = B->fin_flags + i;
       hipchk(hipMalloc((void**)&B->fin_ops, n * sizeof(FiniteOp)), "hipMalloc(finite ops)");
       hipchk(hipMemcpy(B->fin_ops, ops.data(), n * sizeof(FiniteOp), hipMemcpyHostToDevice), "finite ops");
+      std::vector<NormOp> nops(n);
+      for (int i = 0; i < n; ++i) {
+        nops[i].p = (const double*)((const char*)d_states[i] + plans[i]->core_off[0]);
+        nops[i].n = 2 * plans[i]->tree.size(0);
+      }
+      hipchk(hipMalloc((void**)&B->norm_ops, std::max(1, n) * sizeof(NormOp)), "hipMalloc(norm ops)");
+      hipchk(hipMemcpy(B->norm_ops, nops.data(), n * sizeof(NormOp), hipMemcpyHostToDevice), "norm ops");
+      hipchk(hipMalloc((void**)&B->norms, std::max(1, 2 * n) * sizeof(double)), "hipMalloc(norms)");
     }
     hipchk(hipMalloc((void**)&B->rho_buf, std::max<size_t>(rho_bytes, 256)), "hipMalloc(rho)");
     *out = B.release();
@@ -2486,6 +2538,7 @@ int tenso_batch_step_record(tenso_batch* b, const double* t0, const double* dt, 
     }
     const size_t rec = b->rho_off.back() + align256(b->plans.back()->tree.end_dim[0] *
                                                     b->plans.back()->tree.end_dim[0] * 16);
+    batch_norms_before(b, s);
     hipchk(launch_step_inc(b->ctr, 0, s), "ctr");
     run(b->init, b->fp64, b->ctr, s);
     int r = 0;
