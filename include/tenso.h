@@ -198,6 +198,10 @@ int tenso_rank_trajectory(const tenso_plan* p, int32_t* h_ranks, int cap);
  * summed kernel time, launch count, flops and bytes.  Process-wide state. */
 int tenso_profile(int enable);
 int tenso_profile_stats(double* total_ms, int64_t* launches, double* flops, double* bytes);
+/* The same per launch, in launch order: the first min(cap, launches) entries
+ * of ms / flops / bytes (each nullable; host arrays the caller owns) are
+ * filled and *n_out receives the number of recorded launches. */
+int tenso_profile_records(int64_t cap, double* ms, double* flops, double* bytes, int64_t* n_out);
 
 /* ---- batched fixed-rank propagation --------------------------------------
  * Many independent ps1 plans (uneven trees, ranks, dims) advance together:

@@ -57,6 +57,7 @@ SIGS = {
     "tenso_rank_trajectory": (C.c_int, [P, I32P, C.c_int]),
     "tenso_profile": (C.c_int, [C.c_int]),
     "tenso_profile_stats": (C.c_int, [DP, C.POINTER(C.c_int64), DP, DP]),
+    "tenso_profile_records": (C.c_int, [C.c_int64, DP, DP, DP, C.POINTER(C.c_int64)]),
     "tenso_batch_create": (C.c_int, [C.c_int, C.POINTER(P), C.POINTER(P), C.POINTER(P), C.POINTER(P)]),
     "tenso_batch_step": (C.c_int, [P, DP, DP, C.c_int, C.POINTER(P), P]),
     "tenso_batch_reduced_rho": (C.c_int, [P, C.POINTER(C128P), P]),

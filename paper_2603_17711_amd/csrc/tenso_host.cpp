@@ -2298,6 +2298,22 @@ int tenso_profile_stats(double* total_ms, int64_t* launches, double* flops, doub
   });
 }
 
+int tenso_profile_records(int64_t cap, double* ms, double* flops, double* bytes, int64_t* n_out) {
+  return guard([&] {
+    if (cap < 0 || !n_out) fail(TENSO_EINVAL, "bad arguments");
+    const int64_t n = std::min<int64_t>(cap, (int64_t)g_prof.ev.size());
+    for (int64_t i = 0; i < n; ++i) {
+      hipchk(hipEventSynchronize(g_prof.ev[i].second), "hipEventSynchronize");
+      float t = 0;
+      hipchk(hipEventElapsedTime(&t, g_prof.ev[i].first, g_prof.ev[i].second), "hipEventElapsedTime");
+      if (ms) ms[i] = t;
+      if (flops) flops[i] = g_prof.work[i].first;
+      if (bytes) bytes[i] = g_prof.work[i].second;
+    }
+    *n_out = (int64_t)g_prof.ev.size();
+  });
+}
+
 }  // extern "C"
 
 struct tenso_batch {
