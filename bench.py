@@ -45,31 +45,42 @@ def measured_traffic():
     return 1024.0 * (c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"])
 
 
+WORKLOADS = ["batch512", "spin-boson-train", "exciton-7site", "ps2-structured-ternary",
+             "surrogate"]
+# short spellings accepted on the command line
+ALIASES = {"c0": "spin-boson-train", "c1": "exciton-7site", "c2": "batch512",
+           "c3": "ps2-structured-ternary", "c4": "surrogate"}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2", choices=["c0", "c1", "c2", "c3", "c4"],
-                    help="c2 (default): 512-instance ps1 batch; c0, c1: single ps1 instances; "
-                         "c3: ps2 on the structured-bath ternary tree; c4: the surrogate pipeline")
-    ap.add_argument("--instances", type=int, default=512, help="batch size for c2")
+    ap.add_argument("--workload", default="batch512", choices=WORKLOADS + list(ALIASES),
+                    help="batch512 (default): 512 uneven instances, ps1, batched; "
+                         "spin-boson-train, exciton-7site: single ps1 instances; "
+                         "ps2-structured-ternary: ps2 on the structured-bath ternary tree; "
+                         "surrogate: the learned-surrogate pipeline")
+    ap.add_argument("--instances", type=int, default=512, help="batch size for batch512")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU comparison")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the run, a plain 256 MiB streaming kernel (torch.neg) whose "
                          "HBM counters calibrate FETCH_SIZE / WRITE_SIZE")
     ap.add_argument("--autotune", action="store_true",
-                    help="c2: autotune the apply tile size before timing (default: the "
-                         "batch default tile size)")
-    return ap.parse_args()
+                    help="batch512: autotune the apply tile size before timing (default: "
+                         "the batch default tile size)")
+    a = ap.parse_args()
+    a.workload = ALIASES.get(a.workload, a.workload)
+    return a
 
 
 def instance(name, n):
     import workloads
-    if name == "c0":
-        return workloads.config0(n_steps=n), "spin-boson K=3 N=10 train R=8 ps1 (dt 0.01)"
-    return workloads.config1(n_steps=n), "7-site exciton K=28 N=8 binary R=16 ps1 (dt 0.1 fs)"
+    if name == "spin-boson-train":
+        return workloads.spin_boson_train(n_steps=n), "spin-boson K=3 N=10 train R=8 ps1 (dt 0.01)"
+    return workloads.exciton_7site(n_steps=n), "7-site exciton K=28 N=8 binary R=16 ps1 (dt 0.1 fs)"
 
 
 def timed_run(inst, precision, steps, warmup):
@@ -124,7 +135,7 @@ def batch_main(a):
     from paper_2603_17711_amd import api
     from oracle.ttn import trace_distance
 
-    insts = workloads.config2(n_inst=a.instances, n_steps=a.steps + a.warmup)
+    insts = workloads.uneven_batch(n_inst=a.instances, n_steps=a.steps + a.warmup)
     dts = [i.dt for i in insts]
 
     tile_work = {"w": None}
@@ -239,7 +250,7 @@ def batch_main(a):
         from threadpoolctl import threadpool_limits
         from oracle.run import propagate
         ns, k = 8, 2
-        sample = workloads.config2(n_inst=a.instances, n_steps=k)[:ns]
+        sample = workloads.uneven_batch(n_inst=a.instances, n_steps=k)[:ns]
         with threadpool_limits(limits=1):
             t0 = time.perf_counter()
             for inst in sample:
@@ -294,7 +305,7 @@ def ps2_main(a):
     from paper_2603_17711_amd import api
     from paper_2603_17711_amd._lib import check, lib
     cap = 4
-    inst = workloads.config3(n_steps=a.steps + a.warmup)
+    inst = workloads.structured_bath_ternary(n_steps=a.steps + a.warmup)
     wname = "structured bath K=24 N=10 ternary ps2 (eps 1e-6, rank cap 4, dt 0.01)"
 
     def run(precision, steps, warmup, profile=False):
@@ -343,7 +354,7 @@ def ps2_main(a):
         from oracle.run import propagate
         from oracle.ttn import trace_distance
         n_sample = 3
-        cinst = workloads.config3(n_steps=n_sample)
+        cinst = workloads.structured_bath_ternary(n_steps=n_sample)
         with threadpool_limits(limits=1):
             t0 = time.perf_counter()
             _, ro, _, _ = propagate(cinst, n_steps=n_sample, every=n_sample, max_rank=cap)
@@ -359,7 +370,7 @@ def ps2_main(a):
 
 
 def surrogate_main(a):
-    """The surrogate pipeline (config 4) at a bounded size: TTN-HEOM trajectories
+    """The surrogate pipeline (driven spin-boson trajectories) at a bounded size: TTN-HEOM trajectories
     on training seeds, BF16 MLP training, monitored rollout on held-out seeds,
     TTN fallback for tripped trajectories, judged against TTN-HEOM."""
     from paper_2603_17711_amd import surrogate
@@ -392,11 +403,11 @@ def run_main(a):
     import torch
     torch.cuda.set_device(0)
     from paper_2603_17711_amd import api
-    if a.workload == "c2":
+    if a.workload == "batch512":
         return batch_main(a)
-    if a.workload == "c3":
+    if a.workload == "ps2-structured-ternary":
         return ps2_main(a)
-    if a.workload == "c4":
+    if a.workload == "surrogate":
         return surrogate_main(a)
 
     inst, wname = instance(a.workload, a.steps + a.warmup)
@@ -428,7 +439,7 @@ def run_main(a):
         "apply_share_of_step": round(ms / prof_steps / (1e3 * dt_mixed / a.steps), 4),
     }
     if not a.no_cpu:
-        n_sample = 3 if a.workload == "c1" else 400
+        n_sample = 3 if a.workload == "exciton-7site" else 400
         cinst, _ = instance(a.workload, n_sample)
         v_cpu, rhos_cpu = cpu_baseline(cinst, n_sample)
         out["cpu_baseline"] = {

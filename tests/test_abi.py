@@ -44,15 +44,15 @@ def _oracle_tree(kind, M, dims, R):
     return train_tree(M, dims, R) if kind == "train" else nary_tree(M, dims, int(kind[4:]), R)
 
 
-@pytest.mark.parametrize("which", ["c0", "c1", "c3", "c2"])
+@pytest.mark.parametrize("which", ["spin_boson_train", "exciton_7site", "structured_bath_ternary",
+                                   "uneven_batch"])
 def test_tree_ranks_match_oracle(which):
     _lib()
     from paper_2603_17711_amd import api
-    if which == "c2":
-        insts = workloads.config2(n_inst=24, seed=2)
+    if which == "uneven_batch":
+        insts = workloads.uneven_batch(n_inst=24, seed=2)
     else:
-        insts = [{"c0": workloads.config0, "c1": workloads.config1,
-                  "c3": workloads.config3}[which]()]
+        insts = [getattr(workloads, which)()]
     for inst in insts:
         dims = []
         for b in inst.baths:

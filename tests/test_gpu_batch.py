@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 def small_batch(n, seed=7):
     """Uneven small instances in the style of the 512-instance batch."""
     rng = np.random.default_rng(seed)
-    insts = workloads.config2(n_inst=n, seed=seed, n_steps=20)
+    insts = workloads.uneven_batch(n_inst=n, seed=seed, n_steps=20)
     for inst in insts:  # keep the oracle fast
         inst.depth = int(rng.integers(3, 6))
         inst.rank = int(rng.integers(3, 7))

@@ -27,7 +27,7 @@ def test_plan_step_reports_nonfinite_state():
     require_gpu()
     from paper_2603_17711_amd import api
     from paper_2603_17711_amd._lib import TensoError
-    inst = workloads.config0(n_steps=10)
+    inst = workloads.spin_boson_train(n_steps=10)
     print("[failure] NaN planted in a spin-boson state", flush=True)
     p = api.build_instance(inst, precision=api.FP32)
     p.step(2, inst.dt)  # healthy
@@ -42,7 +42,7 @@ def test_batch_flags_the_poisoned_instance():
     import torch
     from paper_2603_17711_amd import api
     from paper_2603_17711_amd._lib import TensoError
-    insts = workloads.config2(n_inst=5, seed=9, n_steps=10)
+    insts = workloads.uneven_batch(n_inst=5, seed=9, n_steps=10)
     for inst in insts:
         inst.depth, inst.rank = 4, 4
     print("[failure] NaN planted in instance 2 of a batch of 5", flush=True)

@@ -38,7 +38,7 @@ def test_full_batch_sampled_against_oracle():
     require_gpu()
     from paper_2603_17711_amd import api
     n = 3
-    insts = workloads.config2(n_inst=512, n_steps=n)
+    insts = workloads.uneven_batch(n_inst=512, n_steps=n)
     sizes = state_sizes(insts)
     largest = [int(i) for i in np.argsort(sizes)[::-1][:2]]
     print(f"[full batch] 512 instances, {n} steps, FP32, default tiles and parts", flush=True)
@@ -67,12 +67,12 @@ def test_full_batch_sampled_against_oracle():
     assert worst < TOL, worst
 
 
-def test_full_config1_against_oracle():
+def test_full_exciton_7site_against_oracle():
     require_gpu()
     from paper_2603_17711_amd import api
     n = 5
-    inst = workloads.config1(n_steps=n)
-    print(f"[full config 1] 7-site exciton model, K = 28, R = 16, {n} FP32 steps", flush=True)
+    inst = workloads.exciton_7site(n_steps=n)
+    print(f"[full size] 7-site exciton model, K = 28, R = 16, {n} FP32 steps", flush=True)
     plan = api.build_instance(inst, precision=api.FP32)
     plan.step(n, inst.dt)
     _, ro, _, _ = propagate(inst, n_steps=n, every=n)

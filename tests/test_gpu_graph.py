@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 
 def _instances(n, seed=11):
     rng = np.random.default_rng(seed)
-    insts = workloads.config2(n_inst=n, seed=seed, n_steps=20)
+    insts = workloads.uneven_batch(n_inst=n, seed=seed, n_steps=20)
     for inst in insts:
         inst.depth = int(rng.integers(3, 7))
         inst.rank = int(rng.integers(3, 9))
@@ -60,7 +60,7 @@ def test_plan_graph_replay_matches_eager(precision):
     require_gpu()
     import torch
     from paper_2603_17711_amd import api
-    inst = workloads.config0(n_steps=30)
+    inst = workloads.spin_boson_train(n_steps=30)
     print(f"[graph plan] spin-boson train precision={precision}", flush=True)
     a = api.build_instance(inst, precision=precision)
     b = api.build_instance(inst, precision=precision)

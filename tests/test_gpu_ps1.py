@@ -31,11 +31,11 @@ def run_gpu(inst, n_steps, precision, every=10):
 
 
 @pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 1e-6)])
-def test_ps1_config0_short(precision, tol):
+def test_ps1_spin_boson_train_short(precision, tol):
     require_gpu()
     n = 100
-    inst = workloads.config0(n_steps=n)
-    print(f"[ps1 parity] config0 steps={n} precision={precision}", flush=True)
+    inst = workloads.spin_boson_train(n_steps=n)
+    print(f"[ps1 parity] spin-boson train steps={n} precision={precision}", flush=True)
     _, ro, _, _ = propagate(inst, n_steps=n, every=10)
     rg = run_gpu(inst, n, precision)
     d = max(trace_distance(a, b) for a, b in zip(rg, ro))
@@ -67,7 +67,7 @@ def test_ps1_binary_multi_bath_short():
 def pulsed(A, w, s=0.15, t0=0.3, n_steps=60):
     """The spin-boson model with a sigma_x pulse A exp(-(t-t0)^2/2s^2) cos(w t)
     centred inside the first n_steps * dt."""
-    base = workloads.config0(n_steps=n_steps)
+    base = workloads.spin_boson_train(n_steps=n_steps)
     return workloads.Instance(f"pulse A={A} w={w}", base.H, base.baths, base.depth, base.tree,
                               base.rank, base.rho0, 0.01, n_steps,
                               drive=(workloads.SX, A, w, s, t0))

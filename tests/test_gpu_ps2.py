@@ -29,7 +29,7 @@ def run_ps2(inst, n_steps, precision, cap, every=5):
 @pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 1e-5)])
 def test_ps2_train(precision, tol):
     require_gpu()
-    inst = workloads.config0(n_steps=20)
+    inst = workloads.spin_boson_train(n_steps=20)
     inst.method, inst.eps, inst.depth = "ps2", 1e-6, 6
     cap, n = 8, 20
     print(f"[ps2 parity] train K=3 N=6 cap={cap} steps={n} precision={precision}", flush=True)
@@ -44,7 +44,7 @@ def test_ps2_train(precision, tol):
 
 def test_ps2_structured_bath_ternary_small_cap():
     require_gpu()
-    inst = workloads.config3(n_steps=6)
+    inst = workloads.structured_bath_ternary(n_steps=6)
     cap, n = 4, 6
     print(f"[ps2 parity] structured bath K=24 ternary cap={cap} steps={n} FP32", flush=True)
     _, ro, rlog, _ = propagate(inst, n_steps=n, every=5, max_rank=cap)

@@ -28,7 +28,7 @@ def test_forced_monitor_trip_runs_the_ttn_fallback():
     from paper_2603_17711_amd import surrogate as S
     print("[surrogate] forced trips on 4 trajectories x 400 steps", flush=True)
     n_steps = 400
-    held = workloads.config4(workloads.HELDOUT_SEEDS[:4], n_steps)
+    held = workloads.driven_spin_boson(workloads.HELDOUT_SEEDS[:4], n_steps)
     rho, _ = S.generate(held, n_steps)
     judge = S.features(rho)
     n_rec = rho.shape[1]

@@ -6,8 +6,9 @@ depths, tree shapes, ranks, initial states and drive pulses.  Everything that
 turns these parameters into features, generators or trees is implemented
 separately on each side.
 
-Units: configs 0, 2, 3 and 4 are dimensionless (hbar = k_B = 1).  Config 1 is
-given in cm^-1 / fs / K and converted here to hbar = 1 with energies in cm^-1:
+Units: every workload is dimensionless (hbar = k_B = 1) except the 7-site
+exciton model, which is given in cm^-1 / fs / K and converted here to hbar = 1
+with energies in cm^-1:
 a time t [fs] becomes t * FS_TO_CM and a temperature T [K] becomes T * KB_CM.
 """
 import numpy as np
@@ -74,7 +75,7 @@ def ground(M):
     return r
 
 
-def config0(n_steps=2000, rank=8):
+def spin_boson_train(n_steps=2000, rank=8):
     """Spin-boson, Drude bath with 2 Matsubara terms (3 features), depth 10,
     tensor train of rank 8, RK4 dt = 0.01."""
     bath = Bath(SZ, 1.0, dl=[(0.1, 1.0)], n_ltc=2)
@@ -82,7 +83,7 @@ def config0(n_steps=2000, rank=8):
                     "train", rank, ground(2), 0.01, n_steps)
 
 
-def config1(n_steps=1000, seed=1):
+def exciton_7site(n_steps=1000, seed=1):
     """7-site exciton model (cm^-1, fs, K) with one Drude bath per site (3
     Matsubara terms each: 28 features), depth 8, binary tree of rank 16,
     dt = 0.1 fs."""
@@ -112,7 +113,7 @@ def stable_dt(dt_max, T, n_ltc, N, wc=1.0):
     return min(dt_max, 0.5 * 2 * 2.78 / rate)
 
 
-def config2(n_inst=512, seed=2, n_steps=200):
+def uneven_batch(n_inst=512, seed=2, n_steps=200):
     """Batch of uneven spin-boson-type instances (time step 0.01, lowered per
     instance where RK4 would be unstable, see stable_dt)."""
     rng = np.random.default_rng(seed)
@@ -136,7 +137,7 @@ def config2(n_inst=512, seed=2, n_steps=200):
     return out
 
 
-def config3(n_steps=100, seed=3, eps=1e-6, max_rank=64):
+def structured_bath_ternary(n_steps=100, seed=3, eps=1e-6, max_rank=64):
     """Two-level system, Drude + 10 Brownian modes + 3 Matsubara terms (24
     features), depth 10, ternary tree, adaptive rank (ps2)."""
     rng = np.random.default_rng(seed)
@@ -147,7 +148,7 @@ def config3(n_steps=100, seed=3, eps=1e-6, max_rank=64):
                     "tree3", max_rank, ground(2), 0.01, n_steps, method="ps2", eps=eps)
 
 
-def config4_drives(seeds):
+def pulse_drives(seeds):
     """Gaussian pulses A exp(-(t-t0)^2/2s^2) cos(w t) sigma_x, one per seed."""
     out = []
     for sd in seeds:
@@ -160,12 +161,12 @@ def config4_drives(seeds):
     return out
 
 
-def config4(seeds, n_steps=2000):
-    """Driven spin-boson trajectories on the config-0 bath."""
-    base = config0(n_steps)
+def driven_spin_boson(seeds, n_steps=2000):
+    """Driven spin-boson trajectories on the bath of spin_boson_train."""
+    base = spin_boson_train(n_steps)
     return [Instance(f"driven seed {sd}", base.H, base.baths, base.depth, base.tree,
                      base.rank, base.rho0, base.dt, n_steps, drive=d)
-            for sd, d in zip(seeds, config4_drives(seeds))]
+            for sd, d in zip(seeds, pulse_drives(seeds))]
 
 
 TRAIN_SEEDS = list(range(1000, 1000 + 3584))
