@@ -47,9 +47,6 @@ def measured_traffic():
 
 WORKLOADS = ["batch512", "spin-boson-train", "exciton-7site", "ps2-structured-ternary",
              "surrogate"]
-# short spellings accepted on the command line
-ALIASES = {"c0": "spin-boson-train", "c1": "exciton-7site", "c2": "batch512",
-           "c3": "ps2-structured-ternary", "c4": "surrogate"}
 
 
 def parse():
@@ -57,7 +54,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="batch512", choices=WORKLOADS + list(ALIASES),
+    ap.add_argument("--workload", default="batch512", choices=WORKLOADS,
                     help="batch512 (default): 512 uneven instances, ps1, batched; "
                          "spin-boson-train, exciton-7site: single ps1 instances; "
                          "ps2-structured-ternary: ps2 on the structured-bath ternary tree; "
@@ -71,9 +68,7 @@ def parse():
     ap.add_argument("--autotune", action="store_true",
                     help="batch512: autotune the apply tile size before timing (default: "
                          "the batch default tile size)")
-    a = ap.parse_args()
-    a.workload = ALIASES.get(a.workload, a.workload)
-    return a
+    return ap.parse_args()
 
 
 def instance(name, n):
