@@ -2,7 +2,7 @@
 GPU path, with the SOP-contraction kernel's roofline and the FP64 CPU oracle
 timed on a bounded sample.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c1|c0]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 
 Prints ONE JSON line (see the keys below).  Inputs are seeded and synthetic
 (workloads.py); the state is resident in HBM before the timed region starts.
