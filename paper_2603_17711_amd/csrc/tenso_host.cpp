@@ -2194,8 +2194,10 @@ int tenso_step_fixed(tenso_plan* p, void* d_state, double t0, double dt, int n_s
       p->built_tile_work = p->tile_work;
       p->b_state = nullptr;
     }
+    // the drive table's row length (4 n_steps + 1) is baked into the launch
+    // descriptors; it matters only when the generator has drive slots
     if (p->b_state != d_state || p->b_ws != d_ws || p->b_dt != dt || p->b_drive != d_drive_tab ||
-        p->b_ld != ld) {
+        (p->gen.n_slots > 0 && p->b_ld != ld)) {
       upload(*p->dev_step, *p->prog_step, d_state, d_ws, dt, d_drive_tab, ld, s);
       upload(*p->dev_init, *p->prog_init, d_state, d_ws, dt, d_drive_tab, ld, s);
       p->graph.reset();
@@ -2460,9 +2462,15 @@ static void batch_advance(tenso_batch* b, const double* dt, int n_steps,
     if (b->plans[i]->gen.n_slots > 0 && !drv[i]) fail(TENSO_EINVAL, "instance with drive slots needs a drive table");
   }
   const int ld = 4 * n_steps + 1;
-  bool stale = false;
-  for (auto* P : b->plans) stale = stale || P->built_tile_work != P->tile_work;
-  if (stale || dts != b->dts || drv != b->drives || ld != b->ld || b->steps.empty()) {
+  bool stale = false, driven = false;
+  for (auto* P : b->plans) {
+    stale = stale || P->built_tile_work != P->tile_work;
+    driven = driven || P->gen.n_slots > 0;
+  }
+  // the drive tables' row length is baked into the programs; it matters only
+  // for instances with drive slots, so other batches keep their programs and
+  // graph when the step count of a call changes
+  if (stale || dts != b->dts || drv != b->drives || (driven && ld != b->ld) || b->steps.empty()) {
     b->dts = dts;
     b->drives = drv;
     b->ld = ld;
@@ -2544,9 +2552,12 @@ int tenso_batch_step_record(tenso_batch* b, const double* t0, const double* dt, 
       if (b->plans[i]->gen.n_slots > 0 && !drv[i]) fail(TENSO_EINVAL, "instance with drive slots needs a drive table");
     }
     const int ld = 4 * n_steps + 1;
-    bool stale = false;
-    for (auto* P : b->plans) stale = stale || P->built_tile_work != P->tile_work;
-    if (stale || dts != b->dts || drv != b->drives || ld != b->ld || b->steps.empty()) {
+    bool stale = false, driven = false;
+    for (auto* P : b->plans) {
+      stale = stale || P->built_tile_work != P->tile_work;
+      driven = driven || P->gen.n_slots > 0;
+    }
+    if (stale || dts != b->dts || drv != b->drives || (driven && ld != b->ld) || b->steps.empty()) {
       b->dts = dts;
       b->drives = drv;
       b->ld = ld;

@@ -3,8 +3,10 @@
 A captured step replays the same kernels on the same buffers in the same
 order as eager launching, so the FP64 master states must agree bit for bit;
 each comparison follows unrelated eager device work and a synchronisation,
-and every replayed round is checked.  The autotuner must hand the states back
-exactly as it found them."""
+and every replayed round is checked.  Calls with different step counts reuse
+the captured step when no drive is bound (and rebuild it when one is); either
+way they must reproduce one call over all the steps bit for bit.  The
+autotuner must hand the states back exactly as it found them."""
 import numpy as np
 import pytest
 
@@ -97,3 +99,32 @@ def test_autotune_restores_states_and_keeps_results():
         d = trace_distance(ra, rb)
         print(f"  instance {k}: tuned vs default tiles {d:.2e}")
         assert d < 1e-6
+
+
+@pytest.mark.parametrize("driven", [False, True])
+def test_calls_of_different_lengths_match_one_call(driven):
+    require_gpu()
+    import torch
+    from paper_2603_17711_amd import api
+    from tests.test_gpu_ps1 import pulsed
+    print(f"[graph] step counts 3 + 5 + 2 against 10, driven={driven}", flush=True)
+    if driven:
+        insts = [pulsed(A, w, n_steps=10) for A, w in [(2.0, 3.0), (1.0, 1.5)]]
+    else:
+        insts = _instances(5)
+    dts = [i.dt for i in insts]
+    one = api.Batch([api.build_instance(i, precision=api.FP32) for i in insts])
+    parts = api.Batch([api.build_instance(i, precision=api.FP32) for i in insts])
+    tabs = [api.drive_table(i, 10) for i in insts] if driven else None
+    one.step(10, dts, drive_tabs=tabs)
+    done = 0
+    for n in (3, 5, 2):
+        sub = None
+        if driven:
+            sub = [t[:, 4 * done:4 * (done + n) + 1].contiguous() for t in tabs]
+        parts.step(n, dts, t0s=[done * d for d in dts], drive_tabs=sub)
+        done += n
+        _other_work()
+    torch.cuda.synchronize()
+    for k, (pa, pb) in enumerate(zip(one.plans, parts.plans)):
+        assert torch.equal(pa.state, pb.state), f"instance {k}"
