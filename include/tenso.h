@@ -18,8 +18,12 @@
  *   - Device buffers (state, workspace, drive tables) are allocated by the
  *     caller and passed as raw device pointers together with a hipStream_t;
  *     their sizes come from tenso_plan_sizes().  The library allocates device
- *     memory only inside tenso_plan_create / batch creation (constant tables)
- *     and never afterwards.
+ *     memory for its constant tables (plan and batch creation) and for its
+ *     launch-descriptor arenas: when a step call first runs, or rebuilds, its
+ *     programs for a binding (buffers, dt, tile size, drive), and in ps2 calls
+ *     for each new combination of sub-flow and bond ranks (the programs are
+ *     kept and replayed once the ranks settle).  The caller's buffers are never
+ *     reallocated.
  *   - Complex numbers are interleaved {double re, double im} on the host.
  *     The device state layout is private to the library; convert with
  *     tenso_state_import / tenso_state_export.

@@ -374,6 +374,14 @@ struct tenso_plan {
   std::unique_ptr<DevProgram> dev_step, dev_init;
   std::map<int, std::unique_ptr<DevProgram>> dev_apply;
   std::unique_ptr<DevProgram> dev_rho;
+  // ps2: uploaded sub-flow programs keyed by sub-flow and current bond ranks,
+  // valid for one binding (buffers, dt, drive, tile size)
+  std::map<std::string, std::unique_ptr<DevProgram>> ps2_progs;
+  const void* ps2_state = nullptr;
+  const void* ps2_ws = nullptr;
+  const double* ps2_drive = nullptr;
+  double ps2_dt = 0, ps2_tile = -1;
+  int ps2_ld = -1;
   // binding of the step program
   void* b_state = nullptr;
   void* b_ws = nullptr;
@@ -1347,7 +1355,12 @@ static void resolve(Program& G, void* state, void* ws, double dt, const double* 
 }
 
 // Upload a resolved program, turning term / rho-node indices into pointers.
-static void upload_resolved(DevProgram& D, const Program& G, hipStream_t s) {
+// Copy a resolved program's descriptors into D's device arena (grown when
+// too small).  Without `hold` the call waits for the copy; with it, the host
+// buffer is kept in *hold and the caller must synchronise the stream before
+// clearing it (the arena itself is reused in stream order).
+static void upload_resolved(DevProgram& D, const Program& G, hipStream_t s,
+                            std::vector<std::vector<char>>* hold = nullptr) {
   std::vector<char> buf;
   D.o_terms = put(buf, G.terms);
   D.o_groups = put(buf, G.groups);
@@ -1383,15 +1396,17 @@ static void upload_resolved(DevProgram& D, const Program& G, hipStream_t s) {
     rp[i].nodes = (const RhoNode*)(base + D.o_rnodes + (v & OFF_MASK) * sizeof(RhoNode));
   }
   hipchk(hipMemcpyAsync(D.arena, buf.data(), buf.size(), hipMemcpyHostToDevice, s), "upload program");
-  hipchk(hipStreamSynchronize(s), "sync upload");
+  if (hold) hold->push_back(std::move(buf));
+  else hipchk(hipStreamSynchronize(s), "sync upload");
   D.launches = G.launches;
 }
 
 static void upload(DevProgram& D, const Program& G0, void* state, void* ws, double dt,
-                   const double* drive, int drive_ld, hipStream_t s) {
+                   const double* drive, int drive_ld, hipStream_t s,
+                   std::vector<std::vector<char>>* hold = nullptr) {
   Program G = G0;
   resolve(G, state, ws, dt, drive, drive_ld);
-  upload_resolved(D, G, s);
+  upload_resolved(D, G, s, hold);
 }
 
 // Merge resolved per-instance programs into one launch sequence: at each
@@ -1717,40 +1732,74 @@ struct Ps2Exec {
   int max_rank;
   double eps;
   int* ctr = nullptr;
-  DevProgram D;
+  // host copies of the programs uploaded since the last synchronisation (the
+  // eigenvalue read of each edge, the end of the call); uploads do not wait
+  std::vector<std::vector<char>> hold;
+  // on every exit, error paths included, no copy may still read `hold`
+  ~Ps2Exec() { (void)hipStreamSynchronize(s); }
 
-  void exec(const Program& G) {
-    upload(D, G, state, ws, dt, drive, ld, s);
-    run(D, P.fp64, ctr, s);
-  }
+
   char* wsb(size_t off) { return (char*)ws + off; }
   double* core(int x) { return (double*)((char*)state + P.core_off[x]); }
 
+  // A sub-flow's program depends only on the plan, the binding and the current
+  // bond ranks: it is built and uploaded the first time and replayed after
+  // (ranks settle at the cap within a few steps).
+  template <class F>
+  void exec_cached(const std::string& tag, F build) {
+    std::string key = tag;
+    for (int r : P.tree.rank) {
+      key += ',';
+      key += std::to_string(r);
+    }
+    auto it = P.ps2_progs.find(key);
+    if (it == P.ps2_progs.end()) {
+      if (P.ps2_progs.size() >= 4096) {  // bound the cache (ranks still moving)
+        hipchk(hipStreamSynchronize(s), "sync");
+        P.ps2_progs.clear();
+      }
+      Program G;
+      build(G);
+      auto D_ = std::make_unique<DevProgram>();
+      upload(*D_, G, state, ws, dt, drive, ld, s, &hold);
+      it = P.ps2_progs.emplace(key, std::move(D_)).first;
+    }
+    run(*it->second, P.fp64, ctr, s);
+  }
+  static std::string tag(char k, std::initializer_list<int> a) {
+    std::string t(1, k);
+    for (int v : a) {
+      t += ':';
+      t += std::to_string(v);
+    }
+    return t + '|';
+  }
+
   void env_down(int x) {
-    Program G;
-    Builder b(P, G);
-    b.emit_env_down(x);
-    exec(G);
+    exec_cached(tag('D', {x}), [&](Program& G) {
+      Builder b(P, G);
+      b.emit_env_down(x);
+    });
   }
   void env_up(int x) {
-    Program G;
-    Builder b(P, G);
-    b.emit_env_up(x);
-    exec(G);
+    exec_cached(tag('U', {x}), [&](Program& G) {
+      Builder b(P, G);
+      b.emit_env_up(x);
+    });
   }
   void node_bwd(int x, int half) {
-    Program G;
-    Builder b(P, G);
-    b.emit_rk4(node_recipe(P, x), b.core(x), P.tree.size(x), -1.0, half);
-    exec(G);
+    exec_cached(tag('N', {x, half}), [&](Program& G) {
+      Builder b(P, G);
+      b.emit_rk4(node_recipe(P, x), b.core(x), P.tree.size(x), -1.0, half);
+    });
   }
   // QR of core `a` toward leg `la`, R absorbed into core `b` on leg `lb`
   void move(int a, int la, int b_, int lb) {
-    Program G;
-    Builder b(P, G);
-    b.emit_qr(a, la, 0);
-    b.emit_absorb(b_, lb, 0);
-    exec(G);
+    exec_cached(tag('M', {a, la, b_, lb}), [&](Program& G) {
+      Builder b(P, G);
+      b.emit_qr(a, la, 0);
+      b.emit_absorb(b_, lb, 0);
+    });
   }
   template <class T>
   const T* put_op(const T& op, size_t slot) {
@@ -1770,12 +1819,10 @@ struct Ps2Exec {
     double* theta = (double*)wsb(P.ws_theta);
     MergeOp mo{core(sn), core(c), theta, (int)rows, (int)cols, r, (int)ppost};
     hipchk(launch_merge(put_op(mo, 0), rows * cols, s), "merge");
-    {
-      Program G;
+    exec_cached(tag('E', {sn, c, half}), [&](Program& G) {
       Builder b(P, G);
       b.emit_rk4(edge_recipe(P, sn, c), b.ws(P.ws_theta), rows * cols, +1.0, half);
-      exec(G);
-    }
+    });
     const int side = rows <= cols ? 0 : 1;
     const int n = (int)std::min(rows, cols);
     EigOp eo{theta, (int)rows, (int)cols, side, (double*)wsb(P.ws_evals), (double*)wsb(P.ws_evecs)};
@@ -1784,6 +1831,7 @@ struct Ps2Exec {
     hipchk(hipMemcpyAsync(lam.data(), wsb(P.ws_evals), n * sizeof(double), hipMemcpyDeviceToHost, s),
            "evals");
     hipchk(hipStreamSynchronize(s), "sync");
+    hold.clear();
     // truncation: singular values s_i = sqrt(max(lambda_i, 0)), descending
     std::vector<double> sv(n);
     double tot2 = 0;
@@ -2226,15 +2274,26 @@ int tenso_step_adaptive(tenso_plan* p, void* d_state, double t0, double dt, int 
     if (p->opts.method != TENSO_PS2) fail(TENSO_EINVAL, "plan is not a ps2 plan");
     if (p->gen.n_slots > 0 && !d_drive_tab) fail(TENSO_EINVAL, "generator has drive slots: drive table needed");
     (void)t0;
-    Ps2Exec X{*p, d_state, d_ws, dt, d_drive_tab, 4 * n_steps + 1, s, std::min(max_rank, p->opts.max_rank), eps};
+    const int ld = 4 * n_steps + 1;
+    // cached sub-flow programs hold this binding's pointers and dt; the drive
+    // table's row length matters only when the generator has drive slots
+    if (p->ps2_state != d_state || p->ps2_ws != d_ws || p->ps2_dt != dt ||
+        p->ps2_drive != d_drive_tab || p->ps2_tile != p->tile_work ||
+        (p->gen.n_slots > 0 && p->ps2_ld != ld)) {
+      hipchk(hipStreamSynchronize(s), "sync");
+      p->ps2_progs.clear();
+      p->ps2_state = d_state;
+      p->ps2_ws = d_ws;
+      p->ps2_dt = dt;
+      p->ps2_drive = d_drive_tab;
+      p->ps2_tile = p->tile_work;
+      p->ps2_ld = ld;
+    }
+    Ps2Exec X{*p, d_state, d_ws, dt, d_drive_tab, p->ps2_ld, s, std::min(max_rank, p->opts.max_rank), eps};
     X.ctr = (int*)((char*)d_ws + p->ws_ctr);
     p->rank_log.clear();
     plan_root_norm(p, d_state, d_ws, 0, s);
-    {
-      Program G;
-      build_init(*p, G);
-      X.exec(G);
-    }
+    X.exec_cached("I|", [&](Program& G) { build_init(*p, G); });
     for (int k = 0; k < n_steps; ++k) {
       hipchk(launch_step_inc(X.ctr, k, s), "ctr");
       X.W(0, 0);
