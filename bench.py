@@ -369,7 +369,7 @@ def surrogate_main(a):
     on training seeds, BF16 MLP training, monitored rollout on held-out seeds,
     TTN fallback for tripped trajectories, judged against TTN-HEOM."""
     from paper_2603_17711_amd import surrogate
-    n_train, n_held, n_steps, epochs = 512, 64, 1000, 10
+    n_train, n_held, n_steps, epochs = 1536, 64, 1000, 60
     res = surrogate.experiment(n_train, n_held, n_steps=n_steps, epochs=epochs, log=lambda *x: None)
     value = n_held * n_steps / res["surrogate_s"]
     out = {
