@@ -1738,7 +1738,6 @@ struct Ps2Exec {
   // on every exit, error paths included, no copy may still read `hold`
   ~Ps2Exec() { (void)hipStreamSynchronize(s); }
 
-
   char* wsb(size_t off) { return (char*)ws + off; }
   double* core(int x) { return (double*)((char*)state + P.core_off[x]); }
 
