@@ -1832,7 +1832,12 @@ __global__ void __launch_bounds__(kEigThreads) k_eig(const EigOp* __restrict__ o
   }
 }
 
-__global__ void __launch_bounds__(256) k_split(const SplitOp* __restrict__ ops) {
+// One workgroup of kSplitThreads lanes: the element-parallel parts (mapping
+// the spectral vectors through Theta, the projections) spread over all of
+// them; the Gram-Schmidt steps reduce per wavefront and over the workgroup.
+constexpr int kSplitThreads = 1024;
+constexpr int kSplitWaves = kSplitThreads / 64;
+__global__ void __launch_bounds__(kSplitThreads) k_split(const SplitOp* __restrict__ ops) {
   const SplitOp op = ops[blockIdx.x];
   const z2* Th = reinterpret_cast<const z2*>(op.Theta);
   const z2* E = reinterpret_cast<const z2*>(op.evecs);
@@ -1841,10 +1846,10 @@ __global__ void __launch_bounds__(256) k_split(const SplitOp* __restrict__ ops) 
   const int miso = op.iso == 0 ? op.rows : op.cols;     // isometry side
   const int k = op.k, rp = op.rp;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  __shared__ double red[2][4];
+  __shared__ double red[2][kSplitWaves];
   __shared__ double sh_norm;
   // first k columns of W: spectral vectors on the isometry side
-  for (long e = tid; e < (long)miso * k; e += 256) {
+  for (long e = tid; e < (long)miso * k; e += kSplitThreads) {
     const int i = (int)(e / k), j = (int)(e % k);
     z2 v;
     if (op.side == op.iso) {
@@ -1897,16 +1902,20 @@ __global__ void __launch_bounds__(256) k_split(const SplitOp* __restrict__ ops) 
         }
       }
       double s2 = 0;
-      for (int i = tid; i < miso; i += 256) {
+      for (int i = tid; i < miso; i += kSplitThreads) {
         const z2 b = W[(long)i * rp + j];
         s2 += b.r * b.r + b.i * b.i;
       }
       s2 = wave_sum(s2);
       if (lane == 0) red[0][wave] = s2;
       __syncthreads();
-      if (tid == 0) sh_norm = sqrt(red[0][0] + red[0][1] + red[0][2] + red[0][3]);
+      if (tid == 0) {
+        double t = 0;
+        for (int w = 0; w < kSplitWaves; ++w) t += red[0][w];
+        sh_norm = sqrt(t);
+      }
       __syncthreads();
-      for (int i = tid; i < miso; i += 256) {
+      for (int i = tid; i < miso; i += kSplitThreads) {
         W[(long)i * rp + j].r /= sh_norm;
         W[(long)i * rp + j].i /= sh_norm;
       }
@@ -1917,7 +1926,7 @@ __global__ void __launch_bounds__(256) k_split(const SplitOp* __restrict__ ops) 
   // twice, accepted when the residual norm exceeds 0.5
   int j = k;
   for (int cand = 0; cand < miso && j < rp; ++cand) {
-    for (int i = tid; i < miso; i += 256) W[(long)i * rp + j] = z2{i == cand ? 1.0 : 0.0, 0.0};
+    for (int i = tid; i < miso; i += kSplitThreads) W[(long)i * rp + j] = z2{i == cand ? 1.0 : 0.0, 0.0};
     __syncthreads();
     for (int pass = 0; pass < 2; ++pass) {
       for (int q = 0; q < j; ++q) {
@@ -1940,17 +1949,21 @@ __global__ void __launch_bounds__(256) k_split(const SplitOp* __restrict__ ops) 
       }
     }
     double s2 = 0;
-    for (int i = tid; i < miso; i += 256) {
+    for (int i = tid; i < miso; i += kSplitThreads) {
       const z2 b = W[(long)i * rp + j];
       s2 += b.r * b.r + b.i * b.i;
     }
     s2 = wave_sum(s2);
     if (lane == 0) red[1][wave] = s2;
     __syncthreads();
-    if (tid == 0) sh_norm = sqrt(red[1][0] + red[1][1] + red[1][2] + red[1][3]);
+    if (tid == 0) {
+      double t = 0;
+      for (int w = 0; w < kSplitWaves; ++w) t += red[1][w];
+      sh_norm = sqrt(t);
+    }
     __syncthreads();
     if (sh_norm > 0.5) {
-      for (int i = tid; i < miso; i += 256) {
+      for (int i = tid; i < miso; i += kSplitThreads) {
         W[(long)i * rp + j].r /= sh_norm;
         W[(long)i * rp + j].i /= sh_norm;
       }
@@ -1966,11 +1979,11 @@ __global__ void __launch_bounds__(256) k_split(const SplitOp* __restrict__ ops) 
     return (long)pre * rp * op.Ppost_s + (long)a * op.Ppost_s + post;
   };
   if (op.iso == 0) {
-    for (long e = tid; e < (long)op.rows * rp; e += 256) {
+    for (long e = tid; e < (long)op.rows * rp; e += kSplitThreads) {
       const int row = (int)(e / rp), a = (int)(e % rp);
       Cs[cs_at(row, a)] = W[(long)row * rp + a];
     }
-    for (long e = tid; e < (long)rp * op.cols; e += 256) {  // Cc = W^H Theta
+    for (long e = tid; e < (long)rp * op.cols; e += kSplitThreads) {  // Cc = W^H Theta
       const int a = (int)(e / op.cols), col = (int)(e % op.cols);
       double sr = 0, si = 0;
       for (int row = 0; row < op.rows; ++row) {
@@ -1981,12 +1994,12 @@ __global__ void __launch_bounds__(256) k_split(const SplitOp* __restrict__ ops) 
       Cc[e] = z2{sr, si};
     }
   } else {
-    for (long e = tid; e < (long)rp * op.cols; e += 256) {  // Cc = W^H
+    for (long e = tid; e < (long)rp * op.cols; e += kSplitThreads) {  // Cc = W^H
       const int a = (int)(e / op.cols), col = (int)(e % op.cols);
       const z2 w = W[(long)col * rp + a];
       Cc[e] = z2{w.r, -w.i};
     }
-    for (long e = tid; e < (long)op.rows * rp; e += 256) {  // Cs = Theta W
+    for (long e = tid; e < (long)op.rows * rp; e += kSplitThreads) {  // Cs = Theta W
       const int row = (int)(e / rp), a = (int)(e % rp);
       double sr = 0, si = 0;
       for (int col = 0; col < op.cols; ++col) {
@@ -2128,7 +2141,7 @@ hipError_t launch_eig(const EigOp* op, hipStream_t s) {
   return hipGetLastError();
 }
 hipError_t launch_split(const SplitOp* op, hipStream_t s) {
-  hipLaunchKernelGGL(k_split, dim3(1), dim3(256), 0, s, op);
+  hipLaunchKernelGGL(k_split, dim3(1), dim3(kSplitThreads), 0, s, op);
   return hipGetLastError();
 }
 
