@@ -121,9 +121,21 @@ int tenso_build_generator(const tenso_tree* t, int n_terms, const tenso_c128* co
 void tenso_gen_destroy(tenso_gen* g);
 
 /* Compile tree + generator into an execution plan (tables uploaded to the
- * current HIP device).  The plan keeps its own copies of tree and generator. */
+ * current HIP device).  The plan keeps its own copies of tree and generator.
+ * Errors: EINVAL (bad options, a generator built for another tree),
+ * EUNSUPPORTED (a term with more than two non-identity legs on one core, a
+ * ps2 edge beyond what the split supports), EHIP. */
 int tenso_plan_create(const tenso_tree* t, const tenso_gen* g, const tenso_plan_opts* opts,
                       tenso_plan** out);
+
+/* Compile the same plan on the host only (no HIP call, no device memory) and
+ * report what tenso_plan_create would need: state and workspace bytes (each
+ * nullable), and for PS1 plans the kernel launches of one step and their
+ * algorithmic apply flops (0 for PS2, whose sweep depends on the ranks).
+ * Same errors as tenso_plan_create, minus EHIP. */
+int tenso_plan_query(const tenso_tree* t, const tenso_gen* g, const tenso_plan_opts* opts,
+                     size_t* state_bytes, size_t* workspace_bytes, int64_t* launches_per_step,
+                     double* apply_flops_per_step);
 void tenso_plan_destroy(tenso_plan* p);
 
 /* Step execution switches (no device work).
@@ -147,7 +159,9 @@ int tenso_plan_shapes(const tenso_plan* p, int32_t* n_legs_out, int32_t* dims_ou
 
 /* Write the initial product state rho_S(0) (x) |0..0> (host M x M rho_s) into
  * d_state: root[i, j, 0..] = rho[i, j]; other cores U[a, beta] =
- * delta(a, flat(beta)).  PS2 plans start at rank 1 on every bond. */
+ * delta(a, flat(beta)).  PS2 plans start at rank 2 on every bond (clamped;
+ * with rank 1 a tree whose inner nodes carry no physical leg has two-site
+ * tensors with a side of dimension 1, and no bond could ever grow). */
 int tenso_state_init(tenso_plan* p, const tenso_c128* rho_s, void* d_state, hipStream_t s);
 
 /* Copy host cores (concatenated, each row-major over its legs at the plan's
@@ -157,14 +171,20 @@ int tenso_state_import(tenso_plan* p, const tenso_c128* h_cores, void* d_state, 
 int tenso_state_export(tenso_plan* p, const void* d_state, tenso_c128* h_cores, int32_t* ranks,
                        hipStream_t s);
 
-/* Effective generator at `center` (Sec. II C): d_out (complex FP64, the
- * center core's shape, row-major) = sum_m coef_m(t) (x)_legs X_{m,l} C_center,
- * with up/down environments on virtual legs, factors on ends and identities
- * skipped.  The state must be canonical toward `center` (every other core an
- * isometry toward it).  drive: host array of one value per slot (nullable if
- * the generator has no slots).  Synchronous on `s` for the result. */
-int tenso_apply_generator(tenso_plan* p, const void* d_state, int center, double t,
-                          const double* drive, void* d_out, void* d_ws, hipStream_t s);
+/* Effective generator at `center` (Sec. II C, the local TDVP right-hand side
+ * of Eq. master_lvn on the tree): d_out (complex FP64, the center core's
+ * shape, row-major, caller-owned device buffer) =
+ * sum_m coef_m f_slot(m) (x)_legs X_{m,l} C_center, with up/down environments
+ * on virtual legs, factors on ends and identities skipped.  The time enters
+ * only through the drive values: drive is a host array of one value f_slot
+ * per slot, taken at the time of interest (nullable if the generator has no
+ * slots).  The state must be canonical toward `center`: every other core an
+ * isometry toward it (checked on the device to 1e-8; EINVAL otherwise).
+ * d_ws is the plan's workspace.  The library allocates the launch
+ * descriptors' device arena for the call and frees it before returning
+ * (errors included).  Synchronous on `s` for the result. */
+int tenso_apply_generator(tenso_plan* p, const void* d_state, int center, const double* drive,
+                          void* d_out, void* d_ws, hipStream_t s);
 
 /* Advance n_steps steps of size dt with ps1 (second-order: a first-order
  * sweep over half a step, then its adjoint).  d_drive_tab (nullable when the
@@ -177,9 +197,12 @@ int tenso_apply_generator(tenso_plan* p, const void* d_state, int center, double
 int tenso_step_fixed(tenso_plan* p, void* d_state, double t0, double dt, int n_steps,
                      const double* d_drive_tab, void* d_ws, hipStream_t s);
 
-/* Same with ps2 (two-site sweeps, SVD truncation: keep the smallest r' with
- * tail norm <= eps * total norm, 1 <= r' <= max_rank).  Synchronises the
- * stream (ranks are decided on the host from device singular values). */
+/* Same with ps2 (two-site sweeps, SVD truncation).  With r_eps the smallest r
+ * whose discarded tail sqrt(sum_{i>=r} s_i^2) is at most eps * sqrt(sum s_i^2),
+ * every split keeps r' = min(max_rank, available, r_eps + 1) directions,
+ * r' >= 1 (one direction beyond r_eps is room for the rank to grow).
+ * Synchronises the stream (ranks are decided on the host from device
+ * singular values). */
 int tenso_step_adaptive(tenso_plan* p, void* d_state, double t0, double dt, int n_steps,
                         double eps, int max_rank, const double* d_drive_tab, void* d_ws,
                         hipStream_t s);

@@ -62,7 +62,7 @@ PS2_GROW = 1           # directions kept beyond the rank needed for eps (room to
 PS2_INIT_RANK = 2      # ps2 starts from the padded initial state at this rank
 
 
-def householder_qr(A, tol=QR_RANK_TOL):
+def householder_qr(A, tol=None):
     """Householder QR A = Q R (Q: m x k, R: k x n, k = min(m, n)) with LAPACK's
     reflector convention (zgeqr2 / zung2r: beta = -sign(Re alpha) * norm,
     tau = 0 when nothing is left to reflect).
@@ -72,6 +72,8 @@ def householder_qr(A, tol=QR_RANK_TOL):
     identity reflector, so the orthonormal completion of a rank-deficient
     matrix is fixed by the well-determined columns alone rather than by
     rounding noise (projector splitting at truncated rank depends on it)."""
+    if tol is None:
+        tol = QR_RANK_TOL
     A = np.array(A, dtype=np.complex128)
     m, n = A.shape
     k = min(m, n)

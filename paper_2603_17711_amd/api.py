@@ -144,7 +144,9 @@ class Plan:
             o += k
         return cores
 
-    def apply(self, center, t=0.0, drive=None):
+    def apply(self, center, drive=None):
+        """Effective generator at `center` (the state must be canonical toward
+        it); drive: one value per slot at the time of interest."""
         import torch
         shape = self.shapes()[center]
         out = torch.zeros(int(np.prod(shape)) * 2, dtype=torch.float64, device=self.state.device)
@@ -152,7 +154,7 @@ class Plan:
         if drive is not None:
             d = np.ascontiguousarray(drive, dtype=np.float64)
             dv = d.ctypes.data_as(C.POINTER(C.c_double))
-        check(lib().tenso_apply_generator(self.h, C.c_void_p(self.state.data_ptr()), center, t, dv,
+        check(lib().tenso_apply_generator(self.h, C.c_void_p(self.state.data_ptr()), center, dv,
                                           C.c_void_p(out.data_ptr()),
                                           C.c_void_p(self.ws.data_ptr()), _stream()))
         o = out.cpu().numpy()
@@ -255,6 +257,38 @@ class Batch:
         check(lib().tenso_batch_step(self.h, t0.ctypes.data_as(C.POINTER(C.c_double)),
                                      dt.ctypes.data_as(C.POINTER(C.c_double)), n_steps, tabs,
                                      _stream()))
+
+    def step_record(self, n_steps, dts, every, t0s=None, drive_tabs=None):
+        """As step(), recording every instance's rho_S before the first step and
+        after every `every` steps (tenso_batch_step_record).  Returns a list of
+        records, each a list of per-instance M_i x M_i complex arrays."""
+        import torch
+        n = len(self.plans)
+        dt = np.ascontiguousarray(np.broadcast_to(np.asarray(dts, np.float64), (n,)))
+        t0 = np.zeros(n) if t0s is None else np.ascontiguousarray(t0s, np.float64)
+        nb = C.c_size_t()
+        offs = (C.c_size_t * n)()
+        check(lib().tenso_batch_record_bytes(self.h, C.byref(nb), offs))
+        n_rec = n_steps // every + 1
+        buf = torch.zeros(n_rec * int(nb.value), dtype=torch.uint8,
+                          device=self.plans[0].state.device)
+        tabs = None
+        if drive_tabs is not None:
+            tabs = (C.c_void_p * n)(*[(t.data_ptr() if t is not None else None)
+                                      for t in drive_tabs])
+        check(lib().tenso_batch_step_record(self.h, t0.ctypes.data_as(C.POINTER(C.c_double)),
+                                            dt.ctypes.data_as(C.POINTER(C.c_double)), n_steps,
+                                            every, tabs, C.c_void_p(buf.data_ptr()), _stream()))
+        raw = buf.cpu().numpy()
+        out = []
+        for j in range(n_rec):
+            rec = raw[j * int(nb.value):(j + 1) * int(nb.value)]
+            mats = []
+            for i, p in enumerate(self.plans):
+                a = rec[offs[i]:offs[i] + 16 * p.M * p.M].view(np.complex128)
+                mats.append(a.reshape(p.M, p.M).copy())
+            out.append(mats)
+        return out
 
     def set_graph(self, enable):
         """Replay batched steps from a captured HIP graph (default) or launch eagerly."""

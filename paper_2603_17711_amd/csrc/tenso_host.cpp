@@ -242,11 +242,16 @@ struct Program {
 struct DevProgram {
   char* arena = nullptr;
   size_t bytes = 0;
+  bool external = false;  // arena owned by the caller: never grown or freed here
   size_t o_terms, o_groups, o_atiles, o_presums, o_combines, o_ctiles, o_qrs, o_absorbs, o_abtiles,
       o_grams, o_rnodes, o_rprogs;
   std::vector<LaunchRec> launches;
+  DevProgram() = default;
+  DevProgram(char* a, size_t b) : arena(a), bytes(b), external(true) {}
+  DevProgram(const DevProgram&) = delete;
+  DevProgram& operator=(const DevProgram&) = delete;
   ~DevProgram() {
-    if (arena) (void)hipFree(arena);
+    if (arena && !external) (void)hipFree(arena);
   }
 };
 
@@ -360,7 +365,8 @@ struct tenso_plan {
   // workspace layout
   std::vector<size_t> envd_off, envu_off;
   size_t ws_presum = 0, ws_xin = 0, ws_acc = 0, ws_parts = 0, ws_envscr = 0, ws_bond = 0,
-         ws_qrv = 0, ws_qrtau = 0, ws_rhovec = 0, ws_rhoout = 0, ws_ctr = 0, ws_bytes = 0;
+         ws_qrv = 0, ws_qrtau = 0, ws_rhovec = 0, ws_rhoout = 0, ws_ctr = 0, ws_drive = 0,
+         ws_check = 0, ws_bytes = 0;
   size_t presum_cap = 0, parts_cap = 0, envscr_cap = 0, qrv_cap = 0;
   size_t ws_theta = 0, ws_evals = 0, ws_evecs = 0, ws_W = 0, theta_cap = 0, W_cap = 0;
   void* opbuf = nullptr;  // device scratch for single-op descriptors (ps2)
@@ -698,6 +704,10 @@ static void layout(tenso_plan& P) {
   P.ws_rhoout = take((size_t)t.end_dim[0] * t.end_dim[0] * 16);
   P.ws_ctr = take(256);  // step counter at 0, finiteness flag at 64, its descriptor at 128,
                          // the root-norm descriptor at 160, norms before / after at 192 / 200
+  // drive values of a one-off apply (one per slot), and the isometry-check
+  // descriptors and results of the canonical-center test (one per node)
+  P.ws_drive = take((size_t)std::max(1, P.gen.n_slots) * sizeof(double));
+  P.ws_check = take(align256((size_t)t.n * sizeof(IsoOp)) + (size_t)t.n * sizeof(double));
   if (P.opts.method == TENSO_PS2) {
     P.ws_theta = take(std::max<size_t>(1, theta) * 16);
     P.ws_evals = take(64 * 8);
@@ -1374,6 +1384,8 @@ static void upload_resolved(DevProgram& D, const Program& G, hipStream_t s,
   D.o_grams = put(buf, G.grams);
   D.o_rnodes = put(buf, G.rnodes);
   D.o_rprogs = put(buf, G.rprogs);
+  if (D.external && D.bytes < buf.size())
+    fail(TENSO_ENOMEM, "launch descriptors exceed the scratch space left for them");
   if (!D.arena || D.bytes < buf.size()) {
     if (D.arena) hipchk(hipFree(D.arena), "hipFree");
     D.arena = nullptr;
@@ -1800,10 +1812,15 @@ struct Ps2Exec {
       b.emit_absorb(b_, lb, 0);
     });
   }
+  // single-op descriptors: the host bytes go into `hold` (alive until the next
+  // synchronisation), like the programs' host buffers
   template <class T>
   const T* put_op(const T& op, size_t slot) {
     char* dst = (char*)P.opbuf + slot * 512;
-    hipchk(hipMemcpyAsync(dst, &op, sizeof(T), hipMemcpyHostToDevice, s), "op upload");
+    std::vector<char> bytes(sizeof(T));
+    memcpy(bytes.data(), &op, sizeof(T));
+    hipchk(hipMemcpyAsync(dst, bytes.data(), sizeof(T), hipMemcpyHostToDevice, s), "op upload");
+    hold.push_back(std::move(bytes));
     return (const T*)dst;
   }
 
@@ -1902,6 +1919,135 @@ struct Ps2Exec {
     }
   }
 };
+
+// Compile tree + generator into a plan: slot analysis, constant tables,
+// buffer layout and recipe validation.  With device = false nothing touches
+// the GPU (the constant tables stay on the host; used to query sizes).
+static std::unique_ptr<tenso_plan> compile_plan(const tenso_tree* t, const tenso_gen* g,
+                                                const tenso_plan_opts* o, bool device) {
+  if (!t || !g || !o) fail(TENSO_EINVAL, "null argument");
+  if (o->precision != TENSO_FP64 && o->precision != TENSO_FP32) fail(TENSO_EINVAL, "bad precision");
+  if (o->method != TENSO_PS1 && o->method != TENSO_PS2) fail(TENSO_EINVAL, "bad method");
+  if (g->n_ends != t->n_ends || g->end_dim != t->end_dim) fail(TENSO_EINVAL, "generator built for another tree");
+  auto P = std::make_unique<tenso_plan>();
+  P->tree = *t;
+  P->gen = *g;
+  P->opts = *o;
+  P->fp64 = o->precision == TENSO_FP64;
+  P->tsz = P->fp64 ? 16 : 8;
+  P->cap = P->tree;
+  if (o->method == TENSO_PS2) {
+    if (o->max_rank < 2) fail(TENSO_EINVAL, "ps2 needs max_rank >= 2");
+    for (int c = 1; c < P->cap.n; ++c) P->cap.rank[c] = o->max_rank;
+    P->cap.clamp();
+    for (int c = 1; c < P->tree.n; ++c) P->tree.rank[c] = std::min(2, P->cap.rank[c]);
+    P->tree.clamp();
+  }
+  analyse_slots(*P);
+  // constant buffer: factor matrices in FP64 and FP32
+  std::vector<char> cb;
+  for (size_t i = 0; i < P->gen.mats.size(); ++i) {
+    const auto& m = P->gen.mats[i];
+    size_t o64 = align256(cb.size());
+    cb.resize(o64 + m.size() * 16);
+    memcpy(cb.data() + o64, m.data(), m.size() * 16);
+    size_t o32 = align256(cb.size());
+    cb.resize(o32 + m.size() * 8);
+    float* f = (float*)(cb.data() + o32);
+    for (size_t q = 0; q < m.size(); ++q) {
+      f[2 * q] = (float)m[q].real();
+      f[2 * q + 1] = (float)m[q].imag();
+    }
+    P->mat_off64.push_back(o64);
+    P->mat_off32.push_back(o32);
+  }
+  if (device) {
+    hipchk(hipMalloc(&P->cbuf, std::max<size_t>(cb.size(), 256)), "hipMalloc(constants)");
+    hipchk(hipMalloc(&P->opbuf, 4096), "hipMalloc(op scratch)");
+    if (!cb.empty())
+      hipchk(hipMemcpy(P->cbuf, cb.data(), cb.size(), hipMemcpyHostToDevice), "upload constants");
+  }
+  layout(*P);
+  // validate that every recipe compiles (throws EUNSUPPORTED otherwise)
+  for (int s = 0; s < P->tree.n; ++s) (void)node_recipe(*P, s);
+  return P;
+}
+
+
+// ---------------------------------------------------------------------------
+// one-off effective generator (tenso_apply_generator and its variants)
+// ---------------------------------------------------------------------------
+// Canonical-center test: every core other than the center must be an
+// isometry toward it (orthonormal rows along the leg that points to the
+// center: the child leg on the root-to-center path, the parent leg
+// elsewhere).  One small kernel, one synchronisation.
+static constexpr double kIsometryTol = 1e-8;
+
+static void check_canonical(tenso_plan* p, const void* d_state, int center, void* d_ws,
+                            hipStream_t s) {
+  const tenso_tree& t = p->tree;
+  std::vector<int> toward(t.n, 0);
+  for (int x = center; x != 0; x = t.parent[x]) toward[t.parent[x]] = t.leg_of_child(t.parent[x], x);
+  std::vector<IsoOp> ops;
+  std::vector<int> node;
+  for (int x = 0; x < t.n; ++x) {
+    if (x == center) continue;
+    const std::vector<int> d = t.shape(x);
+    const int l = toward[x];
+    IsoOp op{};
+    op.C = (const double*)((const char*)d_state + p->core_off[x]);
+    op.p0 = prod(d, 0, l);
+    op.d = d[l];
+    op.p1 = prod(d, l + 1, (int)d.size());
+    ops.push_back(op);
+    node.push_back(x);
+  }
+  if (ops.empty()) return;
+  char* base = (char*)d_ws + p->ws_check;
+  double* dev = (double*)(base + align256(ops.size() * sizeof(IsoOp)));
+  hipchk(hipMemcpyAsync(base, ops.data(), ops.size() * sizeof(IsoOp), hipMemcpyHostToDevice, s),
+         "isometry descriptors");
+  hipchk(launch_isometry((const IsoOp*)base, (int)ops.size(), dev, s), "isometry check");
+  std::vector<double> dv(ops.size());
+  hipchk(hipMemcpyAsync(dv.data(), dev, dv.size() * sizeof(double), hipMemcpyDeviceToHost, s),
+         "isometry readback");
+  hipchk(hipStreamSynchronize(s), "sync");
+  for (size_t i = 0; i < dv.size(); ++i)
+    if (!(dv[i] <= kIsometryTol))
+      fail(TENSO_EINVAL, "state is not canonical toward center " + std::to_string(center) +
+                             ": core " + std::to_string(node[i]) +
+                             " is not an isometry toward it (deviation " + std::to_string(dv[i]) + ")");
+}
+
+// Y = L_eff(center) C_center into d_out, with the workspace d_ws and the
+// launch descriptors in D (its own arena, or caller-provided scratch).
+static void apply_generator_impl(tenso_plan* p, const void* d_state, int center, const double* drive,
+                                 void* d_out, void* d_ws, DevProgram& D, hipStream_t s) {
+  if (!p || !d_state || !d_out || !d_ws) fail(TENSO_EINVAL, "null argument");
+  if (center < 0 || center >= p->tree.n) fail(TENSO_EINVAL, "bad center");
+  if (p->gen.n_slots > 0 && !drive) fail(TENSO_EINVAL, "generator has drive slots: drive values needed");
+  check_canonical(p, d_state, center, d_ws, s);
+  Program G;
+  Builder b(*p, G);
+  b.env_init_toward(center);
+  Recipe R = node_recipe(*p, center);
+  int np = b.emit_apply(R, b.core(center), 1, p->tree.size(center), 0, 1, p->par_target);
+  b.emit_combine(d_out, p->tree.size(center), np, 0, 0.0);
+  // the combine writes y0 = k at stage 0: y0 is the caller's buffer (absolute)
+  G.combines.back().y0 = (double*)d_out;
+  // drive values: one row per slot (ld = 1, index 0), in the workspace
+  std::vector<double> dv(std::max(1, p->gen.n_slots), 0.0);
+  if (drive)
+    for (int k = 0; k < p->gen.n_slots; ++k) dv[k] = drive[k];
+  double* d_drive = (double*)((char*)d_ws + p->ws_drive);
+  hipchk(hipMemcpyAsync(d_drive, dv.data(), dv.size() * sizeof(double), hipMemcpyHostToDevice, s),
+         "drive");
+  upload(D, G, const_cast<void*>(d_state), d_ws, 0.0, d_drive, 1, s);
+  int* ctr = (int*)((char*)d_ws + p->ws_ctr);
+  hipchk(launch_step_inc(ctr, 0, s), "ctr");
+  run(D, p->fp64, ctr, s);
+  hipchk(hipStreamSynchronize(s), "sync");
+}
 
 // ---------------------------------------------------------------------------
 // host-side state helpers
@@ -2054,49 +2200,28 @@ void tenso_gen_destroy(tenso_gen* g) { delete g; }
 int tenso_plan_create(const tenso_tree* t, const tenso_gen* g, const tenso_plan_opts* o,
                       tenso_plan** out) {
   return guard([&] {
-    if (!t || !g || !o || !out) fail(TENSO_EINVAL, "null argument");
-    if (o->precision != TENSO_FP64 && o->precision != TENSO_FP32) fail(TENSO_EINVAL, "bad precision");
-    if (o->method != TENSO_PS1 && o->method != TENSO_PS2) fail(TENSO_EINVAL, "bad method");
-    if (g->n_ends != t->n_ends || g->end_dim != t->end_dim) fail(TENSO_EINVAL, "generator built for another tree");
-    auto P = std::make_unique<tenso_plan>();
-    P->tree = *t;
-    P->gen = *g;
-    P->opts = *o;
-    P->fp64 = o->precision == TENSO_FP64;
-    P->tsz = P->fp64 ? 16 : 8;
-    P->cap = P->tree;
-    if (o->method == TENSO_PS2) {
-      if (o->max_rank < 2) fail(TENSO_EINVAL, "ps2 needs max_rank >= 2");
-      for (int c = 1; c < P->cap.n; ++c) P->cap.rank[c] = o->max_rank;
-      P->cap.clamp();
-      for (int c = 1; c < P->tree.n; ++c) P->tree.rank[c] = std::min(2, P->cap.rank[c]);
-      P->tree.clamp();
+    if (!out) fail(TENSO_EINVAL, "null argument");
+    *out = compile_plan(t, g, o, true).release();
+  });
+}
+
+int tenso_plan_query(const tenso_tree* t, const tenso_gen* g, const tenso_plan_opts* o,
+                     size_t* state_bytes, size_t* workspace_bytes, int64_t* launches_per_step,
+                     double* apply_flops_per_step) {
+  return guard([&] {
+    auto P = compile_plan(t, g, o, false);
+    if (state_bytes) *state_bytes = P->state_bytes;
+    if (workspace_bytes) *workspace_bytes = P->ws_bytes;
+    int64_t nl = 0;
+    double fl = 0;
+    if (P->opts.method == TENSO_PS1) {
+      Program G;
+      build_step(*P, G);
+      nl = (int64_t)G.launches.size();
+      for (const auto& L : G.launches) fl += L.flops;
     }
-    analyse_slots(*P);
-    // constant buffer: factor matrices in FP64 and FP32
-    std::vector<char> cb;
-    for (size_t i = 0; i < P->gen.mats.size(); ++i) {
-      const auto& m = P->gen.mats[i];
-      size_t o64 = align256(cb.size());
-      cb.resize(o64 + m.size() * 16);
-      memcpy(cb.data() + o64, m.data(), m.size() * 16);
-      size_t o32 = align256(cb.size());
-      cb.resize(o32 + m.size() * 8);
-      float* f = (float*)(cb.data() + o32);
-      for (size_t q = 0; q < m.size(); ++q) {
-        f[2 * q] = (float)m[q].real();
-        f[2 * q + 1] = (float)m[q].imag();
-      }
-      P->mat_off64.push_back(o64);
-      P->mat_off32.push_back(o32);
-    }
-    hipchk(hipMalloc(&P->cbuf, std::max<size_t>(cb.size(), 256)), "hipMalloc(constants)");
-    hipchk(hipMalloc(&P->opbuf, 4096), "hipMalloc(op scratch)");
-    if (!cb.empty()) hipchk(hipMemcpy(P->cbuf, cb.data(), cb.size(), hipMemcpyHostToDevice), "upload constants");
-    layout(*P);
-    // validate that every recipe compiles (throws EUNSUPPORTED otherwise)
-    for (int s = 0; s < P->tree.n; ++s) (void)node_recipe(*P, s);
-    *out = P.release();
+    if (launches_per_step) *launches_per_step = nl;
+    if (apply_flops_per_step) *apply_flops_per_step = fl;
   });
 }
 
@@ -2185,35 +2310,12 @@ int tenso_state_export(tenso_plan* p, const void* d_state, tenso_c128* h_cores, 
   });
 }
 
-int tenso_apply_generator(tenso_plan* p, const void* d_state, int center, double t,
-                          const double* drive, void* d_out, void* d_ws, hipStream_t s) {
+int tenso_apply_generator(tenso_plan* p, const void* d_state, int center, const double* drive,
+                          void* d_out, void* d_ws, hipStream_t s) {
   return guard([&] {
-    if (!p || !d_state || !d_out || !d_ws) fail(TENSO_EINVAL, "null argument");
-    if (center < 0 || center >= p->tree.n) fail(TENSO_EINVAL, "bad center");
-    if (p->gen.n_slots > 0 && !drive) fail(TENSO_EINVAL, "generator has drive slots: drive values needed");
-    (void)t;
-    Program G;
-    Builder b(*p, G);
-    b.env_init_toward(center);
-    Recipe R = node_recipe(*p, center);
-    int np = b.emit_apply(R, b.core(center), 1, p->tree.size(center), 0, 1, p->par_target);
-    b.emit_combine(d_out, p->tree.size(center), np, 0, 0.0);
-    // the combine writes y0 = k at stage 0: y0 is the caller's buffer (absolute)
-    G.combines.back().y0 = (double*)d_out;
-    // drive values: one row per slot, ld = 1, index 0
-    std::vector<double> dv(std::max(1, p->gen.n_slots), 0.0);
-    if (drive)
-      for (int k = 0; k < p->gen.n_slots; ++k) dv[k] = drive[k];
-    double* d_drive = nullptr;
-    hipchk(hipMalloc((void**)&d_drive, dv.size() * sizeof(double)), "hipMalloc(drive)");
-    hipchk(hipMemcpyAsync(d_drive, dv.data(), dv.size() * sizeof(double), hipMemcpyHostToDevice, s), "drive");
+    if (!d_ws) fail(TENSO_EINVAL, "null argument");
     DevProgram D;
-    upload(D, G, const_cast<void*>(d_state), d_ws, 0.0, d_drive, 1, s);
-    int* ctr = (int*)((char*)d_ws + p->ws_ctr);
-    hipchk(launch_step_inc(ctr, 0, s), "ctr");
-    run(D, p->fp64, ctr, s);
-    hipchk(hipStreamSynchronize(s), "sync");
-    hipchk(hipFree(d_drive), "hipFree");
+    apply_generator_impl(p, d_state, center, drive, d_out, d_ws, D, s);
   });
 }
 

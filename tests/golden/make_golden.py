@@ -1,0 +1,150 @@
+"""Write the oracle trajectories that the GPU parity tests and bench.py compare with.
+
+Every stored value comes from the FP64 CPU oracle (``oracle/``) run on the seeded
+workloads of ``workloads.py``; nothing here touches the GPU library.
+
+    python tests/golden/make_golden.py [spin_boson|exciton|batch|batch200|all] [--procs N]
+
+Files (numpy .npz, no pickles):
+  spin_boson_train_2000.npz   spin-boson K=3 N=10 train R=8, ps1, 2000 steps,
+                              rho_S at every 10th step
+  exciton_7site_50.npz        7-site exciton K=28 N=8 binary R=16, ps1, 50 steps,
+                              rho_S at every 10th step
+  batch512_25.npz             the 512-instance uneven batch (seed 2), ps1, 25 steps,
+                              rho_S of every instance at every 5th step; instance i's
+                              M_i x M_i matrices are rows offsets[i]:offsets[i+1] of
+                              the flattened record arrays
+  batch512_200_sample.npz     the same batch over its configured 200 steps, rho_S at
+                              every 10th step, for a sample: every 32nd instance, the
+                              instances a too-large RK4 step once made diverge
+                              (61, 121, 153, 267, 304, 387, 429) and instance 393
+                              (the largest trace drift); same record layout, with
+                              `ids` naming the sampled instances
+Each file stores the inputs it depends on (time steps, step counts, a digest of
+the workload parameters) so that a stale file is detected instead of compared.
+"""
+import argparse
+import hashlib
+import os
+import sys
+import time
+from multiprocessing import Pool
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def workload_digest(insts):
+    """Digest of every input parameter of a list of workload instances."""
+    h = hashlib.sha256()
+    for inst in insts:
+        h.update(np.ascontiguousarray(inst.H).tobytes())
+        h.update(np.ascontiguousarray(inst.rho0).tobytes())
+        for b in inst.baths:
+            h.update(np.ascontiguousarray(b.Q).tobytes())
+            h.update(repr((b.T, b.dl, b.bo, b.n_ltc)).encode())
+        h.update(repr((inst.depth, inst.tree, inst.rank, inst.dt, inst.method, inst.eps,
+                       None if inst.drive is None else inst.drive[1:])).encode())
+    return h.hexdigest()
+
+
+def load(fname, insts):
+    """The stored oracle trajectories of `fname`, checked against the inputs of
+    `insts` (a stale file raises instead of being compared)."""
+    with np.load(os.path.join(HERE, fname), allow_pickle=False) as z:
+        out = {k: z[k] for k in z.files}
+    if str(out["digest"]) != workload_digest(insts):
+        raise RuntimeError(f"{fname} was written for other workload inputs: rerun "
+                           "tests/golden/make_golden.py")
+    return out
+
+
+def batch_rhos(g, record):
+    """Per-instance rho_S matrices of one record of a batch file."""
+    off = g["offsets"]
+    out = []
+    for i in range(len(off) - 1):
+        m = int(round(np.sqrt(off[i + 1] - off[i])))
+        out.append(g["rho"][record, off[i]:off[i + 1]].reshape(m, m))
+    return out
+
+
+def _single(args):
+    name, n_steps, every = args
+    import workloads
+    from oracle.run import propagate
+    inst = {"spin_boson": workloads.spin_boson_train,
+            "exciton": workloads.exciton_7site}[name](n_steps=n_steps)
+    steps, rhos, _, _ = propagate(inst, n_steps=n_steps, every=every)
+    return name, inst, steps, rhos
+
+
+BATCH200_IDS = sorted(set(range(0, 512, 32)) | {61, 121, 153, 267, 304, 387, 393, 429})
+
+
+def _batch_one(args):
+    i, n_steps, every = args
+    import workloads
+    from oracle.run import propagate
+    inst = workloads.uneven_batch()[i]
+    steps, rhos, _, _ = propagate(inst, n_steps=n_steps, every=every)
+    return i, steps, rhos
+
+
+def write_single(name, n_steps, every, fname, pool):
+    t0 = time.time()
+    _, inst, steps, rhos = pool.apply(_single, ((name, n_steps, every),))
+    np.savez_compressed(os.path.join(HERE, fname), steps=steps, rho=rhos, dt=inst.dt,
+                        digest=workload_digest([inst]))
+    print(f"{fname}: {len(steps)} records, {time.time() - t0:.1f} s", flush=True)
+
+
+def write_batch(n_steps, every, fname, pool, ids=None):
+    import workloads
+    insts = workloads.uneven_batch()
+    ids = list(range(len(insts))) if ids is None else list(ids)
+    t0 = time.time()
+    res = {}
+    # largest instances first, so that the pool's tail is short
+    order = sorted(ids, key=lambda i: -insts[i].M * insts[i].K * insts[i].depth * insts[i].rank)
+    for i, steps, rhos in pool.imap_unordered(_batch_one, [(i, n_steps, every) for i in order]):
+        res[i] = (steps, rhos)
+    steps = res[ids[0]][0]
+    offsets = np.zeros(len(ids) + 1, dtype=np.int64)
+    for j, i in enumerate(ids):
+        offsets[j + 1] = offsets[j] + insts[i].M * insts[i].M
+    rec = np.zeros((len(steps), int(offsets[-1])), dtype=np.complex128)
+    for j, i in enumerate(ids):
+        assert np.array_equal(res[i][0], steps)
+        rec[:, offsets[j]:offsets[j + 1]] = res[i][1].reshape(len(steps), -1)
+    np.savez_compressed(os.path.join(HERE, fname), steps=steps, rho=rec, offsets=offsets,
+                        ids=np.array(ids), dt=np.array([x.dt for x in insts]),
+                        digest=workload_digest(insts))
+    print(f"{fname}: {len(insts)} instances x {len(steps)} records, "
+          f"{time.time() - t0:.1f} s", flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("what", nargs="?", default="all",
+                    choices=["spin_boson", "exciton", "batch", "batch200", "all"])
+    ap.add_argument("--procs", type=int, default=os.cpu_count())
+    a = ap.parse_args()
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    with Pool(a.procs) as pool:
+        if a.what in ("spin_boson", "all"):
+            write_single("spin_boson", 2000, 10, "spin_boson_train_2000.npz", pool)
+        if a.what in ("exciton", "all"):
+            write_single("exciton", 50, 10, "exciton_7site_50.npz", pool)
+        if a.what in ("batch", "all"):
+            write_batch(25, 5, "batch512_25.npz", pool)
+        if a.what in ("batch200", "all"):
+            write_batch(200, 10, "batch512_200_sample.npz", pool, ids=BATCH200_IDS)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,21 +1,27 @@
-"""Parity at the benchmark sizes, in the launch configuration bench.py times.
+"""Parity at the benchmark sizes and horizons, in the launch configuration
+bench.py times, against the stored FP64 oracle trajectories of
+tests/golden/ (written by tests/golden/make_golden.py, which calls only the
+oracle).
 
-The 512-instance batch runs with its defaults (tile size, four parts replayed
-as branches of one HIP graph); every instance must stay finite with a trace
-within 1e-5 of one (the projected dynamics conserve it up to the projection
-error), and sampled instances are compared with the FP64 oracle one by one:
-fixed ones, the largest states, and the instances with the largest trace and
-Hermiticity deviations (Hermiticity of rho_S is not exact under the fixed-rank
-projection: the oracle itself departs from it, by up to 2e-8 after 3 steps).
-The 7-site exciton model (K = 28, rank 16) runs as a single FP32 plan against
-the oracle.
+* The 512-instance batch runs with its defaults (tile size, four parts
+  replayed as branches of one HIP graph) for the bench's 25 steps, recording
+  rho_S of every instance every 5 steps: every instance at every record is
+  within the fixed-rank bar of the oracle, and none is flagged.
+* The same batch over the configuration's 200 steps: no instance is flagged
+  (non-finite or norm grown 1e6-fold), and a sample (every 32nd instance, the
+  ones an earlier, too large time step made diverge, and the one whose trace
+  drifts most) matches the oracle every 10 steps, trace included: the fixed-rank
+  projection does not conserve the trace exactly, and the GPU drifts as the
+  oracle does.
+* The 7-site exciton model (K = 28, rank 16) as a single FP32 plan over 50
+  steps, rho_S at every 10th step.
 The bar is the fixed-rank one: trace distance of rho_S at most 1e-6."""
 import numpy as np
 import pytest
 
 import workloads
-from oracle.run import build, propagate
 from oracle.ttn import trace_distance
+from tests.golden.make_golden import batch_rhos, load
 from tests.gpu_util import require_gpu
 
 pytestmark = pytest.mark.gpu
@@ -23,59 +29,69 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-6
 
 
-def state_sizes(insts):
-    out = []
-    for inst in insts:
-        _, tree = build(inst)
-        tot = 0
-        for s in range(tree.n):
-            tot += int(np.prod(tree.shape(s)))
-        out.append(tot)
-    return out
-
-
-def test_full_batch_sampled_against_oracle():
+def test_full_batch_every_instance_against_oracle():
     require_gpu()
     from paper_2603_17711_amd import api
-    n = 3
+    n, every = 25, 5
     insts = workloads.uneven_batch(n_inst=512, n_steps=n)
-    sizes = state_sizes(insts)
-    largest = [int(i) for i in np.argsort(sizes)[::-1][:2]]
-    print(f"[full batch] 512 instances, {n} steps, FP32, default tiles and parts", flush=True)
-    plans = [api.build_instance(i, precision=api.FP32) for i in insts]
-    batch = api.Batch(plans)
-    batch.step(n, [i.dt for i in insts])
+    g = load("batch512_25.npz", insts)
+    assert list(g["steps"]) == list(range(0, n + 1, every))
+    print(f"[full batch] 512 instances, {n} steps, FP32, default tiles and parts, "
+          f"rho_S every {every} steps", flush=True)
+    batch = api.Batch([api.build_instance(i, precision=api.FP32) for i in insts])
+    recs = batch.step_record(n, [i.dt for i in insts], every)
     assert not batch.status().any()
-    rho = batch.rho()
-    tr = np.array([np.trace(r).real for r in rho])
-    herm = np.array([np.abs(r - r.conj().T).max() for r in rho])
-    k_tr, k_herm = int(np.argmax(np.abs(tr - 1))), int(np.argmax(herm))
-    print(f"  max |Tr - 1| = {np.abs(tr - 1).max():.2e} (instance {k_tr}), "
-          f"max |rho - rho^H| = {herm.max():.2e} (instance {k_herm})", flush=True)
-    assert all(np.isfinite(r).all() for r in rho)
-    assert np.abs(tr - 1).max() < 1e-5
-    sample = sorted(set([0, 1, 128, 255, 384, 511, k_tr, k_herm] + largest))
-    print(f"  oracle sample {sample}", flush=True)
-    worst = 0.0
-    for k in sample:
-        _, ro, _, _ = propagate(insts[k], n_steps=n, every=n)
-        d = trace_distance(rho[k], ro[-1])
-        ho = np.abs(ro[-1] - ro[-1].conj().T).max()
-        print(f"  instance {k} (state {sizes[k]} elements): trace distance {d:.3e}, "
-              f"|rho - rho^H| GPU {herm[k]:.2e} oracle {ho:.2e}", flush=True)
-        worst = max(worst, d)
-    assert worst < TOL, worst
+    worst, where = 0.0, None
+    for j, rec in enumerate(recs):
+        ref = batch_rhos(g, j)
+        for i in range(len(insts)):
+            d = trace_distance(rec[i], ref[i])
+            if not d <= worst:
+                worst, where = d, (i, int(g["steps"][j]))
+    print(f"  max trace distance over 512 instances x {len(recs)} records = {worst:.3e} "
+          f"(instance {where[0]}, step {where[1]})", flush=True)
+    assert worst < TOL, (worst, where)
+
+
+def test_full_batch_config_horizon_against_oracle_sample():
+    require_gpu()
+    from paper_2603_17711_amd import api
+    n, every = 200, 10
+    insts = workloads.uneven_batch(n_inst=512, n_steps=n)
+    g = load("batch512_200_sample.npz", insts)
+    ids = [int(i) for i in g["ids"]]
+    print(f"[full batch] 512 instances, {n} steps, FP32: none flagged; {len(ids)} sampled "
+          "instances against the oracle every 10 steps", flush=True)
+    batch = api.Batch([api.build_instance(i, precision=api.FP32) for i in insts])
+    recs = batch.step_record(n, [i.dt for i in insts], every)
+    flags = batch.status()
+    assert not flags.any(), np.nonzero(flags)[0]
+    assert all(np.isfinite(r).all() for rec in recs for r in rec)
+    worst, dtr = 0.0, 0.0
+    for j in range(len(recs)):
+        ref = batch_rhos(g, j)
+        for q, i in enumerate(ids):
+            worst = max(worst, trace_distance(recs[j][i], ref[q]))
+            dtr = max(dtr, abs(np.trace(recs[j][i]) - np.trace(ref[q])))
+    tr = np.array([np.trace(r).real for r in recs[-1]])
+    print(f"  sample: max trace distance {worst:.3e}, max |Tr_gpu - Tr_oracle| {dtr:.2e}; "
+          f"all 512: max |Tr - 1| = {np.abs(tr - 1).max():.2e} "
+          f"(instance {int(np.argmax(np.abs(tr - 1)))}, a truncation effect the oracle shares)",
+          flush=True)
+    assert worst < TOL and dtr < TOL
 
 
 def test_full_exciton_7site_against_oracle():
     require_gpu()
     from paper_2603_17711_amd import api
-    n = 5
+    n, every = 50, 10
     inst = workloads.exciton_7site(n_steps=n)
+    g = load("exciton_7site_50.npz", [inst])
     print(f"[full size] 7-site exciton model, K = 28, R = 16, {n} FP32 steps", flush=True)
     plan = api.build_instance(inst, precision=api.FP32)
-    plan.step(n, inst.dt)
-    _, ro, _, _ = propagate(inst, n_steps=n, every=n)
-    d = trace_distance(plan.rho(), ro[-1])
-    print(f"  trace distance {d:.3e}", flush=True)
-    assert d < TOL, d
+    ds = [trace_distance(plan.rho(), g["rho"][0])]
+    for j in range(1, n // every + 1):
+        plan.step(every, inst.dt, t0=(j - 1) * every * inst.dt)
+        ds.append(trace_distance(plan.rho(), g["rho"][j]))
+    print(f"  trace distance per record {['%.2e' % d for d in ds]}", flush=True)
+    assert max(ds) < TOL, ds

@@ -104,13 +104,18 @@ def exciton_7site(n_steps=1000, seed=1):
                     ground(M), 0.1 * FS_TO_CM, n_steps)
 
 
-def stable_dt(dt_max, T, n_ltc, N, wc=1.0):
-    """Time step of a batch instance: dt_max unless the fastest decay rate of
-    the hierarchy, (N - 1) * max(wc, 2 pi n_ltc T), would put a half-step RK4
-    sub-flow outside RK4's real stability interval (|z| < 2.78); then
-    half of that limit."""
-    rate = (N - 1) * max(wc, 2.0 * np.pi * n_ltc * T)
-    return min(dt_max, 0.5 * 2 * 2.78 / rate)
+def stable_dt(dt_max, T, n_ltc, N, H, wc=1.0):
+    """Time step of a batch instance: dt_max unless a half-step RK4 sub-flow
+    would leave half of RK4's real stability interval (|z| < 2.785).
+
+    The rate bound uses input parameters only.  Every feature's level is
+    truncated on its own, so all of them can be excited at once and the
+    hierarchy's decay rates add up: (N - 1) * sum_k |gamma_k|, with
+    |gamma| = wc for the Drude feature and 2 pi m T for Matsubara feature m.
+    The commutator with H_S adds at most 2 ||H_S||_2."""
+    sum_gamma = wc + sum(2.0 * np.pi * m * T for m in range(1, n_ltc + 1))
+    rate = (N - 1) * sum_gamma + 2.0 * float(np.linalg.norm(H, 2))
+    return min(dt_max, 0.5 * 2.0 * 2.785 / rate)
 
 
 def uneven_batch(n_inst=512, seed=2, n_steps=200):
@@ -133,7 +138,7 @@ def uneven_batch(n_inst=512, seed=2, n_steps=200):
         T = float(np.exp(rng.uniform(np.log(0.1), np.log(10.0))))
         bath = Bath(np.diag(q).astype(np.complex128), T, dl=[(lam, 1.0)], n_ltc=K - 1)
         out.append(Instance(f"batch[{i}] M={M} K={K} N={N} R={R}", H, [bath], N, "tree2",
-                            R, ground(M), stable_dt(0.01, T, K - 1, N), n_steps))
+                            R, ground(M), stable_dt(0.01, T, K - 1, N, H), n_steps))
     return out
 
 
