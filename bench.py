@@ -396,16 +396,17 @@ def main():
 
 def ps2_main(a):
     """Adaptive-rank (ps2) propagation of the structured-bath ternary tree at rank
-    cap 4, one instance."""
+    cap 8 with eps 1e-6 (the ranks grow from 2 and eps decides them), one
+    instance."""
     import ctypes as C
     import numpy as np
     import torch
     import workloads
     from paper_2603_17711_amd import api
     from paper_2603_17711_amd._lib import check, lib
-    cap = 4
+    cap = 8
     inst = workloads.structured_bath_ternary(n_steps=a.steps + a.warmup)
-    wname = "structured bath K=24 N=10 ternary ps2 (eps 1e-6, rank cap 4, dt 0.01)"
+    wname = f"structured bath K=24 N=10 ternary ps2 (eps 1e-6, rank cap {cap}, dt 0.01)"
 
     def run(precision, steps, warmup, profile=False):
         plan = api.build_instance(inst, precision=precision, rank=cap)
@@ -418,22 +419,26 @@ def ps2_main(a):
         torch.cuda.synchronize()
         return plan, time.perf_counter() - t0
 
+    log(f"ps2 mixed: {a.warmup} warm-up + {a.steps} timed steps at cap {cap}")
     plan, dt_mixed = run(api.FP32, a.steps, a.warmup)
     value = a.steps / dt_mixed
+    ranks = plan.rank_log()
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "steps/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(1e3 * dt_mixed / a.steps, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "c64 contractions (fp32 MFMA), f64 master/QR/eigen", "data": "synthetic",
+        "dtype": "c64 contractions (fp32 MFMA), f64 master/QR/SVD", "data": "synthetic",
         "config": {"workload": wname, "instances": 1, "precision": "mixed",
-                   "max_rank_reached": int(max(plan.ranks()))},
+                   "max_rank_reached": int(max(ranks)), "ranks_last_step": ranks},
     }
     if not a.no_fp64:
+        log("ps2 FP64 path over the same steps")
         # the same steps as the mixed run: the cost of a ps2 step grows with the ranks
         _, dt64 = run(api.FP64, a.steps, a.warmup)
         out["fp64_gpu_value"] = round(a.steps / dt64, 3)
         out["speedup_vs_fp64_gpu"] = round(value / (a.steps / dt64), 3)
-    prof_steps = max(1, min(a.steps, 10))
+    log("contraction-kernel roofline pass")
+    prof_steps = max(1, min(a.steps, 5))
     _, _ = run(api.FP32, prof_steps, 1, profile=True)
     ms, n, fl, by = C.c_double(), C.c_int64(), C.c_double(), C.c_double()
     check(lib().tenso_profile_stats(C.byref(ms), C.byref(n), C.byref(fl), C.byref(by)))
@@ -448,22 +453,37 @@ def ps2_main(a):
         "algorithmic_flops_per_launch": fl.value / max(1, n.value),
         "algorithmic_bytes_per_launch": by.value / max(1, n.value),
     }
+    # accuracy: a fresh run against the stored oracle trajectory (10 steps)
+    try:
+        from tests.golden.make_golden import load
+        g = load("ps2_ternary_cap8_10.npz", [workloads.structured_bath_ternary(n_steps=10)])
+    except (OSError, RuntimeError):
+        g = None
+    if g is not None:
+        log("accuracy pass against the stored oracle trajectory")
+        cinst = workloads.structured_bath_ternary(n_steps=10)
+        p2 = api.build_instance(cinst, precision=api.FP32, rank=cap)
+        dmax = 0.0
+        for k in range(10):
+            p2.step_adaptive(1, cinst.dt, cinst.eps, cap, t0=k * cinst.dt)
+            dmax = max(dmax, trace_distance(p2.rho(), g["rho"][k + 1]))
+        out["trace_distance_vs_oracle"] = {
+            "value": dmax, "steps": 10,
+            "sample": "every step of 10, against the stored FP64 oracle trajectory (adaptive bar 1e-5)"}
     if not a.no_cpu:
+        log("CPU oracle baseline")
         from threadpoolctl import threadpool_limits
         from oracle.run import propagate
-        n_sample = 3
+        n_sample = 2
         cinst = workloads.structured_bath_ternary(n_steps=n_sample)
         with threadpool_limits(limits=1):
             t0 = time.perf_counter()
-            _, ro, _, _ = propagate(cinst, n_steps=n_sample, every=n_sample, max_rank=cap)
+            propagate(cinst, n_steps=n_sample, every=n_sample, max_rank=cap)
             tc = time.perf_counter() - t0
         out["cpu_baseline"] = {
             "value": round(n_sample / tc, 4), "unit": "steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_sample} ps2 steps of the same workload, FP64 NumPy oracle, 1 BLAS thread"}
-        p2 = api.build_instance(cinst, precision=api.FP32, rank=cap)
-        p2.step_adaptive(n_sample, cinst.dt, cinst.eps, cap)
-        out["trace_distance_vs_oracle"] = {"value": trace_distance(p2.rho(), ro[-1]),
-                                           "steps": n_sample}
+            "sample": f"the first {n_sample} ps2 steps of the same workload (ranks lowest there), "
+                      "FP64 NumPy oracle, 1 BLAS thread", "cpu_model": cpu_model()}
     print(json.dumps(out))
 
 

@@ -197,12 +197,16 @@ int tenso_apply_generator(tenso_plan* p, const void* d_state, int center, const 
 int tenso_step_fixed(tenso_plan* p, void* d_state, double t0, double dt, int n_steps,
                      const double* d_drive_tab, void* d_ws, hipStream_t s);
 
-/* Same with ps2 (two-site sweeps, SVD truncation).  With r_eps the smallest r
- * whose discarded tail sqrt(sum_{i>=r} s_i^2) is at most eps * sqrt(sum s_i^2),
- * every split keeps r' = min(max_rank, available, r_eps + 1) directions,
- * r' >= 1 (one direction beyond r_eps is room for the rank to grow).
- * Synchronises the stream (ranks are decided on the host from device
- * singular values). */
+/* Same with ps2 (two-site sweeps, SVD truncation; the SVD and the decision
+ * are those of tenso_svd_truncate).  With r_eps the smallest r whose discarded
+ * tail sqrt(sum_{i>=r} s_i^2) is at most eps * sqrt(sum s_i^2), every split
+ * keeps r' = min(max_rank, available, r_eps + 1) directions, r' >= 1 (one
+ * direction beyond r_eps is room for the rank to grow): the leading singular
+ * vectors with s_i > 1e-10 s_1, then unit vectors projected onto the
+ * orthogonal complement.  The decision is taken on the device and read back
+ * once per split (the new rank sets the shapes of the following sub-flows),
+ * so the call synchronises the stream per edge.  ENOMEM at plan creation if
+ * a two-site tensor exceeds 2^26 elements at the rank cap. */
 int tenso_step_adaptive(tenso_plan* p, void* d_state, double t0, double dt, int n_steps,
                         double eps, int max_rank, const double* d_drive_tab, void* d_ws,
                         hipStream_t s);
@@ -215,6 +219,32 @@ int tenso_reduced_rho(tenso_plan* p, const void* d_state, tenso_c128* h_rho, dou
 /* Bond ranks chosen by the last ps2 step, one entry per split in sweep order;
  * returns the number of entries (at most cap) or a negative error. */
 int tenso_rank_trajectory(const tenso_plan* p, int32_t* h_ranks, int cap);
+
+/* The SVD behind the ps2 split (Sec. II C: two-site tensors are split by
+ * SVD), on its own: A is a device matrix, rows x cols row-major complex FP64
+ * (at most 2^26 elements, ENOMEM beyond).  It is factorised in FP64 from A
+ * itself (range finder with hashed test columns, Householder QR, one-sided
+ * Jacobi on the projected p x p factor; p = min(64, rows, cols)), which keeps
+ * each singular value accurate to rounding relative to sigma_1.
+ *   h_sigma (host, nullable): the p leading singular values, descending.
+ *   d_vectors (device, caller-owned, n x p complex row-major): the leading
+ *     singular vectors of the left side (iso 0, n = rows) or of the right
+ *     side (iso 1, n = cols; columns of V with A = U S V^H).
+ *   h_decision (host, nullable, 3 entries): the ps2 truncation for (eps,
+ *     max_rank): r' = min(max_rank, min(rows, cols), r_eps + 1), the number k
+ *     <= r' of singular values above 1e-10 sigma_1, and r_eps, the smallest r
+ *     with sqrt(sum_{i>=r} s_i^2) <= eps * ||A||_F (at least 1; eps = 0
+ *     keeps every direction).
+ *   h_missed (host, nullable): the energy outside the captured p-dimensional
+ *     subspace relative to ||A||_F^2, when the subspace may be incomplete
+ *     (p below the smaller side and s_p > 1e-13 s_1), else 0.  Then power
+ *     steps are added until the leading singular values settle (at most
+ *     three).
+ * Allocates its device scratch for the call and frees it before returning.
+ * Synchronous on `s`.  Errors: EINVAL, ENOMEM, EHIP. */
+int tenso_svd_truncate(const void* d_A, int rows, int cols, int iso, double eps, int max_rank,
+                       double* h_sigma, void* d_vectors, int32_t* h_decision, double* h_missed,
+                       hipStream_t s);
 
 /* ---- measurement ---------------------------------------------------------
  * tenso_profile(1) starts recording HIP events on the launching stream around

@@ -15,7 +15,8 @@ from .ttn import Tree, initial_state, nary_tree, train_tree
 def build(inst, rank=None):
     baths = []
     for b in inst.baths:
-        baths.append((b.Q, bath_features(b.T, dl=b.dl, bo=b.bo, n_ltc=b.n_ltc)))
+        baths.append((b.Q, bath_features(b.T, dl=b.dl, bo=b.bo, n_ltc=b.n_ltc,
+                                         method=getattr(b, "decomposition", "matsubara"))))
     drives = [] if inst.drive is None else [(0, inst.drive[0])]
     terms, dims = heom_terms(inst.H, baths, inst.depth, drives=drives)
     K = len(dims) - 2

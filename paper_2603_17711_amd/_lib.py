@@ -57,6 +57,8 @@ SIGS = {
                                       P, P, P]),
     "tenso_reduced_rho": (C.c_int, [P, P, C128P, DP, P, P]),
     "tenso_rank_trajectory": (C.c_int, [P, I32P, C.c_int]),
+    "tenso_svd_truncate": (C.c_int, [P, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, DP, P, I32P,
+                                     DP, P]),
     "tenso_profile": (C.c_int, [C.c_int]),
     "tenso_profile_stats": (C.c_int, [DP, C.POINTER(C.c_int64), DP, DP]),
     "tenso_profile_records": (C.c_int, [C.c_int64, DP, DP, DP, C.POINTER(C.c_int64)]),

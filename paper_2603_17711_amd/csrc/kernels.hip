@@ -601,11 +601,9 @@ __global__ void __launch_bounds__(256) k_combine(const CombineOp* __restrict__ o
 struct z2 {
   double r, i;
 };
-// Relative rank threshold of the gauge-move QR: a residual column with norm at
-// or below QR_RANK_TOL * ||A||_F is treated as exactly zero (identity
-// reflector), so the completion of a rank-deficient core does not follow
-// rounding noise.
-constexpr double QR_RANK_TOL = 1e-10;
+// Rank threshold of the QR (per op, QrOp::tol): a residual column with norm at
+// or below tol * ||A||_F is treated as exactly zero (identity reflector), so
+// the completion of a rank-deficient core does not follow rounding noise.
 __device__ inline z2 zmul(z2 a, z2 b) { return z2{a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
 __device__ inline z2 zconjmul(z2 a, z2 b) {  // conj(a) * b
   return z2{a.r * b.r + a.i * b.i, a.r * b.i - a.i * b.r};
@@ -784,7 +782,7 @@ __device__ void qr_unblocked(const QrOp& op) {
   // residual columns at or below this squared norm count as exact zeros
   double fsum = 0;
   for (int w = 0; w < QR_NW; ++w) fsum += red[QR_NW + w];
-  const double thr2 = QR_RANK_TOL * QR_RANK_TOL * fsum;
+  const double thr2 = op.tol * op.tol * fsum;
   for (int j = 0; j < k; ++j) {
     // xnorm of V[j+1:m, j]
     double s = 0;
@@ -976,7 +974,7 @@ __global__ void __launch_bounds__(QR_NT) k_qr(const QrOp* __restrict__ ops) {
   // residual columns at or below this squared norm count as exact zeros
   double fsum = 0;
   for (int w = 0; w < QR_NW; ++w) fsum += red[0][w][0];
-  const double thr2 = QR_RANK_TOL * QR_RANK_TOL * fsum;
+  const double thr2 = op.tol * op.tol * fsum;
   const int nbk = (k + QR_PB - 1) / QR_PB;
   int nbf = nbk;  // panels actually factored (fewer after an early exit)
   int par = 1;
@@ -1617,311 +1615,28 @@ __global__ void __launch_bounds__(256) k_merge(const MergeOp* __restrict__ ops) 
   }
 }
 
-// Cyclic Jacobi on the n x n Hermitian Gram matrix held in LDS (n <= 64),
-// parallel rounds of the circle-method pairing.  1024 lanes: in each round
-// lane (a, b) = (tid / 32, tid % 32) rotates the 2 x 2 block on the rows of
-// pair a and the columns of pair b, and two eigenvector entries; sixteen
-// waves per CU hide the LDS latency that a round otherwise waits on.
-constexpr int kEigThreads = 1024;
-__global__ void __launch_bounds__(kEigThreads) k_eig(const EigOp* __restrict__ ops) {
-  const EigOp op = ops[blockIdx.x];
-  const int n = op.side == 0 ? op.rows : op.cols;
-  const int m = op.side == 0 ? op.cols : op.rows;
-  // row stride 65: consecutive rows of a column fall in different LDS banks
-  constexpr int LD = 65;
-  __shared__ z2 G[64 * LD];
-  __shared__ z2 U[64 * LD];
-  __shared__ double rot[32][4];  // c, s, cos(phi), sin(phi)
-  __shared__ int pr[32][2];
-  __shared__ double pmax[2][kEigThreads / 64];
-  __shared__ int order[64];
-  const int tid = threadIdx.x;
-  // Gram: side 0: G[i][j] = sum_c Th[i][c] conj(Th[j][c]); side 1: sum_r conj(Th[r][i]) Th[r][j].
-  // Theta is staged 64 entries of the summed index at a time into U as
-  // S[q][i] (coalesced loads along whichever index is contiguous); each lane
-  // accumulates a 2 x 2 block of G (rows bi + 32a, cols bj + 32b).  Side 1 is
-  // the conjugate of the side-0 sum over S.
-  {
-    const gp<const z2> T = gmem(reinterpret_cast<const z2*>(op.Theta));
-    const int bi = tid >> 5, bj = tid & 31;
-    z2 acc[2][2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b) acc[a][b] = z2{0.0, 0.0};
-    for (int q0 = 0; q0 < m; q0 += 64) {
-      const int kq = min(64, m - q0);
-      __syncthreads();
-      if (op.side == 0) {
-        for (int e = tid; e < 64 * n; e += kEigThreads) {
-          const int i = e >> 6, qq = e & 63;
-          z2 v{0.0, 0.0};
-          if (qq < kq) v = T[(long)i * op.cols + q0 + qq];
-          U[qq * LD + i] = v;
-        }
-      } else {
-        for (int e = tid; e < kq * n; e += kEigThreads) {
-          const int qq = e / n, i = e - qq * n;
-          U[qq * LD + i] = T[(long)(q0 + qq) * op.cols + i];
-        }
-      }
-      __syncthreads();
-      for (int qq = 0; qq < kq; ++qq) {
-        z2 x[2], y[2];
-#pragma unroll
-        for (int a = 0; a < 2; ++a) {
-          x[a] = U[qq * LD + bi + 32 * a];
-          y[a] = U[qq * LD + bj + 32 * a];
-        }
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-          for (int b = 0; b < 2; ++b) {  // x * conj(y)
-            acc[a][b].r += x[a].r * y[b].r + x[a].i * y[b].i;
-            acc[a][b].i += x[a].i * y[b].r - x[a].r * y[b].i;
-          }
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        const int i = bi + 32 * a, j = bj + 32 * b;
-        if (i < n && j < n)
-          G[i * LD + j] = z2{acc[a][b].r, op.side == 0 ? acc[a][b].i : -acc[a][b].i};
-      }
-    for (int e = tid; e < n * n; e += kEigThreads) {
-      const int i = e / n, j = e - i * n;
-      U[i * LD + j] = z2{i == j ? 1.0 : 0.0, 0.0};
-    }
-  }
-  __syncthreads();
-  const int np = (n + 1) / 2;  // pairs per round (a dummy player when n is odd)
-  const int nr = 2 * np - 1;   // rounds per sweep; player nr stays in place
-  const int ba = tid >> 5, bb = tid & 31;
-  for (int sweep = 0; sweep < 40; ++sweep) {
-    {  // largest off-diagonal modulus and diagonal magnitude
-      double om = 0, dm = 0;
-      for (int e = tid; e < n * n; e += kEigThreads) {
-        const int i = e / n, j = e - i * n;
-        const z2 g = G[i * LD + j];
-        if (j > i) om = fmax(om, sqrt(g.r * g.r + g.i * g.i));
-        else if (j == i) dm = fmax(dm, fabs(g.r));
-      }
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        om = fmax(om, __shfl_xor(om, o));
-        dm = fmax(dm, __shfl_xor(dm, o));
-      }
-      if ((tid & 63) == 0) {
-        pmax[0][tid >> 6] = om;
-        pmax[1][tid >> 6] = dm;
-      }
-    }
-    __syncthreads();
-    double offmax = 0, diagmax = 0;
-#pragma unroll
-    for (int w = 0; w < kEigThreads / 64; ++w) {
-      offmax = fmax(offmax, pmax[0][w]);
-      diagmax = fmax(diagmax, pmax[1][w]);
-    }
-    if (offmax <= 1e-15 * diagmax || offmax == 0.0) break;  // the same decision in every lane
-    for (int round = 0; round < nr; ++round) {
-      if (tid < np) {
-        int p, q;
-        if (tid == 0) {
-          p = round;
-          q = nr;
-        } else {
-          p = round + tid;
-          if (p >= nr) p -= nr;
-          q = round - tid;
-          if (q < 0) q += nr;
-        }
-        if (p > q) {
-          const int t = p;
-          p = q;
-          q = t;
-        }
-        pr[tid][0] = p;
-        pr[tid][1] = q;
-        double c = 1, sn = 0, cph = 1, sph = 0;
-        if (q < n) {
-          const z2 g = G[p * LD + q];
-          const double h = sqrt(g.r * g.r + g.i * g.i);
-          if (h > 1e-300) {
-            const double a = G[p * LD + p].r, b = G[q * LD + q].r;
-            const double zeta = (b - a) / (2.0 * h);
-            const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-            c = 1.0 / sqrt(1.0 + t * t);
-            sn = t * c;
-            cph = g.r / h;
-            sph = g.i / h;
-          }
-        }
-        rot[tid][0] = c;
-        rot[tid][1] = sn;
-        rot[tid][2] = cph;
-        rot[tid][3] = sph;
-      }
-      __syncthreads();
-      // G <- J^H G J, J = [[c, s], [-s e^{-i phi}, c e^{-i phi}]] per pair, on
-      // the 2 x 2 block (rows of pair ba, columns of pair bb): columns first,
-      // then rows, as two separate passes would; every element is in one
-      // block.  The dummy pair of an odd n (q = n) rotates by the identity, so
-      // its block entries with index n are absent.
-      if (ba < np && bb < np) {
-        const int pa = pr[ba][0], qa = pr[ba][1], pb = pr[bb][0], qb = pr[bb][1];
-        const bool ra = qa < n, rb = qb < n;
-        const double ca = rot[ba][0], sa = rot[ba][1], cb = rot[bb][0], sb = rot[bb][1];
-        const z2 epa{rot[ba][2], rot[ba][3]};   // e^{i phi_a}
-        const z2 emb{rot[bb][2], -rot[bb][3]};  // e^{-i phi_b}
-        const z2 m00 = G[pa * LD + pb];
-        z2 m01{0.0, 0.0}, m10{0.0, 0.0}, m11{0.0, 0.0};
-        if (rb) m01 = G[pa * LD + qb];
-        if (ra) m10 = G[qa * LD + pb];
-        if (ra && rb) m11 = G[qa * LD + qb];
-        const z2 t01 = zmul(m01, emb), t11 = zmul(m11, emb);
-        const z2 n00{cb * m00.r - sb * t01.r, cb * m00.i - sb * t01.i};
-        const z2 n01{sb * m00.r + cb * t01.r, sb * m00.i + cb * t01.i};
-        const z2 n10{cb * m10.r - sb * t11.r, cb * m10.i - sb * t11.i};
-        const z2 n11{sb * m10.r + cb * t11.r, sb * m10.i + cb * t11.i};
-        const z2 u10 = zmul(n10, epa), u11 = zmul(n11, epa);
-        G[pa * LD + pb] = z2{ca * n00.r - sa * u10.r, ca * n00.i - sa * u10.i};
-        if (rb) G[pa * LD + qb] = z2{ca * n01.r - sa * u11.r, ca * n01.i - sa * u11.i};
-        if (ra) G[qa * LD + pb] = z2{sa * n00.r + ca * u10.r, sa * n00.i + ca * u10.i};
-        if (ra && rb) G[qa * LD + qb] = z2{sa * n01.r + ca * u11.r, sa * n01.i + ca * u11.i};
-      }
-      // U <- U J (columns): entry (row, pair k), two per lane
-#pragma unroll
-      for (int it = 0; it < 2; ++it) {
-        const int e = tid + it * kEigThreads;
-        const int k = e >> 6, row = e & 63;
-        if (k < np && row < n) {
-          const int p = pr[k][0], q = pr[k][1];
-          if (q < n) {
-            const double c = rot[k][0], sn = rot[k][1];
-            const z2 emi{rot[k][2], -rot[k][3]};  // e^{-i phi}
-            const z2 xp = U[row * LD + p], xq = U[row * LD + q];
-            const z2 xq_e = zmul(xq, emi);
-            U[row * LD + p] = z2{c * xp.r - sn * xq_e.r, c * xp.i - sn * xq_e.i};
-            U[row * LD + q] = z2{sn * xp.r + c * xq_e.r, sn * xp.i + c * xq_e.i};
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
-  // descending order: rank of each eigenvalue (ties by index)
-  if (tid < n) {
-    const double lj = G[tid * LD + tid].r;
-    int rank = 0;
-    for (int i = 0; i < n; ++i) {
-      const double li = G[i * LD + i].r;
-      if (li > lj || (li == lj && i < tid)) ++rank;
-    }
-    order[tid] = rank;
-    gmem(op.evals)[rank] = lj;
-  }
-  __syncthreads();
-  const gp<z2> ev = gmem(reinterpret_cast<z2*>(op.evecs));
-  for (int e = tid; e < n * n; e += kEigThreads) {
-    const int row = e / n, j = e - row * n;
-    ev[(long)row * n + order[j]] = U[row * LD + j];
-  }
-}
-
-// One workgroup of kSplitThreads lanes: the element-parallel parts (mapping
-// the spectral vectors through Theta, the projections) spread over all of
-// them; the Gram-Schmidt steps reduce per wavefront and over the workgroup.
+// One workgroup of kSplitThreads lanes: the element-parallel parts (copying
+// the singular vectors, the projections) spread over all of them; the
+// Gram-Schmidt steps of the completion reduce per wavefront and over the
+// workgroup.
 constexpr int kSplitThreads = 1024;
 constexpr int kSplitWaves = kSplitThreads / 64;
 __global__ void __launch_bounds__(kSplitThreads) k_split(const SplitOp* __restrict__ ops) {
   const SplitOp op = ops[blockIdx.x];
   const z2* Th = reinterpret_cast<const z2*>(op.Theta);
-  const z2* E = reinterpret_cast<const z2*>(op.evecs);
+  const z2* E = reinterpret_cast<const z2*>(op.E);
   z2* W = reinterpret_cast<z2*>(op.W);
-  const int n = op.side == 0 ? op.rows : op.cols;       // spectral side
   const int miso = op.iso == 0 ? op.rows : op.cols;     // isometry side
   const int k = op.k, rp = op.rp;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   __shared__ double red[2][kSplitWaves];
   __shared__ double sh_norm;
-  // first k columns of W: spectral vectors on the isometry side
+  // first k columns of W: the leading singular vectors of the isometry side
   for (long e = tid; e < (long)miso * k; e += kSplitThreads) {
     const int i = (int)(e / k), j = (int)(e % k);
-    z2 v;
-    if (op.side == op.iso) {
-      v = E[(long)i * n + j];
-    } else {
-      // map through Theta: other side vector = Theta^(H) u_j / sigma_j
-      const double sig = sqrt(fmax(op.evals[j], 0.0));
-      double sr = 0, si = 0;
-      if (op.iso == 1) {  // spectral on rows: w_j = Theta^H u_j / s_j (cols)
-        for (int r = 0; r < op.rows; ++r) {
-          const z2 t = Th[(long)r * op.cols + i];
-          const z2 u = E[(long)r * n + j];
-          sr += t.r * u.r + t.i * u.i;  // conj(t) * u
-          si += t.r * u.i - t.i * u.r;
-        }
-      } else {  // spectral on cols: w_j = Theta v_j / s_j (rows)
-        for (int c = 0; c < op.cols; ++c) {
-          const z2 t = Th[(long)i * op.cols + c];
-          const z2 u = E[(long)c * n + j];
-          sr += t.r * u.r - t.i * u.i;
-          si += t.r * u.i + t.i * u.r;
-        }
-      }
-      v = z2{sr / sig, si / sig};
-    }
-    W[(long)i * rp + j] = v;
+    W[(long)i * rp + j] = E[(long)i * op.ld_e + j];
   }
   __syncthreads();
-  // re-orthonormalise the mapped columns (only needed when mapped through Theta)
-  if (op.side != op.iso) {
-    for (int j = 0; j < k; ++j) {
-      for (int pass = 0; pass < 2; ++pass) {
-        for (int q = 0; q < j; ++q) {
-          double dr = 0, di = 0;
-          for (int i = lane; i < miso; i += 64) {
-            const z2 a = W[(long)i * rp + q], b = W[(long)i * rp + j];
-            dr += a.r * b.r + a.i * b.i;
-            di += a.r * b.i - a.i * b.r;
-          }
-          dr = wave_sum(dr);
-          di = wave_sum(di);
-          __syncthreads();
-          if (wave == 0)
-            for (int i = lane; i < miso; i += 64) {
-              const z2 a = W[(long)i * rp + q];
-              W[(long)i * rp + j].r -= a.r * dr - a.i * di;
-              W[(long)i * rp + j].i -= a.r * di + a.i * dr;
-            }
-          __syncthreads();
-        }
-      }
-      double s2 = 0;
-      for (int i = tid; i < miso; i += kSplitThreads) {
-        const z2 b = W[(long)i * rp + j];
-        s2 += b.r * b.r + b.i * b.i;
-      }
-      s2 = wave_sum(s2);
-      if (lane == 0) red[0][wave] = s2;
-      __syncthreads();
-      if (tid == 0) {
-        double t = 0;
-        for (int w = 0; w < kSplitWaves; ++w) t += red[0][w];
-        sh_norm = sqrt(t);
-      }
-      __syncthreads();
-      for (int i = tid; i < miso; i += kSplitThreads) {
-        W[(long)i * rp + j].r /= sh_norm;
-        W[(long)i * rp + j].i /= sh_norm;
-      }
-      __syncthreads();
-    }
-  }
   // completion: unit vectors e_0, e_1, ... projected out of span(W[:, :j]),
   // twice, accepted when the residual norm exceeds 0.5
   int j = k;
@@ -2134,10 +1849,6 @@ hipError_t launch_finite(const FiniteOp* ops, int n, int* flags, hipStream_t s) 
 hipError_t launch_merge(const MergeOp* op, long n, hipStream_t s) {
   int blocks = (int)std::min<long>(1024, (n + 255) / 256);
   hipLaunchKernelGGL(k_merge, dim3(blocks, 1), dim3(256), 0, s, op);
-  return hipGetLastError();
-}
-hipError_t launch_eig(const EigOp* op, hipStream_t s) {
-  hipLaunchKernelGGL(k_eig, dim3(1), dim3(kEigThreads), 0, s, op);
   return hipGetLastError();
 }
 hipError_t launch_split(const SplitOp* op, hipStream_t s) {

@@ -23,7 +23,10 @@ hipError_t launch_apply(int fp64, int in_fp64, const ApplyGroup* groups, const A
                         hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 size_t apply_lds_bytes(int fp64, int nfl, int d1, int d2);
 hipError_t launch_merge(const MergeOp* op, long n, hipStream_t s);
-hipError_t launch_eig(const EigOp* op, hipStream_t s);
+hipError_t launch_svd_gemm(const SvdGemmOp* op, int M_tiles, int nsplit, hipStream_t s);
+hipError_t launch_svd_reduce(const SvdGemmOp* op, long n_complex, hipStream_t s);
+hipError_t launch_svd_jacobi(const SvdJacobiOp* op, hipStream_t s);
+hipError_t launch_svd_finish(const SvdFinishOp* op, long n_iso_p, hipStream_t s);
 hipError_t launch_split(const SplitOp* op, hipStream_t s);
 hipError_t launch_presum(int fp64, const PresumOp* ops, int n, const int* step_ctr, hipStream_t s);
 hipError_t launch_combine(int fp64, const CombineOp* ops, const void* tiles, int n_tiles,
@@ -197,6 +200,10 @@ struct tenso_gen {
 // plan
 // ---------------------------------------------------------------------------
 static const uint64_t OFF_MASK = (1ull << 56) - 1;
+// Largest ps2 two-site tensor (elements at the rank cap): ENOMEM beyond.
+static constexpr long kPs2ThetaMax = 1L << 26;
+// Most summed-index ranges of one ps2 SVD product.
+static constexpr int kSvdMaxSplit = 8;
 enum { TAG_ABS = 0, TAG_STATE = 2, TAG_WS = 3, TAG_TERM = 4, TAG_RNODE = 5 };
 static inline void* tagp(int tag, uint64_t off) { return (void*)(((uint64_t)tag << 56) | off); }
 
@@ -368,8 +375,16 @@ struct tenso_plan {
          ws_qrv = 0, ws_qrtau = 0, ws_rhovec = 0, ws_rhoout = 0, ws_ctr = 0, ws_drive = 0,
          ws_check = 0, ws_bytes = 0;
   size_t presum_cap = 0, parts_cap = 0, envscr_cap = 0, qrv_cap = 0;
-  size_t ws_theta = 0, ws_evals = 0, ws_evecs = 0, ws_W = 0, theta_cap = 0, W_cap = 0;
-  void* opbuf = nullptr;  // device scratch for single-op descriptors (ps2)
+  size_t ws_theta = 0, ws_W = 0, theta_cap = 0, W_cap = 0, svd_side = 0;
+  // ps2 SVD scratch: range-finder and projection blocks (side x 64, column-
+  // major), split-K partials, QR scratch for sides above the blocked QR,
+  // the small factors, singular values, isometry-side vectors, and the
+  // decision record
+  size_t ws_svd_y = 0, ws_svd_z = 0, ws_svd_part = 0, ws_svd_qrv = 0, ws_svd_r = 0,
+         ws_svd_up = 0, ws_svd_wp = 0, ws_svd_sig = 0, ws_svd_tau = 0, ws_svd_norm = 0,
+         ws_svd_e = 0, ws_svd_rec = 0;
+  void* opbuf = nullptr;  // device scratch for single-op descriptors (ps2): 8 slots of
+                          // 512 bytes, then 4 slots for the SVD
   int par_target = 64;  // tiles wanted per apply (single-instance latency)
   int built_target = -1;  // par_target the cached programs were built with
   double tile_work = 16e6;        // flops per apply tile
@@ -635,7 +650,7 @@ static void layout(tenso_plan& P) {
   for (int c = 1; c < t.n; ++c) maxr = std::max(maxr, t.rank[c]);
   for (int e = 0; e < t.n_ends; ++e) P.max_dim = std::max(P.max_dim, t.end_dim[e]);
   P.max_dim = std::max(P.max_dim, maxr);
-  size_t presum = 0, parts = 0, envscr = 0, qrv = 0, theta = 0, wcap = 0;
+  size_t presum = 0, parts = 0, envscr = 0, qrv = 0, theta = 0, wcap = 0, side = 0;
   auto recipe_caps = [&](const Recipe& R, long n) {
     size_t ps = 0;
     for (auto& g : R.groups) {
@@ -664,9 +679,11 @@ static void layout(tenso_plan& P) {
       if (P.opts.method == TENSO_PS2) {
         const int p = t.parent[s];
         const long rows = t.size(p) / t.rank[s], cols = t.size(s) / t.rank[s];
-        if (std::min(rows, cols) > 64)
-          fail(TENSO_EUNSUPPORTED, "ps2 edge whose smaller side exceeds 64 at the rank cap");
+        if (rows * cols > kPs2ThetaMax)
+          fail(TENSO_ENOMEM, "ps2 two-site tensor of " + std::to_string(rows * cols) +
+                                 " elements at the rank cap (budget 2^26)");
         theta = std::max(theta, (size_t)(rows * cols));
+        side = std::max(side, (size_t)std::max(rows, cols));
         wcap = std::max(wcap, (size_t)std::max(rows, cols) * (size_t)maxr);
         recipe_caps(edge_recipe(P, p, s), rows * cols);
         maxP = std::max<long>(maxP, rows * cols);
@@ -709,9 +726,21 @@ static void layout(tenso_plan& P) {
   P.ws_drive = take((size_t)std::max(1, P.gen.n_slots) * sizeof(double));
   P.ws_check = take(align256((size_t)t.n * sizeof(IsoOp)) + (size_t)t.n * sizeof(double));
   if (P.opts.method == TENSO_PS2) {
+    const size_t blk = std::max<size_t>(1, side) * kSvdP * 16;
+    P.svd_side = side;
     P.ws_theta = take(std::max<size_t>(1, theta) * 16);
-    P.ws_evals = take(64 * 8);
-    P.ws_evecs = take(64 * 64 * 16);
+    P.ws_svd_y = take(blk);
+    P.ws_svd_z = take(blk);
+    P.ws_svd_part = take(kSvdMaxSplit * blk);
+    P.ws_svd_qrv = take(blk);
+    P.ws_svd_r = take(kSvdP * kSvdP * 16);
+    P.ws_svd_up = take(kSvdP * kSvdP * 16);
+    P.ws_svd_wp = take(kSvdP * kSvdP * 16);
+    P.ws_svd_sig = take(kSvdP * 8);
+    P.ws_svd_tau = take(kSvdP * 16);
+    P.ws_svd_norm = take(((side + 63) / 64) * kSvdMaxSplit * 8);
+    P.ws_svd_e = take(blk);
+    P.ws_svd_rec = take(256);
     P.ws_W = take(std::max<size_t>(1, wcap) * 16);
   }
   P.ws_bytes = w;
@@ -1184,6 +1213,7 @@ struct Builder {
     q.m = (int)(t.size(node) / d[leg]);
     q.Ppost = (int)prod(d, leg + 1, (int)d.size());
     q.transposeR = transposeR;
+    q.tol = kQrRankTol;
     // the core is already column-major m x n: factor it in place
     if (q.Ppost == q.m && q.m <= kQrBlockedMaxM) q.V = q.C;
     if (q.m < q.n) fail(TENSO_EUNSUPPORTED, "QR with fewer rows than columns");
@@ -1731,7 +1761,122 @@ static void build_init(tenso_plan& P, Program& G) {
 }
 
 // ---------------------------------------------------------------------------
-// ps2: host-driven two-site sweep (ranks decided on the host per edge)
+// ps2 split: FP64 SVD of the two-site tensor and the truncation decision
+// ---------------------------------------------------------------------------
+// Device scratch of one SVD (see svd.hip for the method).  Sizes for sides up
+// to `side`: y, z, qrv, e hold side x 64 complex; part kSvdMaxSplit times that;
+// r, up, wp 64 x 64; sig 64 doubles; tau 64 complex; norm
+// ceil(side / 64) * kSvdMaxSplit doubles; rec 256 bytes; opbuf 4 x 512 bytes.
+struct SvdScratch {
+  double *y, *z, *part, *qrv, *r, *up, *wp, *sig, *tau, *norm, *e;
+  char* rec;
+  char* opbuf;
+};
+
+static SvdScratch svd_scratch(const tenso_plan& P, void* ws) {
+  char* w = (char*)ws;
+  return SvdScratch{(double*)(w + P.ws_svd_y),   (double*)(w + P.ws_svd_z),
+                    (double*)(w + P.ws_svd_part), (double*)(w + P.ws_svd_qrv),
+                    (double*)(w + P.ws_svd_r),    (double*)(w + P.ws_svd_up),
+                    (double*)(w + P.ws_svd_wp),   (double*)(w + P.ws_svd_sig),
+                    (double*)(w + P.ws_svd_tau),  (double*)(w + P.ws_svd_norm),
+                    (double*)(w + P.ws_svd_e),    w + P.ws_svd_rec, nullptr};
+}
+
+// Single-op descriptor upload into slot `slot` of sc.opbuf; the host bytes
+// stay in `hold` until the caller's next synchronisation.
+template <class T>
+static const T* svd_put(const SvdScratch& sc, int slot, const T& op, hipStream_t s,
+                        std::vector<std::vector<char>>& hold) {
+  char* dst = sc.opbuf + slot * 512;
+  std::vector<char> bytes(sizeof(T));
+  memcpy(bytes.data(), &op, sizeof(T));
+  hipchk(hipMemcpyAsync(dst, bytes.data(), sizeof(T), hipMemcpyHostToDevice, s), "op upload");
+  hold.push_back(std::move(bytes));
+  return (const T*)dst;
+}
+
+// SVD of theta (rows x cols, row-major complex FP64) and the truncation
+// decision for (eps, max_rank, cap_r): sc.e receives the leading singular
+// vectors of the isometry side (iso 0: left, rows x p; iso 1: right, cols x p;
+// row-major, p = min(64, rows, cols)), sc.sig the singular values; rec_i =
+// {r', k, r_eps}, rec_d = {||theta||_F^2, energy outside the captured
+// subspace when it may be incomplete, else 0}.  Synchronises `s` once per
+// pass (the decision is read back).  When p is below the smaller side and
+// s_{p-1} exceeds 1e-13 s_1 (the numerical rank may exceed p), power steps
+// are added until the leading min(p, cap_r + 1) singular values move by at
+// most 1e-14 s_1 between passes, or kSvdMaxPower steps.
+static void svd_truncate(const SvdScratch& sc, const double* theta, long rows, long cols, int iso,
+                         double eps, int max_rank, int cap_r, hipStream_t s,
+                         std::vector<std::vector<char>>& hold, int rec_i[3], double rec_d[2]) {
+  const int p = (int)std::min<long>(kSvdP, std::min(rows, cols));
+  int n_norm = 0;
+  // out = theta B (mode 0) or theta^H B (mode 1); B null: the test matrix
+  auto gemm = [&](int mode, const double* B, double* out, bool norm) {
+    const int M = (int)(mode == 0 ? rows : cols), K = (int)(mode == 0 ? cols : rows);
+    const int mt = (M + 63) / 64;
+    int nsplit = std::min(kSvdMaxSplit, std::max(1, K / 256));
+    const int kchunk = ((K + nsplit - 1) / nsplit + 15) / 16 * 16;
+    nsplit = (K + kchunk - 1) / kchunk;
+    SvdGemmOp g{theta, B, out, sc.part, norm ? sc.norm : nullptr, (int)rows, (int)cols, p, mode,
+                nsplit, kchunk, 0x5EEDu, 0};
+    const SvdGemmOp* d = svd_put(sc, 0, g, s, hold);
+    hipchk(launch_svd_gemm(d, mt, nsplit, s), "svd product");
+    if (nsplit > 1) hipchk(launch_svd_reduce(d, (long)M * p, s), "svd reduce");
+    if (norm) n_norm = mt * nsplit;
+  };
+  auto qr = [&](double* A, int m) {
+    QrOp q{};
+    q.C = A;
+    q.R = sc.r;
+    q.V = m <= kQrBlockedMaxM ? A : sc.qrv;
+    q.tau = sc.tau;
+    q.m = m;
+    q.n = p;
+    q.Ppost = m;
+    q.transposeR = 0;
+    q.tol = 0.0;
+    hipchk(launch_qr(svd_put(sc, 1, q, s, hold), 1, s), "svd qr");
+  };
+  // range finder on theta's column space, then the projection Z = theta^H Q
+  gemm(0, nullptr, sc.y, true);
+  qr(sc.y, (int)rows);
+  const int nwatch = std::min(p, cap_r + 1);
+  double sig[kSvdP], prev[kSvdP];
+  for (int power = 0;; ++power) {
+    gemm(1, sc.y, sc.z, false);
+    qr(sc.z, (int)cols);
+    SvdJacobiOp jo{sc.r, sc.up, sc.wp, sc.sig, p, kSvdMaxSweeps};
+    hipchk(launch_svd_jacobi(svd_put(sc, 2, jo, s, hold), s), "svd jacobi");
+    SvdFinishOp fo{sc.y, sc.z, sc.up, sc.wp, sc.sig, sc.norm, sc.e, (int*)sc.rec,
+                   (double*)(sc.rec + 64), eps, n_norm, (int)rows, (int)cols, p, iso, max_rank,
+                   cap_r, 0};
+    hipchk(launch_svd_finish(svd_put(sc, 3, fo, s, hold), (iso == 0 ? rows : cols) * (long)p, s),
+           "svd finish");
+    hipchk(hipMemcpyAsync(rec_i, sc.rec, 3 * sizeof(int), hipMemcpyDeviceToHost, s), "decision");
+    hipchk(hipMemcpyAsync(rec_d, sc.rec + 64, 2 * sizeof(double), hipMemcpyDeviceToHost, s),
+           "decision");
+    hipchk(hipMemcpyAsync(sig, sc.sig, p * sizeof(double), hipMemcpyDeviceToHost, s), "sigma");
+    hipchk(hipStreamSynchronize(s), "sync");
+    hold.clear();
+    // captured subspace complete (p is the smaller side, or the last captured
+    // singular value is at rounding level), or the leading singular values
+    // settled: done; else one more power step
+    if (p == std::min(rows, cols) || sig[p - 1] <= 1e-13 * sig[0] || power >= kSvdMaxPower) break;
+    if (power > 0) {
+      double moved = 0;
+      for (int j = 0; j < nwatch; ++j) moved = std::max(moved, std::fabs(sig[j] - prev[j]));
+      if (moved <= 1e-14 * sig[0]) break;
+    }
+    for (int j = 0; j < nwatch; ++j) prev[j] = sig[j];
+    gemm(0, sc.z, sc.y, false);
+    qr(sc.y, (int)rows);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// ps2: host-driven two-site sweep (ranks decided on the device per edge and
+// read back, since they set the shapes of the following sub-flows)
 // ---------------------------------------------------------------------------
 struct Ps2Exec {
   tenso_plan& P;
@@ -1839,46 +1984,23 @@ struct Ps2Exec {
       Builder b(P, G);
       b.emit_rk4(edge_recipe(P, sn, c), b.ws(P.ws_theta), rows * cols, +1.0, half);
     });
-    const int side = rows <= cols ? 0 : 1;
-    const int n = (int)std::min(rows, cols);
-    EigOp eo{theta, (int)rows, (int)cols, side, (double*)wsb(P.ws_evals), (double*)wsb(P.ws_evecs)};
-    hipchk(launch_eig(put_op(eo, 1), s), "eig");
-    std::vector<double> lam(n);
-    hipchk(hipMemcpyAsync(lam.data(), wsb(P.ws_evals), n * sizeof(double), hipMemcpyDeviceToHost, s),
-           "evals");
-    hipchk(hipStreamSynchronize(s), "sync");
-    hold.clear();
-    // truncation: singular values s_i = sqrt(max(lambda_i, 0)), descending
-    std::vector<double> sv(n);
-    double tot2 = 0;
-    for (int j = 0; j < n; ++j) {
-      sv[j] = std::sqrt(std::max(lam[j], 0.0));
-      tot2 += sv[j] * sv[j];
-    }
-    int r_eps = n;
-    for (int k = 0; k <= n; ++k) {
-      double tail2 = 0;
-      for (int j = k; j < n; ++j) tail2 += sv[j] * sv[j];
-      if (tail2 <= eps * eps * tot2) {
-        r_eps = k;
-        break;
-      }
-    }
-    r_eps = std::max(1, r_eps);
-    const int cap_r = P.cap.rank[c];
-    const int rp = std::max(1, std::min({max_rank, cap_r, n, r_eps + 1}));
-    int k = 0;
-    if (sv[0] > 0)
-      for (int j = 0; j < n; ++j) k += sv[j] > 1e-10 * sv[0] ? 1 : 0;
-    k = std::min(k, rp);
+    const int iso = center_to_child ? 0 : 1;
+    const int p = (int)std::min<long>(kSvdP, std::min(rows, cols));
+    SvdScratch sc = svd_scratch(P, ws);
+    sc.opbuf = (char*)P.opbuf + 4096;
+    int rec_i[3] = {0, 0, 0};
+    double rec_d[2] = {0, 0};
+    svd_truncate(sc, theta, rows, cols, iso, eps, max_rank, P.cap.rank[c], s, hold, rec_i, rec_d);
+    const int rp = rec_i[0], k = rec_i[1];
+    if (rp < 1 || rp > P.cap.rank[c] || k < 0 || k > rp)
+      fail(TENSO_ENUMERIC, "ps2 truncation decision out of range");
     // the ranks of the new cores must stay within the capacity layout
     t.rank[c] = rp;
     const std::vector<int> ds2 = t.shape(sn);
     long ppost2 = 1;
     for (int j = i + 1; j < (int)ds2.size(); ++j) ppost2 *= ds2[j];
-    SplitOp so{theta, (double*)wsb(P.ws_evecs), (double*)wsb(P.ws_evals), (int)rows, (int)cols,
-               side, center_to_child ? 0 : 1, k, rp, (double*)wsb(P.ws_W), core(sn), core(c),
-               (int)ppost2};
+    SplitOp so{theta, sc.e, (int)rows, (int)cols, iso, k, rp, p,
+               (double*)wsb(P.ws_W), core(sn), core(c), (int)ppost2, 0};
     if ((size_t)std::max(rows, cols) * rp > P.W_cap) fail(TENSO_ENOMEM, "ps2 split scratch");
     hipchk(launch_split(put_op(so, 2), s), "split");
     P.rank_log.push_back(rp);
@@ -1963,7 +2085,7 @@ static std::unique_ptr<tenso_plan> compile_plan(const tenso_tree* t, const tenso
   }
   if (device) {
     hipchk(hipMalloc(&P->cbuf, std::max<size_t>(cb.size(), 256)), "hipMalloc(constants)");
-    hipchk(hipMalloc(&P->opbuf, 4096), "hipMalloc(op scratch)");
+    hipchk(hipMalloc(&P->opbuf, 8192), "hipMalloc(op scratch)");
     if (!cb.empty())
       hipchk(hipMemcpy(P->cbuf, cb.data(), cb.size(), hipMemcpyHostToDevice), "upload constants");
   }
@@ -2431,6 +2553,61 @@ int tenso_rank_trajectory(const tenso_plan* p, int32_t* h, int cap) {
   int n = std::min<int>(cap, (int)p->rank_log.size());
   for (int i = 0; i < n; ++i) h[i] = p->rank_log[i];
   return n;
+}
+
+int tenso_svd_truncate(const void* d_A, int rows, int cols, int iso, double eps, int max_rank,
+                       double* h_sigma, void* d_vectors, int32_t* h_decision, double* h_missed,
+                       hipStream_t s) {
+  return guard([&] {
+    if (!d_A || !d_vectors) fail(TENSO_EINVAL, "null argument");
+    if (rows < 1 || cols < 1 || (iso != 0 && iso != 1) || !(eps >= 0) || max_rank < 1)
+      fail(TENSO_EINVAL, "bad sizes, side, eps or max_rank");
+    if ((long)rows * cols > kPs2ThetaMax) fail(TENSO_ENOMEM, "matrix beyond 2^26 elements");
+    const size_t side = std::max(rows, cols);
+    const size_t blk = align256(side * kSvdP * 16);
+    const size_t nrm = align256(((side + 63) / 64) * kSvdMaxSplit * 8);
+    const size_t sq = align256((size_t)kSvdP * kSvdP * 16);
+    const size_t total = blk * (3 + kSvdMaxSplit) + 3 * sq + 2 * 1024 + nrm + 256 + 4 * 512;
+    struct DevMem {
+      char* p = nullptr;
+      ~DevMem() {
+        if (p) (void)hipFree(p);
+      }
+    } mem;
+    hipchk(hipMalloc((void**)&mem.p, total), "hipMalloc(svd scratch)");
+    char* w = mem.p;
+    auto take = [&](size_t b) {
+      char* q = w;
+      w += b;
+      return q;
+    };
+    SvdScratch sc{};
+    sc.y = (double*)take(blk);
+    sc.z = (double*)take(blk);
+    sc.qrv = (double*)take(blk);
+    sc.part = (double*)take(kSvdMaxSplit * blk);
+    sc.r = (double*)take(sq);
+    sc.up = (double*)take(sq);
+    sc.wp = (double*)take(sq);
+    sc.sig = (double*)take(1024);
+    sc.tau = (double*)take(1024);
+    sc.norm = (double*)take(nrm);
+    sc.rec = take(256);
+    sc.opbuf = take(4 * 512);
+    sc.e = (double*)d_vectors;
+    std::vector<std::vector<char>> hold;
+    int rec_i[3] = {0, 0, 0};
+    double rec_d[2] = {0, 0};
+    svd_truncate(sc, (const double*)d_A, rows, cols, iso, eps, max_rank, std::min(rows, cols), s,
+                 hold, rec_i, rec_d);
+    const int p = std::min({kSvdP, rows, cols});
+    if (h_sigma)
+      hipchk(hipMemcpyAsync(h_sigma, sc.sig, p * sizeof(double), hipMemcpyDeviceToHost, s), "sigma");
+    hipchk(hipStreamSynchronize(s), "sync");
+    if (h_decision)
+      for (int q = 0; q < 3; ++q) h_decision[q] = rec_i[q];
+    if (h_missed) *h_missed = rec_d[1] / std::max(rec_d[0], 1e-300);
+  });
 }
 
 int tenso_profile(int enable) {

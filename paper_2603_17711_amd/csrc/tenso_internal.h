@@ -98,12 +98,18 @@ struct CombineOp {
 // column-by-column form, which needs V apart from C).
 constexpr int kQrBlockedMaxM = 1024;
 
+// Residual columns at or below tol * ||A||_F count as exact zeros (identity
+// reflector): kQrRankTol for gauge moves; 0 (plain Householder) inside the
+// ps2 SVD, whose range finder needs no fixed completion.
+constexpr double kQrRankTol = 1e-10;
+
 struct QrOp {
   double* C;           // FP64 complex core
   double* R;           // out: n x n (or its transpose when transposeR)
   double* V;           // scratch m x n complex (may be C when Ppost == m <= kQrBlockedMaxM)
   double* tau;         // scratch n complex
   int m, n, Ppost, transposeR;
+  double tol;          // relative rank threshold
 };
 
 // In-place mode product of an FP64 core with an n x n FP64 matrix on one leg:
@@ -153,28 +159,71 @@ struct MergeOp {           // Theta[row, col] = sum_a Cs[pre, a, post] Cc[a, col
   int rows, cols, r, Ppost;  // row = pre * Ppost + post
 };
 
-// Hermitian eigen-decomposition (cyclic Jacobi, descending order) of the Gram
-// matrix of Theta on one side: side 0 -> Theta Theta^H (rows), 1 -> Theta^H Theta.
-struct EigOp {
+// ps2 SVD of Theta (see svd.hip).  Test-matrix width, the most power steps
+// the caller adds while the leading singular values still move, and the
+// sweep cap of the small Jacobi SVD.
+constexpr int kSvdP = 64;
+constexpr int kSvdMaxPower = 3;
+constexpr int kSvdMaxSweeps = 40;
+
+// out (M x p, column-major) = Theta * B (mode 0, M = rows, summed over cols) or
+// Theta^H * B (mode 1, M = cols, summed over rows).  B: column-major K x p, or
+// null for the hashed test matrix of `seed`.  nsplit > 1: summed-index ranges
+// of kchunk write partial slabs into `part` (nsplit x M x p), summed by the
+// reduce kernel.  Mode 0 with norm_part: per-workgroup partial sums of
+// |Theta|^2 (grid order).
+struct SvdGemmOp {
   const double* Theta;
-  int rows, cols, side;
-  double* evals;           // n eigenvalues, descending
-  double* evecs;           // n x n complex, column j = eigenvector j
+  const double* B;
+  double* out;
+  double* part;
+  double* norm_part;
+  int rows, cols, p, mode;
+  int nsplit, kchunk;
+  uint32_t seed;
+  int pad_;
 };
 
-// Split Theta into an isometry W (m_iso x r', first k columns from the
-// spectral basis, the rest completed by projecting unit vectors) and the
-// projected other core.  iso 0: W on the rows (new C_s), C_c = W^H Theta;
-// iso 1: W on the cols (new C_c = W^H as r' x cols), C_s = Theta W.
+// One-sided Jacobi SVD of R^H (R: p x p row-major): sigma descending, Up and
+// Wp (p x p column-major) its left and right singular vectors.
+struct SvdJacobiOp {
+  const double* R;
+  double* Up;
+  double* Wp;
+  double* sigma;
+  int p, max_sweeps;
+};
+
+// Singular vectors of the isometry side (iso 0: Q Up, rows x p; iso 1: W Wp,
+// cols x p; row-major into `out`) and the truncation decision (FP64).
+struct SvdFinishOp {
+  const double* Q;         // rows x p column-major
+  const double* W;         // cols x p column-major
+  const double* Up;
+  const double* Wp;
+  const double* sigma;
+  const double* norm_part;
+  double* out;
+  int* rec_i;              // r', k, r_eps
+  double* rec_d;           // ||Theta||_F^2, energy outside the captured subspace
+  double eps;
+  int n_norm_part, rows, cols, p, iso, max_rank, cap_r, pad_;
+};
+
+// Split Theta into an isometry W (m_iso x r': the first k columns are the
+// leading singular vectors of the isometry side, E (m_iso x ld_e, row-major),
+// the rest completed by projecting unit vectors) and the projected other
+// core.  iso 0: W on the rows (new C_s), C_c = W^H Theta; iso 1: W on the
+// cols (new C_c = W^H as r' x cols), C_s = Theta W.
 struct SplitOp {
   const double* Theta;
-  const double* evecs;
-  const double* evals;
-  int rows, cols, side, iso, k, rp;
+  const double* E;
+  int rows, cols, iso, k, rp, ld_e;
   double* W;               // scratch m_iso x rp complex
   double* Cs;              // new core s: (rows x rp) scattered with leg i in place
   double* Cc;              // new core c: rp x cols
   int Ppost_s;             // product of s's legs after leg i (for the scatter)
+  int pad_;
 };
 
 }  // namespace tenso

@@ -46,7 +46,8 @@ def heom_table(H, baths, depth, drive_ops=()):
     dims = []
     k = 0
     for b in baths:
-        c, cb, g = _bath.features(b.T, b.dl, b.bo, b.n_ltc)
+        c, cb, g = _bath.features(b.T, b.dl, b.bo, b.n_ltc,
+                                  method=getattr(b, "decomposition", "matsubara"))
         Q = np.asarray(b.Q, dtype=np.complex128)
         for j in range(len(c)):
             N = depth if np.isscalar(depth) else depth[k]

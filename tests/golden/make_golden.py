@@ -3,7 +3,7 @@
 Every stored value comes from the FP64 CPU oracle (``oracle/``) run on the seeded
 workloads of ``workloads.py``; nothing here touches the GPU library.
 
-    python tests/golden/make_golden.py [spin_boson|exciton|batch|batch200|all] [--procs N]
+    python tests/golden/make_golden.py [spin_boson|exciton|batch|batch200|ps2|pade|all] [--procs N]
 
 Files (numpy .npz, no pickles):
   spin_boson_train_2000.npz   spin-boson K=3 N=10 train R=8, ps1, 2000 steps,
@@ -19,7 +19,18 @@ Files (numpy .npz, no pickles):
                               instances a too-large RK4 step once made diverge
                               (61, 121, 153, 267, 304, 387, 429) and instance 393
                               (the largest trace drift); same record layout, with
-                              `ids` naming the sampled instances
+                              `ids` naming the sampled instances and `spread` the
+                              largest trace distance, over the records, between
+                              the oracle at QR rank thresholds 1e-10 and 1e-12:
+                              how far the truncated-rank trajectory itself
+                              depends on that convention
+  pade_structured_500.npz     the paper's Sec. III A 1 structured spin-boson model
+                              (Pade, K=4, depth 25, train R=16, dt 0.1 fs), ps1,
+                              500 steps (50 fs), rho_S at every 50th step
+  ps2_ternary_cap8_10.npz     structured bath K=24 N=10 on the ternary tree, ps2 with
+                              eps 1e-6 and rank cap 8, 10 steps: rho_S at every step
+                              and the rank chosen at every split (`ranks`, one row
+                              per step in sweep order)
 Each file stores the inputs it depends on (time steps, step counts, a digest of
 the workload parameters) so that a stale file is detected instead of compared.
 """
@@ -47,6 +58,8 @@ def workload_digest(insts):
         for b in inst.baths:
             h.update(np.ascontiguousarray(b.Q).tobytes())
             h.update(repr((b.T, b.dl, b.bo, b.n_ltc)).encode())
+            if getattr(b, "decomposition", "matsubara") != "matsubara":
+                h.update(b.decomposition.encode())
         h.update(repr((inst.depth, inst.tree, inst.rank, inst.dt, inst.method, inst.eps,
                        None if inst.drive is None else inst.drive[1:])).encode())
     return h.hexdigest()
@@ -78,7 +91,8 @@ def _single(args):
     import workloads
     from oracle.run import propagate
     inst = {"spin_boson": workloads.spin_boson_train,
-            "exciton": workloads.exciton_7site}[name](n_steps=n_steps)
+            "exciton": workloads.exciton_7site,
+            "pade": workloads.structured_spin_boson_pade}[name](n_steps=n_steps)
     steps, rhos, _, _ = propagate(inst, n_steps=n_steps, every=every)
     return name, inst, steps, rhos
 
@@ -87,12 +101,41 @@ BATCH200_IDS = sorted(set(range(0, 512, 32)) | {61, 121, 153, 267, 304, 387, 393
 
 
 def _batch_one(args):
-    i, n_steps, every = args
+    i, n_steps, every = args[:3]
     import workloads
+    import oracle.integrators as integ
     from oracle.run import propagate
+    from oracle.ttn import trace_distance
     inst = workloads.uneven_batch()[i]
     steps, rhos, _, _ = propagate(inst, n_steps=n_steps, every=every)
-    return i, steps, rhos
+    spread = 0.0
+    if len(args) > 3 and args[3]:
+        old = integ.QR_RANK_TOL
+        integ.QR_RANK_TOL = 1e-12
+        try:
+            _, alt, _, _ = propagate(inst, n_steps=n_steps, every=every)
+        finally:
+            integ.QR_RANK_TOL = old
+        spread = max(trace_distance(a, b) for a, b in zip(rhos, alt))
+    return i, steps, rhos, spread
+
+
+def _ps2(args):
+    n_steps, cap = args
+    import workloads
+    from oracle.run import propagate
+    inst = workloads.structured_bath_ternary(n_steps=n_steps)
+    steps, rhos, ranks, _ = propagate(inst, n_steps=n_steps, every=1, max_rank=cap)
+    return inst, steps, rhos, ranks
+
+
+def write_ps2(n_steps, cap, fname, pool):
+    t0 = time.time()
+    inst, steps, rhos, ranks = pool.apply(_ps2, ((n_steps, cap),))
+    np.savez_compressed(os.path.join(HERE, fname), steps=steps, rho=rhos,
+                        ranks=np.array(ranks, dtype=np.int32), cap=cap, eps=inst.eps,
+                        digest=workload_digest([inst]))
+    print(f"{fname}: {len(steps)} records, {time.time() - t0:.1f} s", flush=True)
 
 
 def write_single(name, n_steps, every, fname, pool):
@@ -103,7 +146,7 @@ def write_single(name, n_steps, every, fname, pool):
     print(f"{fname}: {len(steps)} records, {time.time() - t0:.1f} s", flush=True)
 
 
-def write_batch(n_steps, every, fname, pool, ids=None):
+def write_batch(n_steps, every, fname, pool, ids=None, spread=False):
     import workloads
     insts = workloads.uneven_batch()
     ids = list(range(len(insts))) if ids is None else list(ids)
@@ -111,8 +154,11 @@ def write_batch(n_steps, every, fname, pool, ids=None):
     res = {}
     # largest instances first, so that the pool's tail is short
     order = sorted(ids, key=lambda i: -insts[i].M * insts[i].K * insts[i].depth * insts[i].rank)
-    for i, steps, rhos in pool.imap_unordered(_batch_one, [(i, n_steps, every) for i in order]):
+    spreads = {}
+    for i, steps, rhos, sp in pool.imap_unordered(_batch_one,
+                                                  [(i, n_steps, every, spread) for i in order]):
         res[i] = (steps, rhos)
+        spreads[i] = sp
     steps = res[ids[0]][0]
     offsets = np.zeros(len(ids) + 1, dtype=np.int64)
     for j, i in enumerate(ids):
@@ -123,6 +169,7 @@ def write_batch(n_steps, every, fname, pool, ids=None):
         rec[:, offsets[j]:offsets[j + 1]] = res[i][1].reshape(len(steps), -1)
     np.savez_compressed(os.path.join(HERE, fname), steps=steps, rho=rec, offsets=offsets,
                         ids=np.array(ids), dt=np.array([x.dt for x in insts]),
+                        spread=np.array([spreads[i] for i in ids]),
                         digest=workload_digest(insts))
     print(f"{fname}: {len(insts)} instances x {len(steps)} records, "
           f"{time.time() - t0:.1f} s", flush=True)
@@ -131,7 +178,7 @@ def write_batch(n_steps, every, fname, pool, ids=None):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("what", nargs="?", default="all",
-                    choices=["spin_boson", "exciton", "batch", "batch200", "all"])
+                    choices=["spin_boson", "exciton", "batch", "batch200", "ps2", "pade", "all"])
     ap.add_argument("--procs", type=int, default=os.cpu_count())
     a = ap.parse_args()
     os.environ.setdefault("OMP_NUM_THREADS", "1")
@@ -143,7 +190,11 @@ def main():
         if a.what in ("batch", "all"):
             write_batch(25, 5, "batch512_25.npz", pool)
         if a.what in ("batch200", "all"):
-            write_batch(200, 10, "batch512_200_sample.npz", pool, ids=BATCH200_IDS)
+            write_batch(200, 10, "batch512_200_sample.npz", pool, ids=BATCH200_IDS, spread=True)
+        if a.what in ("pade", "all"):
+            write_single("pade", 500, 50, "pade_structured_500.npz", pool)
+        if a.what in ("ps2", "all"):
+            write_ps2(10, 8, "ps2_ternary_cap8_10.npz", pool)
 
 
 if __name__ == "__main__":

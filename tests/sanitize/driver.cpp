@@ -25,7 +25,10 @@ namespace tenso {
 hipError_t launch_apply(int, int, const ApplyGroup*, const ApplyTile*, int, const int*, size_t,
                         hipStream_t, hipEvent_t, hipEvent_t) STUB()
 hipError_t launch_merge(const MergeOp*, long, hipStream_t) STUB()
-hipError_t launch_eig(const EigOp*, hipStream_t) STUB()
+hipError_t launch_svd_gemm(const SvdGemmOp*, int, int, hipStream_t) STUB()
+hipError_t launch_svd_reduce(const SvdGemmOp*, long, hipStream_t) STUB()
+hipError_t launch_svd_jacobi(const SvdJacobiOp*, hipStream_t) STUB()
+hipError_t launch_svd_finish(const SvdFinishOp*, long, hipStream_t) STUB()
 hipError_t launch_split(const SplitOp*, hipStream_t) STUB()
 hipError_t launch_presum(int, const PresumOp*, int, const int*, hipStream_t) STUB()
 hipError_t launch_combine(int, const CombineOp*, const void*, int, hipStream_t) STUB()

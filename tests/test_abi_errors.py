@@ -175,3 +175,18 @@ def test_plan_query_rejects_bad_options():
     rc = _L().lib().tenso_plan_query(t.h, g2.h, C.byref(_L().PlanOpts(1, 0, 0)), None, None,
                                      None, None)
     assert rc == EINVAL  # a generator built for another tree
+
+
+def test_plan_query_ps2_two_site_budget():
+    """A ps2 plan sizes every buffer at the rank cap: the structured-bath
+    ternary tree fits at caps 8 and 16; from cap 32 its largest two-site tensor
+    (4 r^2 x r^3 elements on the edge below the root's child) exceeds the
+    2^26-element budget: ENOMEM."""
+    t, g = _instance_tree_gen(workloads.structured_bath_ternary(), rank=8)
+    for cap in (8, 16):
+        rc, sb, wb, _, _, msg = _plan_query(t, g, method=1, max_rank=cap)
+        assert rc == 0, (cap, msg)
+        assert wb > sb > 0
+    for cap in (32, 64):
+        rc, _, _, _, _, msg = _plan_query(t, g, method=1, max_rank=cap)
+        assert rc == ENOMEM and "two-site" in msg

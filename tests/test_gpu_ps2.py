@@ -1,6 +1,8 @@
 """GPU parity of ps2 (adaptive rank) against the oracle: rho_S trace distance
-and the rank decisions, on a train and on the structured-bath ternary tree at
-a small rank cap."""
+and the rank decisions, on a train, on the structured-bath ternary tree at a
+small rank cap, and on the same tree at rank cap 8 against the stored oracle
+trajectory (tests/golden), where eps = 1e-6 decides the ranks (they stay
+below the cap over the 10 steps)."""
 import numpy as np
 import pytest
 
@@ -53,3 +55,27 @@ def test_ps2_structured_bath_ternary_small_cap():
     flat_o = [r for step in rlog for r in step]
     print(f"  max trace distance {d:.3e}; ranks match: {flat_o == rl_gpu}")
     assert d < 1e-5
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_ps2_structured_bath_ternary_cap8(precision):
+    require_gpu()
+    from paper_2603_17711_amd import api
+    from tests.golden.make_golden import load
+    n, cap = 10, 8
+    inst = workloads.structured_bath_ternary(n_steps=n)
+    g = load("ps2_ternary_cap8_10.npz", [inst])
+    print(f"[ps2 parity] structured bath K=24 ternary cap={cap} eps={inst.eps} steps={n} "
+          f"precision={precision}", flush=True)
+    plan = api.build_instance(inst, precision=precision, rank=cap)
+    ds, same = [trace_distance(plan.rho(), g["rho"][0])], 0
+    for k in range(n):
+        plan.step_adaptive(1, inst.dt, inst.eps, cap, t0=k * inst.dt)
+        ds.append(trace_distance(plan.rho(), g["rho"][k + 1]))
+        rl = plan.rank_log()
+        same += int(list(rl) == list(g["ranks"][k]))
+    print(f"  trace distance per step {['%.1e' % d for d in ds]}; rank logs equal in "
+          f"{same}/{n} steps; final ranks {list(g['ranks'][-1])} (oracle) vs "
+          f"{plan.rank_log()} (gpu); max rank {int(g['ranks'].max())} < cap {cap}", flush=True)
+    assert int(g["ranks"].max()) < cap  # eps decides, not the cap
+    assert max(ds) < 1e-5

@@ -22,14 +22,16 @@ SX = np.array([[0.0, 1.0], [1.0, 0.0]], dtype=np.complex128)
 
 class Bath:
     """One bath: coupling operator Q, temperature T, Drude terms (lam, wc),
-    Brownian terms (lam, w0, eta) and the number of Matsubara corrections."""
+    Brownian terms (lam, w0, eta), the number of low-temperature corrections
+    and how they are taken ("matsubara" or "pade")."""
 
-    def __init__(self, Q, T, dl=(), bo=(), n_ltc=0):
+    def __init__(self, Q, T, dl=(), bo=(), n_ltc=0, decomposition="matsubara"):
         self.Q = np.asarray(Q, dtype=np.complex128)
         self.T = float(T)
         self.dl = [tuple(map(float, x)) for x in dl]
         self.bo = [tuple(map(float, x)) for x in bo]
         self.n_ltc = int(n_ltc)
+        self.decomposition = decomposition
 
     def n_features(self):
         return len(self.dl) + 2 * len(self.bo) + self.n_ltc
@@ -102,6 +104,26 @@ def exciton_7site(n_steps=1000, seed=1):
         baths.append(Bath(Q, 300.0 * KB_CM, dl=[(35.0, 106.18)], n_ltc=3))
     return Instance("7-site exciton K=28 N=8 binary R=16", H, baths, 8, "tree2", 16,
                     ground(M), 0.1 * FS_TO_CM, n_steps)
+
+
+def structured_spin_boson_pade(n_steps=50, depth=25, rank=16, dt_fs=0.1):
+    """The paper's complete-input-file example (Sec. III A 1, its Table and
+    listing): a two-level system H_S = [[-750, 300], [300, 750]] cm^-1 coupled
+    through Q = diag(-0.5, 0.5) to a Drude bath (lambda 540, cut-off 70 cm^-1)
+    plus one Brownian mode (lambda 161.6, damped frequency w0' = 1243 and width
+    10 cm^-1) at 300 K, Pade decomposition with one low-temperature term
+    (4 features), depth 25, rho_S(0) = |1><1|.  Here on a tensor train of rank
+    16 with RK4 steps of 0.1 fs (the listing's 1 fs suits an adaptive
+    integrator; a fixed RK4 step needs dt below 0.15 fs at this hierarchy)."""
+    eta, w0p = 10.0, 1243.0
+    bath = Bath(np.diag([-0.5, 0.5]).astype(np.complex128), 300.0 * KB_CM,
+                dl=[(540.0, 70.0)], bo=[(161.6, float(np.sqrt(w0p ** 2 + eta ** 2)), eta)],
+                n_ltc=1, decomposition="pade")
+    H = np.array([[-750.0, 300.0], [300.0, 750.0]], dtype=np.complex128)
+    rho0 = np.zeros((2, 2), dtype=np.complex128)
+    rho0[1, 1] = 1.0
+    return Instance("structured spin-boson, Pade, K=4 N=25 train R=16", H, [bath], depth,
+                    "train", rank, rho0, dt_fs * FS_TO_CM, n_steps)
 
 
 def stable_dt(dt_max, T, n_ltc, N, H, wc=1.0):
