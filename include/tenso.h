@@ -186,6 +186,19 @@ int tenso_state_export(tenso_plan* p, const void* d_state, tenso_c128* h_cores, 
 int tenso_apply_generator(tenso_plan* p, const void* d_state, int center, const double* drive,
                           void* d_out, void* d_ws, hipStream_t s);
 
+/* The same with no device allocation in the call, for callers that cannot
+ * allocate (code under stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Workspace and launch descriptors live in a static
+ * device array of TENSO_NOALLOC_SCRATCH_MIB MiB that each GPU the library
+ * runs on holds until the process ends; the caller passes no workspace.
+ * The result equals tenso_apply_generator's.  ENOMEM when the plan's
+ * workspace plus descriptors exceed the array.  Every call on a GPU shares
+ * that GPU's array and clears it first: calls that overlap on one GPU (two
+ * streams, two threads) race and must not be issued.  Synchronous on `s`. */
+#define TENSO_NOALLOC_SCRATCH_MIB 64
+int tenso_apply_generator_noalloc(tenso_plan* p, const void* d_state, int center,
+                                  const double* drive, void* d_out, hipStream_t s);
+
 /* Advance n_steps steps of size dt with ps1 (second-order: a first-order
  * sweep over half a step, then its adjoint).  d_drive_tab (nullable when the
  * generator has no slots) holds f_slot at t0 + j*dt/4, j = 0..4*n_steps,

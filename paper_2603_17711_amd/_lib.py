@@ -50,6 +50,7 @@ SIGS = {
     "tenso_state_import": (C.c_int, [P, C128P, P, P]),
     "tenso_state_export": (C.c_int, [P, P, C128P, I32P, P]),
     "tenso_apply_generator": (C.c_int, [P, P, C.c_int, DP, P, P, P]),
+    "tenso_apply_generator_noalloc": (C.c_int, [P, P, C.c_int, DP, P, P]),
     "tenso_plan_query": (C.c_int, [P, P, C.POINTER(PlanOpts), C.POINTER(C.c_size_t),
                                    C.POINTER(C.c_size_t), C.POINTER(C.c_int64), DP]),
     "tenso_step_fixed": (C.c_int, [P, P, C.c_double, C.c_double, C.c_int, P, P, P]),

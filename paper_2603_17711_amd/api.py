@@ -144,9 +144,10 @@ class Plan:
             o += k
         return cores
 
-    def apply(self, center, drive=None):
+    def apply(self, center, drive=None, noalloc=False):
         """Effective generator at `center` (the state must be canonical toward
-        it); drive: one value per slot at the time of interest."""
+        it); drive: one value per slot at the time of interest.  noalloc=True
+        calls the variant that allocates nothing (static scratch, no workspace)."""
         import torch
         shape = self.shapes()[center]
         out = torch.zeros(int(np.prod(shape)) * 2, dtype=torch.float64, device=self.state.device)
@@ -154,9 +155,14 @@ class Plan:
         if drive is not None:
             d = np.ascontiguousarray(drive, dtype=np.float64)
             dv = d.ctypes.data_as(C.POINTER(C.c_double))
-        check(lib().tenso_apply_generator(self.h, C.c_void_p(self.state.data_ptr()), center, dv,
-                                          C.c_void_p(out.data_ptr()),
-                                          C.c_void_p(self.ws.data_ptr()), _stream()))
+        if noalloc:
+            check(lib().tenso_apply_generator_noalloc(self.h, C.c_void_p(self.state.data_ptr()),
+                                                      center, dv, C.c_void_p(out.data_ptr()),
+                                                      _stream()))
+        else:
+            check(lib().tenso_apply_generator(self.h, C.c_void_p(self.state.data_ptr()), center, dv,
+                                              C.c_void_p(out.data_ptr()),
+                                              C.c_void_p(self.ws.data_ptr()), _stream()))
         o = out.cpu().numpy()
         return (o[0::2] + 1j * o[1::2]).reshape(shape)
 

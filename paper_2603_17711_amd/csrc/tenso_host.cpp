@@ -2171,6 +2171,31 @@ static void apply_generator_impl(tenso_plan* p, const void* d_state, int center,
   hipchk(hipStreamSynchronize(s), "sync");
 }
 
+namespace tenso {
+// The variant of tenso_apply_generator that allocates nothing: workspace and
+// launch descriptors both live in caller-provided device scratch (the
+// workspace first, zeroed by a kernel, then the descriptor arena).
+int apply_generator_scratch(tenso_plan* p, const void* d_state, int center, const double* drive,
+                            void* d_out, void* scratch, size_t scratch_bytes, hipStream_t s) {
+  return guard([&] {
+    if (!p || !scratch) fail(TENSO_EINVAL, "null argument");
+    const size_t ws = align256(p->ws_bytes);
+    if (ws + 256 > scratch_bytes)
+      fail(TENSO_ENOMEM, "plan workspace (" + std::to_string(p->ws_bytes) +
+                             " bytes) exceeds the static scratch (" + std::to_string(scratch_bytes) +
+                             " bytes)");
+    hipchk(launch_zero(scratch, ws, s), "zero scratch");
+    DevProgram D((char*)scratch + ws, scratch_bytes - ws);
+    apply_generator_impl(p, d_state, center, drive, d_out, scratch, D, s);
+  });
+}
+
+int set_last_error(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+}  // namespace tenso
+
 // ---------------------------------------------------------------------------
 // host-side state helpers
 // ---------------------------------------------------------------------------
