@@ -65,6 +65,9 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the run, a plain 256 MiB streaming kernel (torch.neg) whose "
                          "HBM counters calibrate FETCH_SIZE / WRITE_SIZE")
+    ap.add_argument("--timed-only", action="store_true",
+                    help="batch512: only the warm-up and one timed call of the mixed batch (for "
+                         "hardware-counter runs, where every other pass is too slow)")
     ap.add_argument("--autotune", action="store_true",
                     help="batch512: autotune the apply tile size before timing (default: "
                          "the batch default tile size)")
@@ -267,7 +270,8 @@ def batch_main(a):
         return plans, b, times
 
     log(f"mixed batch: {len(insts)} instances, {a.warmup} warm-up + 3 x {a.steps} timed steps")
-    plans, batch, times = run_batch(api.FP32, a.steps, a.warmup, tune=a.autotune, repeats=3)
+    plans, batch, times = run_batch(api.FP32, a.steps, a.warmup, tune=a.autotune,
+                                    repeats=1 if a.timed_only else 3)
     dt_mixed = times[0]
     flags = batch.status()
     n_ok = int(len(insts) - flags.sum())
@@ -287,6 +291,10 @@ def batch_main(a):
                     "note": "value is the first of three back-to-back timed calls of "
                             f"{a.steps} steps on the same batch"},
     }
+    if a.timed_only:
+        out["note"] = "timed call only (no accuracy, FP64, roofline or CPU passes)"
+        print(json.dumps(out))
+        return
     rho_mixed = batch.rho()
     flagged = [int(i) for i in np.nonzero(flags)[0]]
     nonfinite = [i for i in flagged if not np.isfinite(rho_mixed[i]).all()]

@@ -237,8 +237,9 @@ int tenso_rank_trajectory(const tenso_plan* p, int32_t* h_ranks, int cap);
  * SVD), on its own: A is a device matrix, rows x cols row-major complex FP64
  * (at most 2^26 elements, ENOMEM beyond).  It is factorised in FP64 from A
  * itself (range finder with hashed test columns, Householder QR, one-sided
- * Jacobi on the projected p x p factor; p = min(64, rows, cols)), which keeps
- * each singular value accurate to rounding relative to sigma_1.
+ * Jacobi on the projected p x p factor; p = min(64, rows, cols,
+ * 2 min(max_rank, rows, cols) + 8)), which keeps each singular value accurate
+ * to rounding relative to sigma_1.
  *   h_sigma (host, nullable): the p leading singular values, descending.
  *   d_vectors (device, caller-owned, n x p complex row-major): the leading
  *     singular vectors of the left side (iso 0, n = rows) or of the right
@@ -247,7 +248,8 @@ int tenso_rank_trajectory(const tenso_plan* p, int32_t* h_ranks, int cap);
  *     max_rank): r' = min(max_rank, min(rows, cols), r_eps + 1), the number k
  *     <= r' of singular values above 1e-10 sigma_1, and r_eps, the smallest r
  *     with sqrt(sum_{i>=r} s_i^2) <= eps * ||A||_F (at least 1; eps = 0
- *     keeps every direction).
+ *     keeps every direction; min(rows, cols) when r_eps exceeds the p
+ *     computed directions, which then all lie above the cap).
  *   h_missed (host, nullable): the energy outside the captured p-dimensional
  *     subspace relative to ||A||_F^2, when the subspace may be incomplete
  *     (p below the smaller side and s_p > 1e-13 s_1), else 0.  Then power

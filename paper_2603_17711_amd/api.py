@@ -216,20 +216,22 @@ def svd_truncate(A, iso=0, eps=0.0, max_rank=None):
     """FP64 SVD of a complex matrix on the device by the ps2 split's method
     (tenso_svd_truncate).  A: complex128 array or torch tensor (rows x cols).
     Returns (sigma, vectors, (r', k, r_eps), missed): the p = min(64, rows,
-    cols) leading singular values, the leading singular vectors of the left
+    cols, 2 min(max_rank, rows, cols) + 8) leading singular values, the leading
+    singular vectors of the left
     (iso 0, rows x p) or right (iso 1, cols x p) side, the truncation decision
     for (eps, max_rank) and the energy fraction outside the captured subspace."""
     import torch
     t = torch.as_tensor(A).to(device="cuda", dtype=torch.complex128).contiguous()
     rows, cols = t.shape
-    p = min(64, rows, cols)
+    mr = int(max_rank if max_rank is not None else min(rows, cols))
+    p = min(64, rows, cols, 2 * min(mr, rows, cols) + 8)
     n = rows if iso == 0 else cols
     vec = torch.zeros((n, p), dtype=torch.complex128, device="cuda")
     sig = np.zeros(p)
     dec = np.zeros(3, np.int32)
     missed = C.c_double()
     check(lib().tenso_svd_truncate(C.c_void_p(t.data_ptr()), rows, cols, iso, float(eps),
-                                   int(max_rank if max_rank is not None else min(rows, cols)),
+                                   mr,
                                    sig.ctypes.data_as(C.POINTER(C.c_double)),
                                    C.c_void_p(vec.data_ptr()),
                                    dec.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(missed),

@@ -148,8 +148,10 @@ __global__ void __launch_bounds__(256) k_svd_reduce(const SvdGemmOp* __restrict_
 
 // One-sided Jacobi SVD of Mx = R^H (R: p x p row-major, p <= 64): columns of
 // Mx are rotated pairwise (round-robin pairing, all p/2 pairs of a round in
-// parallel, one half-wavefront per pair) until every pair is orthogonal to
-// 1e-15 relative to the product of their norms.  Then s_j = ||col_j||,
+// parallel, one half-wavefront per pair) until every pair x, y satisfies
+// |x^H y| <= p eps ||x|| ||y|| (eps = 2^-52: what a length-p FP64 dot product
+// resolves), pairs whose norm product is below 1e-30 ||Mx||_F^2 counting as
+// orthogonal (their singular values are below 1e-15 s_1).  Then s_j = ||col_j||,
 // U'[:, j] = col_j / s_j, W'[:, j] = the accumulated rotations, sorted by
 // decreasing s (ties by index).
 constexpr int kJacThreads = 1024;
@@ -163,6 +165,7 @@ __global__ void __launch_bounds__(kJacThreads) k_svd_jacobi(const SvdJacobiOp* _
   c2* V = A + 64 * kJacLd;
   __shared__ int rotated;
   __shared__ double sig[64];
+  __shared__ double fro2;
   __shared__ int order[64];
   const int tid = threadIdx.x, h = tid >> 5, l = tid & 31;
   const c2* __restrict__ R = reinterpret_cast<const c2*>(op.R);
@@ -177,6 +180,18 @@ __global__ void __launch_bounds__(kJacThreads) k_svd_jacobi(const SvdJacobiOp* _
     V[j * kJacLd + i] = c2{i == j && j < p ? 1.0 : 0.0, 0.0};
   }
   __syncthreads();
+  if (tid < 64) {
+    double f = 0.0;
+    for (int j = 0; j < p; ++j) {
+      const c2 v = A[j * kJacLd + tid];
+      f += v.r * v.r + v.i * v.i;
+    }
+    for (int off = 32; off > 0; off >>= 1) f += __shfl_xor(f, off, 64);
+    if (tid == 0) fro2 = f;
+  }
+  __syncthreads();
+  const double tol = p * 2.220446049250313e-16;
+  const double tiny = 1e-30 * fro2;
   for (int sweep = 0; sweep < op.max_sweeps; ++sweep) {
     if (tid == 0) rotated = 0;
     __syncthreads();
@@ -204,7 +219,8 @@ __global__ void __launch_bounds__(kJacThreads) k_svd_jacobi(const SvdJacobiOp* _
           gi += __shfl_xor(gi, off, 32);
         }
         const double g = sqrt(gr * gr + gi * gi);
-        if (g > 0.0 && g > 1e-15 * sqrt(al * be)) {
+        const double nn = sqrt(al * be);
+        if (g > 0.0 && nn > tiny && g > tol * nn) {
           // x' = c x - s e^{-i phi} y, y' = s e^{i phi} x + c y with
           // x^H y = g e^{i phi}: makes x'^H y' = 0
           const double zeta = (be - al) / (2.0 * g);

@@ -1799,78 +1799,98 @@ static const T* svd_put(const SvdScratch& sc, int slot, const T& op, hipStream_t
 // SVD of theta (rows x cols, row-major complex FP64) and the truncation
 // decision for (eps, max_rank, cap_r): sc.e receives the leading singular
 // vectors of the isometry side (iso 0: left, rows x p; iso 1: right, cols x p;
-// row-major, p = min(64, rows, cols)), sc.sig the singular values; rec_i =
-// {r', k, r_eps}, rec_d = {||theta||_F^2, energy outside the captured
-// subspace when it may be incomplete, else 0}.  Synchronises `s` once per
-// pass (the decision is read back).  When p is below the smaller side and
-// s_{p-1} exceeds 1e-13 s_1 (the numerical rank may exceed p), power steps
-// are added until the leading min(p, cap_r + 1) singular values move by at
-// most 1e-14 s_1 between passes, or kSvdMaxPower steps.
-static void svd_truncate(const SvdScratch& sc, const double* theta, long rows, long cols, int iso,
-                         double eps, int max_rank, int cap_r, hipStream_t s,
-                         std::vector<std::vector<char>>& hold, int rec_i[3], double rec_d[2]) {
-  const int p = (int)std::min<long>(kSvdP, std::min(rows, cols));
-  int n_norm = 0;
-  // out = theta B (mode 0) or theta^H B (mode 1); B null: the test matrix
-  auto gemm = [&](int mode, const double* B, double* out, bool norm) {
-    const int M = (int)(mode == 0 ? rows : cols), K = (int)(mode == 0 ? cols : rows);
-    const int mt = (M + 63) / 64;
-    int nsplit = std::min(kSvdMaxSplit, std::max(1, K / 256));
-    const int kchunk = ((K + nsplit - 1) / nsplit + 15) / 16 * 16;
-    nsplit = (K + kchunk - 1) / kchunk;
-    SvdGemmOp g{theta, B, out, sc.part, norm ? sc.norm : nullptr, (int)rows, (int)cols, p, mode,
-                nsplit, kchunk, 0x5EEDu, 0};
-    const SvdGemmOp* d = svd_put(sc, 0, g, s, hold);
-    hipchk(launch_svd_gemm(d, mt, nsplit, s), "svd product");
-    if (nsplit > 1) hipchk(launch_svd_reduce(d, (long)M * p, s), "svd reduce");
-    if (norm) n_norm = mt * nsplit;
-  };
-  auto qr = [&](double* A, int m) {
-    QrOp q{};
-    q.C = A;
-    q.R = sc.r;
-    q.V = m <= kQrBlockedMaxM ? A : sc.qrv;
-    q.tau = sc.tau;
-    q.m = m;
-    q.n = p;
-    q.Ppost = m;
-    q.transposeR = 0;
-    q.tol = 0.0;
-    hipchk(launch_qr(svd_put(sc, 1, q, s, hold), 1, s), "svd qr");
-  };
-  // range finder on theta's column space, then the projection Z = theta^H Q
-  gemm(0, nullptr, sc.y, true);
-  qr(sc.y, (int)rows);
-  const int nwatch = std::min(p, cap_r + 1);
-  double sig[kSvdP], prev[kSvdP];
-  for (int power = 0;; ++power) {
-    gemm(1, sc.y, sc.z, false);
-    qr(sc.z, (int)cols);
-    SvdJacobiOp jo{sc.r, sc.up, sc.wp, sc.sig, p, kSvdMaxSweeps};
-    hipchk(launch_svd_jacobi(svd_put(sc, 2, jo, s, hold), s), "svd jacobi");
-    SvdFinishOp fo{sc.y, sc.z, sc.up, sc.wp, sc.sig, sc.norm, sc.e, (int*)sc.rec,
-                   (double*)(sc.rec + 64), eps, n_norm, (int)rows, (int)cols, p, iso, max_rank,
-                   cap_r, 0};
-    hipchk(launch_svd_finish(svd_put(sc, 3, fo, s, hold), (iso == 0 ? rows : cols) * (long)p, s),
-           "svd finish");
-    hipchk(hipMemcpyAsync(rec_i, sc.rec, 3 * sizeof(int), hipMemcpyDeviceToHost, s), "decision");
-    hipchk(hipMemcpyAsync(rec_d, sc.rec + 64, 2 * sizeof(double), hipMemcpyDeviceToHost, s),
-           "decision");
-    hipchk(hipMemcpyAsync(sig, sc.sig, p * sizeof(double), hipMemcpyDeviceToHost, s), "sigma");
-    hipchk(hipStreamSynchronize(s), "sync");
-    hold.clear();
-    // captured subspace complete (p is the smaller side, or the last captured
-    // singular value is at rounding level), or the leading singular values
-    // settled: done; else one more power step
-    if (p == std::min(rows, cols) || sig[p - 1] <= 1e-13 * sig[0] || power >= kSvdMaxPower) break;
-    if (power > 0) {
-      double moved = 0;
-      for (int j = 0; j < nwatch; ++j) moved = std::max(moved, std::fabs(sig[j] - prev[j]));
-      if (moved <= 1e-14 * sig[0]) break;
-    }
-    for (int j = 0; j < nwatch; ++j) prev[j] = sig[j];
-    gemm(0, sc.z, sc.y, false);
+// row-major with leading dimension p), sc.sig the p singular values; the
+// width p is returned.  rec_i = {r', k, r_eps}, rec_d = {||theta||_F^2,
+// energy outside the captured subspace when it may be incomplete, else 0}.
+// Synchronises `s` once per pass (the decision is read back).
+//   Width: first svd_width(...) test columns (the kept rank plus room, at most
+// 64).  When p is below the smaller side and s_{p-1} exceeds 1e-13 s_1 (the
+// numerical rank may exceed p), power steps are added until the leading
+// min(p, cap_r + 1) singular values move by at most 1e-14 s_1 between passes
+// (at most kSvdMaxPower); but if after the first pass s_{p-1} exceeds 0.01
+// s_{keep-1} (a flat spectrum, where power steps converge slowly), the
+// factorisation restarts at the full width min(64, rows, cols).
+static int svd_width(long rows, long cols, int max_rank, int cap_r) {
+  const long keep = std::min(max_rank, cap_r);
+  return (int)std::min<long>({(long)kSvdP, rows, cols, 2 * keep + 8});
+}
+
+static int svd_truncate(const SvdScratch& sc, const double* theta, long rows, long cols, int iso,
+                        double eps, int max_rank, int cap_r, hipStream_t s,
+                        std::vector<std::vector<char>>& hold, int rec_i[3], double rec_d[2]) {
+  const int full = (int)std::min<long>({(long)kSvdP, rows, cols});
+  int p = svd_width(rows, cols, max_rank, cap_r);
+  const int keep = std::max(1, std::min({max_rank, cap_r, p}));
+  for (;;) {
+    int n_norm = 0;
+    // out = theta B (mode 0) or theta^H B (mode 1); B null: the test matrix
+    auto gemm = [&](int mode, const double* B, double* out, bool norm) {
+      const int M = (int)(mode == 0 ? rows : cols), K = (int)(mode == 0 ? cols : rows);
+      const int mt = (M + 63) / 64;
+      int nsplit = std::min(kSvdMaxSplit, std::max(1, K / 256));
+      const int kchunk = ((K + nsplit - 1) / nsplit + 15) / 16 * 16;
+      nsplit = (K + kchunk - 1) / kchunk;
+      SvdGemmOp g{theta, B, out, sc.part, norm ? sc.norm : nullptr, (int)rows, (int)cols, p, mode,
+                  nsplit, kchunk, 0x5EEDu, 0};
+      const SvdGemmOp* d = svd_put(sc, 0, g, s, hold);
+      hipchk(launch_svd_gemm(d, mt, nsplit, s), "svd product");
+      if (nsplit > 1) hipchk(launch_svd_reduce(d, (long)M * p, s), "svd reduce");
+      if (norm) n_norm = mt * nsplit;
+    };
+    auto qr = [&](double* A, int m) {
+      QrOp q{};
+      q.C = A;
+      q.R = sc.r;
+      q.V = m <= kQrBlockedMaxM ? A : sc.qrv;
+      q.tau = sc.tau;
+      q.m = m;
+      q.n = p;
+      q.Ppost = m;
+      q.transposeR = 0;
+      q.tol = 0.0;
+      hipchk(launch_qr(svd_put(sc, 1, q, s, hold), 1, s), "svd qr");
+    };
+    // range finder on theta's column space, then the projection Z = theta^H Q
+    gemm(0, nullptr, sc.y, true);
     qr(sc.y, (int)rows);
+    const int nwatch = std::min(p, cap_r + 1);
+    double sig[kSvdP], prev[kSvdP];
+    bool widen = false;
+    for (int power = 0;; ++power) {
+      gemm(1, sc.y, sc.z, false);
+      qr(sc.z, (int)cols);
+      SvdJacobiOp jo{sc.r, sc.up, sc.wp, sc.sig, p, kSvdMaxSweeps};
+      hipchk(launch_svd_jacobi(svd_put(sc, 2, jo, s, hold), s), "svd jacobi");
+      SvdFinishOp fo{sc.y, sc.z, sc.up, sc.wp, sc.sig, sc.norm, sc.e, (int*)sc.rec,
+                     (double*)(sc.rec + 64), eps, n_norm, (int)rows, (int)cols, p, iso, max_rank,
+                     cap_r, 0};
+      hipchk(launch_svd_finish(svd_put(sc, 3, fo, s, hold), (iso == 0 ? rows : cols) * (long)p, s),
+             "svd finish");
+      hipchk(hipMemcpyAsync(rec_i, sc.rec, 3 * sizeof(int), hipMemcpyDeviceToHost, s), "decision");
+      hipchk(hipMemcpyAsync(rec_d, sc.rec + 64, 2 * sizeof(double), hipMemcpyDeviceToHost, s),
+             "decision");
+      hipchk(hipMemcpyAsync(sig, sc.sig, p * sizeof(double), hipMemcpyDeviceToHost, s), "sigma");
+      hipchk(hipStreamSynchronize(s), "sync");
+      hold.clear();
+      // captured subspace complete (p is the smaller side, or the last captured
+      // singular value is at rounding level): done
+      if (p == std::min(rows, cols) || sig[p - 1] <= 1e-13 * sig[0]) break;
+      if (power == 0 && p < full && sig[p - 1] > 0.01 * sig[keep - 1]) {
+        widen = true;
+        break;
+      }
+      if (power >= kSvdMaxPower) break;
+      if (power > 0) {
+        double moved = 0;
+        for (int j = 0; j < nwatch; ++j) moved = std::max(moved, std::fabs(sig[j] - prev[j]));
+        if (moved <= 1e-14 * sig[0]) break;
+      }
+      for (int j = 0; j < nwatch; ++j) prev[j] = sig[j];
+      gemm(0, sc.z, sc.y, false);
+      qr(sc.y, (int)rows);
+    }
+    if (!widen) return p;
+    p = full;
   }
 }
 
@@ -1985,12 +2005,12 @@ struct Ps2Exec {
       b.emit_rk4(edge_recipe(P, sn, c), b.ws(P.ws_theta), rows * cols, +1.0, half);
     });
     const int iso = center_to_child ? 0 : 1;
-    const int p = (int)std::min<long>(kSvdP, std::min(rows, cols));
     SvdScratch sc = svd_scratch(P, ws);
     sc.opbuf = (char*)P.opbuf + 4096;
     int rec_i[3] = {0, 0, 0};
     double rec_d[2] = {0, 0};
-    svd_truncate(sc, theta, rows, cols, iso, eps, max_rank, P.cap.rank[c], s, hold, rec_i, rec_d);
+    const int p =
+        svd_truncate(sc, theta, rows, cols, iso, eps, max_rank, P.cap.rank[c], s, hold, rec_i, rec_d);
     const int rp = rec_i[0], k = rec_i[1];
     if (rp < 1 || rp > P.cap.rank[c] || k < 0 || k > rp)
       fail(TENSO_ENUMERIC, "ps2 truncation decision out of range");
@@ -2592,7 +2612,7 @@ int tenso_svd_truncate(const void* d_A, int rows, int cols, int iso, double eps,
     const size_t blk = align256(side * kSvdP * 16);
     const size_t nrm = align256(((side + 63) / 64) * kSvdMaxSplit * 8);
     const size_t sq = align256((size_t)kSvdP * kSvdP * 16);
-    const size_t total = blk * (3 + kSvdMaxSplit) + 3 * sq + 2 * 1024 + nrm + 256 + 4 * 512;
+    const size_t total = blk * (4 + kSvdMaxSplit) + 3 * sq + 2 * 1024 + nrm + 256 + 4 * 512;
     struct DevMem {
       char* p = nullptr;
       ~DevMem() {
@@ -2619,13 +2639,18 @@ int tenso_svd_truncate(const void* d_A, int rows, int cols, int iso, double eps,
     sc.norm = (double*)take(nrm);
     sc.rec = take(256);
     sc.opbuf = take(4 * 512);
-    sc.e = (double*)d_vectors;
+    sc.e = (double*)take(blk);
     std::vector<std::vector<char>> hold;
     int rec_i[3] = {0, 0, 0};
     double rec_d[2] = {0, 0};
-    svd_truncate(sc, (const double*)d_A, rows, cols, iso, eps, max_rank, std::min(rows, cols), s,
-                 hold, rec_i, rec_d);
-    const int p = std::min({kSvdP, rows, cols});
+    const int pw = svd_truncate(sc, (const double*)d_A, rows, cols, iso, eps, max_rank,
+                                std::min(rows, cols), s, hold, rec_i, rec_d);
+    // the caller's buffer holds the documented width p <= pw
+    const int p = svd_width(rows, cols, max_rank, std::min(rows, cols));
+    const size_t n_iso = iso == 0 ? rows : cols;
+    hipchk(hipMemcpy2DAsync(d_vectors, p * 16, sc.e, pw * 16, p * 16, n_iso, hipMemcpyDeviceToDevice,
+                            s),
+           "vectors");
     if (h_sigma)
       hipchk(hipMemcpyAsync(h_sigma, sc.sig, p * sizeof(double), hipMemcpyDeviceToHost, s), "sigma");
     hipchk(hipStreamSynchronize(s), "sync");
