@@ -12,7 +12,7 @@ Ends (open legs) are numbered 0 = ket (dim M), 1 = bra (dim M), 2 + k = feature 
 (dim N_k, number basis n = 0..N_k - 1).
 
 Metric (reading; the listing that defines it is elided): z_k = f_k * identity
-with f_k = sqrt((|c_k| + |cbar_k|) / 2), TENSO's 'abs' option (Sec. VII C).
+with f_k = sqrt((|c_k| + |cbar_k|) / 2), TENSO's 'abs' option (Sec. VII D).
 Then <n+1| z^-1 a^dag |n> = sqrt(n+1) / f_k and <n| a z |n+1> = f_k sqrt(n+1).
 A feature with zero coefficients takes f_k = 1.
 
