@@ -15,6 +15,8 @@
 #include <hip/hip_ext.h>
 #include <math.h>
 #include <algorithm>
+#include <type_traits>
+#include <utility>
 #include "tenso_internal.h"
 
 namespace tenso {
@@ -117,22 +119,22 @@ __device__ inline UnitGeo unit_geo(const ApplyGroup& G, int u, int njb, int c) {
   return r;
 }
 
-template <typename T>
-__device__ inline void load_scaled(const T* M, int d, int row, int kk, double cr, double ci, T& ar,
-                                   T& ai) {
-  ar = 0;
-  ai = 0;
-  if (row < d && kk < d) {
-    const double a0 = M[2 * ((long)row * d + kk)], a1 = M[2 * ((long)row * d + kk) + 1];
-    ar = (T)(a0 * cr - a1 * ci);
-    ai = (T)(a0 * ci + a1 * cr);
-  }
+// Compile-time loop: f(std::integral_constant<int, I>) for I = 0 .. N - 1, so
+// that register arrays indexed by I are addressed statically.
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_(F& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_(f, std::make_integer_sequence<int, N>{});
 }
 
 // LDS layout of one apply tile (T elements; complex values interleaved):
 //   X : nfl x D1 x (D2 + 1)     the tile's input slices X_f, zero padded
-//   A : D1 x (D1 + 1)           coefficient-scaled operand of the current term
-//   B : D2 x (D2 + 1)
+//   A : 2 x D1 x (D1 + 1)       coefficient-scaled operand, two buffers: term m
+//   B : 2 x D2 x (D2 + 1)       is read from one while term m + 1 is written
+//                               to the other
 //   Z : 4 wavefronts x D1 x 16  per-wave X_f B^T of one unit
 // with D = 16 * ceil(d / 16).  Every MFMA operand is then one LDS vector load
 // without bounds checks.
@@ -142,173 +144,173 @@ constexpr int ZS1 = 17;
 
 __host__ __device__ inline long apply_lds_elems(int nfl, int d1, int d2) {
   const long D1 = 16 * ((d1 + 15) / 16), D2 = 16 * ((d2 + 15) / 16);
-  return 2 * (nfl * D1 * (D2 + 1) + D1 * (D1 + 1) + D2 * (D2 + 1) + kApplyWaves * D1 * ZS1);
+  return 2 * (nfl * D1 * (D2 + 1) + 2 * (D1 * (D1 + 1) + D2 * (D2 + 1)) +
+              kApplyWaves * D1 * ZS1);
 }
 
 template <typename T> struct V2;
 template <> struct V2<float> { typedef float2 t; };
 template <> struct V2<double> { typedef double2 t; };
 
-// Units of the apply tile for one term, with NIB 16-row tiles of leg 1.
-// Operands of k-step q + 1 are read from LDS before the MFMAs of step q are
-// issued, so LDS latency overlaps the matrix cores.  (NIB and TLO are
-// compile-time so that every register array is indexed statically.)
-//   Two-sided terms, Y += A_t (X_f B^T)[:, col block], in two products per
-// unit: first Z = X_f B^T (16-column block) into the wavefront's slab zu ...
-template <typename T, int NIB, typename C2>
-__device__ inline void apply_z(const C2* xf, const C2* bs, C2* zu, int col, int c, int g, int nq1,
-                               int xs1, int bs1) {
-  typedef typename MT<T>::v4 v4;
-  v4 zr[NIB], zi[NIB];
+// K loop of one unit product, acc[TLO + t] += Aop_t Bop over nq k-steps of 4:
+// lane (c, g) reads Aop_t[c][k] at ar[t * ars16 + k] (ar already offset to
+// row c) and Bop[k][col] at bc[k * bks] (bc offset to the lane's column),
+// k = 4 q + g.  Operands of k-step q + 1 are read from LDS into the second
+// register set while the MFMAs of step q run (two sets used in turn, so no
+// register copies between steps).  NIB and TLO are compile-time so that every
+// register array is indexed statically.
+template <typename T, int NIB, int TLO, int NA, typename C2>
+__device__ __forceinline__ void mma_loop(typename MT<T>::v4 (&accr)[NA],
+                                         typename MT<T>::v4 (&acci)[NA], const C2* ar, int ars16,
+                                         const C2* bc, int bks, int nq, int g) {
+  C2 b0, b1, a0[NIB], a1[NIB];
+  auto ld = [&](int q, C2& b, C2(&a)[NIB]) {
+    const int kk = 4 * q + g;
+    b = bc[kk * bks];
 #pragma unroll
-  for (int t = 0; t < NIB; ++t) {
-    zr[t] = v4{0, 0, 0, 0};
-    zi[t] = v4{0, 0, 0, 0};
+    for (int t = 0; t < NIB; ++t) a[t] = ar[t * ars16 + kk];
+  };
+  auto mm = [&](const C2& b, const C2(&a)[NIB]) {
+#pragma unroll
+    for (int t = 0; t < NIB; ++t) cmma<T>(accr[TLO + t], acci[TLO + t], a[t].x, a[t].y, b.x, b.y);
+  };
+  // both products of an iteration are unconditional, so the accumulators
+  // stay in place across iterations; an odd last step follows the loop
+  ld(0, b0, a0);
+  int q = 0;
+  for (; q + 1 < nq; q += 2) {
+    ld(q + 1, b1, a1);
+    mm(b0, a0);
+    if (q + 2 < nq) ld(q + 2, b0, a0);
+    mm(b1, a1);
   }
-  C2 bc = bs[col * bs1 + g], xc[NIB];
+  if (q < nq) mm(b0, a0);
+}
+
+// Operand staging: lanes over the columns of a row, 64 / D rows per
+// wavefront pass for D = 16, 32, 64 (one row for D = 48, lanes 48..63 idle).
+// For D <= 32 a thread holds at most kApplyPf entries (rows i0, i0 + step,
+// ...); those are read from global memory one term ahead, while the current
+// term is multiplied.
+constexpr int kApplyPf = 4;
+
+struct OpLane {
+  int i0, step, j;
+  bool on;
+};
+__device__ inline OpLane op_lane(int D, int lane, int wave) {
+  const bool p2 = (D & (D - 1)) == 0;
+  const int rpw = p2 ? 64 / D : 1;
+  OpLane o;
+  o.i0 = wave * rpw + (p2 ? lane / D : 0);
+  o.step = kApplyWaves * rpw;
+  o.j = p2 ? (lane & (D - 1)) : lane;
+  o.on = o.j < D;
+  return o;
+}
+
+template <typename T, typename C2>
+__device__ __forceinline__ void op_fetch(const T* M, int d, int D, const OpLane& o,
+                                         C2 (&r)[kApplyPf]) {
 #pragma unroll
-  for (int t = 0; t < NIB; ++t) xc[t] = xf[(16 * t + c) * xs1 + g];
-  for (int q = 0; q < nq1; ++q) {
-    C2 bn = bc, xn[NIB];
-#pragma unroll
-    for (int t = 0; t < NIB; ++t) xn[t] = xc[t];
-    if (q + 1 < nq1) {
-      const int kk = 4 * (q + 1) + g;
-      bn = bs[col * bs1 + kk];
-#pragma unroll
-      for (int t = 0; t < NIB; ++t) xn[t] = xf[(16 * t + c) * xs1 + kk];
+  for (int k = 0; k < kApplyPf; ++k) {
+    const int i = o.i0 + k * o.step;
+    C2 v;
+    v.x = 0;
+    v.y = 0;
+    if (o.on && i < D && i < d && o.j < d) {
+      const gp<const T> e = gmem(M) + 2 * (i * d + o.j);
+      v.x = e[0];
+      v.y = e[1];
     }
-#pragma unroll
-    for (int t = 0; t < NIB; ++t) cmma<T>(zr[t], zi[t], xc[t].x, xc[t].y, bc.x, bc.y);
-    bc = bn;
-#pragma unroll
-    for (int t = 0; t < NIB; ++t) xc[t] = xn[t];
-  }
-#pragma unroll
-  for (int t = 0; t < NIB; ++t) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      C2 v;
-      v.x = zr[t][r];
-      v.y = zi[t][r];
-      zu[(16 * t + MT<T>::drow(g, r)) * ZS1 + c] = v;
-    }
+    r[k] = v;
   }
 }
 
-// ... then Y += A Z_u into accumulator tiles TLO .. TLO + NIB - 1.
-template <typename T, int NIB, int TLO, typename C2>
-__device__ inline void apply_az(const C2* as, const C2* zu, int c, int g, int nq2, int as1,
-                                typename MT<T>::v4 (&yr)[MT<T>::NT],
-                                typename MT<T>::v4 (&yi)[MT<T>::NT]) {
-  C2 zc = zu[g * ZS1 + c], ac[NIB];
+// entries scaled by the coefficient unless it is exactly 1 (in the compute
+// precision: one rounding, as for the operand itself)
+template <typename T, typename C2>
+__device__ __forceinline__ C2 op_scale(C2 v, bool unit, T sr, T si) {
+  if (!unit) {
+    const T a0 = v.x, a1 = v.y;
+    v.x = a0 * sr - a1 * si;
+    v.y = a0 * si + a1 * sr;
+  }
+  return v;
+}
+
+template <typename T, typename C2>
+__device__ __forceinline__ void op_put(const C2 (&r)[kApplyPf], int D, int ld, const OpLane& o,
+                                       C2* dst, double sr, double si) {
+  if (!o.on) return;
+  const bool unit = sr == 1.0 && si == 0.0;
 #pragma unroll
-  for (int t = 0; t < NIB; ++t) ac[t] = as[(16 * t + c) * as1 + g];
-  for (int q = 0; q < nq2; ++q) {
-    C2 zn = zc, an[NIB];
-#pragma unroll
-    for (int t = 0; t < NIB; ++t) an[t] = ac[t];
-    if (q + 1 < nq2) {
-      const int kk = 4 * (q + 1) + g;
-      zn = zu[kk * ZS1 + c];
-#pragma unroll
-      for (int t = 0; t < NIB; ++t) an[t] = as[(16 * t + c) * as1 + kk];
-    }
-#pragma unroll
-    for (int t = 0; t < NIB; ++t) cmma<T>(yr[TLO + t], yi[TLO + t], ac[t].x, ac[t].y, zc.x, zc.y);
-    zc = zn;
-#pragma unroll
-    for (int t = 0; t < NIB; ++t) ac[t] = an[t];
+  for (int k = 0; k < kApplyPf; ++k) {
+    const int i = o.i0 + k * o.step;
+    if (i < D) dst[i * ld + o.j] = op_scale<T>(r[k], unit, (T)sr, (T)si);
   }
 }
 
-// One-sided terms, one unit at a time, into accumulator tiles TLO .. TLO +
-// NIB - 1: Y += A_t X_f[:, col block] (kind 1) or X_f B^T (kind 2).
-template <typename T, int NIB, int TLO, typename C2>
-__device__ inline void apply_unit(int kind, const C2* xf, const C2* as, const C2* bs,
-                                  int col, int c, int g, int nq1, int nq2, int xs1, int as1,
-                                  int bs1, typename MT<T>::v4 (&yr)[MT<T>::NT],
-                                  typename MT<T>::v4 (&yi)[MT<T>::NT]) {
-  if (kind == 1) {  // A only: Y += A X_f[:, col block]
-    C2 xc = xf[g * xs1 + col], ac[NIB];
-#pragma unroll
-    for (int t = 0; t < NIB; ++t) ac[t] = as[(16 * t + c) * as1 + g];
-    for (int q = 0; q < nq2; ++q) {
-      C2 xn = xc, an[NIB];
-#pragma unroll
-      for (int t = 0; t < NIB; ++t) an[t] = ac[t];
-      if (q + 1 < nq2) {
-        const int kk = 4 * (q + 1) + g;
-        xn = xf[kk * xs1 + col];
-#pragma unroll
-        for (int t = 0; t < NIB; ++t) an[t] = as[(16 * t + c) * as1 + kk];
-      }
-#pragma unroll
-      for (int t = 0; t < NIB; ++t) cmma<T>(yr[TLO + t], yi[TLO + t], ac[t].x, ac[t].y, xc.x, xc.y);
-      xc = xn;
-#pragma unroll
-      for (int t = 0; t < NIB; ++t) ac[t] = an[t];
+// D > 32: read and written in one pass (no look-ahead)
+template <typename T, typename C2>
+__device__ void op_stage(const T* M, int d, int D, int ld, const OpLane& o, C2* dst, double sr,
+                         double si) {
+  if (!o.on) return;
+  const bool unit = sr == 1.0 && si == 0.0;
+  for (int i = o.i0; i < D; i += o.step) {
+    C2 v;
+    v.x = 0;
+    v.y = 0;
+    if (i < d && o.j < d) {
+      const gp<const T> e = gmem(M) + 2 * (i * d + o.j);
+      v.x = e[0];
+      v.y = e[1];
     }
-  } else if (kind == 2) {  // B only: Y += X_f B^T (16-column block)
-    C2 bc = bs[col * bs1 + g], xc[NIB];
-#pragma unroll
-    for (int t = 0; t < NIB; ++t) xc[t] = xf[(16 * t + c) * xs1 + g];
-    for (int q = 0; q < nq1; ++q) {
-      C2 bn = bc, xn[NIB];
-#pragma unroll
-      for (int t = 0; t < NIB; ++t) xn[t] = xc[t];
-      if (q + 1 < nq1) {
-        const int kk = 4 * (q + 1) + g;
-        bn = bs[col * bs1 + kk];
-#pragma unroll
-        for (int t = 0; t < NIB; ++t) xn[t] = xf[(16 * t + c) * xs1 + kk];
-      }
-#pragma unroll
-      for (int t = 0; t < NIB; ++t) cmma<T>(yr[TLO + t], yi[TLO + t], xc[t].x, xc[t].y, bc.x, bc.y);
-      bc = bn;
-#pragma unroll
-      for (int t = 0; t < NIB; ++t) xc[t] = xn[t];
-    }
+    dst[i * ld + o.j] = op_scale<T>(v, unit, (T)sr, (T)si);
   }
 }
 
-template <typename T, typename Tin>
-__global__ void __launch_bounds__(64 * kApplyWaves) k_apply(const ApplyGroup* __restrict__ groups,
-                                               const ApplyTile* __restrict__ tiles,
-                                               const int* __restrict__ step_ctr) {
+#define TENSO_WAVE_SYNC()                                \
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront"); \
+  __builtin_amdgcn_wave_barrier();                       \
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront")
+
+// One tile with NIB 16-row blocks of leg 1: each wavefront owns up to
+// MT<T>::NT / NIB units of the tile and accumulates them over all terms.
+template <typename T, typename Tin, int NIB>
+__device__ __forceinline__ void apply_tile(const ApplyGroup& G, const ApplyTile& tile,
+                                           char* smem_raw, long* sbase, int step) {
   typedef typename MT<T>::v4 v4;
   typedef typename V2<T>::t c2;
-  constexpr int NT = MT<T>::NT;
-  extern __shared__ char smem_raw[];
+  constexpr int UPW = MT<T>::NT / NIB;  // units per wavefront
+  constexpr int NA = UPW * NIB;         // accumulator tiles used
+  constexpr int AW = kApplyWaves;
+  constexpr int D1 = 16 * NIB;
+  constexpr int as1 = D1 + 1;
   c2* smem = reinterpret_cast<c2*>(smem_raw);
-  const ApplyTile tile = tiles[blockIdx.x];
-  const ApplyGroup& G = groups[tile.group];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int c = lane & 15;   // MFMA row / column within a 16-block
-  const int g = lane >> 4;   // K sub-index (0..3)
+  const int c = lane & 15;  // MFMA row / column within a 16-block
+  const int g = lane >> 4;  // K sub-index (0..3)
   const int d1 = G.d1, d2 = G.d2;
-  const int nib = (d1 + 15) >> 4, njb = (d2 + 15) >> 4;
-  const int D1 = 16 * nib, D2 = 16 * njb;
-  const int xs1 = D2 + 1, as1 = D1 + 1, bs1 = D2 + 1;  // padded row strides
-  const int nq1 = (d2 + 3) >> 2;  // K steps of X_f B^T
-  const int nq2 = (d1 + 3) >> 2;  // K steps of A Z
+  const int njb = (d2 + 15) >> 4;
+  const int D2 = 16 * njb;
+  const int xs1 = D2 + 1, bs1 = D2 + 1;  // padded row strides
+  const int nq1 = (d2 + 3) >> 2;         // K steps of X_f B^T
+  const int nq2 = (d1 + 3) >> 2;         // K steps of A Z
   const long sb = G.P2;
   const long sa = (long)G.P1 * d2 * G.P2;
-  const int step = step_ctr ? gmem(step_ctr)[0] : 0;
   const int jdrv = 4 * step + G.rel;
   const int f_first = tile.u0 / njb;
   const int nfl = (tile.u0 + tile.nu - 1) / njb - f_first + 1;
   c2* xs = smem;
-  c2* as = xs + (long)nfl * D1 * xs1;
-  c2* bs = as + (long)D1 * as1;
-  c2* zs = bs + (long)D2 * bs1 + (long)wave * D1 * ZS1;
+  c2* asb = xs + (long)nfl * D1 * xs1;
+  c2* bsb = asb + 2 * D1 * as1;
+  c2* zs = bsb + 2 * (long)D2 * bs1 + (long)wave * D1 * ZS1;
 
   // stage the tile's input slices (zero padded, compute precision): slice
   // bases once, then lanes over the columns of a row (D2 = 16, 32, 64: 64/D2
   // rows per wavefront pass; D2 = 48: one row, lanes 48..63 idle)
-  constexpr int AW = kApplyWaves;
-  __shared__ long sbase[kApplyMaxUnits + 1];
   if ((int)threadIdx.x < nfl)
     sbase[threadIdx.x] = unit_geo(G, (f_first + (int)threadIdx.x) * njb, njb, 0).base;
   __syncthreads();
@@ -319,7 +321,7 @@ __global__ void __launch_bounds__(64 * kApplyWaves) k_apply(const ApplyGroup* __
     const int bcol = p2 ? (lane & (D2 - 1)) : lane;
     if (bcol < D2 && (p2 || lane < D2)) {
       // rows (fl, a) in steps of AW * rpw
-      const int step = AW * rpw;
+      const int stp = AW * rpw;
       int fl = 0, a = wave * rpw + sub;
       c2* dst = xs + (long)a * xs1 + bcol;
       while (a >= D1) {  // the first row may already lie in a later slice
@@ -329,7 +331,7 @@ __global__ void __launch_bounds__(64 * kApplyWaves) k_apply(const ApplyGroup* __
       long src = fl < nfl ? sbase[fl] + (long)bcol * sb : 0;
       const bool colok = bcol < d2;
 #pragma unroll 4
-      for (int ra = a; ra < nfl * D1; ra += step) {
+      for (int ra = a; ra < nfl * D1; ra += stp) {
         c2 v;
         v.x = 0;
         v.y = 0;
@@ -339,8 +341,8 @@ __global__ void __launch_bounds__(64 * kApplyWaves) k_apply(const ApplyGroup* __
           v.y = x.im;
         }
         *dst = v;
-        dst += (long)step * xs1;
-        a += step;
+        dst += (long)stp * xs1;
+        a += stp;
         if (a >= D1) {
           do {
             a -= D1;
@@ -352,141 +354,165 @@ __global__ void __launch_bounds__(64 * kApplyWaves) k_apply(const ApplyGroup* __
     }
   }
 
+  // this wavefront's units (at most UPW: the host sizes tiles to fit)
   int n_my = tile.nu > wave ? (tile.nu - wave + AW - 1) / AW : 0;
-  if (n_my * nib > NT) n_my = NT / nib;
-  v4 yr[NT], yi[NT];
+  if (n_my > UPW) n_my = UPW;
+  int xoff[UPW], ucol[UPW];
+  long ubase[UPW];
+  static_for<UPW>([&](auto uc) {
+    constexpr int UU = decltype(uc)::value;
+    const int u = tile.u0 + wave + AW * UU;
+    xoff[UU] = (u / njb - f_first) * D1 * xs1;
+    ucol[UU] = 16 * (u % njb) + c;
+    ubase[UU] = unit_geo(G, u, njb, c).base;
+  });
+  v4 yr[NA], yi[NA];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
+  for (int t = 0; t < NA; ++t) {
     yr[t] = v4{0, 0, 0, 0};
     yi[t] = v4{0, 0, 0, 0};
   }
 
   // write the wavefront's accumulators (its units of this tile) to Yb
   auto store_out = [&](gp<T> Yb) {
+    static_for<UPW>([&](auto uc) {
+      constexpr int UU = decltype(uc)::value;
+      if (UU < n_my) {
+        const int col = ucol[UU];
 #pragma unroll
-    for (int ti = 0; ti < NT; ++ti) {
-      if (ti < n_my * nib) {
-        const int uu = ti / nib, t = ti % nib;
-        const UnitGeo ug = unit_geo(G, tile.u0 + wave + AW * uu, njb, c);
+        for (int t = 0; t < NIB; ++t) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = 16 * t + MT<T>::drow(g, r);
-          if (row < d1 && ug.col < d2) {
-            const long o = 2 * (ug.base + row * sa + (long)ug.col * sb);
-            if (G.accumulate) {
-              Yb[o] += yr[ti][r];
-              Yb[o + 1] += yi[ti][r];
-            } else {
-              Yb[o] = yr[ti][r];
-              Yb[o + 1] = yi[ti][r];
+          for (int r = 0; r < 4; ++r) {
+            const int row = 16 * t + MT<T>::drow(g, r);
+            if (row < d1 && col < d2) {
+              const long o = 2 * (ubase[UU] + row * sa + (long)col * sb);
+              if (G.accumulate) {
+                Yb[o] += yr[UU * NIB + t][r];
+                Yb[o + 1] += yi[UU * NIB + t][r];
+              } else {
+                Yb[o] = yr[UU * NIB + t][r];
+                Yb[o + 1] = yi[UU * NIB + t][r];
+              }
             }
           }
         }
       }
+    });
+  };
+
+  // operands: term m + 1 is read (D <= 32) while term m is multiplied, and
+  // written to the other LDS buffer after it
+  const OpLane oa = op_lane(D1, lane, wave), ob = op_lane(D2, lane, wave);
+  const bool pfa = D1 <= 32, pfb = D2 <= 32;
+  c2 ra[kApplyPf], rb[kApplyPf];
+  auto fetch = [&](const TermRef& t) {
+    if (t.A && pfa) op_fetch<T>(reinterpret_cast<const T*>(t.A), d1, D1, oa, ra);
+    if (t.B && pfb) op_fetch<T>(reinterpret_cast<const T*>(t.B), d2, D2, ob, rb);
+  };
+  auto put = [&](const TermRef& t, double cr, double ci, int buf) {
+    c2* as = asb + buf * D1 * as1;
+    c2* bs = bsb + (long)buf * D2 * bs1;
+    if (t.A) {  // A carries the coefficient
+      if (pfa) op_put<T>(ra, D1, as1, oa, as, cr, ci);
+      else op_stage<T>(reinterpret_cast<const T*>(t.A), d1, D1, as1, oa, as, cr, ci);
+    }
+    if (t.B) {  // B only when alone
+      const double sr = t.A ? 1.0 : cr, si = t.A ? 0.0 : ci;
+      if (pfb) op_put<T>(rb, D2, bs1, ob, bs, sr, si);
+      else op_stage<T>(reinterpret_cast<const T*>(t.B), d2, D2, bs1, ob, bs, sr, si);
     }
   };
-  for (int m = 0; m < G.n_terms; ++m) {
-    const TermRef tr = gmem(G.terms)[m];
+  TermRef tr{};
+  if (G.n_terms > 0) {
     double cr, ci;
+    tr = gmem(G.terms)[0];
     coef_at(tr, G.drive, G.drive_ld, jdrv, cr, ci);
-    const T* Am = reinterpret_cast<const T*>(tr.A);
-    const T* Bm = reinterpret_cast<const T*>(tr.B);
-    __syncthreads();  // previous term's operands are no longer read
-    // operand tiles: lanes over columns, rows per wavefront pass as for X;
-    // entries are scaled by the coefficient unless it is exactly 1
-    auto stage_op = [&](const T* M, int d, int D, int ld, c2* dst, double sr, double si) {
-      const bool p2 = (D & (D - 1)) == 0;
-      const int rpw = p2 ? 64 / D : 1;
-      const int sub = p2 ? lane / D : 0;
-      const int j = p2 ? (lane & (D - 1)) : lane;
-      if (j >= D || (!p2 && lane >= D)) return;
-      // the coefficient is applied in the compute precision (one rounding,
-      // as for the operand itself)
-      const bool unit = sr == 1.0 && si == 0.0;
-      const T sr_t = (T)sr, si_t = (T)si;
-      const bool jok = j < d;
-      for (int i = wave * rpw + sub; i < D; i += AW * rpw) {
-        c2 v;
-        v.x = 0;
-        v.y = 0;
-        if (i < d && jok) {
-          const gp<const T> e = gmem(M) + 2 * (i * d + j);
-          const T a0 = e[0], a1 = e[1];
-          if (unit) {
-            v.x = a0;
-            v.y = a1;
-          } else {
-            v.x = a0 * sr_t - a1 * si_t;
-            v.y = a0 * si_t + a1 * sr_t;
-          }
-        }
-        dst[i * ld + j] = v;
-      }
-    };
-    if (Am) stage_op(Am, d1, D1, as1, as, cr, ci);  // A carries the coefficient
-    if (Bm) stage_op(Bm, d2, D2, bs1, bs, Am ? 1.0 : cr, Am ? 0.0 : ci);  // B only when alone
-    __syncthreads();
-    const int kind = (Am ? 1 : 0) | (Bm ? 2 : 0);
-    if (kind == 3) {
-      // one unit at a time: X_f B^T into the wavefront's slab, then A times it
-      for (int uu = 0; uu < n_my; ++uu) {
-        const int u = tile.u0 + wave + AW * uu;
-        const int fl = u / njb - f_first, jb = u % njb;
-        const c2* xf = xs + (long)fl * D1 * xs1;
-        const int col = 16 * jb + c;
-#define TENSO_ZAZ(NIB, TLO)                                               \
-  apply_z<T, NIB>(xf, bs, zs, col, c, g, nq1, xs1, bs1);                  \
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");                  \
-  __builtin_amdgcn_wave_barrier();                                        \
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");                  \
-  apply_az<T, NIB, TLO>(as, zs, c, g, nq2, as1, yr, yi)
-        switch (4 * nib + uu * nib) {
-          case 4: TENSO_ZAZ(1, 0); break;
-          case 5: TENSO_ZAZ(1, 1); break;
-          case 6: TENSO_ZAZ(1, 2); break;
-          case 7: TENSO_ZAZ(1, 3); break;
-          case 8: TENSO_ZAZ(2, 0); break;
-          case 10: TENSO_ZAZ(2, 2); break;
-          case 12: TENSO_ZAZ(3, 0); break;
-          default: TENSO_ZAZ(4, 0); break;
-        }
-#undef TENSO_ZAZ
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      }
-    } else {
-      for (int uu = 0; uu < n_my; ++uu) {
-        const int u = tile.u0 + wave + AW * uu;
-        const int fl = u / njb - f_first, jb = u % njb;
-        const c2* xf = xs + (long)fl * D1 * xs1;
-        const int col = 16 * jb + c;
-        const int t_lo = uu * nib;
-#define TENSO_UNIT(NIB, TLO) \
-  apply_unit<T, NIB, TLO>(kind, xf, as, bs, col, c, g, nq1, nq2, xs1, as1, bs1, yr, yi)
-        switch (4 * nib + t_lo) {
-          case 4: TENSO_UNIT(1, 0); break;
-          case 5: TENSO_UNIT(1, 1); break;
-          case 6: TENSO_UNIT(1, 2); break;
-          case 7: TENSO_UNIT(1, 3); break;
-          case 8: TENSO_UNIT(2, 0); break;
-          case 10: TENSO_UNIT(2, 2); break;
-          case 12: TENSO_UNIT(3, 0); break;
-          default: TENSO_UNIT(4, 0); break;
-        }
-#undef TENSO_UNIT
-      }
+    fetch(tr);
+    put(tr, cr, ci, 0);
+  }
+  __syncthreads();
+  for (int m = 0; m < G.n_terms; ++m) {
+    const int buf = m & 1;
+    const bool more = m + 1 < G.n_terms;
+    TermRef tn{};
+    double cnr = 0, cni = 0;
+    if (more) {
+      tn = gmem(G.terms)[m + 1];
+      coef_at(tn, G.drive, G.drive_ld, jdrv, cnr, cni);
+      fetch(tn);
     }
+    const c2* as = asb + buf * D1 * as1;
+    const c2* bs = bsb + (long)buf * D2 * bs1;
+    const int kind = (tr.A ? 1 : 0) | (tr.B ? 2 : 0);
+    // Y += A X_f B^T (kind 3: Z = X_f B^T for the unit's 16 columns into the
+    // wavefront's slab first, then A Z), A X_f (kind 1) or X_f B^T (kind 2):
+    // every unit's accumulators are updated at one place in the code
+    const bool two = kind == 3;
+    const int nq = kind == 2 ? nq1 : nq2;
+    const int ars16 = 16 * (kind == 2 ? xs1 : as1);
+    const int bks = kind == 3 ? ZS1 : kind == 1 ? xs1 : 1;
+    static_for<UPW>([&](auto uc) {
+      constexpr int UU = decltype(uc)::value;
+      if (UU < n_my) {
+        const c2* xf = xs + xoff[UU];
+        const int col = ucol[UU];
+        if (two) {
+          v4 zr[NIB], zi[NIB];
+#pragma unroll
+          for (int t = 0; t < NIB; ++t) {
+            zr[t] = v4{0, 0, 0, 0};
+            zi[t] = v4{0, 0, 0, 0};
+          }
+          mma_loop<T, NIB, 0, NIB>(zr, zi, xf + c * xs1, 16 * xs1, bs + col * bs1, 1, nq1, g);
+#pragma unroll
+          for (int t = 0; t < NIB; ++t) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              c2 v;
+              v.x = zr[t][r];
+              v.y = zi[t][r];
+              zs[(16 * t + MT<T>::drow(g, r)) * ZS1 + c] = v;
+            }
+          }
+          TENSO_WAVE_SYNC();
+        }
+        const c2* ar = kind == 2 ? xf + c * xs1 : as + c * as1;
+        const c2* bc = two ? zs + c : kind == 1 ? xf + col : bs + col * bs1;
+        mma_loop<T, NIB, UU * NIB, NA>(yr, yi, ar, ars16, bc, bks, nq, g);
+        if (two) TENSO_WAVE_SYNC();
+      }
+    });
     if (G.per_term_out) {  // this term's result goes to its own slab
       store_out(gmem(reinterpret_cast<T*>(G.Y)) + 2 * (long)G.F * d1 * d2 * m);
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
+      for (int t = 0; t < NA; ++t) {
         yr[t] = v4{0, 0, 0, 0};
         yi[t] = v4{0, 0, 0, 0};
       }
     }
+    if (more) put(tn, cnr, cni, buf ^ 1);
+    __syncthreads();  // the next term's operands are in place; this term's are free
+    tr = tn;
   }
   if (!G.per_term_out) store_out(gmem(reinterpret_cast<T*>(G.Y)));
+}
+#undef TENSO_WAVE_SYNC
+
+template <typename T, typename Tin>
+__global__ void __launch_bounds__(64 * kApplyWaves) k_apply(const ApplyGroup* __restrict__ groups,
+                                                            const ApplyTile* __restrict__ tiles,
+                                                            const int* __restrict__ step_ctr) {
+  extern __shared__ char smem_raw[];
+  __shared__ long sbase[kApplyMaxUnits + 1];
+  const ApplyTile tile = tiles[blockIdx.x];
+  const ApplyGroup& G = groups[tile.group];
+  const int step = step_ctr ? gmem(step_ctr)[0] : 0;
+  switch ((G.d1 + 15) >> 4) {  // uniform per tile
+    case 1: apply_tile<T, Tin, 1>(G, tile, smem_raw, sbase, step); break;
+    case 2: apply_tile<T, Tin, 2>(G, tile, smem_raw, sbase, step); break;
+    case 3: apply_tile<T, Tin, 3>(G, tile, smem_raw, sbase, step); break;
+    default: apply_tile<T, Tin, 4>(G, tile, smem_raw, sbase, step); break;
+  }
 }
 
 // ---------------------------------------------------------------------------

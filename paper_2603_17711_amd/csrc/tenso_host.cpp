@@ -832,7 +832,7 @@ struct Builder {
     const double per_unit = unit_work(d1, d2) * std::max(1, n_terms);
     long want = std::max<long>(target, (long)std::ceil(units * per_unit / P.tile_work));
     long per = std::max<long>(1, (units + want - 1) / want);
-    per = std::min<long>(per, (long)(kApplyMaxUnits / nib));
+    per = std::min<long>(per, (long)(kApplyWaves * (NT / nib)));  // each wavefront's accumulators
     while (per > 1 && apply_lds_bytes(P.fp64, (int)((per + njb - 1) / njb + 1), d1, d2) > budget)
       per /= 2;
     return per;

@@ -38,8 +38,8 @@ struct ApplyGroup {
 };
 
 // Wavefronts of an apply workgroup, accumulator tiles per wavefront, and the
-// most units of one tile (kApplyMaxUnits / nib for nib 16-row blocks of leg 1;
-// at most kApplyWaves * kApplyAccTiles / nib, the accumulators of a workgroup).
+// most units of one tile (kApplyWaves * (kApplyAccTiles / nib) for nib 16-row
+// blocks of leg 1: every wavefront's units fit its accumulators).
 constexpr int kApplyWaves = 4;
 constexpr int kApplyAccTiles = 4;
 constexpr int kApplyMaxUnits = 16;
