@@ -835,6 +835,9 @@ struct Builder {
     per = std::min<long>(per, (long)(kApplyWaves * (NT / nib)));  // each wavefront's accumulators
     while (per > 1 && apply_lds_bytes(P.fp64, (int)((per + njb - 1) / njb + 1), d1, d2) > budget)
       per /= 2;
+    while (per > 1 && apply_lds_bytes(P.fp64, (int)((per + njb - 1) / njb + 1), d1, d2) >
+                          (size_t)kApplyLdsShare)
+      per /= 2;
     return per;
   }
 
