@@ -948,10 +948,183 @@ __device__ void qr_unblocked(const QrOp& op) {
 }
 
 
+// Column-by-column form with the whole matrix in LDS (m * n <= kQrLdsElems,
+// column-major): reflector j is formed by the wavefront that owns column j
+// (columns are dealt to the wavefronts in turn), then every wavefront applies
+// it to its own later columns (one wave reduction per column, no block
+// reduction); the orthonormal factor is formed in place in the same way
+// (LAPACK zung2r order).  Reflectors, taus, the rank rule and the phases of R
+// are those of the other forms; only the rounding order differs.
+constexpr int kQrLdsElems = QR_MAX_M * QR_PB;  // fits the kernel's dynamic LDS
+
+__device__ void qr_lds(const QrOp& op, z2* __restrict__ L) {
+  const int m = op.m, n = op.n, k = m < n ? m : n;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ double red[QR_NW];
+  __shared__ z2 tauS[64];
+  __shared__ double phS[2 * 64];
+  __shared__ int skipS;
+  const gp<z2> C = gmem(reinterpret_cast<z2*>(op.C));
+  const gp<z2> R = gmem(reinterpret_cast<z2*>(op.R));
+  const int ppost = op.Ppost;
+  const int cstride = n * ppost;
+  const double pinv = 1.0 / ppost;
+  auto crow = [=](int row) -> int {
+    const int q = qr_div(row, ppost, pinv);
+    return q * cstride + (row - q * ppost);
+  };
+  // C -> L and the Frobenius norm
+  double fro = 0;
+  for (int row = tid; row < m; row += QR_NT) {
+    const int cb = crow(row);
+    for (int c = 0; c < n; ++c) {
+      const z2 v = C[cb + c * ppost];
+      L[c * m + row] = v;
+      fro += v.r * v.r + v.i * v.i;
+    }
+  }
+  fro = wave_sum(fro);
+  if (lane == 0) red[wave] = fro;
+  __syncthreads();
+  double fsum = 0;
+  for (int w = 0; w < QR_NW; ++w) fsum += red[w];
+  // residual columns at or below this squared norm count as exact zeros
+  const double thr2 = op.tol * op.tol * fsum;
+
+  for (int j = 0; j < k; ++j) {
+    z2* __restrict__ Lj = L + j * m;
+    if (wave == j % QR_NW) {  // reflector of column j (uniform per wavefront)
+      double xn2 = 0;
+      for (int r = j + 1 + lane; r < m; r += 64) {
+        const z2 x = Lj[r];
+        xn2 = fma(x.r, x.r, fma(x.i, x.i, xn2));
+      }
+      xn2 = wave_sum(xn2);
+      const z2 alpha = Lj[j];
+      z2 t{0.0, 0.0};
+      int skip;
+      if (alpha.r * alpha.r + alpha.i * alpha.i + xn2 <= thr2) {
+        // numerically zero residual: identity reflector, zero column
+        skip = 2;
+        for (int r = j + lane; r < m; r += 64) Lj[r] = z2{0.0, 0.0};
+      } else if (xn2 == 0.0 && alpha.i == 0.0) {
+        skip = 1;
+      } else {
+        skip = 0;
+        const double nrm = sqrt(alpha.r * alpha.r + alpha.i * alpha.i + xn2);
+        // beta = -sign(Re alpha) * nrm (LAPACK zlarfg; a zero counts as positive)
+        const double beta = alpha.r >= 0.0 ? -nrm : nrm;
+        t = z2{(beta - alpha.r) / beta, -alpha.i / beta};
+        const double dr = alpha.r - beta, di = alpha.i;
+        const double den = dr * dr + di * di;
+        const z2 sc{dr / den, -di / den};  // 1 / (alpha - beta)
+        for (int r = j + 1 + lane; r < m; r += 64) Lj[r] = zmul(Lj[r], sc);
+        if (lane == 0) Lj[j] = z2{beta, 0.0};
+      }
+      if (lane == 0) {
+        tauS[j] = t;
+        skipS = skip;
+        gmem(reinterpret_cast<z2*>(op.tau))[j] = t;
+      }
+    }
+    __syncthreads();
+    if (skipS == 0) {
+      // H^H = I - conj(tau) v v^H on the later columns of this wavefront
+      const z2 t = tauS[j];
+      const z2 ct{t.r, -t.i};
+      for (int c = j + 1; c < n; ++c) {
+        if (c % QR_NW != wave) continue;
+        z2* __restrict__ Lc = L + c * m;
+        double wr = 0, wi = 0;
+        for (int r = j + lane; r < m; r += 64) {
+          const z2 v = r == j ? z2{1.0, 0.0} : Lj[r];
+          const z2 p = zconjmul(v, Lc[r]);
+          wr += p.r;
+          wi += p.i;
+        }
+        wr = wave_sum(wr);
+        wi = wave_sum(wi);
+        const z2 f = zmul(ct, z2{wr, wi});
+        for (int r = j + lane; r < m; r += 64) {
+          const z2 v = r == j ? z2{1.0, 0.0} : Lj[r];
+          const z2 pv = zmul(f, v);
+          Lc[r] = z2{Lc[r].r - pv.r, Lc[r].i - pv.i};
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // phases that make diag(R) real non-negative; R with its rows rephased
+  if (tid < n) {
+    const z2 dd = tid < k ? L[tid * m + tid] : z2{0.0, 0.0};
+    const double a = sqrt(dd.r * dd.r + dd.i * dd.i);
+    phS[2 * tid] = a > 0 ? dd.r / a : 1.0;
+    phS[2 * tid + 1] = a > 0 ? dd.i / a : 0.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < n * n; e += QR_NT) {
+    const int i = e / n, c = e % n;
+    const z2 v = (i <= c && i < k) ? zmul(z2{phS[2 * i], -phS[2 * i + 1]}, L[c * m + i])
+                                   : z2{0.0, 0.0};
+    if (op.transposeR) R[c * n + i] = v;
+    else R[i * n + c] = v;
+  }
+  __syncthreads();  // R is read out before Q overwrites it
+  // Q = H_0 ... H_{k-1} [I; 0], formed in place from the last reflector back
+  for (int i = k - 1; i >= 0; --i) {
+    const z2 t = tauS[i];
+    z2* __restrict__ Li = L + i * m;
+    if (t.r != 0.0 || t.i != 0.0) {
+      for (int c = i + 1; c < k; ++c) {
+        if (c % QR_NW != wave) continue;
+        z2* __restrict__ Lc = L + c * m;
+        double wr = 0, wi = 0;
+        for (int r = i + lane; r < m; r += 64) {
+          const z2 v = r == i ? z2{1.0, 0.0} : Li[r];
+          const z2 p = zconjmul(v, Lc[r]);
+          wr += p.r;
+          wi += p.i;
+        }
+        wr = wave_sum(wr);
+        wi = wave_sum(wi);
+        const z2 f = zmul(t, z2{wr, wi});
+        for (int r = i + lane; r < m; r += 64) {
+          const z2 v = r == i ? z2{1.0, 0.0} : Li[r];
+          const z2 pv = zmul(f, v);
+          Lc[r] = z2{Lc[r].r - pv.r, Lc[r].i - pv.i};
+        }
+      }
+    }
+    __syncthreads();  // every wavefront is done with v_i
+    if (wave == i % QR_NW) {
+      for (int r = lane; r < m; r += 64) {
+        z2 q{0.0, 0.0};
+        if (r == i) q = z2{1.0 - t.r, -t.i};
+        else if (r > i) {
+          const z2 p = zmul(t, Li[r]);
+          q = z2{-p.r, -p.i};
+        }
+        Li[r] = q;
+      }
+    }
+    __syncthreads();
+  }
+  // Q (m x k) into the core, with the phases of R
+  for (int row = tid; row < m; row += QR_NT) {
+    const int cb = crow(row);
+    for (int c = 0; c < k; ++c) C[cb + c * ppost] = zmul(L[c * m + row], z2{phS[2 * c], phS[2 * c + 1]});
+  }
+}
+
 __global__ void __launch_bounds__(QR_NT) k_qr(const QrOp* __restrict__ ops) {
   const QrOp op = ops[blockIdx.x];
   if (op.m > QR_MAX_M) {
     qr_unblocked(op);
+    return;
+  }
+  extern __shared__ char qr_smem[];
+  if (op.m * op.n <= kQrLdsElems) {
+    qr_lds(op, reinterpret_cast<z2*>(qr_smem));
     return;
   }
   const int m = op.m, n = op.n, k = m < n ? m : n;
