@@ -948,22 +948,27 @@ __device__ void qr_unblocked(const QrOp& op) {
 }
 
 
-// Column-by-column form with the whole matrix in LDS (m * n <= kQrLdsElems,
-// column-major): reflector j is formed by the wavefront that owns column j
-// (columns are dealt to the wavefronts in turn), then every wavefront applies
-// it to its own later columns (one wave reduction per column, no block
-// reduction); the orthonormal factor is formed in place in the same way
-// (LAPACK zung2r order).  Reflectors, taus, the rank rule and the phases of R
-// are those of the other forms; only the rounding order differs.
-constexpr int kQrLdsElems = QR_MAX_M * QR_PB;  // fits the kernel's dynamic LDS
+// Column-by-column form with the whole matrix in LDS (m <= kQrLdsMaxM,
+// m * n <= kQrLdsElems, column-major).  Columns are dealt to the wavefronts
+// in turn.  Every wavefront forms reflector j itself from column j (the same
+// arithmetic on the same data in each, so no broadcast is needed) and applies
+// it to its own later columns; one barrier per column (the owner writes the
+// finished column after it, once every wavefront has read the column).  The orthonormal
+// factor is formed column by column from the stored reflectors
+// (Q e_c = H_0 ... H_c e_c, the LAPACK zung2r result), each column by its
+// owner in registers, with no barrier.  A lane holds rows lane + 64 q
+// (q < RPL, m <= 64 RPL) of a column in registers.  Reflectors, taus, the
+// rank rule and the phases of R are those of the other forms; only the
+// rounding order differs.
+static_assert(kQrLdsElems * 16 <= 128 * 1024, "LDS form within the CU's LDS");
 
+template <int RPL>
 __device__ void qr_lds(const QrOp& op, z2* __restrict__ L) {
   const int m = op.m, n = op.n, k = m < n ? m : n;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   __shared__ double red[QR_NW];
   __shared__ z2 tauS[64];
   __shared__ double phS[2 * 64];
-  __shared__ int skipS;
   const gp<z2> C = gmem(reinterpret_cast<z2*>(op.C));
   const gp<z2> R = gmem(reinterpret_cast<z2*>(op.R));
   const int ppost = op.Ppost;
@@ -973,14 +978,20 @@ __device__ void qr_lds(const QrOp& op, z2* __restrict__ L) {
     const int q = qr_div(row, ppost, pinv);
     return q * cstride + (row - q * ppost);
   };
-  // C -> L and the Frobenius norm
+  // C -> L and the Frobenius norm (16 columns of a row read at once)
   double fro = 0;
   for (int row = tid; row < m; row += QR_NT) {
     const int cb = crow(row);
-    for (int c = 0; c < n; ++c) {
-      const z2 v = C[cb + c * ppost];
-      L[c * m + row] = v;
-      fro += v.r * v.r + v.i * v.i;
+    for (int c0 = 0; c0 < n; c0 += 16) {
+      z2 t[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) t[u] = c0 + u < n ? C[cb + (c0 + u) * ppost] : z2{0.0, 0.0};
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (c0 + u < n) {
+          L[(c0 + u) * m + row] = t[u];
+          fro += t[u].r * t[u].r + t[u].i * t[u].i;
+        }
     }
   }
   fro = wave_sum(fro);
@@ -990,70 +1001,113 @@ __device__ void qr_lds(const QrOp& op, z2* __restrict__ L) {
   for (int w = 0; w < QR_NW; ++w) fsum += red[w];
   // residual columns at or below this squared norm count as exact zeros
   const double thr2 = op.tol * op.tol * fsum;
-
-  for (int j = 0; j < k; ++j) {
-    z2* __restrict__ Lj = L + j * m;
-    if (wave == j % QR_NW) {  // reflector of column j (uniform per wavefront)
-      double xn2 = 0;
-      for (int r = j + 1 + lane; r < m; r += 64) {
-        const z2 x = Lj[r];
-        xn2 = fma(x.r, x.r, fma(x.i, x.i, xn2));
-      }
-      xn2 = wave_sum(xn2);
-      const z2 alpha = Lj[j];
-      z2 t{0.0, 0.0};
-      int skip;
-      if (alpha.r * alpha.r + alpha.i * alpha.i + xn2 <= thr2) {
-        // numerically zero residual: identity reflector, zero column
-        skip = 2;
-        for (int r = j + lane; r < m; r += 64) Lj[r] = z2{0.0, 0.0};
-      } else if (xn2 == 0.0 && alpha.i == 0.0) {
-        skip = 1;
-      } else {
-        skip = 0;
-        const double nrm = sqrt(alpha.r * alpha.r + alpha.i * alpha.i + xn2);
-        // beta = -sign(Re alpha) * nrm (LAPACK zlarfg; a zero counts as positive)
-        const double beta = alpha.r >= 0.0 ? -nrm : nrm;
-        t = z2{(beta - alpha.r) / beta, -alpha.i / beta};
-        const double dr = alpha.r - beta, di = alpha.i;
-        const double den = dr * dr + di * di;
-        const z2 sc{dr / den, -di / den};  // 1 / (alpha - beta)
-        for (int r = j + 1 + lane; r < m; r += 64) Lj[r] = zmul(Lj[r], sc);
-        if (lane == 0) Lj[j] = z2{beta, 0.0};
-      }
-      if (lane == 0) {
-        tauS[j] = t;
-        skipS = skip;
-        gmem(reinterpret_cast<z2*>(op.tau))[j] = t;
-      }
+  // rows r >= r0 of a column into registers (zeros elsewhere); row r0 reads
+  // as 1 when `unit` (the reflector's implicit leading entry)
+  auto ldcol = [&](const z2* Lc, int r0, bool unit, z2(&y)[RPL]) {
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const int r = lane + 64 * q;
+      y[q] = r >= r0 && r < m ? Lc[r] : z2{0.0, 0.0};
+      if (unit && r == r0) y[q] = z2{1.0, 0.0};
     }
-    __syncthreads();
-    if (skipS == 0) {
-      // H^H = I - conj(tau) v v^H on the later columns of this wavefront
-      const z2 t = tauS[j];
+  };
+  auto stcol = [&](z2* Lc, int r0, const z2(&y)[RPL]) {
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const int r = lane + 64 * q;
+      if (r >= r0 && r < m) Lc[r] = y[q];
+    }
+  };
+  // w = v^H y over the lane's rows, summed over the wavefront
+  auto vdot = [&](const z2(&v)[RPL], const z2(&y)[RPL]) {
+    double wr = 0, wi = 0;
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const z2 p = zconjmul(v[q], y[q]);
+      wr += p.r;
+      wi += p.i;
+    }
+    return z2{wave_sum(wr), wave_sum(wi)};
+  };
+  auto axpy = [&](z2(&y)[RPL], const z2(&v)[RPL], z2 f) {  // y -= f v
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const z2 pv = zmul(f, v[q]);
+      y[q] = z2{y[q].r - pv.r, y[q].i - pv.i};
+    }
+  };
+
+  // the owner's store of a finished column waits for the next barrier, so
+  // that every wavefront has read the column first
+  z2 pv[RPL];
+  int pj = -1;
+  for (int j = 0; j < k; ++j) {
+    if (pj >= 0) {
+      stcol(L + pj * m, pj, pv);
+      pj = -1;
+    }
+    z2* __restrict__ Lj = L + j * m;
+    z2 v[RPL];
+    ldcol(Lj, j, false, v);
+    double xn2 = 0;
+#pragma unroll
+    for (int q = 0; q < RPL; ++q)
+      if (lane + 64 * q > j) xn2 = fma(v[q].r, v[q].r, fma(v[q].i, v[q].i, xn2));
+    xn2 = wave_sum(xn2);
+    const z2 alpha = Lj[j];
+    const bool own_j = wave == j % QR_NW;
+    z2 t{0.0, 0.0};
+    bool apply = false;
+    if (alpha.r * alpha.r + alpha.i * alpha.i + xn2 <= thr2) {
+      // numerically zero residual: identity reflector, zero column
+      if (own_j) {
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) pv[q] = z2{0.0, 0.0};
+        pj = j;
+      }
+    } else if (!(xn2 == 0.0 && alpha.i == 0.0)) {
+      apply = true;
+      const double nrm = sqrt(alpha.r * alpha.r + alpha.i * alpha.i + xn2);
+      // beta = -sign(Re alpha) * nrm (LAPACK zlarfg; a zero counts as positive)
+      const double beta = alpha.r >= 0.0 ? -nrm : nrm;
+      t = z2{(beta - alpha.r) / beta, -alpha.i / beta};
+      const double dr = alpha.r - beta, di = alpha.i;
+      const double den = dr * dr + di * di;
+      const z2 sc{dr / den, -di / den};  // 1 / (alpha - beta)
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) {
+        const int r = lane + 64 * q;
+        v[q] = r == j ? z2{beta, 0.0} : zmul(v[q], sc);
+      }
+      if (own_j) {
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) pv[q] = v[q];
+        pj = j;
+      }
+#pragma unroll
+      for (int q = 0; q < RPL; ++q)
+        if (lane + 64 * q == j) v[q] = z2{1.0, 0.0};
+    }
+    if (own_j && lane == 0) {
+      tauS[j] = t;
+      gmem(reinterpret_cast<z2*>(op.tau))[j] = t;
+    }
+    if (apply) {
+      // H^H = I - conj(tau) v v^H on this wavefront's later columns
       const z2 ct{t.r, -t.i};
       for (int c = j + 1; c < n; ++c) {
         if (c % QR_NW != wave) continue;
         z2* __restrict__ Lc = L + c * m;
-        double wr = 0, wi = 0;
-        for (int r = j + lane; r < m; r += 64) {
-          const z2 v = r == j ? z2{1.0, 0.0} : Lj[r];
-          const z2 p = zconjmul(v, Lc[r]);
-          wr += p.r;
-          wi += p.i;
-        }
-        wr = wave_sum(wr);
-        wi = wave_sum(wi);
-        const z2 f = zmul(ct, z2{wr, wi});
-        for (int r = j + lane; r < m; r += 64) {
-          const z2 v = r == j ? z2{1.0, 0.0} : Lj[r];
-          const z2 pv = zmul(f, v);
-          Lc[r] = z2{Lc[r].r - pv.r, Lc[r].i - pv.i};
-        }
+        z2 y[RPL];
+        ldcol(Lc, j, false, y);
+        axpy(y, v, zmul(ct, vdot(v, y)));
+        stcol(Lc, j, y);
       }
     }
     __syncthreads();
   }
+  if (pj >= 0) stcol(L + pj * m, pj, pv);
+  __syncthreads();
   // phases that make diag(R) real non-negative; R with its rows rephased
   if (tid < n) {
     const z2 dd = tid < k ? L[tid * m + tid] : z2{0.0, 0.0};
@@ -1064,55 +1118,40 @@ __device__ void qr_lds(const QrOp& op, z2* __restrict__ L) {
   __syncthreads();
   for (int e = tid; e < n * n; e += QR_NT) {
     const int i = e / n, c = e % n;
-    const z2 v = (i <= c && i < k) ? zmul(z2{phS[2 * i], -phS[2 * i + 1]}, L[c * m + i])
+    const z2 x = (i <= c && i < k) ? zmul(z2{phS[2 * i], -phS[2 * i + 1]}, L[c * m + i])
                                    : z2{0.0, 0.0};
-    if (op.transposeR) R[c * n + i] = v;
-    else R[i * n + c] = v;
+    if (op.transposeR) R[c * n + i] = x;
+    else R[i * n + c] = x;
   }
-  __syncthreads();  // R is read out before Q overwrites it
-  // Q = H_0 ... H_{k-1} [I; 0], formed in place from the last reflector back
-  for (int i = k - 1; i >= 0; --i) {
-    const z2 t = tauS[i];
-    z2* __restrict__ Li = L + i * m;
-    if (t.r != 0.0 || t.i != 0.0) {
-      for (int c = i + 1; c < k; ++c) {
-        if (c % QR_NW != wave) continue;
-        z2* __restrict__ Lc = L + c * m;
-        double wr = 0, wi = 0;
-        for (int r = i + lane; r < m; r += 64) {
-          const z2 v = r == i ? z2{1.0, 0.0} : Li[r];
-          const z2 p = zconjmul(v, Lc[r]);
-          wr += p.r;
-          wi += p.i;
-        }
-        wr = wave_sum(wr);
-        wi = wave_sum(wi);
-        const z2 f = zmul(t, z2{wr, wi});
-        for (int r = i + lane; r < m; r += 64) {
-          const z2 v = r == i ? z2{1.0, 0.0} : Li[r];
-          const z2 pv = zmul(f, v);
-          Lc[r] = z2{Lc[r].r - pv.r, Lc[r].i - pv.i};
-        }
+  // Q column c = H_0 ... H_c e_c: e_c - tau_c v_c, then H_{c-1}, ..., H_0 in
+  // turn; the reflectors in L are only read from here on
+  for (int c = wave; c < k; c += QR_NW) {
+    z2 y[RPL];
+    {
+      z2 vc[RPL];
+      ldcol(L + c * m, c, true, vc);
+      const z2 tc = tauS[c];
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) {
+        const int r = lane + 64 * q;
+        const z2 p = zmul(tc, vc[q]);
+        y[q] = r >= c ? z2{(r == c ? 1.0 : 0.0) - p.r, -p.i} : z2{0.0, 0.0};
       }
     }
-    __syncthreads();  // every wavefront is done with v_i
-    if (wave == i % QR_NW) {
-      for (int r = lane; r < m; r += 64) {
-        z2 q{0.0, 0.0};
-        if (r == i) q = z2{1.0 - t.r, -t.i};
-        else if (r > i) {
-          const z2 p = zmul(t, Li[r]);
-          q = z2{-p.r, -p.i};
-        }
-        Li[r] = q;
-      }
+    for (int i = c - 1; i >= 0; --i) {
+      const z2 ti = tauS[i];
+      if (ti.r == 0.0 && ti.i == 0.0) continue;
+      z2 vi[RPL];
+      ldcol(L + i * m, i, true, vi);
+      axpy(y, vi, zmul(ti, vdot(vi, y)));
     }
-    __syncthreads();
-  }
-  // Q (m x k) into the core, with the phases of R
-  for (int row = tid; row < m; row += QR_NT) {
-    const int cb = crow(row);
-    for (int c = 0; c < k; ++c) C[cb + c * ppost] = zmul(L[c * m + row], z2{phS[2 * c], phS[2 * c + 1]});
+    // into the core, with the phase of R's row c
+    const z2 ph{phS[2 * c], phS[2 * c + 1]};
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const int r = lane + 64 * q;
+      if (r < m) C[crow(r) + c * ppost] = zmul(y[q], ph);
+    }
   }
 }
 
@@ -1120,11 +1159,6 @@ __global__ void __launch_bounds__(QR_NT) k_qr(const QrOp* __restrict__ ops) {
   const QrOp op = ops[blockIdx.x];
   if (op.m > QR_MAX_M) {
     qr_unblocked(op);
-    return;
-  }
-  extern __shared__ char qr_smem[];
-  if (op.m * op.n <= kQrLdsElems) {
-    qr_lds(op, reinterpret_cast<z2*>(qr_smem));
     return;
   }
   const int m = op.m, n = op.n, k = m < n ? m : n;
@@ -1448,6 +1482,16 @@ __global__ void __launch_bounds__(QR_NT) k_qr(const QrOp* __restrict__ ops) {
       }
     }
   }
+}
+
+// Launches whose every op fits the LDS form (m <= kQrLdsMaxM, m n <= kQrLdsElems).
+__global__ void __launch_bounds__(QR_NT) k_qr_lds(const QrOp* __restrict__ ops) {
+  const QrOp op = ops[blockIdx.x];
+  extern __shared__ char qr_smem[];
+  z2* L = reinterpret_cast<z2*>(qr_smem);
+  if (op.m <= 128) qr_lds<2>(op, L);  // uniform per workgroup
+  else if (op.m <= 256) qr_lds<4>(op, L);
+  else qr_lds<8>(op, L);
 }
 
 // ---------------------------------------------------------------------------
@@ -1999,15 +2043,18 @@ hipError_t launch_combine(int fp64, const CombineOp* ops, const void* tiles, int
   return hipGetLastError();
 }
 
-hipError_t launch_qr(const QrOp* ops, int n, hipStream_t s) {
+hipError_t launch_qr(const QrOp* ops, int n, int lds_form, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   static bool attr = false;
   if (!attr) {
     (void)hipFuncSetAttribute((const void*)k_qr, hipFuncAttributeMaxDynamicSharedMemorySize,
                               QR_MAX_M * QR_PB * 16);
+    (void)hipFuncSetAttribute((const void*)k_qr_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kQrLdsElems * 16);
     attr = true;
   }
-  hipLaunchKernelGGL(k_qr, dim3(n), dim3(QR_NT), QR_MAX_M * QR_PB * 16, s, ops);
+  if (lds_form) hipLaunchKernelGGL(k_qr_lds, dim3(n), dim3(QR_NT), kQrLdsElems * 16, s, ops);
+  else hipLaunchKernelGGL(k_qr, dim3(n), dim3(QR_NT), QR_MAX_M * QR_PB * 16, s, ops);
   return hipGetLastError();
 }
 

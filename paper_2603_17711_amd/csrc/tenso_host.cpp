@@ -31,7 +31,7 @@ hipError_t launch_split(const SplitOp* op, hipStream_t s);
 hipError_t launch_presum(int fp64, const PresumOp* ops, int n, const int* step_ctr, hipStream_t s);
 hipError_t launch_combine(int fp64, const CombineOp* ops, const void* tiles, int n_tiles,
                           hipStream_t s);
-hipError_t launch_qr(const QrOp* ops, int n, hipStream_t s);
+hipError_t launch_qr(const QrOp* ops, int n, int lds_form, hipStream_t s);
 hipError_t launch_absorb(const AbsorbOp* ops, const void* tiles, int n_tiles, size_t lds,
                          hipStream_t s);
 hipError_t launch_gram(int fp64, const GramOp* ops, int n, hipStream_t s);
@@ -1444,6 +1444,12 @@ static void upload_resolved(DevProgram& D, const Program& G, hipStream_t s,
   if (hold) hold->push_back(std::move(buf));
   else hipchk(hipStreamSynchronize(s), "sync upload");
   D.launches = G.launches;
+  for (auto& L : D.launches)  // QR launches: lds = 1 when every op fits the LDS form
+    if (L.kind == LK_QR) {
+      bool all = true;
+      for (int k = L.first; k < L.first + L.count; ++k) all = all && qr_lds_form(G.qrs[k]);
+      L.lds = all ? 1 : 0;
+    }
 }
 
 static void upload(DevProgram& D, const Program& G0, void* state, void* ws, double dt,
@@ -1634,7 +1640,7 @@ static void run(const DevProgram& D, int fp64, const int* ctr, hipStream_t s) {
                            (const CombineTileH*)(b + D.o_ctiles) + L.tfirst, L.tcount, s);
         break;
       case LK_QR:
-        e = launch_qr((const QrOp*)(b + D.o_qrs) + L.first, L.count, s);
+        e = launch_qr((const QrOp*)(b + D.o_qrs) + L.first, L.count, (int)L.lds, s);
         break;
       case LK_ABSORB:
         e = launch_absorb((const AbsorbOp*)(b + D.o_absorbs),
@@ -1851,7 +1857,7 @@ static int svd_truncate(const SvdScratch& sc, const double* theta, long rows, lo
       q.Ppost = m;
       q.transposeR = 0;
       q.tol = 0.0;
-      hipchk(launch_qr(svd_put(sc, 1, q, s, hold), 1, s), "svd qr");
+      hipchk(launch_qr(svd_put(sc, 1, q, s, hold), 1, qr_lds_form(q) ? 1 : 0, s), "svd qr");
     };
     // range finder on theta's column space, then the projection Z = theta^H Q
     gemm(0, nullptr, sc.y, true);

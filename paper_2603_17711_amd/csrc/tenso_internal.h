@@ -117,6 +117,12 @@ struct QrOp {
   double tol;          // relative rank threshold
 };
 
+// QR ops small enough to be factored with the whole matrix in LDS; a QR
+// launch whose every op qualifies runs the LDS form.
+constexpr int kQrLdsMaxM = 512;
+constexpr int kQrLdsElems = 8192;
+inline bool qr_lds_form(const QrOp& q) { return q.m <= kQrLdsMaxM && q.m * q.n <= kQrLdsElems; }
+
 // In-place mode product of an FP64 core with an n x n FP64 matrix on one leg:
 // C[pre, a, post] <- sum_a' Mx[a, a'] C[pre, a', post], Mx = M or M^T.
 struct AbsorbOp {
