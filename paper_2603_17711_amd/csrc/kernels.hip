@@ -948,8 +948,9 @@ __device__ void qr_unblocked(const QrOp& op) {
 }
 
 
-// Column-by-column form with the whole matrix in LDS (m <= kQrLdsMaxM,
-// m * n <= kQrLdsElems, column-major).  Columns are dealt to the wavefronts
+// Column-by-column form on a column-major working copy L of the matrix: in
+// LDS (m <= kQrLdsMaxM, m * n <= kQrLdsElems) or the scratch V in global
+// memory (m <= QR_MAX_M; V apart from C).  Columns are dealt to the wavefronts
 // in turn.  Every wavefront forms reflector j itself from column j (the same
 // arithmetic on the same data in each, so no broadcast is needed) and applies
 // it to its own later columns; one barrier per column (the owner writes the
@@ -961,9 +962,11 @@ __device__ void qr_unblocked(const QrOp& op) {
 // rank rule and the phases of R are those of the other forms; only the
 // rounding order differs.
 static_assert(kQrLdsElems * 16 <= 128 * 1024, "LDS form within the CU's LDS");
+// The same algorithm runs on the scratch copy V in global memory (L2
+// resident) for the larger ops, m <= QR_MAX_M.
 
-template <int RPL>
-__device__ void qr_lds(const QrOp& op, z2* __restrict__ L) {
+template <int RPL, typename ZP>
+__device__ void qr_cols(const QrOp& op, ZP L) {
   const int m = op.m, n = op.n, k = m < n ? m : n;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   __shared__ double red[QR_NW];
@@ -979,6 +982,7 @@ __device__ void qr_lds(const QrOp& op, z2* __restrict__ L) {
     return q * cstride + (row - q * ppost);
   };
   // C -> L and the Frobenius norm (16 columns of a row read at once)
+  __syncthreads();  // a previous op of this workgroup no longer reads L
   double fro = 0;
   for (int row = tid; row < m; row += QR_NT) {
     const int cb = crow(row);
@@ -1003,7 +1007,7 @@ __device__ void qr_lds(const QrOp& op, z2* __restrict__ L) {
   const double thr2 = op.tol * op.tol * fsum;
   // rows r >= r0 of a column into registers (zeros elsewhere); row r0 reads
   // as 1 when `unit` (the reflector's implicit leading entry)
-  auto ldcol = [&](const z2* Lc, int r0, bool unit, z2(&y)[RPL]) {
+  auto ldcol = [&](ZP Lc, int r0, bool unit, z2(&y)[RPL]) {
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
       const int r = lane + 64 * q;
@@ -1011,7 +1015,7 @@ __device__ void qr_lds(const QrOp& op, z2* __restrict__ L) {
       if (unit && r == r0) y[q] = z2{1.0, 0.0};
     }
   };
-  auto stcol = [&](z2* Lc, int r0, const z2(&y)[RPL]) {
+  auto stcol = [&](ZP Lc, int r0, const z2(&y)[RPL]) {
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
       const int r = lane + 64 * q;
@@ -1029,6 +1033,20 @@ __device__ void qr_lds(const QrOp& op, z2* __restrict__ L) {
     }
     return z2{wave_sum(wr), wave_sum(wi)};
   };
+  // v^H ya and v^H yb: the four wave reductions are independent chains
+  auto vdot2 = [&](const z2(&v)[RPL], const z2(&ya)[RPL], const z2(&yb)[RPL], z2& da, z2& db) {
+    double ar = 0, ai = 0, br = 0, bi = 0;
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const z2 pa = zconjmul(v[q], ya[q]), pb = zconjmul(v[q], yb[q]);
+      ar += pa.r;
+      ai += pa.i;
+      br += pb.r;
+      bi += pb.i;
+    }
+    da = z2{wave_sum(ar), wave_sum(ai)};
+    db = z2{wave_sum(br), wave_sum(bi)};
+  };
   auto axpy = [&](z2(&y)[RPL], const z2(&v)[RPL], z2 f) {  // y -= f v
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
@@ -1037,17 +1055,27 @@ __device__ void qr_lds(const QrOp& op, z2* __restrict__ L) {
     }
   };
 
-  // the owner's store of a finished column waits for the next barrier, so
-  // that every wavefront has read the column first
-  z2 pv[RPL];
-  int pj = -1;
-  for (int j = 0; j < k; ++j) {
-    if (pj >= 0) {
-      stcol(L + pj * m, pj, pv);
-      pj = -1;
+  // The owner's store of a finished column waits for the next barrier, so
+  // that every wavefront has read the column first: the owner keeps the
+  // reflector in v (unit leading entry) and writes it with beta in front.
+  z2 v[RPL];
+  int pj = -1;       // column whose store is pending (-1: none)
+  double pbeta = 0;  // its diagonal entry; pzero: the column is zero
+  bool pzero = false;
+  auto flush = [&]() {
+    if (pj < 0) return;
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const int r = lane + 64 * q;
+      if (pzero) v[q] = z2{0.0, 0.0};
+      else if (r == pj) v[q] = z2{pbeta, 0.0};
     }
-    z2* __restrict__ Lj = L + j * m;
-    z2 v[RPL];
+    stcol(L + pj * m, pj, v);
+    pj = -1;
+  };
+  for (int j = 0; j < k; ++j) {
+    flush();
+    ZP Lj = L + j * m;
     ldcol(Lj, j, false, v);
     double xn2 = 0;
 #pragma unroll
@@ -1061,9 +1089,8 @@ __device__ void qr_lds(const QrOp& op, z2* __restrict__ L) {
     if (alpha.r * alpha.r + alpha.i * alpha.i + xn2 <= thr2) {
       // numerically zero residual: identity reflector, zero column
       if (own_j) {
-#pragma unroll
-        for (int q = 0; q < RPL; ++q) pv[q] = z2{0.0, 0.0};
         pj = j;
+        pzero = true;
       }
     } else if (!(xn2 == 0.0 && alpha.i == 0.0)) {
       apply = true;
@@ -1080,9 +1107,9 @@ __device__ void qr_lds(const QrOp& op, z2* __restrict__ L) {
         v[q] = r == j ? z2{beta, 0.0} : zmul(v[q], sc);
       }
       if (own_j) {
-#pragma unroll
-        for (int q = 0; q < RPL; ++q) pv[q] = v[q];
         pj = j;
+        pbeta = beta;
+        pzero = false;
       }
 #pragma unroll
       for (int q = 0; q < RPL; ++q)
@@ -1095,9 +1122,21 @@ __device__ void qr_lds(const QrOp& op, z2* __restrict__ L) {
     if (apply) {
       // H^H = I - conj(tau) v v^H on this wavefront's later columns
       const z2 ct{t.r, -t.i};
-      for (int c = j + 1; c < n; ++c) {
-        if (c % QR_NW != wave) continue;
-        z2* __restrict__ Lc = L + c * m;
+      int c = j + 1 + ((wave - (j + 1)) % QR_NW + QR_NW) % QR_NW;  // first own column
+      // two columns at a time where the registers allow
+      for (; RPL <= 4 && c + QR_NW < n; c += 2 * QR_NW) {
+        ZP La = L + c * m, Lb = L + (c + QR_NW) * m;
+        z2 ya[RPL], yb[RPL], da, db;
+        ldcol(La, j, false, ya);
+        ldcol(Lb, j, false, yb);
+        vdot2(v, ya, yb, da, db);
+        axpy(ya, v, zmul(ct, da));
+        axpy(yb, v, zmul(ct, db));
+        stcol(La, j, ya);
+        stcol(Lb, j, yb);
+      }
+      for (; c < n; c += QR_NW) {
+        ZP Lc = L + c * m;
         z2 y[RPL];
         ldcol(Lc, j, false, y);
         axpy(y, v, zmul(ct, vdot(v, y)));
@@ -1106,7 +1145,7 @@ __device__ void qr_lds(const QrOp& op, z2* __restrict__ L) {
     }
     __syncthreads();
   }
-  if (pj >= 0) stcol(L + pj * m, pj, pv);
+  flush();
   __syncthreads();
   // phases that make diag(R) real non-negative; R with its rows rephased
   if (tid < n) {
@@ -1124,38 +1163,81 @@ __device__ void qr_lds(const QrOp& op, z2* __restrict__ L) {
     else R[i * n + c] = x;
   }
   // Q column c = H_0 ... H_c e_c: e_c - tau_c v_c, then H_{c-1}, ..., H_0 in
-  // turn; the reflectors in L are only read from here on
-  for (int c = wave; c < k; c += QR_NW) {
-    z2 y[RPL];
-    {
-      z2 vc[RPL];
-      ldcol(L + c * m, c, true, vc);
-      const z2 tc = tauS[c];
+  // turn; the reflectors in L are only read from here on.  For m <= 256 a
+  // wavefront builds its columns two at a time (ca < cb): cb alone down to
+  // H_ca, then both from H_{ca-1}, each reflector read once for the two.
+  auto qinit = [&](int c, z2(&y)[RPL]) {
+    z2 vc[RPL];
+    ldcol(L + c * m, c, true, vc);
+    const z2 tc = tauS[c];
 #pragma unroll
-      for (int q = 0; q < RPL; ++q) {
-        const int r = lane + 64 * q;
-        const z2 p = zmul(tc, vc[q]);
-        y[q] = r >= c ? z2{(r == c ? 1.0 : 0.0) - p.r, -p.i} : z2{0.0, 0.0};
-      }
+    for (int q = 0; q < RPL; ++q) {
+      const int r = lane + 64 * q;
+      const z2 p = zmul(tc, vc[q]);
+      y[q] = r >= c ? z2{(r == c ? 1.0 : 0.0) - p.r, -p.i} : z2{0.0, 0.0};
     }
-    for (int i = c - 1; i >= 0; --i) {
-      const z2 ti = tauS[i];
-      if (ti.r == 0.0 && ti.i == 0.0) continue;
-      z2 vi[RPL];
-      ldcol(L + i * m, i, true, vi);
-      axpy(y, vi, zmul(ti, vdot(vi, y)));
-    }
-    // into the core, with the phase of R's row c
+  };
+  auto qstore = [&](int c, const z2(&y)[RPL]) {  // with the phase of R's row c
     const z2 ph{phS[2 * c], phS[2 * c + 1]};
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
       const int r = lane + 64 * q;
       if (r < m) C[crow(r) + c * ppost] = zmul(y[q], ph);
     }
+  };
+  for (int ca = wave; ca < k; ca += (RPL <= 4 ? 2 : 1) * QR_NW) {
+    const int cb = ca + QR_NW;
+    z2 ya[RPL];
+    if (RPL <= 4 && cb < k) {
+      z2 yb[RPL];
+      qinit(cb, yb);
+      for (int i = cb - 1; i >= ca; --i) {
+        const z2 ti = tauS[i];
+        if (ti.r == 0.0 && ti.i == 0.0) continue;
+        z2 vi[RPL];
+        ldcol(L + i * m, i, true, vi);
+        axpy(yb, vi, zmul(ti, vdot(vi, yb)));
+      }
+      qinit(ca, ya);
+      for (int i = ca - 1; i >= 0; --i) {
+        const z2 ti = tauS[i];
+        if (ti.r == 0.0 && ti.i == 0.0) continue;
+        z2 vi[RPL], da, db;
+        ldcol(L + i * m, i, true, vi);
+        vdot2(vi, ya, yb, da, db);
+        axpy(ya, vi, zmul(ti, da));
+        axpy(yb, vi, zmul(ti, db));
+      }
+      qstore(cb, yb);
+    } else {
+      qinit(ca, ya);
+      for (int i = ca - 1; i >= 0; --i) {
+        const z2 ti = tauS[i];
+        if (ti.r == 0.0 && ti.i == 0.0) continue;
+        z2 vi[RPL];
+        ldcol(L + i * m, i, true, vi);
+        axpy(ya, vi, zmul(ti, vdot(vi, ya)));
+      }
+    }
+    qstore(ca, ya);
   }
 }
 
 __global__ void __launch_bounds__(QR_NT) k_qr(const QrOp* __restrict__ ops) {
+  const QrOp op = ops[blockIdx.x];
+  if (op.m > QR_MAX_M) {
+    qr_unblocked(op);
+    return;
+  }
+  const gp<z2> V = gmem(reinterpret_cast<z2*>(op.V));
+  if (op.m <= 128) qr_cols<2>(op, V);  // uniform per workgroup
+  else if (op.m <= 256) qr_cols<4>(op, V);
+  else qr_cols<8>(op, V);
+}
+
+// Launches with an op taller than kQrLdsMaxM: the blocked form (and the
+// column-by-column form in global memory above QR_MAX_M).
+__global__ void __launch_bounds__(QR_NT) k_qr_blocked(const QrOp* __restrict__ ops) {
   const QrOp op = ops[blockIdx.x];
   if (op.m > QR_MAX_M) {
     qr_unblocked(op);
@@ -1489,9 +1571,9 @@ __global__ void __launch_bounds__(QR_NT) k_qr_lds(const QrOp* __restrict__ ops) 
   const QrOp op = ops[blockIdx.x];
   extern __shared__ char qr_smem[];
   z2* L = reinterpret_cast<z2*>(qr_smem);
-  if (op.m <= 128) qr_lds<2>(op, L);  // uniform per workgroup
-  else if (op.m <= 256) qr_lds<4>(op, L);
-  else qr_lds<8>(op, L);
+  if (op.m <= 128) qr_cols<2>(op, L);  // uniform per workgroup
+  else if (op.m <= 256) qr_cols<4>(op, L);
+  else qr_cols<8>(op, L);
 }
 
 // ---------------------------------------------------------------------------
@@ -2043,18 +2125,19 @@ hipError_t launch_combine(int fp64, const CombineOp* ops, const void* tiles, int
   return hipGetLastError();
 }
 
-hipError_t launch_qr(const QrOp* ops, int n, int lds_form, hipStream_t s) {
+hipError_t launch_qr(const QrOp* ops, int n, int form, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   static bool attr = false;
   if (!attr) {
-    (void)hipFuncSetAttribute((const void*)k_qr, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              QR_MAX_M * QR_PB * 16);
     (void)hipFuncSetAttribute((const void*)k_qr_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
                               kQrLdsElems * 16);
+    (void)hipFuncSetAttribute((const void*)k_qr_blocked,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, QR_MAX_M * QR_PB * 16);
     attr = true;
   }
-  if (lds_form) hipLaunchKernelGGL(k_qr_lds, dim3(n), dim3(QR_NT), kQrLdsElems * 16, s, ops);
-  else hipLaunchKernelGGL(k_qr, dim3(n), dim3(QR_NT), QR_MAX_M * QR_PB * 16, s, ops);
+  if (form == kQrFormLds) hipLaunchKernelGGL(k_qr_lds, dim3(n), dim3(QR_NT), kQrLdsElems * 16, s, ops);
+  else if (form == kQrFormColumns) hipLaunchKernelGGL(k_qr, dim3(n), dim3(QR_NT), 0, s, ops);
+  else hipLaunchKernelGGL(k_qr_blocked, dim3(n), dim3(QR_NT), QR_MAX_M * QR_PB * 16, s, ops);
   return hipGetLastError();
 }
 

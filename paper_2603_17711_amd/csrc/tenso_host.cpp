@@ -31,7 +31,7 @@ hipError_t launch_split(const SplitOp* op, hipStream_t s);
 hipError_t launch_presum(int fp64, const PresumOp* ops, int n, const int* step_ctr, hipStream_t s);
 hipError_t launch_combine(int fp64, const CombineOp* ops, const void* tiles, int n_tiles,
                           hipStream_t s);
-hipError_t launch_qr(const QrOp* ops, int n, int lds_form, hipStream_t s);
+hipError_t launch_qr(const QrOp* ops, int n, int form, hipStream_t s);
 hipError_t launch_absorb(const AbsorbOp* ops, const void* tiles, int n_tiles, size_t lds,
                          hipStream_t s);
 hipError_t launch_gram(int fp64, const GramOp* ops, int n, hipStream_t s);
@@ -1217,8 +1217,6 @@ struct Builder {
     q.Ppost = (int)prod(d, leg + 1, (int)d.size());
     q.transposeR = transposeR;
     q.tol = kQrRankTol;
-    // the core is already column-major m x n: factor it in place
-    if (q.Ppost == q.m && q.m <= kQrBlockedMaxM) q.V = q.C;
     if (q.m < q.n) fail(TENSO_EUNSUPPORTED, "QR with fewer rows than columns");
     if (q.n > 64) fail(TENSO_EUNSUPPORTED, "QR of a bond wider than 64");
     int qi = (int)G.qrs.size();
@@ -1444,11 +1442,11 @@ static void upload_resolved(DevProgram& D, const Program& G, hipStream_t s,
   if (hold) hold->push_back(std::move(buf));
   else hipchk(hipStreamSynchronize(s), "sync upload");
   D.launches = G.launches;
-  for (auto& L : D.launches)  // QR launches: lds = 1 when every op fits the LDS form
+  for (auto& L : D.launches)  // QR launches: lds holds the form that serves every op
     if (L.kind == LK_QR) {
-      bool all = true;
-      for (int k = L.first; k < L.first + L.count; ++k) all = all && qr_lds_form(G.qrs[k]);
-      L.lds = all ? 1 : 0;
+      int f = kQrFormLds;
+      for (int k = L.first; k < L.first + L.count; ++k) f = qr_form_join(f, qr_form(G.qrs[k]));
+      L.lds = (size_t)f;
     }
 }
 
@@ -1850,14 +1848,14 @@ static int svd_truncate(const SvdScratch& sc, const double* theta, long rows, lo
       QrOp q{};
       q.C = A;
       q.R = sc.r;
-      q.V = m <= kQrBlockedMaxM ? A : sc.qrv;
+      q.V = sc.qrv;
       q.tau = sc.tau;
       q.m = m;
       q.n = p;
       q.Ppost = m;
       q.transposeR = 0;
       q.tol = 0.0;
-      hipchk(launch_qr(svd_put(sc, 1, q, s, hold), 1, qr_lds_form(q) ? 1 : 0, s), "svd qr");
+      hipchk(launch_qr(svd_put(sc, 1, q, s, hold), 1, qr_form(q), s), "svd qr");
     };
     // range finder on theta's column space, then the projection Z = theta^H Q
     gemm(0, nullptr, sc.y, true);

@@ -99,8 +99,9 @@ struct CombineOp {
 // (other legs, row-major) x (leg of dim n); Q replaces the core in place.
 // The m x n matrix element (row = pre*Ppost + post, col) sits at
 // pre*n*Ppost + col*Ppost + post.
-// Tallest QR factored by the blocked kernel (taller ones take the
-// column-by-column form, which needs V apart from C).
+// Tallest QR whose columns are worked on in registers (taller ones take a
+// form with every row loop in global memory).  Every form works on the
+// scratch V, apart from C.
 constexpr int kQrBlockedMaxM = 1024;
 
 // Residual columns at or below tol * ||A||_F count as exact zeros (identity
@@ -111,17 +112,27 @@ constexpr double kQrRankTol = 1e-10;
 struct QrOp {
   double* C;           // FP64 complex core
   double* R;           // out: n x n (or its transpose when transposeR)
-  double* V;           // scratch m x n complex (may be C when Ppost == m <= kQrBlockedMaxM)
+  double* V;           // scratch m x n complex, apart from C
   double* tau;         // scratch n complex
   int m, n, Ppost, transposeR;
   double tol;          // relative rank threshold
 };
 
-// QR ops small enough to be factored with the whole matrix in LDS; a QR
-// launch whose every op qualifies runs the LDS form.
+// Forms of a QR launch, chosen from its ops: the whole matrix in LDS (every
+// op m <= kQrLdsMaxM and m n <= kQrLdsElems), column by column on the scratch
+// copy (every op m <= kQrLdsMaxM), or blocked (any taller op).
 constexpr int kQrLdsMaxM = 512;
 constexpr int kQrLdsElems = 8192;
-inline bool qr_lds_form(const QrOp& q) { return q.m <= kQrLdsMaxM && q.m * q.n <= kQrLdsElems; }
+enum { kQrFormColumns = 0, kQrFormLds = 1, kQrFormBlocked = 2 };
+inline int qr_form(const QrOp& q) {
+  if (q.m > kQrLdsMaxM) return kQrFormBlocked;
+  return q.m * q.n <= kQrLdsElems ? kQrFormLds : kQrFormColumns;
+}
+// the form that serves every op of a launch
+inline int qr_form_join(int a, int b) {
+  if (a == kQrFormBlocked || b == kQrFormBlocked) return kQrFormBlocked;
+  return (a == kQrFormLds && b == kQrFormLds) ? kQrFormLds : kQrFormColumns;
+}
 
 // In-place mode product of an FP64 core with an n x n FP64 matrix on one leg:
 // C[pre, a, post] <- sum_a' Mx[a, a'] C[pre, a', post], Mx = M or M^T.
