@@ -26,8 +26,8 @@ COPY_PROBE_BYTES = 256 << 20
 # (KiB), each scaled by what the counter reads for the copy probe of known size.
 # Reported only while the kernel sources are the ones the counters were taken on.
 HBM_COUNTERS = {
-    "sources_sha256": "d98d0b9d85b16178baff138ba2493adab570ef681c6c13cdc15e9b436c711e7b",
-    "fetch_kib": 8796.0, "write_kib": 16965.8, "fetch_scale": 2.000, "write_scale": 1.000,
+    "sources_sha256": "11b8294ed81ce412233bb0642a2f111a4f53e8d06ed381127fae60846e4eeff2",
+    "fetch_kib": 10522.1, "write_kib": 20753.4, "fetch_scale": 2.000, "write_scale": 1.000,
 }
 KERNEL_SOURCES = ("paper_2603_17711_amd/csrc/kernels.hip", "paper_2603_17711_amd/csrc/tenso_internal.h")
 
