@@ -18,7 +18,8 @@ def build(inst, rank=None):
         baths.append((b.Q, bath_features(b.T, dl=b.dl, bo=b.bo, n_ltc=b.n_ltc,
                                          method=getattr(b, "decomposition", "matsubara"))))
     drives = [] if inst.drive is None else [(0, inst.drive[0])]
-    terms, dims = heom_terms(inst.H, baths, inst.depth, drives=drives)
+    terms, dims = heom_terms(inst.H, baths, inst.depth, drives=drives,
+                             metric=getattr(inst, "metric", "abs"))
     K = len(dims) - 2
     R = inst.rank if rank is None else rank
     if inst.method == "ps2":

@@ -11,10 +11,17 @@ A^< B = B A^dagger acts on the bra leg with matrix conj(A).
 Ends (open legs) are numbered 0 = ket (dim M), 1 = bra (dim M), 2 + k = feature k
 (dim N_k, number basis n = 0..N_k - 1).
 
-Metric (reading; the listing that defines it is elided): z_k = f_k * identity
-with f_k = sqrt((|c_k| + |cbar_k|) / 2), TENSO's 'abs' option (Sec. VII D).
+Metric (Sec. VII D, reading): z_k = f_k * identity on feature k, with
+* 'abs' (the default here): f_k = sqrt((|c_k| + |cbar_k|) / 2);
+* 're': f_k = sqrt(|Re c_k + Re cbar_k| / 2), with its sign flipped when
+  Im c_k + Im cbar_k exceeds METRIC_EPS (the listing's threshold is not
+  printed; a round-off level is taken);
+* a complex constant: f_k equal to it for every feature.
 Then <n+1| z^-1 a^dag |n> = sqrt(n+1) / f_k and <n| a z |n+1> = f_k sqrt(n+1).
-A feature with zero coefficients takes f_k = 1.
+A feature whose factor comes out zero takes f_k = 1.  Every choice is a
+similarity transform of the hierarchy that leaves the n = 0 component, and so
+rho_S, unchanged, also at finite depth (the transform maps the truncated
+subspace onto itself).
 
 A term is a dict {'coef': complex, 'slot': int, 'factors': {end: matrix}}; a
 term with slot >= 0 is multiplied by the drive value f_slot(t).  Ends missing
@@ -29,11 +36,37 @@ import numpy as np
 import scipy.sparse as sp
 
 
+METRIC_EPS = 1e-14
+
+
 def metric_abs(c, cbar):
     """TENSO 'abs' metric factor f_k = sqrt((|c_k| + |cbar_k|)/2); a feature
     with c_k = cbar_k = 0 (no coupling) takes f_k = 1, any metric being valid."""
     f = np.sqrt((np.abs(c) + np.abs(cbar)) / 2.0)
     return np.where(f > 0.0, f, 1.0)
+
+
+def metric_re(c, cbar):
+    """TENSO 're' metric factor f_k = sqrt(|Re c_k + Re cbar_k| / 2), negated when
+    Im c_k + Im cbar_k > METRIC_EPS; zero becomes 1."""
+    c, cbar = np.asarray(c), np.asarray(cbar)
+    f = np.sqrt(np.abs(c.real + cbar.real) / 2.0)
+    f = np.where(c.imag + cbar.imag > METRIC_EPS, -f, f)
+    return np.where(f != 0.0, f, 1.0)
+
+
+def metric_factors(metric, c, cbar):
+    """Per-feature factors for a metric choice: 'abs', 're', a complex constant,
+    or an explicit array of factors."""
+    if metric is None or (isinstance(metric, str) and metric == 'abs'):
+        return metric_abs(c, cbar)
+    if isinstance(metric, str) and metric == 're':
+        return metric_re(c, cbar)
+    if np.isscalar(metric):
+        if metric == 0:
+            raise ValueError("a metric factor must be nonzero")
+        return np.full(len(np.atleast_1d(c)), complex(metric))
+    return np.asarray(metric)
 
 
 def raising(N, f):
@@ -63,7 +96,8 @@ def heom_terms(H, baths, depth, drives=(), metric=None):
     baths  : list of (Q, (c, cbar, gamma)) -- one coupling operator per bath
     depth  : int or per-feature list, N_k = dimension of feature k
     drives : list of (slot, H_d) time-dependent Hamiltonian terms f_slot(t) H_d
-    metric : None for 'abs', or an array of per-feature factors f_k
+    metric : None or 'abs', 're', a complex constant, or an array of
+             per-feature factors f_k
     Returns (terms, end_dims).
     """
     H = np.asarray(H, dtype=np.complex128)
@@ -74,8 +108,8 @@ def heom_terms(H, baths, depth, drives=(), metric=None):
             feats.append((np.asarray(Q, dtype=np.complex128), c[k], cb[k], g[k]))
     K = len(feats)
     dims = [depth] * K if np.isscalar(depth) else list(depth)
-    if metric is None:
-        fk = [metric_abs(c, cb) for (_, c, cb, _) in feats]
+    if metric is None or isinstance(metric, str) or np.isscalar(metric):
+        fk = [metric_factors(metric, np.array([c]), np.array([cb]))[0] for (_, c, cb, _) in feats]
     else:
         fk = list(metric)
     terms = []

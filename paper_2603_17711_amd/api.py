@@ -243,7 +243,8 @@ def build_instance(inst, precision=FP32, rank=None, device="cuda"):
     """Tree + generator + plan for a workloads.Instance (ps1, or ps2 when
     inst.method == "ps2": `rank` is then the rank cap)."""
     drive_ops = [] if inst.drive is None else [inst.drive[0]]
-    table, dims = heom_table(inst.H, inst.baths, inst.depth, drive_ops)
+    table, dims = heom_table(inst.H, inst.baths, inst.depth, drive_ops,
+                             metric=getattr(inst, "metric", "abs"))
     R = inst.rank if rank is None else rank
     if inst.tree == "train":
         tree = Tree.train(inst.M, dims, R)

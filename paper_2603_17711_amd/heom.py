@@ -1,7 +1,10 @@
 """SOP term table of the bexcitonic HEOM for the C ABI (paper Eqs. heom-std,
 dissipator, master_lvn).
 
-Per feature k (bath coupling Q, metric factor f_k = sqrt((|c_k|+|cbar_k|)/2)):
+Per feature k (bath coupling Q, metric factor f_k of Sec. VII D: 'abs'
+f_k = sqrt((|c_k|+|cbar_k|)/2), 're' f_k = +-sqrt(|Re c_k + Re cbar_k|/2) with
+the sign negative when Im c_k + Im cbar_k > 1e-14, or one complex constant;
+a zero factor becomes 1):
   gamma_k n_k ; c_k Q> (x) a+_k/f_k ; -cbar_k Q< (x) a+_k/f_k ;
   -Q> (x) f_k a_k ; +Q< (x) f_k a_k
 plus -i H> and +i H< (and -i f(t) Hd>, +i f(t) Hd< per drive slot), where
@@ -36,8 +39,30 @@ class TermTable:
         return len(self.coef)
 
 
-def heom_table(H, baths, depth, drive_ops=()):
-    """baths: list of workloads.Bath-like objects (Q, T, dl, bo, n_ltc).
+_METRIC_EPS = 1e-14
+
+
+def metric_factor(metric, c, cb):
+    """f_k for one feature."""
+    if isinstance(metric, str):
+        if metric == "abs":
+            f = np.sqrt((abs(c) + abs(cb)) / 2.0)
+        elif metric == "re":
+            f = np.sqrt(abs(c.real + cb.real) / 2.0)
+            if c.imag + cb.imag > _METRIC_EPS:
+                f = -f
+        else:
+            raise ValueError(f"unknown metric {metric!r}")
+    else:
+        f = complex(metric)
+        if f == 0:
+            raise ValueError("a metric factor must be nonzero")
+    return 1.0 if f == 0 else f
+
+
+def heom_table(H, baths, depth, drive_ops=(), metric="abs"):
+    """baths: list of workloads.Bath-like objects (Q, T, dl, bo, n_ltc);
+    metric: "abs", "re" or a complex constant (Sec. VII D).
     Returns (TermTable, feature dims)."""
     H = np.asarray(H, dtype=np.complex128)
     tab = TermTable()
@@ -51,9 +76,7 @@ def heom_table(H, baths, depth, drive_ops=()):
         Q = np.asarray(b.Q, dtype=np.complex128)
         for j in range(len(c)):
             N = depth if np.isscalar(depth) else depth[k]
-            f = np.sqrt((abs(c[j]) + abs(cb[j])) / 2.0)
-            if f == 0.0:
-                f = 1.0
+            f = metric_factor(metric, complex(c[j]), complex(cb[j]))
             n = np.arange(N, dtype=float)
             num = np.diag(n).astype(np.complex128)
             up = np.diag(np.sqrt(n[1:]) / f, -1).astype(np.complex128)

@@ -62,6 +62,8 @@ def workload_digest(insts):
                 h.update(b.decomposition.encode())
         h.update(repr((inst.depth, inst.tree, inst.rank, inst.dt, inst.method, inst.eps,
                        None if inst.drive is None else inst.drive[1:])).encode())
+        if getattr(inst, "metric", "abs") != "abs":
+            h.update(repr(inst.metric).encode())
     return h.hexdigest()
 
 

@@ -32,7 +32,7 @@ hipError_t launch_svd_finish(const SvdFinishOp*, long, hipStream_t) STUB()
 hipError_t launch_split(const SplitOp*, hipStream_t) STUB()
 hipError_t launch_presum(int, const PresumOp*, int, const int*, hipStream_t) STUB()
 hipError_t launch_combine(int, const CombineOp*, const void*, int, hipStream_t) STUB()
-hipError_t launch_qr(const QrOp*, int, hipStream_t) STUB()
+hipError_t launch_qr(const QrOp*, int, int, hipStream_t) STUB()
 hipError_t launch_absorb(const AbsorbOp*, const void*, int, size_t, hipStream_t) STUB()
 hipError_t launch_gram(int, const GramOp*, int, hipStream_t) STUB()
 hipError_t launch_rho(const RhoProg*, int, hipStream_t) STUB()

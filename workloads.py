@@ -41,7 +41,7 @@ class Instance:
     """One TTN-HEOM problem."""
 
     def __init__(self, name, H, baths, depth, tree, rank, rho0, dt, n_steps,
-                 method="ps1", eps=0.0, drive=None):
+                 method="ps1", eps=0.0, drive=None, metric="abs"):
         self.name = name
         self.H = np.asarray(H, dtype=np.complex128)
         self.baths = baths
@@ -54,6 +54,7 @@ class Instance:
         self.method = method
         self.eps = eps
         self.drive = drive        # None or (H_d, A, w, s, t0)
+        self.metric = metric      # HEOM metric: "abs", "re" or a complex constant
 
     @property
     def M(self):
