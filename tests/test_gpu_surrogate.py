@@ -15,8 +15,16 @@ def test_surrogate_pipeline_small():
     print("[surrogate] 384 training + 32 held-out trajectories x 2000 steps", flush=True)
     r = S.experiment(n_train=384, n_held=32, epochs=8)
     print("  ", {k: (round(v, 5) if isinstance(v, float) else v) for k, v in r.items()})
+    print(f"  gain {r['gain']:.3f} (TTN-HEOM {r['ttn_heldout_s']:.3f} s against the surrogate's "
+          f"{r['surrogate_s']:.3f} s, spot checks {r['spot_s']:.3f} s); median feature error "
+          f"{r['median_feature_error']:.2e}, monitor bar 1e-3, trips {r['monitor_trips']}")
     assert r["train_mse_first_last"][1] < r["train_mse_first_last"][0]
     assert np.isfinite(r["max_feature_error"])
+    # the gain charges the rollout, the TTN warm-up windows, the spot checks and
+    # the fallback runs; tripped spot-checked trajectories reuse their TTN run
+    expect = r["rollout_s"] + r["ttn_heldout_s"] * 16 / (r["steps"] // 10 + 1) + r["spot_s"]
+    assert r["surrogate_s"] >= expect - 1e-9
+    assert abs(r["gain"] - r["ttn_heldout_s"] / r["surrogate_s"]) < 1e-12
 
 
 def test_forced_monitor_trip_runs_the_ttn_fallback():
