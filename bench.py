@@ -46,6 +46,7 @@ def measured_traffic():
 
 
 WORKLOADS = ["batch512", "spin-boson-train", "exciton-7site", "ps2-structured-ternary",
+             "tfd-mctdh",
              "surrogate"]
 
 
@@ -58,6 +59,7 @@ def parse():
                     help="batch512 (default): 512 uneven instances, ps1, batched; "
                          "spin-boson-train, exciton-7site: single ps1 instances; "
                          "ps2-structured-ternary: ps2 on the structured-bath ternary tree; "
+                         "tfd-mctdh: the thermofield ML-MCTDH listing (wavefunction TTN); "
                          "surrogate: the learned-surrogate pipeline")
     ap.add_argument("--instances", type=int, default=512, help="batch size for batch512")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -524,6 +526,87 @@ def surrogate_main(a):
     print(json.dumps(out))
 
 
+def tfd_main(a):
+    """The thermofield ML-MCTDH listing (Sec. III A 5): 50 star modes of Fock
+    dimension 8 on a binary tree of rank 16, a wavefunction under -iH, ps1 with
+    1 fs steps; one instance."""
+    import ctypes as C
+    import torch
+    import workloads
+    from paper_2603_17711_amd import api
+    from paper_2603_17711_amd._lib import check, lib
+    from paper_2603_17711_amd.mctdh import build_tfd
+    inst = workloads.tfd_spin_boson()
+
+    def timed(precision, steps, warmup):
+        plan = build_tfd(inst, precision=precision)
+        plan.step(warmup, inst.dt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.step(steps, inst.dt, t0=warmup * inst.dt)
+        torch.cuda.synchronize()
+        return plan, time.perf_counter() - t0
+
+    log("thermofield: timed FP32 run")
+    _, dt_mixed = timed(api.FP32, a.steps, a.warmup)
+    value = a.steps / dt_mixed
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "steps/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(1e3 * dt_mixed / a.steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64 contractions (fp32 MFMA), f64 master/QR", "data": "synthetic",
+        "config": {"workload": inst.name + ", -iH on a wavefunction, ps1, 1 fs steps",
+                   "instances": 1, "precision": "mixed"},
+    }
+    if not a.no_fp64:
+        _, dt64 = timed(api.FP64, max(1, a.steps // 2), 2)
+        out["fp64_gpu_value"] = round(max(1, a.steps // 2) / dt64, 3)
+    # accuracy: 100 steps against the stored oracle trajectory
+    from tests.golden.make_golden import load
+    g = load("tfd_spin_boson_100.npz", [inst])
+    plan = build_tfd(inst, precision=api.FP32)
+    dmax = trace_distance(plan.rho_pure(), g["rho"][0])
+    for k in range(1, 11):
+        plan.step(10, inst.dt, t0=10 * (k - 1) * inst.dt)
+        dmax = max(dmax, trace_distance(plan.rho_pure(), g["rho"][k]))
+    out["trace_distance_vs_oracle"] = {"value": dmax, "steps": 100,
+                                       "sample": "every 10th step against the stored oracle"}
+    prof_steps = max(1, min(a.steps, 10))
+    plan = build_tfd(inst, precision=api.FP32)
+    plan.step(1, inst.dt)
+    torch.cuda.synchronize()
+    check(lib().tenso_profile(1))
+    plan.step(prof_steps, inst.dt)
+    torch.cuda.synchronize()
+    ms, n, fl, by = C.c_double(), C.c_int64(), C.c_double(), C.c_double()
+    check(lib().tenso_profile_stats(C.byref(ms), C.byref(n), C.byref(fl), C.byref(by)))
+    check(lib().tenso_profile(0))
+    avg_ms = ms.value / max(1, n.value)
+    achieved = fl.value / max(1, n.value) / (avg_ms * 1e-3) / 1e12
+    out["roofline"] = {
+        "kernel": "k_apply<float> (SOP contraction, MFMA 16x16x4 f32)",
+        "bound": "mfma", "achieved": round(achieved, 4), "peak": PEAK_FP32_MFMA,
+        "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MFMA, 6), "traffic": None,
+        "avg_launch_us": round(1e3 * avg_ms, 3), "launches": int(n.value),
+        "algorithmic_flops_per_launch": fl.value / max(1, n.value),
+        "algorithmic_bytes_per_launch": by.value / max(1, n.value),
+    }
+    if not a.no_cpu:
+        from threadpoolctl import threadpool_limits
+        from oracle.tfd import propagate_tfd
+        n_sample = 5
+        log("thermofield: CPU oracle baseline")
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            propagate_tfd(inst, n_steps=n_sample, every=n_sample)
+            t_cpu = time.perf_counter() - t0
+        out["cpu_baseline"] = {
+            "value": round(n_sample / t_cpu, 4), "unit": "steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_sample} steps of the same workload, FP64 NumPy oracle, 1 BLAS thread",
+        }
+    print(json.dumps(out))
+
+
 def run_main(a):
     import numpy as np
     import torch
@@ -535,6 +618,8 @@ def run_main(a):
         return ps2_main(a)
     if a.workload == "surrogate":
         return surrogate_main(a)
+    if a.workload == "tfd-mctdh":
+        return tfd_main(a)
 
     inst, wname = instance(a.workload, a.steps + a.warmup)
     plan, dt_mixed = timed_run(inst, api.FP32, a.steps, a.warmup)

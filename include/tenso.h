@@ -81,7 +81,8 @@ const char* tenso_last_error(void);
 
 /* Build a tree from a parent array and an end map (general TTN, Sec. II C).
  * parent[0] = -1 and 0 <= parent[s] < s.  end_node[e] / end_dim[e] give the
- * node and dimension of end e (ends 0 and 1 must sit on node 0).  bond_rank
+ * node and dimension of end e (ends 0 and 1 must sit on node 0; end 1 has
+ * end 0's dimension for a density state, or 1 for a wavefunction).  bond_rank
  * (nullable, indexed by child node, entry 0 ignored) requests per-bond ranks,
  * otherwise max_rank is requested everywhere; both are clamped (see above).
  * Errors: EINVAL on a malformed tree or dims < 1. */
@@ -157,8 +158,9 @@ int tenso_plan_sizes(const tenso_plan* p, size_t* state_bytes, size_t* workspace
  * dims_out[8*s + l], unused entries 0).  Host call, no device work. */
 int tenso_plan_shapes(const tenso_plan* p, int32_t* n_legs_out, int32_t* dims_out);
 
-/* Write the initial product state rho_S(0) (x) |0..0> (host M x M rho_s) into
- * d_state: root[i, j, 0..] = rho[i, j]; other cores U[a, beta] =
+/* Write the initial product state rho_S(0) (x) |0..0> (host rho_s, row-major
+ * over ends 0 and 1: M x M for a density, M x 1 for a wavefunction psi(0))
+ * into d_state: root[i, j, 0..] = rho[i, j]; other cores U[a, beta] =
  * delta(a, flat(beta)).  PS2 plans start at rank 2 on every bond (clamped;
  * with rank 1 a tree whose inner nodes carry no physical leg has two-site
  * tensors with a side of dimension 1, and no bond could ever grow). */
@@ -228,6 +230,16 @@ int tenso_step_adaptive(tenso_plan* p, void* d_state, double t0, double dt, int 
  * (M x M) and its trace into h_trace (nullable).  Synchronises the stream. */
 int tenso_reduced_rho(tenso_plan* p, const void* d_state, tenso_c128* h_rho, double* h_trace,
                       void* d_ws, hipStream_t s);
+
+/* Reduced density of a wavefunction state (Sec. III A 5: ML-MCTDH on the same
+ * tree and kernels): the tree's end 1 has dimension 1, and
+ * rho_S = Tr_bath |psi><psi| (M x M, host h_rho; its trace into h_trace,
+ * nullable), formed on the device from the root core, which holds the
+ * state's norm: the state must be canonical toward the root, as it is after
+ * tenso_state_init and every step call.  EINVAL if end 1 is not of dimension
+ * 1.  Synchronises the stream. */
+int tenso_reduced_rho_pure(tenso_plan* p, const void* d_state, tenso_c128* h_rho, double* h_trace,
+                           void* d_ws, hipStream_t s);
 
 /* Bond ranks chosen by the last ps2 step, one entry per split in sweep order;
  * returns the number of entries (at most cap) or a negative error. */

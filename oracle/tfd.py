@@ -29,27 +29,38 @@ propagation up to the RK4 error; Tr rho_S = 1.
 """
 import numpy as np
 
-from .bath import f_be, j_bo
+from .bath import j_bo
 from .ttn import Tree, initial_state, nary_tree
 
 
 def thermal_sd(w, lam, w0, eta, T):
-    """J_T(w) = J(w) f_BE(w / T) (its limit J'(0) T at w = 0)."""
-    w = np.asarray(w, dtype=float)
-    small = np.abs(w) < 1e-12
-    ws = np.where(small, 1e-12, w)
-    out = np.real(j_bo(ws, lam, w0, eta) * f_be(ws / T))
-    return out
+    """J_T(w) = J(w) f_BE(w / T), with f_BE(x) = 1 / (1 - exp(-x)) evaluated as
+    -1 / expm1(-x) (no cancellation near w = 0) and the limit T J'(0) at w = 0
+    (J is odd, so J(h) / h is J'(0) to O(h^2))."""
+    scalar = np.ndim(w) == 0
+    w = np.atleast_1d(np.asarray(w, dtype=float))
+    out = np.empty_like(w)
+    zero = w == 0.0
+    nz = ~zero
+    out[nz] = np.real(j_bo(w[nz], lam, w0, eta)) / (-np.expm1(-w[nz] / T))
+    h = 1e-8
+    out[zero] = T * np.real(j_bo(h, lam, w0, eta)) / h
+    return out[0] if scalar else out
 
 
-def gauss_bath(lam, w0, eta, T, cutoff, n, n_fine=400001):
+def gauss_bath(lam, w0, eta, T, cutoff, n, panels=4000, order=16):
     """Nodes and couplings (w_j, g_j) of the n-point Gauss quadrature of the
-    measure J_T(w) dw on [-cutoff, cutoff]: the Stieltjes procedure on a fine
-    midpoint rule of the measure gives the three-term recurrence of its
-    orthonormal polynomials, whose Jacobi matrix has the nodes as eigenvalues
-    and mu_0 (first eigenvector component)^2 as weights (Golub-Welsch)."""
-    h = 2.0 * cutoff / n_fine
-    x = -cutoff + h * (np.arange(n_fine) + 0.5)
+    measure J_T(w) dw on [-cutoff, cutoff]: the measure is first resolved by a
+    composite Gauss-Legendre rule (`panels` panels of `order` points, exact to
+    rounding for this smooth density), the Stieltjes procedure on that discrete
+    measure gives the three-term recurrence of its orthonormal polynomials, and
+    the recurrence's Jacobi matrix has the nodes as eigenvalues and
+    mu_0 (first eigenvector component)^2 as weights (Golub-Welsch)."""
+    xg, wg = np.polynomial.legendre.leggauss(order)
+    edges = np.linspace(-cutoff, cutoff, panels + 1)
+    x = np.concatenate([0.5 * (lo + hi) + 0.5 * (hi - lo) * xg
+                        for lo, hi in zip(edges[:-1], edges[1:])])
+    h = np.concatenate([0.5 * (hi - lo) * wg for lo, hi in zip(edges[:-1], edges[1:])])
     m = thermal_sd(x, lam, w0, eta, T) * h
     mu0 = m.sum()
     a = np.zeros(n)
@@ -118,3 +129,21 @@ def reduced_rho_pure(tree, cores):
             Ag = np.moveaxis(np.tensordot(Ag, gram(x), axes=([i], [0])), -1, i)
     M = A.shape[0]
     return Ag.reshape(M, -1) @ A.conj().reshape(M, -1).T
+
+
+def propagate_tfd(inst, n_steps=None, every=10):
+    """ps1 propagation of a workloads.TfdInstance; rho_S at every `every`-th
+    step and the last.  Returns (steps, rhos)."""
+    from .integrators import Propagator
+    w, g = gauss_bath(inst.lam, inst.w0, inst.eta, inst.T, inst.cutoff, inst.n_modes)
+    terms, _ = tfd_terms(inst.H, inst.Q, w, g, inst.dim)
+    tree = tfd_tree(inst.H.shape[0], inst.n_modes, inst.dim, inst.rank, inst.n_ary)
+    P = Propagator(tree, terms, initial_wavefunction(tree, inst.psi0))
+    n = inst.n_steps if n_steps is None else n_steps
+    steps, rhos = [0], [reduced_rho_pure(P.tree, P.C)]
+    for s in range(n):
+        P.step_ps1(s * inst.dt, inst.dt)
+        if (s + 1) % every == 0 or s + 1 == n:
+            steps.append(s + 1)
+            rhos.append(reduced_rho_pure(P.tree, P.C))
+    return np.array(steps), np.array(rhos)

@@ -57,6 +57,7 @@ SIGS = {
     "tenso_step_adaptive": (C.c_int, [P, P, C.c_double, C.c_double, C.c_int, C.c_double, C.c_int,
                                       P, P, P]),
     "tenso_reduced_rho": (C.c_int, [P, P, C128P, DP, P, P]),
+    "tenso_reduced_rho_pure": (C.c_int, [P, P, C128P, DP, P, P]),
     "tenso_rank_trajectory": (C.c_int, [P, I32P, C.c_int]),
     "tenso_svd_truncate": (C.c_int, [P, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, DP, P, I32P,
                                      DP, P]),

@@ -205,6 +205,16 @@ class Plan:
                                       C.c_void_p(self.ws.data_ptr()), _stream()))
         return out
 
+    def rho_pure(self):
+        """Tr_bath |psi><psi| of a wavefunction state (bra end of dimension 1)."""
+        M = self.M
+        out = np.zeros((M, M), np.complex128)
+        tr = C.c_double()
+        check(lib().tenso_reduced_rho_pure(self.h, C.c_void_p(self.state.data_ptr()),
+                                           out.ctypes.data_as(C.POINTER(c128)), C.byref(tr),
+                                           C.c_void_p(self.ws.data_ptr()), _stream()))
+        return out
+
     def __del__(self):
         L = getattr(_lib, "_lib", None) if _lib is not None else None
         if getattr(self, "h", None) and L is not None:  # modules may be torn down at exit

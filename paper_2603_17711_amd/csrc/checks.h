@@ -32,6 +32,12 @@ struct IsoOp {
 // per op.
 hipError_t launch_isometry(const IsoOp* ops, int n, double* out, hipStream_t s);
 
+// out (d x d complex, row-major) = C C^H for a root core C viewed as [d, p1]
+// (complex FP64): the reduced density of a wavefunction whose system end is
+// the core's first index, when the core holds the state's norm (canonical
+// toward the root).  One workgroup per entry.
+hipError_t launch_rho_pure(const double* C, int d, long p1, double* out, hipStream_t s);
+
 // Zero `bytes` bytes at p (a kernel, so that it may sit in captured graphs).
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 

@@ -1,5 +1,6 @@
 // Root-core norms (FP64) for the norm-growth check of the step calls, the
-// isometry test behind the canonical-center check, and a zero fill.
+// isometry test behind the canonical-center check, the reduced density of a
+// wavefunction state, and a zero fill.
 #include "checks.h"
 
 #include <algorithm>
@@ -59,6 +60,42 @@ __global__ void __launch_bounds__(256) k_isometry(const IsoOp* __restrict__ ops,
 hipError_t launch_isometry(const IsoOp* ops, int n, double* out, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_isometry, dim3(n), dim3(256), 0, s, ops, out);
+  return hipGetLastError();
+}
+
+// Reduced density of a wavefunction held by a root core viewed as [d, p1]
+// (its first end is the system, every other index is traced):
+// out[a, b] = sum_y C[a, y] conj(C[b, y]), one workgroup per entry (a, b).
+__global__ void __launch_bounds__(256) k_rho_pure(const double* __restrict__ C, int d, long p1,
+                                                  double* __restrict__ out) {
+  const long a = blockIdx.x / d, b = blockIdx.x % d;
+  double re = 0, im = 0;
+  for (long y = threadIdx.x; y < p1; y += 256) {
+    const double* u = C + 2 * (a * p1 + y);
+    const double* v = C + 2 * (b * p1 + y);
+    re += u[0] * v[0] + u[1] * v[1];
+    im += u[1] * v[0] - u[0] * v[1];
+  }
+  __shared__ double rr[256], ri[256];
+  rr[threadIdx.x] = re;
+  ri[threadIdx.x] = im;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      rr[threadIdx.x] += rr[threadIdx.x + w];
+      ri[threadIdx.x] += ri[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[2 * blockIdx.x] = rr[0];
+    out[2 * blockIdx.x + 1] = ri[0];
+  }
+}
+
+hipError_t launch_rho_pure(const double* C, int d, long p1, double* out, hipStream_t s) {
+  if (d <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rho_pure, dim3(d * d), dim3(256), 0, s, C, d, p1, out);
   return hipGetLastError();
 }
 

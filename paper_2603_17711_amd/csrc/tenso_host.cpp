@@ -165,7 +165,8 @@ static tenso_tree* make_tree(int n, const int32_t* parent, int n_ends, const int
     if (end_dim[e] < 1) fail(TENSO_EINVAL, "end dims must be >= 1");
   }
   if (end_node[0] != 0 || end_node[1] != 0) fail(TENSO_EINVAL, "ket and bra ends must sit on the root");
-  if (end_dim[0] != end_dim[1]) fail(TENSO_EINVAL, "ket and bra dims differ");
+  if (end_dim[1] != end_dim[0] && end_dim[1] != 1)
+    fail(TENSO_EINVAL, "the bra end has the ket's dimension (a density) or 1 (a wavefunction)");
   if (max_rank < 1 && !bond_rank) fail(TENSO_EINVAL, "max_rank must be >= 1");
   auto t = std::make_unique<tenso_tree>();
   t->n = n;
@@ -2232,11 +2233,12 @@ static std::vector<cd> initial_cores(const tenso_plan& P, const tenso_c128* rho)
   for (int s = 0; s < t.n; ++s) {
     cd* C = h.data() + P.core_off[s] / 16;
     std::vector<int> d = t.shape(s);
-    if (s == 0) {
-      const int M = t.end_dim[0];
-      long rest = t.size(0) / ((long)M * M);
-      for (int i = 0; i < M; ++i)
-        for (int j = 0; j < M; ++j) C[((long)i * M + j) * rest] = cd(rho[i * M + j].re, rho[i * M + j].im);
+    if (s == 0) {  // ends 0 and 1 are the root's first legs
+      const int M1 = t.end_dim[0], M2 = t.end_dim[1];
+      long rest = t.size(0) / ((long)M1 * M2);
+      for (int i = 0; i < M1; ++i)
+        for (int j = 0; j < M2; ++j)
+          C[((long)i * M2 + j) * rest] = cd(rho[i * M2 + j].re, rho[i * M2 + j].im);
     } else {
       long cols = t.size(s) / d[0];
       for (int a = 0; a < d[0]; ++a) C[(long)a * cols + a] = 1.0;
@@ -2591,6 +2593,27 @@ int tenso_reduced_rho(tenso_plan* p, const void* d_state, tenso_c128* h_rho, dou
     const int M = p->tree.end_dim[0];
     hipchk(hipMemcpyAsync(h_rho, (char*)d_ws + p->ws_rhoout, (size_t)M * M * 16, hipMemcpyDeviceToHost, s),
            "rho readback");
+    hipchk(hipStreamSynchronize(s), "sync");
+    if (h_trace) {
+      double tr = 0;
+      for (int i = 0; i < M; ++i) tr += h_rho[i * M + i].re;
+      *h_trace = tr;
+    }
+  });
+}
+
+int tenso_reduced_rho_pure(tenso_plan* p, const void* d_state, tenso_c128* h_rho, double* h_trace,
+                           void* d_ws, hipStream_t s) {
+  return guard([&] {
+    if (!p || !d_state || !h_rho || !d_ws) fail(TENSO_EINVAL, "null argument");
+    const tenso_tree& t = p->tree;
+    if (t.end_node.size() < 2 || t.end_node[0] != 0 || t.end_node[1] != 0 || t.end_dim[1] != 1)
+      fail(TENSO_EINVAL, "a wavefunction state has ends 0 (system) and 1 (dimension 1) on the root");
+    const int M = t.end_dim[0];  // the workspace holds an M x M result (ws_rhoout)
+    const double* C = (const double*)((const char*)d_state + p->core_off[0]);
+    double* out = (double*)((char*)d_ws + p->ws_rhoout);
+    hipchk(launch_rho_pure(C, M, t.size(0) / M, out, s), "rho_pure");
+    hipchk(hipMemcpyAsync(h_rho, out, (size_t)M * M * 16, hipMemcpyDeviceToHost, s), "rho readback");
     hipchk(hipStreamSynchronize(s), "sync");
     if (h_trace) {
       double tr = 0;

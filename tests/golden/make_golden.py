@@ -3,7 +3,7 @@
 Every stored value comes from the FP64 CPU oracle (``oracle/``) run on the seeded
 workloads of ``workloads.py``; nothing here touches the GPU library.
 
-    python tests/golden/make_golden.py [spin_boson|exciton|batch|batch200|ps2|pade|all] [--procs N]
+    python tests/golden/make_golden.py [spin_boson|exciton|batch|batch200|ps2|pade|tfd|all] [--procs N]
 
 Files (numpy .npz, no pickles):
   spin_boson_train_2000.npz   spin-boson K=3 N=10 train R=8, ps1, 2000 steps,
@@ -27,6 +27,10 @@ Files (numpy .npz, no pickles):
   pade_structured_500.npz     the paper's Sec. III A 1 structured spin-boson model
                               (Pade, K=4, depth 25, train R=16, dt 0.1 fs), ps1,
                               500 steps (50 fs), rho_S at every 50th step
+  tfd_spin_boson_100.npz      the paper's Sec. III A 5 thermofield ML-MCTDH listing
+                              (50 star modes of Fock dimension 8, binary tree R=16,
+                              1 fs steps), ps1 on the wavefunction, 100 steps, rho_S
+                              at every 10th step
   ps2_ternary_cap8_10.npz     structured bath K=24 N=10 on the ternary tree, ps2 with
                               eps 1e-6 and rank cap 8, 10 steps: rho_S at every step
                               and the rank chosen at every split (`ranks`, one row
@@ -67,12 +71,23 @@ def workload_digest(insts):
     return h.hexdigest()
 
 
+def tfd_digest(inst):
+    """Digest of every input parameter of a thermofield instance."""
+    h = hashlib.sha256()
+    for a in (inst.H, inst.Q, inst.psi0):
+        h.update(np.ascontiguousarray(a).tobytes())
+    h.update(repr((inst.lam, inst.w0, inst.eta, inst.T, inst.cutoff, inst.n_modes, inst.dim,
+                   inst.n_ary, inst.rank, inst.dt)).encode())
+    return h.hexdigest()
+
+
 def load(fname, insts):
     """The stored oracle trajectories of `fname`, checked against the inputs of
     `insts` (a stale file raises instead of being compared)."""
     with np.load(os.path.join(HERE, fname), allow_pickle=False) as z:
         out = {k: z[k] for k in z.files}
-    if str(out["digest"]) != workload_digest(insts):
+    want = tfd_digest(insts[0]) if hasattr(insts[0], "psi0") else workload_digest(insts)
+    if str(out["digest"]) != want:
         raise RuntimeError(f"{fname} was written for other workload inputs: rerun "
                            "tests/golden/make_golden.py")
     return out
@@ -148,6 +163,17 @@ def write_single(name, n_steps, every, fname, pool):
     print(f"{fname}: {len(steps)} records, {time.time() - t0:.1f} s", flush=True)
 
 
+def write_tfd(n_steps, every, fname):
+    import workloads
+    from oracle.tfd import propagate_tfd
+    t0 = time.time()
+    inst = workloads.tfd_spin_boson()
+    steps, rhos = propagate_tfd(inst, n_steps=n_steps, every=every)
+    np.savez_compressed(os.path.join(HERE, fname), steps=steps, rho=rhos, dt=inst.dt,
+                        digest=tfd_digest(inst))
+    print(f"{fname}: {len(steps)} records, {time.time() - t0:.1f} s", flush=True)
+
+
 def write_batch(n_steps, every, fname, pool, ids=None, spread=False):
     import workloads
     insts = workloads.uneven_batch()
@@ -180,7 +206,8 @@ def write_batch(n_steps, every, fname, pool, ids=None, spread=False):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("what", nargs="?", default="all",
-                    choices=["spin_boson", "exciton", "batch", "batch200", "ps2", "pade", "all"])
+                    choices=["spin_boson", "exciton", "batch", "batch200", "ps2", "pade", "tfd",
+                             "all"])
     ap.add_argument("--procs", type=int, default=os.cpu_count())
     a = ap.parse_args()
     os.environ.setdefault("OMP_NUM_THREADS", "1")
@@ -197,6 +224,8 @@ def main():
             write_single("pade", 500, 50, "pade_structured_500.npz", pool)
         if a.what in ("ps2", "all"):
             write_ps2(10, 8, "ps2_ternary_cap8_10.npz", pool)
+        if a.what in ("tfd", "all"):
+            write_tfd(100, 10, "tfd_spin_boson_100.npz")
 
 
 if __name__ == "__main__":

@@ -40,6 +40,7 @@ hipError_t launch_step_inc(int*, int, hipStream_t) STUB()
 hipError_t launch_finite(const FiniteOp*, int, int*, hipStream_t) STUB()
 hipError_t launch_norms(const NormOp*, int, double*, hipStream_t) STUB()
 hipError_t launch_isometry(const IsoOp*, int, double*, hipStream_t) STUB()
+hipError_t launch_rho_pure(const double*, int, long, double*, hipStream_t) STUB()
 hipError_t launch_zero(void*, size_t, hipStream_t) STUB()
 // Shared-memory footprint of an apply tile: the planner only compares it with
 // its budget, so any monotone size serves this host-only build.

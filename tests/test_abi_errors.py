@@ -48,7 +48,7 @@ def build_tree(parent, end_node, end_dim, max_rank=4, bond_rank=None):
     ("ket off the root", [-1, 0], [1, 0, 1], [2, 2, 3]),
     ("end on a missing node", [-1, 0], [0, 0, 7], [2, 2, 3]),
     ("zero end dimension", [-1, 0], [0, 0, 1], [2, 2, 0]),
-    ("ket and bra of different size", [-1, 0], [0, 0, 1], [2, 3, 3]),
+    ("bra neither the ket's size nor 1", [-1, 0], [0, 0, 1], [2, 3, 3]),
     ("fewer than two ends", [-1], [0], [2]),
 ])
 def test_build_tree_rejects_malformed_input(case, parent, end_node, end_dim):

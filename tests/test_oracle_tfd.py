@@ -79,3 +79,16 @@ def test_full_rank_ttn_wavefunction_equals_dense_schrodinger():
     rho = reduced_rho_pure(P.tree, P.C)
     assert np.abs(rho - rho_exact).max() < 1e-9
     assert abs(np.trace(rho) - 1.0) < 1e-9
+
+
+def test_product_star_bath_matches_oracle():
+    """The product's star bath (Lanczos on its own Gauss-Legendre resolution of
+    the measure) against the oracle's (Stieltjes on another)."""
+    from paper_2603_17711_amd.mctdh import star_bath, thermal_density
+    w1, g1 = gauss_bath(LAM, W0, ETA, T, CUT, 50)
+    w2, g2 = star_bath(LAM, W0, ETA, T, CUT, 50)
+    assert np.abs(w1 - w2).max() < 1e-9 * CUT
+    assert (np.abs(g1 - g2) / g1).max() < 1e-9
+    x = np.array([-120.0, -1e-9, 0.0, 3.0, 77.0])
+    assert np.allclose(thermal_density(x, LAM, W0, ETA, T), thermal_sd(x, LAM, W0, ETA, T),
+                       rtol=1e-6, atol=0)

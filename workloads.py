@@ -127,6 +127,36 @@ def structured_spin_boson_pade(n_steps=50, depth=25, rank=16, dt_fs=0.1):
                     "train", rank, rho0, dt_fs * FS_TO_CM, n_steps)
 
 
+class TfdInstance:
+    """A thermofield ML-MCTDH problem: system H_S, coupling Q, one Brownian
+    bath (lam, w0, eta) at T discretised into n_modes star modes on
+    [-cutoff, cutoff], Fock dimension dim per mode, n-ary tree, rank, psi(0)."""
+
+    def __init__(self, name, H, Q, lam, w0, eta, T, cutoff, n_modes, dim, n_ary, rank, psi0,
+                 dt, n_steps):
+        self.name = name
+        self.H = np.asarray(H, dtype=np.complex128)
+        self.Q = np.asarray(Q, dtype=np.complex128)
+        self.lam, self.w0, self.eta, self.T = float(lam), float(w0), float(eta), float(T)
+        self.cutoff = float(cutoff)
+        self.n_modes, self.dim, self.n_ary, self.rank = int(n_modes), int(dim), int(n_ary), int(rank)
+        self.psi0 = np.asarray(psi0, dtype=np.complex128)
+        self.dt, self.n_steps = float(dt), int(n_steps)
+
+
+def tfd_spin_boson(n_modes=50, dim=8, rank=16, n_steps=200, dt_fs=1.0):
+    """The paper's MCTDH listing (Sec. III A 5): H_S = [[-750, 300], [300, 750]]
+    cm^-1, Q = diag(-0.5, 0.5), one Brownian mode (reorganisation 200, width 10,
+    damped frequency 50 cm^-1) at 300 K, cut-off 200 cm^-1, 50 modes of Fock
+    dimension 8, psi(0) = |1>, 1 fs steps over 200 fs.  The listing gives no
+    rank; a binary tree of rank 16 here."""
+    eta, w0p = 10.0, 50.0
+    return TfdInstance(f"thermofield spin-boson {n_modes} modes dim {dim} binary R={rank}",
+                       [[-750.0, 300.0], [300.0, 750.0]], np.diag([-0.5, 0.5]), 200.0,
+                       float(np.sqrt(w0p ** 2 + eta ** 2)), eta, 300.0 * KB_CM, 200.0, n_modes,
+                       dim, 2, rank, [0.0, 1.0], dt_fs * FS_TO_CM, n_steps)
+
+
 def stable_dt(dt_max, T, n_ltc, N, H, wc=1.0):
     """Time step of a batch instance: dt_max unless a half-step RK4 sub-flow
     would leave half of RK4's real stability interval (|z| < 2.785).
