@@ -315,6 +315,15 @@ def batch_main(a):
         out["trace_distance_vs_oracle"] = acc
         if acc["value"] > 1e-6:
             out["accuracy_note"] = "trace distance above the 1e-6 fixed-rank bar"
+    log("FP32 batch with three real products per complex product, and its accuracy pass")
+    st3 = max(1, a.steps // 2)
+    plans3, b3, t3 = run_batch(api.FP32_3M, st3, 1)
+    out["fp32_3m_batched_value"] = round(len(insts) * st3 / t3[0], 2)
+    del b3, plans3
+    torch.cuda.empty_cache()
+    acc3 = batch_accuracy(insts, api.FP32_3M)
+    if acc3 is not None:
+        out["fp32_3m_trace_distance_vs_oracle"] = acc3["value"]
     if not a.no_fp64:
         log("FP64 batch, its accuracy pass and the plain FP64 sample")
         st64 = max(1, a.steps // 4)

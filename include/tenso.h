@@ -66,12 +66,15 @@ typedef struct tenso_batch tenso_batch;
 
 #define TENSO_FP64 0          /* every contraction in complex FP64 (plain reference path) */
 #define TENSO_FP32 1          /* contractions in complex FP32 on MFMA, FP64 master state */
+#define TENSO_FP32_3M 2       /* as TENSO_FP32, each complex product of the contraction from
+                                 three real MFMA products (Gauss: Re a Re b, Im a Im b,
+                                 (Re a + Im a)(Re b + Im b)) instead of four */
 
 #define TENSO_PS1 0           /* fixed-rank projector splitting */
 #define TENSO_PS2 1           /* adaptive-rank projector splitting */
 
 typedef struct {
-  int precision;   /* TENSO_FP64 | TENSO_FP32 */
+  int precision;   /* TENSO_FP64 | TENSO_FP32 | TENSO_FP32_3M */
   int method;      /* TENSO_PS1 | TENSO_PS2 */
   int max_rank;    /* PS2: cap on any bond rank (also sizes the state) */
 } tenso_plan_opts;

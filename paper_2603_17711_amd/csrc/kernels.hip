@@ -159,9 +159,13 @@ template <> struct V2<double> { typedef double2 t; };
 // register set while the MFMAs of step q run (two sets used in turn, so no
 // register copies between steps).  NIB and TLO are compile-time so that every
 // register array is indexed statically.
-template <typename T, int NIB, int TLO, int NA, typename C2>
+// With M3 the complex product takes three real products (Gauss): accr
+// collects Re a Re b, accx Im a Im b and acci (Re a + Im a)(Re b + Im b); the
+// product is Re = accr - accx, Im = acci - accr - accx (m3_re, m3_im).
+template <typename T, int NIB, int TLO, int NA, bool M3, typename C2>
 __device__ __forceinline__ void mma_loop(typename MT<T>::v4 (&accr)[NA],
-                                         typename MT<T>::v4 (&acci)[NA], const C2* ar, int ars16,
+                                         typename MT<T>::v4 (&acci)[NA],
+                                         typename MT<T>::v4 (&accx)[NA], const C2* ar, int ars16,
                                          const C2* bc, int bks, int nq, int g) {
   C2 b0, b1, a0[NIB], a1[NIB];
   auto ld = [&](int q, C2& b, C2(&a)[NIB]) {
@@ -171,8 +175,18 @@ __device__ __forceinline__ void mma_loop(typename MT<T>::v4 (&accr)[NA],
     for (int t = 0; t < NIB; ++t) a[t] = ar[t * ars16 + kk];
   };
   auto mm = [&](const C2& b, const C2(&a)[NIB]) {
+    if constexpr (M3) {
+      const T bs = b.x + b.y;
 #pragma unroll
-    for (int t = 0; t < NIB; ++t) cmma<T>(accr[TLO + t], acci[TLO + t], a[t].x, a[t].y, b.x, b.y);
+      for (int t = 0; t < NIB; ++t) {
+        accr[TLO + t] = MT<T>::mma(a[t].x, b.x, accr[TLO + t]);
+        accx[TLO + t] = MT<T>::mma(a[t].y, b.y, accx[TLO + t]);
+        acci[TLO + t] = MT<T>::mma(a[t].x + a[t].y, bs, acci[TLO + t]);
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < NIB; ++t) cmma<T>(accr[TLO + t], acci[TLO + t], a[t].x, a[t].y, b.x, b.y);
+    }
   };
   // both products of an iteration are unconditional, so the accumulators
   // stay in place across iterations; an odd last step follows the loop
@@ -277,7 +291,10 @@ __device__ void op_stage(const T* M, int d, int D, int ld, const OpLane& o, C2* 
 
 // One tile with NIB 16-row blocks of leg 1: each wavefront owns up to
 // MT<T>::NT / NIB units of the tile and accumulates them over all terms.
-template <typename T, typename Tin, int NIB>
+template <typename T> __device__ inline T m3_re(T r, T i, T x) { return r - x; }
+template <typename T> __device__ inline T m3_im(T r, T i, T x) { return i - r - x; }
+
+template <typename T, typename Tin, int NIB, bool M3>
 __device__ __forceinline__ void apply_tile(const ApplyGroup& G, const ApplyTile& tile,
                                            char* smem_raw, long* sbase, int step) {
   typedef typename MT<T>::v4 v4;
@@ -366,11 +383,12 @@ __device__ __forceinline__ void apply_tile(const ApplyGroup& G, const ApplyTile&
     ucol[UU] = 16 * (u % njb) + c;
     ubase[UU] = unit_geo(G, u, njb, c).base;
   });
-  v4 yr[NA], yi[NA];
+  v4 yr[NA], yi[NA], yx[NA];  // yx: M3 only
 #pragma unroll
   for (int t = 0; t < NA; ++t) {
     yr[t] = v4{0, 0, 0, 0};
     yi[t] = v4{0, 0, 0, 0};
+    yx[t] = v4{0, 0, 0, 0};
   }
 
   // write the wavefront's accumulators (its units of this tile) to Yb
@@ -386,12 +404,18 @@ __device__ __forceinline__ void apply_tile(const ApplyGroup& G, const ApplyTile&
             const int row = 16 * t + MT<T>::drow(g, r);
             if (row < d1 && col < d2) {
               const long o = 2 * (ubase[UU] + row * sa + (long)col * sb);
+              T vr = yr[UU * NIB + t][r], vi = yi[UU * NIB + t][r];
+              if constexpr (M3) {
+                const T vx = yx[UU * NIB + t][r];
+                vi = m3_im(vr, vi, vx);
+                vr = m3_re(vr, vi, vx);
+              }
               if (G.accumulate) {
-                Yb[o] += yr[UU * NIB + t][r];
-                Yb[o + 1] += yi[UU * NIB + t][r];
+                Yb[o] += vr;
+                Yb[o + 1] += vi;
               } else {
-                Yb[o] = yr[UU * NIB + t][r];
-                Yb[o + 1] = yi[UU * NIB + t][r];
+                Yb[o] = vr;
+                Yb[o + 1] = vi;
               }
             }
           }
@@ -457,13 +481,14 @@ __device__ __forceinline__ void apply_tile(const ApplyGroup& G, const ApplyTile&
         const c2* xf = xs + xoff[UU];
         const int col = ucol[UU];
         if (two) {
-          v4 zr[NIB], zi[NIB];
+          v4 zr[NIB], zi[NIB], zx[NIB];
 #pragma unroll
           for (int t = 0; t < NIB; ++t) {
             zr[t] = v4{0, 0, 0, 0};
             zi[t] = v4{0, 0, 0, 0};
+            zx[t] = v4{0, 0, 0, 0};
           }
-          mma_loop<T, NIB, 0, NIB>(zr, zi, xf + c * xs1, 16 * xs1, bs + col * bs1, 1, nq1, g);
+          mma_loop<T, NIB, 0, NIB, M3>(zr, zi, zx, xf + c * xs1, 16 * xs1, bs + col * bs1, 1, nq1, g);
 #pragma unroll
           for (int t = 0; t < NIB; ++t) {
 #pragma unroll
@@ -471,6 +496,10 @@ __device__ __forceinline__ void apply_tile(const ApplyGroup& G, const ApplyTile&
               c2 v;
               v.x = zr[t][r];
               v.y = zi[t][r];
+              if constexpr (M3) {
+                v.y = m3_im(zr[t][r], zi[t][r], zx[t][r]);
+                v.x = m3_re(zr[t][r], zi[t][r], zx[t][r]);
+              }
               zs[(16 * t + MT<T>::drow(g, r)) * ZS1 + c] = v;
             }
           }
@@ -478,7 +507,7 @@ __device__ __forceinline__ void apply_tile(const ApplyGroup& G, const ApplyTile&
         }
         const c2* ar = kind == 2 ? xf + c * xs1 : as + c * as1;
         const c2* bc = two ? zs + c : kind == 1 ? xf + col : bs + col * bs1;
-        mma_loop<T, NIB, UU * NIB, NA>(yr, yi, ar, ars16, bc, bks, nq, g);
+        mma_loop<T, NIB, UU * NIB, NA, M3>(yr, yi, yx, ar, ars16, bc, bks, nq, g);
         if (two) TENSO_WAVE_SYNC();
       }
     });
@@ -488,6 +517,7 @@ __device__ __forceinline__ void apply_tile(const ApplyGroup& G, const ApplyTile&
       for (int t = 0; t < NA; ++t) {
         yr[t] = v4{0, 0, 0, 0};
         yi[t] = v4{0, 0, 0, 0};
+        yx[t] = v4{0, 0, 0, 0};
       }
     }
     if (more) put(tn, cnr, cni, buf ^ 1);
@@ -498,7 +528,7 @@ __device__ __forceinline__ void apply_tile(const ApplyGroup& G, const ApplyTile&
 }
 #undef TENSO_WAVE_SYNC
 
-template <typename T, typename Tin>
+template <typename T, typename Tin, bool M3>
 __global__ void __launch_bounds__(64 * kApplyWaves) k_apply(const ApplyGroup* __restrict__ groups,
                                                             const ApplyTile* __restrict__ tiles,
                                                             const int* __restrict__ step_ctr) {
@@ -508,10 +538,10 @@ __global__ void __launch_bounds__(64 * kApplyWaves) k_apply(const ApplyGroup* __
   const ApplyGroup& G = groups[tile.group];
   const int step = step_ctr ? gmem(step_ctr)[0] : 0;
   switch ((G.d1 + 15) >> 4) {  // uniform per tile
-    case 1: apply_tile<T, Tin, 1>(G, tile, smem_raw, sbase, step); break;
-    case 2: apply_tile<T, Tin, 2>(G, tile, smem_raw, sbase, step); break;
-    case 3: apply_tile<T, Tin, 3>(G, tile, smem_raw, sbase, step); break;
-    default: apply_tile<T, Tin, 4>(G, tile, smem_raw, sbase, step); break;
+    case 1: apply_tile<T, Tin, 1, M3>(G, tile, smem_raw, sbase, step); break;
+    case 2: apply_tile<T, Tin, 2, M3>(G, tile, smem_raw, sbase, step); break;
+    case 3: apply_tile<T, Tin, 3, M3>(G, tile, smem_raw, sbase, step); break;
+    default: apply_tile<T, Tin, 4, M3>(G, tile, smem_raw, sbase, step); break;
   }
 }
 
@@ -2081,18 +2111,24 @@ size_t apply_lds_bytes(int fp64, int nfl, int d1, int d2) {
 
 // With t0/t1 given, the events are taken by the kernel's own dispatch (start
 // and end of its execution), not by separate stream markers.
-hipError_t launch_apply(int fp64, int in_fp64, const ApplyGroup* groups, const ApplyTile* tiles,
+// mode: 0 complex FP32 (four real products), 1 complex FP64, 2 complex FP32
+// with three real products per complex product
+hipError_t launch_apply(int mode, int in_fp64, const ApplyGroup* groups, const ApplyTile* tiles,
                         int n_tiles, const int* step_ctr, size_t lds, hipStream_t s,
                         hipEvent_t t0, hipEvent_t t1) {
   if (n_tiles <= 0) return hipSuccess;
   static bool attr_set = false;
   if (!attr_set) {
     const int cap = kApplyLdsBudget;
-    (void)hipFuncSetAttribute((const void*)k_apply<float, float>,
+    (void)hipFuncSetAttribute((const void*)k_apply<float, float, false>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, cap);
-    (void)hipFuncSetAttribute((const void*)k_apply<float, double>,
+    (void)hipFuncSetAttribute((const void*)k_apply<float, double, false>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, cap);
-    (void)hipFuncSetAttribute((const void*)k_apply<double, double>,
+    (void)hipFuncSetAttribute((const void*)k_apply<double, double, false>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, cap);
+    (void)hipFuncSetAttribute((const void*)k_apply<float, float, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, cap);
+    (void)hipFuncSetAttribute((const void*)k_apply<float, double, true>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, cap);
     attr_set = true;
   }
@@ -2103,9 +2139,12 @@ hipError_t launch_apply(int fp64, int in_fp64, const ApplyGroup* groups, const A
     else
       hipLaunchKernelGGL(kern, dim3(n_tiles), dim3(64 * kApplyWaves), lds, s, groups, tiles, step_ctr);
   };
-  if (fp64) go(k_apply<double, double>);
-  else if (in_fp64) go(k_apply<float, double>);
-  else go(k_apply<float, float>);
+  if (mode == 1) go(k_apply<double, double, false>);
+  else if (mode == 2) {
+    if (in_fp64) go(k_apply<float, double, true>);
+    else go(k_apply<float, float, true>);
+  } else if (in_fp64) go(k_apply<float, double, false>);
+  else go(k_apply<float, float, false>);
   return hipGetLastError();
 }
 

@@ -18,7 +18,7 @@
 #include "checks.h"
 
 namespace tenso {
-hipError_t launch_apply(int fp64, int in_fp64, const ApplyGroup* groups, const ApplyTile* tiles,
+hipError_t launch_apply(int mode, int in_fp64, const ApplyGroup* groups, const ApplyTile* tiles,
                         int n_tiles, const int* step_ctr, size_t lds, hipStream_t s,
                         hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 size_t apply_lds_bytes(int fp64, int nfl, int d1, int d2);
@@ -216,6 +216,7 @@ struct LaunchRec {
   size_t lds;
   double flops = 0;    // algorithmic flops of an apply launch (8 per complex MAC)
   double bytes = 0;    // algorithmic HBM bytes of an apply launch
+  int m3 = 0;          // apply launch of an FP32 plan with three real products per complex one
 };
 enum { LK_APPLY, LK_PRESUM, LK_COMBINE, LK_QR, LK_ABSORB, LK_GRAM, LK_RHO };
 
@@ -358,6 +359,7 @@ struct tenso_plan {
   tenso_plan_opts opts;
   std::vector<int> slot_r;  // env slot stride (capacity rank) per node
   int fp64 = 0;
+  int m3 = 0;      // TENSO_FP32_3M: complex products from three real ones
   size_t tsz = 8;  // bytes per complex in compute precision
   int max_dim = 1;
   // env slots
@@ -758,6 +760,7 @@ struct Builder {
   void launch(int kind, int in_fp64, int first, int count, int tfirst, int tcount, size_t lds = 0) {
     LaunchRec L{kind, in_fp64, first, count, tfirst, tcount, lds};
     if (kind == LK_APPLY) {
+      L.m3 = P_.m3;
       size_t mx = 0;
       for (int t = tfirst; t < tfirst + tcount; ++t) {
         const ApplyTile& tl = G.atiles[t];
@@ -836,8 +839,9 @@ struct Builder {
     per = std::min<long>(per, (long)(kApplyWaves * (NT / nib)));  // each wavefront's accumulators
     while (per > 1 && apply_lds_bytes(P.fp64, (int)((per + njb - 1) / njb + 1), d1, d2) > budget)
       per /= 2;
-    while (per > 1 && apply_lds_bytes(P.fp64, (int)((per + njb - 1) / njb + 1), d1, d2) >
-                          (size_t)kApplyLdsShare)
+    // (the FP64 kernel's registers allow one workgroup per CU anyway)
+    while (!P.fp64 && per > 1 &&
+           apply_lds_bytes(P.fp64, (int)((per + njb - 1) / njb + 1), d1, d2) > (size_t)kApplyLdsShare)
       per /= 2;
     return per;
   }
@@ -1511,6 +1515,7 @@ static Program merge_programs(std::vector<Program>& progs) {
       Program& P = progs[i];
       ML.flops += L.flops;
       ML.bytes += L.bytes;
+      ML.m3 = L.m3;
       ML.lds = std::max(ML.lds, L.lds);
       switch (kind) {
         case LK_APPLY: {
@@ -1621,14 +1626,16 @@ static void run(const DevProgram& D, int fp64, const int* ctr, hipStream_t s) {
       case LK_APPLY:
         if (g_prof.on) {
           hipEvent_t e0 = g_prof.get(), e1 = g_prof.get();
-          e = launch_apply(fp64, L.in_fp64, (const ApplyGroup*)(b + D.o_groups) + L.first,
+          e = launch_apply(fp64 ? 1 : L.m3 ? 2 : 0, L.in_fp64,
+                           (const ApplyGroup*)(b + D.o_groups) + L.first,
                            (const ApplyTile*)(b + D.o_atiles) + L.tfirst, L.tcount, ctr, L.lds, s,
                            e0, e1);
           g_prof.ev.push_back({e0, e1});
           g_prof.work.push_back({L.flops, L.bytes});
           break;
         }
-        e = launch_apply(fp64, L.in_fp64, (const ApplyGroup*)(b + D.o_groups) + L.first,
+        e = launch_apply(fp64 ? 1 : L.m3 ? 2 : 0, L.in_fp64,
+                         (const ApplyGroup*)(b + D.o_groups) + L.first,
                          (const ApplyTile*)(b + D.o_atiles) + L.tfirst, L.tcount, ctr, L.lds, s);
         break;
       case LK_PRESUM:
@@ -2076,7 +2083,8 @@ struct Ps2Exec {
 static std::unique_ptr<tenso_plan> compile_plan(const tenso_tree* t, const tenso_gen* g,
                                                 const tenso_plan_opts* o, bool device) {
   if (!t || !g || !o) fail(TENSO_EINVAL, "null argument");
-  if (o->precision != TENSO_FP64 && o->precision != TENSO_FP32) fail(TENSO_EINVAL, "bad precision");
+  if (o->precision != TENSO_FP64 && o->precision != TENSO_FP32 && o->precision != TENSO_FP32_3M)
+    fail(TENSO_EINVAL, "bad precision");
   if (o->method != TENSO_PS1 && o->method != TENSO_PS2) fail(TENSO_EINVAL, "bad method");
   if (g->n_ends != t->n_ends || g->end_dim != t->end_dim) fail(TENSO_EINVAL, "generator built for another tree");
   auto P = std::make_unique<tenso_plan>();
@@ -2084,6 +2092,7 @@ static std::unique_ptr<tenso_plan> compile_plan(const tenso_tree* t, const tenso
   P->gen = *g;
   P->opts = *o;
   P->fp64 = o->precision == TENSO_FP64;
+  P->m3 = o->precision == TENSO_FP32_3M;
   P->tsz = P->fp64 ? 16 : 8;
   P->cap = P->tree;
   if (o->method == TENSO_PS2) {
@@ -2911,7 +2920,8 @@ int tenso_batch_create(int n, tenso_plan* const* plans, void* const* d_states,
     for (int i = 0; i < n; ++i) {
       if (!plans[i] || !d_states[i] || !d_wss[i]) fail(TENSO_EINVAL, "null plan or buffer");
       if (plans[i]->opts.method != TENSO_PS1) fail(TENSO_EINVAL, "batches take ps1 plans");
-      if (i > 0 && plans[i]->fp64 != plans[0]->fp64) fail(TENSO_EINVAL, "mixed precisions in a batch");
+      if (i > 0 && (plans[i]->fp64 != plans[0]->fp64 || plans[i]->m3 != plans[0]->m3))
+        fail(TENSO_EINVAL, "mixed precisions in a batch");
       B->plans.push_back(plans[i]);
       B->states.push_back(d_states[i]);
       B->wss.push_back(d_wss[i]);

@@ -51,10 +51,10 @@ static_assert(kApplyMaxUnits <= kApplyWaves * kApplyAccTiles, "tile units");
 // Dynamic LDS available to one apply tile: the 160 KB of a CU less 1 KB
 // kept for the kernel's static LDS.
 constexpr int kApplyLdsBudget = 159 * 1024;
-// Tiles are shrunk (fewer units) until their LDS fits this share, when they
-// can: two workgroups then share a CU (the register budget allows two), so
-// one wavefront's LDS and barrier waits overlap the other's MFMAs.  A launch
-// takes the largest LDS of its tiles.
+// FP32 tiles are shrunk (fewer units) until their LDS fits this share, when
+// they can: two workgroups then share a CU (the register budget allows two),
+// so one wavefront's LDS and barrier waits overlap the other's MFMAs.  A
+// launch takes the largest LDS of its tiles.
 constexpr int kApplyLdsShare = 78 * 1024;
 
 struct ApplyTile {
