@@ -69,12 +69,16 @@ typedef struct tenso_batch tenso_batch;
 #define TENSO_FP32_3M 2       /* as TENSO_FP32, each complex product of the contraction from
                                  three real MFMA products (Gauss: Re a Re b, Im a Im b,
                                  (Re a + Im a)(Re b + Im b)) instead of four */
+#define TENSO_BF16 3          /* precision study: as TENSO_FP32 with every contraction operand
+                                 (input slices, scaled operator entries, the intermediate
+                                 X B^T) rounded to BF16; the products then equal a BF16 MFMA's
+                                 with FP32 accumulation (run on the FP32 MFMA) */
 
 #define TENSO_PS1 0           /* fixed-rank projector splitting */
 #define TENSO_PS2 1           /* adaptive-rank projector splitting */
 
 typedef struct {
-  int precision;   /* TENSO_FP64 | TENSO_FP32 | TENSO_FP32_3M */
+  int precision;   /* TENSO_FP64 | TENSO_FP32 | TENSO_FP32_3M | TENSO_BF16 */
   int method;      /* TENSO_PS1 | TENSO_PS2 */
   int max_rank;    /* PS2: cap on any bond rank (also sizes the state) */
 } tenso_plan_opts;

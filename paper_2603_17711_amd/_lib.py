@@ -20,7 +20,7 @@ class PlanOpts(C.Structure):
     _fields_ = [("precision", C.c_int), ("method", C.c_int), ("max_rank", C.c_int)]
 
 
-FP64, FP32, FP32_3M = 0, 1, 2
+FP64, FP32, FP32_3M, BF16 = 0, 1, 2, 3
 PS1, PS2 = 0, 1
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENUMERIC", -5: "EUNSUPPORTED"}
 

@@ -9,7 +9,7 @@ import ctypes as C
 import numpy as np
 
 from . import _lib
-from ._lib import FP32, FP32_3M, FP64, PS1, PS2, PlanOpts, c128, check, lib
+from ._lib import BF16, FP32, FP32_3M, FP64, PS1, PS2, PlanOpts, c128, check, lib
 from .heom import heom_table
 
 

@@ -152,6 +152,16 @@ template <typename T> struct V2;
 template <> struct V2<float> { typedef float2 t; };
 template <> struct V2<double> { typedef double2 t; };
 
+// Rounding of an FP32 value to the nearest BF16 value (ties to even), kept in
+// FP32: products of two such values are exact in FP32, so an FP32 MFMA on
+// them gives the products of a BF16 MFMA with FP32 accumulation.
+__device__ inline float bf16_round(float x) {
+  unsigned u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return __uint_as_float(u & 0xFFFF0000u);
+}
+__device__ inline double bf16_round(double x) { return x; }
+
 // K loop of one unit product, acc[TLO + t] += Aop_t Bop over nq k-steps of 4:
 // lane (c, g) reads Aop_t[c][k] at ar[t * ars16 + k] (ar already offset to
 // row c) and Bop[k][col] at bc[k * bks] (bc offset to the lane's column),
@@ -253,7 +263,16 @@ __device__ __forceinline__ C2 op_scale(C2 v, bool unit, T sr, T si) {
   return v;
 }
 
-template <typename T, typename C2>
+template <typename T, bool RB, typename C2>
+__device__ __forceinline__ C2 op_round(C2 v) {
+  if constexpr (RB) {
+    v.x = bf16_round(v.x);
+    v.y = bf16_round(v.y);
+  }
+  return v;
+}
+
+template <typename T, bool RB, typename C2>
 __device__ __forceinline__ void op_put(const C2 (&r)[kApplyPf], int D, int ld, const OpLane& o,
                                        C2* dst, double sr, double si) {
   if (!o.on) return;
@@ -261,12 +280,12 @@ __device__ __forceinline__ void op_put(const C2 (&r)[kApplyPf], int D, int ld, c
 #pragma unroll
   for (int k = 0; k < kApplyPf; ++k) {
     const int i = o.i0 + k * o.step;
-    if (i < D) dst[i * ld + o.j] = op_scale<T>(r[k], unit, (T)sr, (T)si);
+    if (i < D) dst[i * ld + o.j] = op_round<T, RB>(op_scale<T>(r[k], unit, (T)sr, (T)si));
   }
 }
 
 // D > 32: read and written in one pass (no look-ahead)
-template <typename T, typename C2>
+template <typename T, bool RB, typename C2>
 __device__ void op_stage(const T* M, int d, int D, int ld, const OpLane& o, C2* dst, double sr,
                          double si) {
   if (!o.on) return;
@@ -280,7 +299,7 @@ __device__ void op_stage(const T* M, int d, int D, int ld, const OpLane& o, C2* 
       v.x = e[0];
       v.y = e[1];
     }
-    dst[i * ld + o.j] = op_scale<T>(v, unit, (T)sr, (T)si);
+    dst[i * ld + o.j] = op_round<T, RB>(op_scale<T>(v, unit, (T)sr, (T)si));
   }
 }
 
@@ -294,7 +313,11 @@ __device__ void op_stage(const T* M, int d, int D, int ld, const OpLane& o, C2* 
 template <typename T> __device__ inline T m3_re(T r, T i, T x) { return r - x; }
 template <typename T> __device__ inline T m3_im(T r, T i, T x) { return i - r - x; }
 
-template <typename T, typename Tin, int NIB, bool M3>
+
+// AMODE: 0 complex products from four real MFMA products, 1 from three
+// (Gauss), 2 four products on operands rounded to BF16 (X slices, scaled
+// operator entries and the intermediate X B^T).
+template <typename T, typename Tin, int NIB, int AMODE>
 __device__ __forceinline__ void apply_tile(const ApplyGroup& G, const ApplyTile& tile,
                                            char* smem_raw, long* sbase, int step) {
   typedef typename MT<T>::v4 v4;
@@ -304,6 +327,15 @@ __device__ __forceinline__ void apply_tile(const ApplyGroup& G, const ApplyTile&
   constexpr int AW = kApplyWaves;
   constexpr int D1 = 16 * NIB;
   constexpr int as1 = D1 + 1;
+  constexpr bool M3 = AMODE == 1;
+  constexpr bool RB = AMODE == 2;
+  auto rbf = [](c2 v) {  // BF16 rounding of staged operands (AMODE 2)
+    if constexpr (RB) {
+      v.x = bf16_round(v.x);
+      v.y = bf16_round(v.y);
+    }
+    return v;
+  };
   c2* smem = reinterpret_cast<c2*>(smem_raw);
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -357,7 +389,7 @@ __device__ __forceinline__ void apply_tile(const ApplyGroup& G, const ApplyTile&
           v.x = x.re;
           v.y = x.im;
         }
-        *dst = v;
+        *dst = rbf(v);
         dst += (long)stp * xs1;
         a += stp;
         if (a >= D1) {
@@ -437,13 +469,13 @@ __device__ __forceinline__ void apply_tile(const ApplyGroup& G, const ApplyTile&
     c2* as = asb + buf * D1 * as1;
     c2* bs = bsb + (long)buf * D2 * bs1;
     if (t.A) {  // A carries the coefficient
-      if (pfa) op_put<T>(ra, D1, as1, oa, as, cr, ci);
-      else op_stage<T>(reinterpret_cast<const T*>(t.A), d1, D1, as1, oa, as, cr, ci);
+      if (pfa) op_put<T, RB>(ra, D1, as1, oa, as, cr, ci);
+      else op_stage<T, RB>(reinterpret_cast<const T*>(t.A), d1, D1, as1, oa, as, cr, ci);
     }
     if (t.B) {  // B only when alone
       const double sr = t.A ? 1.0 : cr, si = t.A ? 0.0 : ci;
-      if (pfb) op_put<T>(rb, D2, bs1, ob, bs, sr, si);
-      else op_stage<T>(reinterpret_cast<const T*>(t.B), d2, D2, bs1, ob, bs, sr, si);
+      if (pfb) op_put<T, RB>(rb, D2, bs1, ob, bs, sr, si);
+      else op_stage<T, RB>(reinterpret_cast<const T*>(t.B), d2, D2, bs1, ob, bs, sr, si);
     }
   };
   TermRef tr{};
@@ -500,7 +532,7 @@ __device__ __forceinline__ void apply_tile(const ApplyGroup& G, const ApplyTile&
                 v.y = m3_im(zr[t][r], zi[t][r], zx[t][r]);
                 v.x = m3_re(zr[t][r], zi[t][r], zx[t][r]);
               }
-              zs[(16 * t + MT<T>::drow(g, r)) * ZS1 + c] = v;
+              zs[(16 * t + MT<T>::drow(g, r)) * ZS1 + c] = rbf(v);
             }
           }
           TENSO_WAVE_SYNC();
@@ -528,7 +560,7 @@ __device__ __forceinline__ void apply_tile(const ApplyGroup& G, const ApplyTile&
 }
 #undef TENSO_WAVE_SYNC
 
-template <typename T, typename Tin, bool M3>
+template <typename T, typename Tin, int AMODE>
 __global__ void __launch_bounds__(64 * kApplyWaves) k_apply(const ApplyGroup* __restrict__ groups,
                                                             const ApplyTile* __restrict__ tiles,
                                                             const int* __restrict__ step_ctr) {
@@ -538,10 +570,10 @@ __global__ void __launch_bounds__(64 * kApplyWaves) k_apply(const ApplyGroup* __
   const ApplyGroup& G = groups[tile.group];
   const int step = step_ctr ? gmem(step_ctr)[0] : 0;
   switch ((G.d1 + 15) >> 4) {  // uniform per tile
-    case 1: apply_tile<T, Tin, 1, M3>(G, tile, smem_raw, sbase, step); break;
-    case 2: apply_tile<T, Tin, 2, M3>(G, tile, smem_raw, sbase, step); break;
-    case 3: apply_tile<T, Tin, 3, M3>(G, tile, smem_raw, sbase, step); break;
-    default: apply_tile<T, Tin, 4, M3>(G, tile, smem_raw, sbase, step); break;
+    case 1: apply_tile<T, Tin, 1, AMODE>(G, tile, smem_raw, sbase, step); break;
+    case 2: apply_tile<T, Tin, 2, AMODE>(G, tile, smem_raw, sbase, step); break;
+    case 3: apply_tile<T, Tin, 3, AMODE>(G, tile, smem_raw, sbase, step); break;
+    default: apply_tile<T, Tin, 4, AMODE>(G, tile, smem_raw, sbase, step); break;
   }
 }
 
@@ -2112,7 +2144,8 @@ size_t apply_lds_bytes(int fp64, int nfl, int d1, int d2) {
 // With t0/t1 given, the events are taken by the kernel's own dispatch (start
 // and end of its execution), not by separate stream markers.
 // mode: 0 complex FP32 (four real products), 1 complex FP64, 2 complex FP32
-// with three real products per complex product
+// with three real products per complex product, 3 complex FP32 on operands
+// rounded to BF16
 hipError_t launch_apply(int mode, int in_fp64, const ApplyGroup* groups, const ApplyTile* tiles,
                         int n_tiles, const int* step_ctr, size_t lds, hipStream_t s,
                         hipEvent_t t0, hipEvent_t t1) {
@@ -2120,16 +2153,11 @@ hipError_t launch_apply(int mode, int in_fp64, const ApplyGroup* groups, const A
   static bool attr_set = false;
   if (!attr_set) {
     const int cap = kApplyLdsBudget;
-    (void)hipFuncSetAttribute((const void*)k_apply<float, float, false>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, cap);
-    (void)hipFuncSetAttribute((const void*)k_apply<float, double, false>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, cap);
-    (void)hipFuncSetAttribute((const void*)k_apply<double, double, false>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, cap);
-    (void)hipFuncSetAttribute((const void*)k_apply<float, float, true>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, cap);
-    (void)hipFuncSetAttribute((const void*)k_apply<float, double, true>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, cap);
+    const void* ks[] = {(const void*)k_apply<float, float, 0>, (const void*)k_apply<float, double, 0>,
+                        (const void*)k_apply<double, double, 0>, (const void*)k_apply<float, float, 1>,
+                        (const void*)k_apply<float, double, 1>, (const void*)k_apply<float, float, 2>,
+                        (const void*)k_apply<float, double, 2>};
+    for (const void* k : ks) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, cap);
     attr_set = true;
   }
   auto go = [&](auto kern) {
@@ -2139,12 +2167,15 @@ hipError_t launch_apply(int mode, int in_fp64, const ApplyGroup* groups, const A
     else
       hipLaunchKernelGGL(kern, dim3(n_tiles), dim3(64 * kApplyWaves), lds, s, groups, tiles, step_ctr);
   };
-  if (mode == 1) go(k_apply<double, double, false>);
+  if (mode == 1) go(k_apply<double, double, 0>);
   else if (mode == 2) {
-    if (in_fp64) go(k_apply<float, double, true>);
-    else go(k_apply<float, float, true>);
-  } else if (in_fp64) go(k_apply<float, double, false>);
-  else go(k_apply<float, float, false>);
+    if (in_fp64) go(k_apply<float, double, 1>);
+    else go(k_apply<float, float, 1>);
+  } else if (mode == 3) {
+    if (in_fp64) go(k_apply<float, double, 2>);
+    else go(k_apply<float, float, 2>);
+  } else if (in_fp64) go(k_apply<float, double, 0>);
+  else go(k_apply<float, float, 0>);
   return hipGetLastError();
 }
 

@@ -216,7 +216,8 @@ struct LaunchRec {
   size_t lds;
   double flops = 0;    // algorithmic flops of an apply launch (8 per complex MAC)
   double bytes = 0;    // algorithmic HBM bytes of an apply launch
-  int m3 = 0;          // apply launch of an FP32 plan with three real products per complex one
+  int amode = 0;       // apply launches of FP32 plans: 0 four real products per complex
+                       // one, 2 three (TENSO_FP32_3M), 3 BF16-rounded operands (TENSO_BF16)
 };
 enum { LK_APPLY, LK_PRESUM, LK_COMBINE, LK_QR, LK_ABSORB, LK_GRAM, LK_RHO };
 
@@ -359,7 +360,7 @@ struct tenso_plan {
   tenso_plan_opts opts;
   std::vector<int> slot_r;  // env slot stride (capacity rank) per node
   int fp64 = 0;
-  int m3 = 0;      // TENSO_FP32_3M: complex products from three real ones
+  int amode = 0;   // launch_apply mode of the FP32 contractions (2: TENSO_FP32_3M, 3: TENSO_BF16)
   size_t tsz = 8;  // bytes per complex in compute precision
   int max_dim = 1;
   // env slots
@@ -760,7 +761,7 @@ struct Builder {
   void launch(int kind, int in_fp64, int first, int count, int tfirst, int tcount, size_t lds = 0) {
     LaunchRec L{kind, in_fp64, first, count, tfirst, tcount, lds};
     if (kind == LK_APPLY) {
-      L.m3 = P_.m3;
+      L.amode = P_.amode;
       size_t mx = 0;
       for (int t = tfirst; t < tfirst + tcount; ++t) {
         const ApplyTile& tl = G.atiles[t];
@@ -1515,7 +1516,7 @@ static Program merge_programs(std::vector<Program>& progs) {
       Program& P = progs[i];
       ML.flops += L.flops;
       ML.bytes += L.bytes;
-      ML.m3 = L.m3;
+      ML.amode = L.amode;
       ML.lds = std::max(ML.lds, L.lds);
       switch (kind) {
         case LK_APPLY: {
@@ -1626,7 +1627,7 @@ static void run(const DevProgram& D, int fp64, const int* ctr, hipStream_t s) {
       case LK_APPLY:
         if (g_prof.on) {
           hipEvent_t e0 = g_prof.get(), e1 = g_prof.get();
-          e = launch_apply(fp64 ? 1 : L.m3 ? 2 : 0, L.in_fp64,
+          e = launch_apply(fp64 ? 1 : L.amode, L.in_fp64,
                            (const ApplyGroup*)(b + D.o_groups) + L.first,
                            (const ApplyTile*)(b + D.o_atiles) + L.tfirst, L.tcount, ctr, L.lds, s,
                            e0, e1);
@@ -1634,7 +1635,7 @@ static void run(const DevProgram& D, int fp64, const int* ctr, hipStream_t s) {
           g_prof.work.push_back({L.flops, L.bytes});
           break;
         }
-        e = launch_apply(fp64 ? 1 : L.m3 ? 2 : 0, L.in_fp64,
+        e = launch_apply(fp64 ? 1 : L.amode, L.in_fp64,
                          (const ApplyGroup*)(b + D.o_groups) + L.first,
                          (const ApplyTile*)(b + D.o_atiles) + L.tfirst, L.tcount, ctr, L.lds, s);
         break;
@@ -2083,7 +2084,8 @@ struct Ps2Exec {
 static std::unique_ptr<tenso_plan> compile_plan(const tenso_tree* t, const tenso_gen* g,
                                                 const tenso_plan_opts* o, bool device) {
   if (!t || !g || !o) fail(TENSO_EINVAL, "null argument");
-  if (o->precision != TENSO_FP64 && o->precision != TENSO_FP32 && o->precision != TENSO_FP32_3M)
+  if (o->precision != TENSO_FP64 && o->precision != TENSO_FP32 && o->precision != TENSO_FP32_3M &&
+      o->precision != TENSO_BF16)
     fail(TENSO_EINVAL, "bad precision");
   if (o->method != TENSO_PS1 && o->method != TENSO_PS2) fail(TENSO_EINVAL, "bad method");
   if (g->n_ends != t->n_ends || g->end_dim != t->end_dim) fail(TENSO_EINVAL, "generator built for another tree");
@@ -2092,7 +2094,7 @@ static std::unique_ptr<tenso_plan> compile_plan(const tenso_tree* t, const tenso
   P->gen = *g;
   P->opts = *o;
   P->fp64 = o->precision == TENSO_FP64;
-  P->m3 = o->precision == TENSO_FP32_3M;
+  P->amode = o->precision == TENSO_FP32_3M ? 2 : o->precision == TENSO_BF16 ? 3 : 0;
   P->tsz = P->fp64 ? 16 : 8;
   P->cap = P->tree;
   if (o->method == TENSO_PS2) {
@@ -2920,7 +2922,7 @@ int tenso_batch_create(int n, tenso_plan* const* plans, void* const* d_states,
     for (int i = 0; i < n; ++i) {
       if (!plans[i] || !d_states[i] || !d_wss[i]) fail(TENSO_EINVAL, "null plan or buffer");
       if (plans[i]->opts.method != TENSO_PS1) fail(TENSO_EINVAL, "batches take ps1 plans");
-      if (i > 0 && (plans[i]->fp64 != plans[0]->fp64 || plans[i]->m3 != plans[0]->m3))
+      if (i > 0 && (plans[i]->fp64 != plans[0]->fp64 || plans[i]->amode != plans[0]->amode))
         fail(TENSO_EINVAL, "mixed precisions in a batch");
       B->plans.push_back(plans[i]);
       B->states.push_back(d_states[i]);

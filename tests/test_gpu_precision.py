@@ -2,7 +2,8 @@
 train over its 2000 steps in complex FP64, complex FP32 with four real MFMA
 products per complex product, and FP32 with three (Gauss), each against the
 stored FP64 oracle trajectory; the trace distance is printed at several
-horizons and bounded at the end."""
+horizons and bounded at the end.  BF16 operands (8-bit mantissa) are run for
+the record only: they miss the fixed-rank 1e-6 bar by orders of magnitude."""
 import numpy as np
 import pytest
 
@@ -14,7 +15,7 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("name,precision,tol", [("fp64", 0, 1e-9), ("fp32", 1, 1e-6),
-                                                 ("fp32-3m", 2, 1e-6)])
+                                                 ("fp32-3m", 2, 1e-6), ("bf16", 3, 1.0)])
 def test_precision_study_spin_boson_train(name, precision, tol):
     require_gpu()
     from paper_2603_17711_amd import api
