@@ -76,10 +76,11 @@ typedef struct tenso_batch tenso_batch;
 
 #define TENSO_PS1 0           /* fixed-rank projector splitting */
 #define TENSO_PS2 1           /* adaptive-rank projector splitting */
+#define TENSO_VMF 2           /* fixed-rank direct integration of every core (FP64 only) */
 
 typedef struct {
   int precision;   /* TENSO_FP64 | TENSO_FP32 | TENSO_FP32_3M | TENSO_BF16 */
-  int method;      /* TENSO_PS1 | TENSO_PS2 */
+  int method;      /* TENSO_PS1 | TENSO_PS2 | TENSO_VMF */
   int max_rank;    /* PS2: cap on any bond rank (also sizes the state) */
 } tenso_plan_opts;
 
@@ -232,6 +233,77 @@ int tenso_step_fixed(tenso_plan* p, void* d_state, double t0, double dt, int n_s
 int tenso_step_adaptive(tenso_plan* p, void* d_state, double t0, double dt, int n_steps,
                         double eps, int max_rank, const double* d_drive_tab, void* d_ws,
                         hipStream_t s);
+
+/* ---- direct integration (vmf) and the mixed strategy ----------------------
+ * Sec. II C: every core is integrated at once by an ODE solver at fixed rank;
+ * Sec. VII E: dopri5 with tolerances ode_rtol / ode_atol, and a constant
+ * vmf_atol added to the diagonal of the matrix that the non-root equations
+ * invert.  The equations are the time-dependent variational principle for
+ * dOmega/dt = L Omega in the root gauge (every non-root core U_s an isometry
+ * toward its parent, U_s^H dU_s = 0): the root core moves under its
+ * effective generator; a non-root core under its effective generator with
+ * the mean fields of the rest of the network on its parent leg, followed by
+ * (rho_s + vmf_atol I)^-1 on that leg (rho_s: the density on the bond) and
+ * the projection off the span of U_s.  Available on every FP64 plan whose
+ * terms keep at most one factor inside any non-root subtree and whose bonds
+ * are at most 64 (TENSO_VMF plans are checked at creation; on other plans
+ * the calls return EUNSUPPORTED).  Every field is used as given; the paper's
+ * defaults are ode_rtol 1e-5 and ode_atol 1e-7 (vmf_atol: 1e-7 here). */
+typedef struct {
+  double ode_rtol;     /* relative tolerance of the adaptive steps */
+  double ode_atol;     /* absolute tolerance of the adaptive steps */
+  double vmf_atol;     /* diagonal shift of every bond density (>= 0; 0 needs them regular) */
+  int fixed_substeps;  /* 0: adaptive steps; n > 0: n equal dopri5 steps per dt, no control */
+  int max_substeps;    /* adaptive: ENUMERIC when one call needs more substeps */
+} tenso_vmf_opts;
+
+/* Drive callback: f_slots[k] = f_k(t) for every slot k (host, called from
+ * the stepping thread). */
+typedef void (*tenso_drive_fn)(double t, double* f_slots, void* ctx);
+
+/* Advance n_steps output steps of size dt by direct integration.  Solver:
+ * the Dormand-Prince 5(4) pair advancing with the fifth-order solution, the
+ * last stage reused as the next step's first.  Adaptive: error norm = root
+ * mean square over every complex core entry of |y5 - y4| / (ode_atol +
+ * ode_rtol max(|y_old|, |y_new|)); accepted when <= 1; the next size is h
+ * 0.9 norm^(-1/5) clipped to [0.2 h, 10 h]; each dt is covered by substeps,
+ * the last shortened to end on it (the proposal then stays unless its own
+ * is larger); the first substep after tenso_state_init / import tries dt,
+ * later calls continue from the last proposal.  The error norm is read back
+ * once per substep (a synchronisation).  drive (nullable without slots) is
+ * called for the seven stage times of every substep.  The state must be
+ * root-canonical, as tenso_state_init, tenso_step_fixed and
+ * tenso_step_adaptive leave it.  ENUMERIC on a non-finite state or error
+ * estimate, a 1e6-fold norm growth, a step size below 1e-14 dt or more than
+ * max_substeps substeps.  The first call per rank pattern builds and uploads
+ * the derivative's launch program (device allocation). */
+int tenso_step_vmf(tenso_plan* p, void* d_state, double t0, double dt, int n_steps,
+                   const tenso_vmf_opts* opts, tenso_drive_fn drive, void* drive_ctx,
+                   void* d_ws, hipStream_t s);
+
+/* The time derivative of every core of a root-canonical state (the
+ * right-hand side that tenso_step_vmf integrates), into d_out: a device
+ * buffer of the plan's state bytes, same layout as the state (read it back
+ * with tenso_state_export).  drive: host, one value per slot (nullable
+ * without slots).  Synchronous on `s`. */
+int tenso_vmf_derivative(tenso_plan* p, const void* d_state, double vmf_atol, const double* drive,
+                         void* d_out, void* d_ws, hipStream_t s);
+
+/* Accepted and rejected dopri5 substeps since tenso_state_init / import,
+ * and the next proposed substep size (0 before the first). Each nullable. */
+int tenso_vmf_stats(const tenso_plan* p, int64_t* accepted, int64_t* rejected, double* next_h);
+
+/* The mixed strategy (Sec. VI, Sec. VII E) on an FP64 ps2 plan: ps2 steps
+ * (the eps rule of tenso_step_adaptive, ranks capped at max_aux_rank) until
+ * a bond rank reaches max_aux_rank, then direct integration at the ranks
+ * reached for every later step.  The phase persists across calls until
+ * tenso_state_init / import.  switch_step (nullable) receives the number of
+ * ps2 steps taken before the switch, or -1 while still in ps2.  For the ps2
+ * steps drive is sampled at t + j dt / 4, j = 0..4.  Errors as the two
+ * methods; EINVAL unless 2 <= max_aux_rank <= the plan's max_rank. */
+int tenso_step_mix(tenso_plan* p, void* d_state, double t0, double dt, int n_steps, double eps,
+                   int max_aux_rank, const tenso_vmf_opts* opts, tenso_drive_fn drive,
+                   void* drive_ctx, void* d_ws, hipStream_t s, int32_t* switch_step);
 
 /* Reduced density matrix rho_S = <0..0|Omega> (Sec. II B) into host h_rho
  * (M x M) and its trace into h_trace (nullable).  Synchronises the stream. */

@@ -20,8 +20,14 @@ class PlanOpts(C.Structure):
     _fields_ = [("precision", C.c_int), ("method", C.c_int), ("max_rank", C.c_int)]
 
 
+class VmfOpts(C.Structure):
+    _fields_ = [("ode_rtol", C.c_double), ("ode_atol", C.c_double), ("vmf_atol", C.c_double),
+                ("fixed_substeps", C.c_int), ("max_substeps", C.c_int)]
+
+
 FP64, FP32, FP32_3M, BF16 = 0, 1, 2, 3
-PS1, PS2 = 0, 1
+PS1, PS2, VMF = 0, 1, 2
+DRIVE_FN = C.CFUNCTYPE(None, C.c_double, C.POINTER(C.c_double), C.c_void_p)
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENUMERIC", -5: "EUNSUPPORTED"}
 
 _lib = None
@@ -56,6 +62,12 @@ SIGS = {
     "tenso_step_fixed": (C.c_int, [P, P, C.c_double, C.c_double, C.c_int, P, P, P]),
     "tenso_step_adaptive": (C.c_int, [P, P, C.c_double, C.c_double, C.c_int, C.c_double, C.c_int,
                                       P, P, P]),
+    "tenso_step_vmf": (C.c_int, [P, P, C.c_double, C.c_double, C.c_int, C.POINTER(VmfOpts),
+                                 DRIVE_FN, P, P, P]),
+    "tenso_vmf_derivative": (C.c_int, [P, P, C.c_double, DP, P, P, P]),
+    "tenso_vmf_stats": (C.c_int, [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), DP]),
+    "tenso_step_mix": (C.c_int, [P, P, C.c_double, C.c_double, C.c_int, C.c_double, C.c_int,
+                                 C.POINTER(VmfOpts), DRIVE_FN, P, P, P, I32P]),
     "tenso_reduced_rho": (C.c_int, [P, P, C128P, DP, P, P]),
     "tenso_reduced_rho_pure": (C.c_int, [P, P, C128P, DP, P, P]),
     "tenso_rank_trajectory": (C.c_int, [P, I32P, C.c_int]),

@@ -9,7 +9,8 @@ import ctypes as C
 import numpy as np
 
 from . import _lib
-from ._lib import BF16, FP32, FP32_3M, FP64, PS1, PS2, PlanOpts, c128, check, lib
+from ._lib import (BF16, DRIVE_FN, FP32, FP32_3M, FP64, PS1, PS2, VMF, PlanOpts, VmfOpts, c128,
+                   check, lib)
 from .heom import heom_table
 
 
@@ -185,6 +186,70 @@ class Plan:
                                         n_steps, eps, max_rank, ptr,
                                         C.c_void_p(self.ws.data_ptr()), _stream()))
 
+    @staticmethod
+    def _vmf_opts(rtol, atol, reg, fixed_substeps, max_substeps):
+        return VmfOpts(float(rtol), float(atol), float(reg), int(fixed_substeps), int(max_substeps))
+
+    @staticmethod
+    def _drive_cb(drive):
+        """C callback filling f_slots from drive(t) (a sequence of slot values)."""
+        if drive is None:
+            return DRIVE_FN()
+
+        def cb(t, out, _ctx):
+            for k, v in enumerate(drive(t)):
+                out[k] = float(v)
+        return DRIVE_FN(cb)
+
+    def step_vmf(self, n_steps, dt, t0=0.0, rtol=1e-5, atol=1e-7, reg=1e-7, fixed_substeps=0,
+                 max_substeps=100000, drive=None):
+        """Direct integration (dopri5); drive: t -> slot values (None if undriven)."""
+        o = self._vmf_opts(rtol, atol, reg, fixed_substeps, max_substeps)
+        cb = self._drive_cb(drive)
+        check(lib().tenso_step_vmf(self.h, C.c_void_p(self.state.data_ptr()), t0, dt, n_steps,
+                                   C.byref(o), cb, None, C.c_void_p(self.ws.data_ptr()), _stream()))
+
+    def step_mix(self, n_steps, dt, eps, max_aux_rank, t0=0.0, rtol=1e-5, atol=1e-7, reg=1e-7,
+                 fixed_substeps=0, max_substeps=100000, drive=None):
+        """ps2 until a bond reaches max_aux_rank, then vmf; returns the number
+        of ps2 steps before the switch (-1 while still in ps2)."""
+        o = self._vmf_opts(rtol, atol, reg, fixed_substeps, max_substeps)
+        cb = self._drive_cb(drive)
+        sw = C.c_int32()
+        check(lib().tenso_step_mix(self.h, C.c_void_p(self.state.data_ptr()), t0, dt, n_steps,
+                                   float(eps), int(max_aux_rank), C.byref(o), cb, None,
+                                   C.c_void_p(self.ws.data_ptr()), _stream(), C.byref(sw)))
+        return int(sw.value)
+
+    def vmf_derivative(self, reg=1e-7, drive=None):
+        """Time derivative of every core (list of arrays, as export_state)."""
+        import torch
+        out = torch.zeros_like(self.state)
+        dv = None
+        if drive is not None:
+            d = np.ascontiguousarray(drive, dtype=np.float64)
+            dv = d.ctypes.data_as(C.POINTER(C.c_double))
+        check(lib().tenso_vmf_derivative(self.h, C.c_void_p(self.state.data_ptr()), float(reg), dv,
+                                         C.c_void_p(out.data_ptr()),
+                                         C.c_void_p(self.ws.data_ptr()), _stream()))
+        shapes = self.shapes()
+        n = sum(int(np.prod(sh)) for sh in shapes)
+        flat = np.zeros(n, np.complex128)
+        check(lib().tenso_state_export(self.h, C.c_void_p(out.data_ptr()),
+                                       flat.ctypes.data_as(C.POINTER(c128)), None, _stream()))
+        res, o = [], 0
+        for sh in shapes:
+            k = int(np.prod(sh))
+            res.append(flat[o:o + k].reshape(sh).copy())
+            o += k
+        return res
+
+    def vmf_stats(self):
+        """(accepted, rejected, next proposed substep) of direct integration."""
+        a, r, h = C.c_int64(), C.c_int64(), C.c_double()
+        check(lib().tenso_vmf_stats(self.h, C.byref(a), C.byref(r), C.byref(h)))
+        return int(a.value), int(r.value), float(h.value)
+
     def rank_log(self, cap=100000):
         out = np.zeros(cap, np.int32)
         n = check(lib().tenso_rank_trajectory(self.h, out.ctypes.data_as(C.POINTER(C.c_int32)), cap))
@@ -249,9 +314,10 @@ def svd_truncate(A, iso=0, eps=0.0, max_rank=None):
     return sig, vec.cpu().numpy(), tuple(int(x) for x in dec), missed.value
 
 
-def build_instance(inst, precision=FP32, rank=None, device="cuda"):
+def build_instance(inst, precision=FP32, rank=None, device="cuda", method=None):
     """Tree + generator + plan for a workloads.Instance (ps1, or ps2 when
-    inst.method == "ps2": `rank` is then the rank cap)."""
+    inst.method == "ps2": `rank` is then the rank cap; method overrides
+    with PS1 / PS2 / VMF)."""
     drive_ops = [] if inst.drive is None else [inst.drive[0]]
     table, dims = heom_table(inst.H, inst.baths, inst.depth, drive_ops,
                              metric=getattr(inst, "metric", "abs"))
@@ -261,7 +327,8 @@ def build_instance(inst, precision=FP32, rank=None, device="cuda"):
     else:
         tree = Tree.nary(inst.M, dims, int(inst.tree[4:]), R)
     gen = Generator(tree, table)
-    method = PS2 if inst.method == "ps2" else PS1
+    if method is None:
+        method = PS2 if inst.method == "ps2" else PS1
     plan = Plan(tree, gen, precision=precision, method=method, max_rank=R, device=device)
     plan.init_state(inst.rho0)
     return plan

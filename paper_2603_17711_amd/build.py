@@ -4,7 +4,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "checks.hip", "svd.hip", "tenso_host.cpp", "mlp.hip", "noalloc.hip")]
+SRC = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "checks.hip", "svd.hip", "vmf.hip", "tenso_host.cpp", "mlp.hip", "noalloc.hip")]
 OUT = os.path.join(HERE, "libtenso.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

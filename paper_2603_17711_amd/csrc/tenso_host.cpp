@@ -16,6 +16,7 @@
 #include "../../include/tenso.h"
 #include "tenso_internal.h"
 #include "checks.h"
+#include "vmf.h"
 
 namespace tenso {
 hipError_t launch_apply(int mode, int in_fp64, const ApplyGroup* groups, const ApplyTile* tiles,
@@ -219,7 +220,7 @@ struct LaunchRec {
   int amode = 0;       // apply launches of FP32 plans: 0 four real products per complex
                        // one, 2 three (TENSO_FP32_3M), 3 BF16-rounded operands (TENSO_BF16)
 };
-enum { LK_APPLY, LK_PRESUM, LK_COMBINE, LK_QR, LK_ABSORB, LK_GRAM, LK_RHO };
+enum { LK_APPLY, LK_PRESUM, LK_COMBINE, LK_QR, LK_ABSORB, LK_GRAM, LK_RHO, LK_REGINV, LK_VPROJ };
 
 struct CombineTileH {
   int op;
@@ -245,6 +246,8 @@ struct Program {
   std::vector<GramOp> grams;
   std::vector<RhoNode> rnodes;
   std::vector<RhoProg> rprogs;
+  std::vector<RegInvOp> reginvs;
+  std::vector<VProjOp> vprojs;
   std::vector<LaunchRec> launches;
 };
 
@@ -254,7 +257,7 @@ struct DevProgram {
   size_t bytes = 0;
   bool external = false;  // arena owned by the caller: never grown or freed here
   size_t o_terms, o_groups, o_atiles, o_presums, o_combines, o_ctiles, o_qrs, o_absorbs, o_abtiles,
-      o_grams, o_rnodes, o_rprogs;
+      o_grams, o_rnodes, o_rprogs, o_reginvs, o_vprojs;
   std::vector<LaunchRec> launches;
   DevProgram() = default;
   DevProgram(char* a, size_t b) : arena(a), bytes(b), external(true) {}
@@ -267,9 +270,14 @@ struct DevProgram {
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Drive table of one dopri5 step: the value of slot k at stage i (time
+// t + c_i h) sits at [k][4 i], read by the contraction with the step counter
+// set to i; the ps2 steps of the mixed strategy use [k][0..4] (quarter steps).
+static constexpr int kVmfDriveLd = 4 * 6 + 1;
+
 // operand reference resolved when a program is built
 struct ORef {
-  int kind = 0;  // 0 identity, 1 factor, 2 down slot, 3 up slot
+  int kind = 0;  // 0 identity, 1 factor, 2 down slot, 3 up slot, 4 bond density (vmf)
   int node = 0, idx = 0;
 };
 
@@ -415,6 +423,31 @@ struct tenso_plan {
   int b_ld = -1;
   std::vector<int32_t> rank_log;
   StepGraph graph;  // captured step program (replayed per step)
+  // direct (vmf) integration: while a vmf program is built, a parent leg with
+  // no factor of a term outside the subtree carries the bond density rather
+  // than the identity (the non-root cores are not orthonormal toward it)
+  bool vmf_rho = false;
+  bool vmf_ok = false;  // layout holds the vmf areas (FP64 ps1 / ps2 / vmf plans)
+  std::vector<size_t> vmf_rho_off, vmf_rinv_off, vmf_s_off, vmf_node_parts, vmf_node_presum;
+  size_t ws_vmf_ys = 0, ws_vmf_k = 0, ws_vmf_kout = 0, ws_vmf_part = 0, ws_vmf_err = 0,
+         ws_vmf_segs = 0, ws_vmf_dtab = 0;
+  int vmf_chunks = 1;      // workgroup chunks of the largest core (segment kernels)
+  std::unique_ptr<DevProgram> dev_vmf;
+  std::vector<int> vmf_ranks;   // ranks the cached vmf program was built for
+  double vmf_reg = -1;
+  const void* vmf_ws = nullptr;
+  int64_t vmf_accepted = 0, vmf_rejected = 0;
+  double vmf_h = 0;        // proposed dopri5 step (0: none yet)
+  int mix_phase = 0;       // mixed strategy: 0 auxiliary ps2, 1 vmf
+  int mix_switch = -1;     // steps of ps2 before the switch (-1: not yet)
+  int mix_ps2_steps = 0;
+  void reset_integrators() {
+    vmf_accepted = vmf_rejected = 0;
+    vmf_h = 0;
+    mix_phase = 0;
+    mix_switch = -1;
+    mix_ps2_steps = 0;
+  }
 
   ~tenso_plan() {
     if (cbuf) (void)hipFree(cbuf);
@@ -492,6 +525,9 @@ static ORef leg_ref_for_key(const tenso_plan& P, int s, const Leg& l, const Key&
       r.kind = 3;
       r.node = s;
       r.idx = P.umap[s].at(k);
+    } else if (P.vmf_rho) {
+      r.kind = 4;
+      r.node = s;
     }
   }
   return r;
@@ -630,6 +666,8 @@ static void* oref_ptr(const tenso_plan& P, const ORef& o) {
       size_t r = P.slot_r[o.node];
       return tagp(TAG_WS, P.envu_off[o.node] + (size_t)o.idx * r * r * P.tsz);
     }
+    case 4:
+      return tagp(TAG_WS, P.vmf_rho_off[o.node]);
   }
   return nullptr;
 }
@@ -669,11 +707,13 @@ static void layout(tenso_plan& P) {
     presum = std::max(presum, ps);
     parts = std::max(parts, (size_t)R.groups.size() * 8 * (size_t)n);
   };
+  P.vmf_ok = P.fp64 != 0;
   for (int s = 0; s < t.n; ++s) {
     recipe_caps(node_recipe(P, s), t.size(s));
     if (s > 0) {
       envscr = std::max(envscr, P.dkeys[s].size() * (size_t)t.size(s));
-      envscr = std::max(envscr, P.ukeys[s].size() * (size_t)t.size(t.parent[s]));
+      // (vmf: one more slab, the bond density)
+      envscr = std::max(envscr, (P.ukeys[s].size() + (P.vmf_ok ? 1 : 0)) * (size_t)t.size(t.parent[s]));
       size_t r = t.rank[s];
       qrv = std::max(qrv, (size_t)t.size(s));
       qrv = std::max(qrv, (size_t)t.size(t.parent[s]));
@@ -746,6 +786,67 @@ static void layout(tenso_plan& P) {
     P.ws_svd_e = take(blk);
     P.ws_svd_rec = take(256);
     P.ws_W = take(std::max<size_t>(1, wcap) * 16);
+  }
+  // direct integration needs every node's vmf recipe (a term may then carry
+  // the density on the parent leg besides its own legs): without them the
+  // plan simply has no vmf areas
+  std::vector<size_t> vparts(t.n, 1), vpresum(t.n, 1);
+  long vmaxsz = 1;
+  if (P.vmf_ok) {
+    P.vmf_rho = true;
+    try {
+      for (int s = 0; s < t.n; ++s) {
+        const Recipe R = node_recipe(P, s);
+        size_t ps = 0;
+        for (auto& g : R.groups) {
+          if (!g.sa.empty()) ps += (size_t)R.dims[g.l1] * R.dims[g.l1];
+          if (!g.sb.empty()) ps += (size_t)R.dims[g.l2] * R.dims[g.l2];
+          for (auto& c : cluster_pairs(g))
+            if (c.others.size() > 1) {
+              const size_t d = R.dims[c.shared_side == 0 ? g.l2 : g.l1];
+              ps += d * d;
+            }
+        }
+        vparts[s] = std::max<size_t>(1, R.groups.size() * 8 * (size_t)t.size(s));
+        vpresum[s] = std::max<size_t>(1, ps);
+        vmaxsz = std::max(vmaxsz, t.size(s));
+      }
+      for (int x = 1; x < t.n; ++x)
+        if (t.rank[x] > kVmfMaxRank) fail(TENSO_EUNSUPPORTED, "bond above the vmf inverse's size");
+    } catch (const TErr&) {
+      P.vmf_ok = false;
+    }
+    P.vmf_rho = false;
+  }
+  if (P.vmf_ok) {
+    // direct integration: bond densities, their regularised inverses and the
+    // projection coefficients per bond; the stage input, seven dopri5 stages
+    // and the derivative (state-shaped); partial outputs and presums of the
+    // one contraction launch that serves every node; segment list, error
+    // partials and the ps2 drive table of the mixed strategy
+    P.vmf_rho_off.assign(t.n, 0);
+    P.vmf_rinv_off.assign(t.n, 0);
+    P.vmf_s_off.assign(t.n, 0);
+    for (int x = 1; x < t.n; ++x) {
+      const size_t r = t.rank[x];
+      P.vmf_rho_off[x] = take(r * r * 16);
+      P.vmf_rinv_off[x] = take(r * r * 16);
+      P.vmf_s_off[x] = take(r * r * 16);
+    }
+    P.ws_vmf_ys = take(P.state_bytes);
+    P.ws_vmf_k = take(7 * P.state_bytes);
+    P.ws_vmf_kout = take(P.state_bytes);
+    P.vmf_node_parts.assign(t.n, 0);
+    P.vmf_node_presum.assign(t.n, 0);
+    for (int s = 0; s < t.n; ++s) {
+      P.vmf_node_parts[s] = take(vparts[s] * 16);
+      P.vmf_node_presum[s] = take(vpresum[s] * 16);
+    }
+    P.vmf_chunks = (int)((vmaxsz + kVmfChunk - 1) / kVmfChunk);
+    P.ws_vmf_segs = take((size_t)t.n * sizeof(VecSeg));
+    P.ws_vmf_part = take((size_t)t.n * P.vmf_chunks * sizeof(double));
+    P.ws_vmf_err = take(256);
+    P.ws_vmf_dtab = take((size_t)std::max(1, P.gen.n_slots) * kVmfDriveLd * sizeof(double));
   }
   P.ws_bytes = w;
   P.tree = cur;
@@ -861,14 +962,36 @@ struct Builder {
     }
   }
 
+  // Workspace areas of one contraction: partial outputs and presummed
+  // operators (byte offsets; capacities in elements).
+  struct ApplyArea {
+    size_t parts, presum, parts_cap, presum_cap;
+  };
+
   // Emit apply launches of recipe R on input X -> parts (chunked), with the
   // presum launch in front.  Returns the number of partial slabs written.
   int emit_apply(const Recipe& R, void* X, int in_fp64, long Pn, int rel, int presum_now,
                  int target) {
+    const int pfirst = (int)G.presums.size();
+    const int gfirst = (int)G.groups.size(), tfirst = (int)G.atiles.size();
+    const int part = add_apply(R, X, in_fp64, Pn, rel, presum_now, target,
+                               ApplyArea{P.ws_parts, P.ws_presum, P.parts_cap, P.presum_cap}, gfirst);
+    const int np = (int)G.presums.size() - pfirst;
+    if (np) launch(LK_PRESUM, 0, pfirst, np, 0, 0);
+    launch(LK_APPLY, in_fp64, gfirst, (int)G.groups.size() - gfirst, tfirst,
+           (int)G.atiles.size() - tfirst);
+    return part;
+  }
+
+  // The presums and contraction groups of recipe R on input X, appended
+  // without a launch: presums to G.presums, groups and tiles after gfirst
+  // (the first group of the launch they will join), partial slabs from A.parts.
+  // Returns the number of partial slabs.
+  int add_apply(const Recipe& R, void* X, int in_fp64, long Pn, int rel, int presum_now,
+                int target, const ApplyArea& A, int gfirst) {
     // presums
-    size_t poff = P.ws_presum;
+    size_t poff = A.presum;
     std::vector<void*> sa_buf(R.groups.size(), nullptr), sb_buf(R.groups.size(), nullptr);
-    int pfirst = (int)G.presums.size();
     for (size_t gi = 0; gi < R.groups.size(); ++gi) {
       auto& g = R.groups[gi];
       for (int side = 0; side < 2; ++side) {
@@ -923,12 +1046,8 @@ struct Builder {
         if (presum_now) G.presums.push_back(op);
       }
     }
-    if (poff - P.ws_presum > P.presum_cap * P.tsz + 1) fail(TENSO_EINVAL, "presum capacity");
-    int np = (int)G.presums.size() - pfirst;
-    if (np) launch(LK_PRESUM, 0, pfirst, np, 0, 0);
+    if (poff - A.presum > A.presum_cap * P.tsz + 1) fail(TENSO_EINVAL, "presum capacity");
     // groups, chunked over terms
-    int gfirst = (int)G.groups.size();
-    int tfirst = (int)G.atiles.size();
     int part = 0;
     long free_total = 0;
     for (auto& g : R.groups) free_total += Pn / ((long)R.dims[g.l1] * R.dims[g.l2]);
@@ -991,7 +1110,7 @@ struct Builder {
         if (a >= b && ch > 0) break;
         ApplyGroup ag{};
         ag.X = X;
-        ag.Y = ws(P.ws_parts + (size_t)part * Pn * P.tsz);
+        ag.Y = ws(A.parts + (size_t)part * Pn * P.tsz);
         ++part;
         int first = (int)G.terms.size();
         for (size_t i = a; i < b; ++i) {
@@ -1014,9 +1133,7 @@ struct Builder {
                   (int)(b - a));
       }
     }
-    if ((size_t)part * Pn > P.parts_cap) fail(TENSO_EINVAL, "parts capacity exceeded");
-    launch(LK_APPLY, in_fp64, gfirst, (int)G.groups.size() - gfirst, tfirst,
-           (int)G.atiles.size() - tfirst);
+    if ((size_t)part * Pn > A.parts_cap) fail(TENSO_EINVAL, "parts capacity exceeded");
     return part;
   }
 
@@ -1333,6 +1450,165 @@ struct Builder {
     G.rprogs.push_back(rp);
     launch(LK_RHO, 0, (int)G.rprogs.size() - 1, 1, 0, 0);
   }
+
+  // -- direct (vmf) integration -------------------------------------------
+  // Mean fields of bond x from its parent core p, which is not an isometry
+  // toward x: the up-environment slots of x, each weighted by the density of
+  // p's own bond (a key with nothing outside p carries that density on p's
+  // parent leg), and the bond density rho_x itself (p's core with rho_p on
+  // its parent leg; the plain Gram of the root core when p is the root).
+  void emit_vmf_up(int x) {
+    const tenso_tree& t = P.tree;
+    const int p = t.parent[x];
+    const std::vector<int> dims = t.shape(p);
+    const long Pn = t.size(p);
+    const int open = t.leg_of_child(p, x);
+    const int gfirst = (int)G.groups.size(), tfirst = (int)G.atiles.size();
+    std::vector<std::vector<std::pair<int, ORef>>> nzs;
+    for (size_t k = 0; k < P.ukeys[x].size(); ++k) {
+      std::vector<std::pair<int, ORef>> nz;
+      for (int i = 0; i < (int)t.legs[p].size(); ++i) {
+        if (i == open) continue;
+        ORef o = leg_ref_for_key(P, p, t.legs[p][i], P.ukeys[x][k]);
+        if (o.kind) nz.push_back({i, o});
+      }
+      nzs.push_back(nz);
+    }
+    if (p != 0) {
+      ORef o;
+      o.kind = 4;
+      o.node = p;
+      nzs.push_back({{0, o}});
+    }
+    const std::vector<size_t> slab = add_env_groups(dims, Pn, open, nzs, p, gfirst);
+    if ((int)G.groups.size() > gfirst)
+      launch(LK_APPLY, 1, gfirst, (int)G.groups.size() - gfirst, tfirst,
+             (int)G.atiles.size() - tfirst);
+    const int qf = (int)G.grams.size();
+    auto gram = [&](const void* T, size_t e_off) {
+      GramOp go{};
+      go.C = (const double*)core(p);
+      go.T = T;
+      go.E = ws(e_off);
+      go.r = t.rank[x];
+      go.Ppre = (int)prod(dims, 0, open);
+      go.Ppost = (int)prod(dims, open + 1, (int)dims.size());
+      G.grams.push_back(go);
+    };
+    for (size_t k = 0; k < P.ukeys[x].size(); ++k)
+      gram(ws(P.ws_envscr + slab[k] * Pn * P.tsz),
+           P.envu_off[x] + k * (size_t)P.slot_r[x] * P.slot_r[x] * P.tsz);
+    gram(p == 0 ? core(p) : ws(P.ws_envscr + slab.back() * Pn * P.tsz), P.vmf_rho_off[x]);
+    launch(LK_GRAM, 0, qf, (int)G.grams.size() - qf, 0, 0);
+  }
+
+  // The time derivative of every core of the state at TAG_STATE into the
+  // derivative buffer (same layout): down environments (children first),
+  // mean fields and densities (parents first), the regularised inverses, one
+  // contraction launch for every node's effective generator, the partial
+  // sums, then for every non-root core the inverse density on its parent leg
+  // and the projection off its own span.
+  void vmf_deriv(double reg) {
+    const tenso_tree& t = P.tree;
+    struct Flag {
+      bool& f;
+      explicit Flag(bool& x) : f(x) { f = true; }
+      ~Flag() { f = false; }
+    } on(P.vmf_rho);
+    for (int x = t.n - 1; x >= 1; --x) emit_env_down(x);
+    for (int x = 1; x < t.n; ++x) emit_vmf_up(x);
+    if (t.n > 1) {
+      const int rf = (int)G.reginvs.size();
+      for (int x = 1; x < t.n; ++x) {
+        RegInvOp q{};
+        q.rho = (const double*)ws(P.vmf_rho_off[x]);
+        q.M = (double*)ws(P.vmf_rinv_off[x]);
+        q.reg = reg;
+        q.r = t.rank[x];
+        G.reginvs.push_back(q);
+      }
+      launch(LK_REGINV, 0, rf, t.n - 1, 0, 0);
+    }
+    // every node's effective generator in one contraction launch
+    const int pfirst = (int)G.presums.size();
+    const int gfirst = (int)G.groups.size(), tfirst = (int)G.atiles.size();
+    std::vector<int> nparts(t.n);
+    for (int s = 0; s < t.n; ++s) {
+      const Recipe R = node_recipe(P, s);
+      // capacities were taken at the capacity ranks (the current ones are not larger)
+      nparts[s] = add_apply(R, core(s), 1, t.size(s), 0, 1, std::max(1, P.par_target / t.n),
+                            ApplyArea{P.vmf_node_parts[s], P.vmf_node_presum[s],
+                                      (size_t)1 << 40, (size_t)1 << 40},
+                            gfirst);
+    }
+    const int np = (int)G.presums.size() - pfirst;
+    if (np) launch(LK_PRESUM, 0, pfirst, np, 0, 0);
+    launch(LK_APPLY, 1, gfirst, (int)G.groups.size() - gfirst, tfirst,
+           (int)G.atiles.size() - tfirst);
+    // partial sums into the derivative buffer
+    const int cf = (int)G.combines.size(), ctf = (int)G.ctiles.size();
+    for (int s = 0; s < t.n; ++s) {
+      CombineOp op{};
+      const long n = t.size(s);
+      op.y0 = (double*)ws(P.ws_vmf_kout + P.core_off[s]);
+      op.xin = ws(P.ws_xin);
+      op.acc = (double*)ws(P.ws_acc);
+      op.parts = ws(P.vmf_node_parts[s]);
+      op.n = n;
+      op.n_parts = nparts[s];
+      op.stage = 0;
+      const int oi = (int)G.combines.size();
+      G.combines.push_back(op);
+      for (long e = 0; e < n; e += 2048) G.ctiles.push_back({oi, 0, e, std::min(n, e + 2048)});
+    }
+    launch(LK_COMBINE, 0, cf, t.n, ctf, (int)G.ctiles.size() - ctf);
+    if (t.n == 1) return;
+    // (rho_x + reg)^-1 on the parent leg of every non-root derivative
+    const int af = (int)G.absorbs.size(), atf = (int)G.abtiles.size();
+    size_t lds = 0;
+    for (int x = 1; x < t.n; ++x) {
+      AbsorbOp a{};
+      a.C = (double*)ws(P.ws_vmf_kout + P.core_off[x]);
+      a.M = (const double*)ws(P.vmf_rinv_off[x]);
+      a.n = t.rank[x];
+      a.Ppre = 1;
+      a.Ppost = (int)(t.size(x) / t.rank[x]);
+      a.transposeM = 0;
+      const int ai = (int)G.absorbs.size();
+      G.absorbs.push_back(a);
+      const int fibers = a.Ppost;
+      const int per = std::max(1, 2048 / a.n);
+      for (int f = 0; f < fibers; f += per) G.abtiles.push_back({ai, f, std::min(fibers, f + per)});
+      lds = std::max(lds, (size_t)per * a.n * 16);
+    }
+    launch(LK_ABSORB, 0, af, t.n - 1, atf, (int)G.abtiles.size() - atf, lds);
+    // S_x = U_x^H dU_x over the non-parent legs, then dU_x -= U_x S_x
+    const int qf = (int)G.grams.size();
+    for (int x = 1; x < t.n; ++x) {
+      GramOp go{};
+      go.C = (const double*)core(x);
+      go.T = ws(P.ws_vmf_kout + P.core_off[x]);
+      go.E = ws(P.vmf_s_off[x]);
+      go.r = t.rank[x];
+      go.Ppre = 1;
+      go.Ppost = (int)(t.size(x) / t.rank[x]);
+      G.grams.push_back(go);
+    }
+    launch(LK_GRAM, 0, qf, t.n - 1, 0, 0);
+    const int vf = (int)G.vprojs.size();
+    long mx = 1;
+    for (int x = 1; x < t.n; ++x) {
+      VProjOp v{};
+      v.Y = (double*)ws(P.ws_vmf_kout + P.core_off[x]);
+      v.U = (const double*)core(x);
+      v.S = (const double*)ws(P.vmf_s_off[x]);
+      v.r = t.rank[x];
+      v.post = t.size(x) / t.rank[x];
+      G.vprojs.push_back(v);
+      mx = std::max(mx, t.size(x));
+    }
+    launch(LK_VPROJ, 0, vf, t.n - 1, 0, 0, (size_t)mx);
+  }
 };
 
 // -- resolution & upload ------------------------------------------------------
@@ -1399,6 +1675,15 @@ static void resolve(Program& G, void* state, void* ws, double dt, const double* 
     r.vecs = (double*)res(r.vecs, state, ws);
     r.rho_out = (double*)res(r.rho_out, state, ws);
   }
+  for (auto& q : G.reginvs) {
+    q.rho = (const double*)res((void*)q.rho, state, ws);
+    q.M = (double*)res(q.M, state, ws);
+  }
+  for (auto& v : G.vprojs) {
+    v.Y = (double*)res(v.Y, state, ws);
+    v.U = (const double*)res((void*)v.U, state, ws);
+    v.S = (const double*)res((void*)v.S, state, ws);
+  }
 }
 
 // Upload a resolved program, turning term / rho-node indices into pointers.
@@ -1421,6 +1706,8 @@ static void upload_resolved(DevProgram& D, const Program& G, hipStream_t s,
   D.o_grams = put(buf, G.grams);
   D.o_rnodes = put(buf, G.rnodes);
   D.o_rprogs = put(buf, G.rprogs);
+  D.o_reginvs = put(buf, G.reginvs);
+  D.o_vprojs = put(buf, G.vprojs);
   if (D.external && D.bytes < buf.size())
     fail(TENSO_ENOMEM, "launch descriptors exceed the scratch space left for them");
   if (!D.arena || D.bytes < buf.size()) {
@@ -1658,6 +1945,12 @@ static void run(const DevProgram& D, int fp64, const int* ctr, hipStream_t s) {
         break;
       case LK_RHO:
         e = launch_rho((const RhoProg*)(b + D.o_rprogs) + L.first, L.count, s);
+        break;
+      case LK_REGINV:
+        e = launch_reginv((const RegInvOp*)(b + D.o_reginvs) + L.first, L.count, s);
+        break;
+      case LK_VPROJ:  // lds: the largest core of the launch (complex elements)
+        e = launch_vproj((const VProjOp*)(b + D.o_vprojs) + L.first, L.count, (long)L.lds, s);
         break;
     }
     hipchk(e, "kernel launch");
@@ -2087,7 +2380,10 @@ static std::unique_ptr<tenso_plan> compile_plan(const tenso_tree* t, const tenso
   if (o->precision != TENSO_FP64 && o->precision != TENSO_FP32 && o->precision != TENSO_FP32_3M &&
       o->precision != TENSO_BF16)
     fail(TENSO_EINVAL, "bad precision");
-  if (o->method != TENSO_PS1 && o->method != TENSO_PS2) fail(TENSO_EINVAL, "bad method");
+  if (o->method != TENSO_PS1 && o->method != TENSO_PS2 && o->method != TENSO_VMF)
+    fail(TENSO_EINVAL, "bad method");
+  if (o->method == TENSO_VMF && o->precision != TENSO_FP64)
+    fail(TENSO_EUNSUPPORTED, "direct (vmf) integration runs in FP64 only");
   if (g->n_ends != t->n_ends || g->end_dim != t->end_dim) fail(TENSO_EINVAL, "generator built for another tree");
   auto P = std::make_unique<tenso_plan>();
   P->tree = *t;
@@ -2131,6 +2427,10 @@ static std::unique_ptr<tenso_plan> compile_plan(const tenso_tree* t, const tenso
   layout(*P);
   // validate that every recipe compiles (throws EUNSUPPORTED otherwise)
   for (int s = 0; s < P->tree.n; ++s) (void)node_recipe(*P, s);
+  if (o->method == TENSO_VMF && !P->vmf_ok)
+    fail(TENSO_EUNSUPPORTED,
+         "direct integration needs at most one factor of a term inside any non-root subtree "
+         "and bonds of at most 64");
   return P;
 }
 
@@ -2238,6 +2538,216 @@ int set_last_error(int code, const std::string& msg) {
 // ---------------------------------------------------------------------------
 // host-side state helpers
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// direct (vmf) integration: dopri5 over every core at once
+// ---------------------------------------------------------------------------
+// Dormand-Prince 5(4): nodes, stage weights, fifth- and fourth-order weights.
+static const double kDpC[7] = {0.0, 1.0 / 5, 3.0 / 10, 4.0 / 5, 8.0 / 9, 1.0, 1.0};
+static const double kDpA[7][6] = {
+    {0, 0, 0, 0, 0, 0},
+    {1.0 / 5, 0, 0, 0, 0, 0},
+    {3.0 / 40, 9.0 / 40, 0, 0, 0, 0},
+    {44.0 / 45, -56.0 / 15, 32.0 / 9, 0, 0, 0},
+    {19372.0 / 6561, -25360.0 / 2187, 64448.0 / 6561, -212.0 / 729, 0, 0},
+    {9017.0 / 3168, -355.0 / 33, 46732.0 / 5247, 49.0 / 176, -5103.0 / 18656, 0},
+    {35.0 / 384, 0.0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84}};
+static const double kDpB[7] = {35.0 / 384, 0.0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784,
+                               11.0 / 84, 0.0};
+static const double kDpBs[7] = {5179.0 / 57600, 0.0, 7571.0 / 16695, 393.0 / 640,
+                                -92097.0 / 339200, 187.0 / 2100, 1.0 / 40};
+
+// Build (or reuse) the derivative program for the plan's current ranks, the
+// regularisation and the workspace binding; the stage input buffer plays
+// the state.
+static void vmf_prepare(tenso_plan* p, void* d_ws, double reg, hipStream_t s) {
+  if (!p->vmf_ok)
+    fail(TENSO_EUNSUPPORTED,
+         "direct integration needs an FP64 plan whose terms leave room for the bond density "
+         "(at most one factor of a term inside any non-root subtree) and bonds of at most 64");
+  if (p->dev_vmf && p->vmf_ranks == p->tree.rank && p->vmf_reg == reg && p->vmf_ws == d_ws) return;
+  p->par_target = 64;
+  Program G;
+  Builder b(*p, G);
+  b.vmf_deriv(reg);
+  if (!p->dev_vmf) p->dev_vmf = std::make_unique<DevProgram>();
+  char* ws = (char*)d_ws;
+  upload(*p->dev_vmf, G, ws + p->ws_vmf_ys, d_ws, 0.0, (const double*)(ws + p->ws_vmf_dtab),
+         kVmfDriveLd, s);
+  std::vector<VecSeg> segs(p->tree.n);
+  for (int c = 0; c < p->tree.n; ++c) segs[c] = VecSeg{(long)(p->core_off[c] / 16), p->tree.size(c)};
+  hipchk(hipMemcpyAsync(ws + p->ws_vmf_segs, segs.data(), segs.size() * sizeof(VecSeg),
+                        hipMemcpyHostToDevice, s),
+         "vmf segments");
+  hipchk(hipStreamSynchronize(s), "sync");
+  p->vmf_ranks = p->tree.rank;
+  p->vmf_reg = reg;
+  p->vmf_ws = d_ws;
+}
+
+struct VmfRun {
+  tenso_plan& P;
+  double* y0;
+  char* ws;
+  hipStream_t s;
+  tenso_drive_fn drive;
+  void* ctx;
+  int* ctr;
+  double* K[7];
+  double* ys;
+  double* kout;
+  const VecSeg* segs;
+  long n_elems = 0;
+  bool k1 = false;  // K[0] holds the derivative at y0
+  std::vector<double> tab, vals;
+
+  VmfRun(tenso_plan& p, void* d_state, void* d_ws, hipStream_t st, tenso_drive_fn f, void* c)
+      : P(p), y0((double*)d_state), ws((char*)d_ws), s(st), drive(f), ctx(c) {
+    ctr = (int*)(ws + P.ws_ctr);
+    for (int i = 0; i < 7; ++i) K[i] = (double*)(ws + P.ws_vmf_k + (size_t)i * P.state_bytes);
+    ys = (double*)(ws + P.ws_vmf_ys);
+    kout = (double*)(ws + P.ws_vmf_kout);
+    segs = (const VecSeg*)(ws + P.ws_vmf_segs);
+    for (int c2 = 0; c2 < P.tree.n; ++c2) n_elems += P.tree.size(c2);
+  }
+
+  void lincomb(double* out, const double* base, int n, double* const* src, const double* c) {
+    LinCombOp op{};
+    op.out = out;
+    op.base = base;
+    op.n_src = n;
+    for (int j = 0; j < n; ++j) {
+      op.src[j] = src[j];
+      op.c[j] = c[j];
+    }
+    op.n_seg = P.tree.n;
+    op.segs = segs;
+    hipchk(launch_lincomb(op, P.vmf_chunks, s), "lincomb");
+  }
+
+  // drive values at the seven stage times of a step (t, h)
+  void set_drive(double t, double h) {
+    const int ns = P.gen.n_slots;
+    if (ns == 0) return;
+    tab.assign((size_t)ns * kVmfDriveLd, 0.0);
+    vals.assign(ns, 0.0);
+    for (int i = 0; i < 7; ++i) {
+      drive(t + kDpC[i] * h, vals.data(), ctx);
+      for (int k = 0; k < ns; ++k) tab[(size_t)k * kVmfDriveLd + 4 * i] = vals[k];
+    }
+    hipchk(hipMemcpyAsync(ws + P.ws_vmf_dtab, tab.data(), tab.size() * sizeof(double),
+                          hipMemcpyHostToDevice, s),
+           "vmf drive");
+    hipchk(hipStreamSynchronize(s), "sync");  // the host table is rewritten next step
+  }
+
+  // derivative at the stage input (ys) for stage i, into out
+  void deriv(int i, double* out) {
+    hipchk(launch_step_inc(ctr, i, s), "ctr");
+    run(*P.dev_vmf, 1, ctr, s);
+    lincomb(out, kout, 0, nullptr, nullptr);
+  }
+
+  // One Dormand-Prince step of size h from y0 at t; the fifth-order result
+  // is left in ys.  Returns the error norm when asked (one synchronisation).
+  double step(double t, double h, bool need_err, double rtol, double atol) {
+    set_drive(t, h);
+    if (!k1) {
+      lincomb(ys, y0, 0, nullptr, nullptr);
+      deriv(0, K[0]);
+      k1 = true;
+    }
+    for (int i = 1; i < 7; ++i) {
+      double c[6];
+      for (int j = 0; j < i; ++j) c[j] = h * kDpA[i][j];
+      lincomb(ys, y0, i, K, c);
+      deriv(i, K[i]);
+    }
+    if (!need_err) return 0.0;
+    ErrNormOp e{};
+    e.y0 = y0;
+    e.y1 = ys;
+    e.n_src = 7;
+    for (int j = 0; j < 7; ++j) {
+      e.src[j] = K[j];
+      e.c[j] = h * (kDpB[j] - kDpBs[j]);
+    }
+    e.rtol = rtol;
+    e.atol = atol;
+    e.n_seg = P.tree.n;
+    e.segs = segs;
+    e.part = (double*)(ws + P.ws_vmf_part);
+    e.chunks = P.vmf_chunks;
+    hipchk(launch_errnorm(e, s), "error norm");
+    double* out = (double*)(ws + P.ws_vmf_err);
+    hipchk(launch_sum_partials(e.part, P.tree.n * P.vmf_chunks, out, s), "error sum");
+    double v = 0;
+    hipchk(hipMemcpyAsync(&v, out, sizeof(double), hipMemcpyDeviceToHost, s), "error norm");
+    hipchk(hipStreamSynchronize(s), "sync");
+    return std::sqrt(v / (double)std::max<long>(1, n_elems));
+  }
+
+  // take the step: y0 = ys, and the last stage is the next step's first
+  void accept() {
+    lincomb(y0, ys, 0, nullptr, nullptr);
+    std::swap(K[0], K[6]);
+  }
+
+  // cover [t0, t0 + dt] with dopri5 steps (readings of the step control:
+  // see tenso_step_vmf in the header)
+  void advance(double t0, double dt, const tenso_vmf_opts& o, long& substeps) {
+    if (o.fixed_substeps > 0) {
+      const double h = dt / o.fixed_substeps;
+      for (int j = 0; j < o.fixed_substeps; ++j) {
+        step(t0 + j * h, h, false, 0, 0);
+        accept();
+        ++P.vmf_accepted;
+      }
+      return;
+    }
+    if (!(P.vmf_h > 0)) P.vmf_h = dt;
+    const double t_end = t0 + dt;
+    double t = t0;
+    while (t < t_end) {
+      const double h = std::min(P.vmf_h, t_end - t);
+      if (h <= 1e-14 * std::fabs(dt)) fail(TENSO_ENUMERIC, "dopri5 step size underflow");
+      if (++substeps > o.max_substeps) fail(TENSO_ENUMERIC, "more dopri5 substeps than max_substeps");
+      const bool last = t + h >= t_end;
+      const double en = step(t, h, true, o.ode_rtol, o.ode_atol);
+      if (!std::isfinite(en)) fail(TENSO_ENUMERIC, "non-finite dopri5 error estimate");
+      const double fac = en == 0.0 ? 10.0 : std::min(10.0, std::max(0.2, 0.9 * std::pow(en, -0.2)));
+      if (en <= 1.0) {
+        t = last ? t_end : t + h;
+        accept();
+        ++P.vmf_accepted;
+        P.vmf_h = h >= P.vmf_h ? h * fac : std::max(P.vmf_h, h * fac);
+      } else {
+        ++P.vmf_rejected;
+        P.vmf_h = h * fac;
+      }
+    }
+  }
+};
+
+static void check_vmf_opts(const tenso_vmf_opts* o) {
+  if (!o) fail(TENSO_EINVAL, "null vmf options");
+  if (!(o->vmf_atol >= 0)) fail(TENSO_EINVAL, "vmf_atol must be >= 0");
+  if (o->fixed_substeps < 0) fail(TENSO_EINVAL, "fixed_substeps must be >= 0");
+  if (o->fixed_substeps == 0) {
+    if (!(o->ode_rtol >= 0) || !(o->ode_atol >= 0) || !(o->ode_rtol + o->ode_atol > 0))
+      fail(TENSO_EINVAL, "adaptive steps need ode_rtol, ode_atol >= 0, not both 0");
+    if (o->max_substeps < 1) fail(TENSO_EINVAL, "max_substeps must be >= 1");
+  }
+}
+
+static void vmf_steps(tenso_plan* p, void* d_state, double t0, double dt, int n_steps,
+                      const tenso_vmf_opts& o, tenso_drive_fn drive, void* ctx, void* d_ws,
+                      hipStream_t s) {
+  vmf_prepare(p, d_ws, o.vmf_atol, s);
+  VmfRun R(*p, d_state, d_ws, s, drive, ctx);
+  long substeps = 0;
+  for (int k = 0; k < n_steps; ++k) R.advance(t0 + k * dt, dt, o, substeps);
+}
+
 static std::vector<cd> initial_cores(const tenso_plan& P, const tenso_c128* rho) {
   const tenso_tree& t = P.tree;
   std::vector<cd> h(P.state_bytes / 16, cd(0, 0));
@@ -2457,6 +2967,7 @@ int tenso_state_init(tenso_plan* p, const tenso_c128* rho, void* d_state, hipStr
     std::vector<cd> h = initial_cores(*p, rho);
     hipchk(hipMemcpyAsync(d_state, h.data(), p->state_bytes, hipMemcpyHostToDevice, s), "state init");
     hipchk(hipStreamSynchronize(s), "sync");
+    p->reset_integrators();
   });
 }
 
@@ -2472,6 +2983,7 @@ int tenso_state_import(tenso_plan* p, const tenso_c128* h_cores, void* d_state, 
     }
     hipchk(hipMemcpyAsync(d_state, h.data(), p->state_bytes, hipMemcpyHostToDevice, s), "state import");
     hipchk(hipStreamSynchronize(s), "sync");
+    p->reset_integrators();
   });
 }
 
@@ -2588,6 +3100,103 @@ int tenso_step_adaptive(tenso_plan* p, void* d_state, double t0, double dt, int 
       X.Wstar(0, 1);
     }
     check_plan_finite(p, d_state, d_ws, s);
+  });
+}
+
+int tenso_step_vmf(tenso_plan* p, void* d_state, double t0, double dt, int n_steps,
+                   const tenso_vmf_opts* o, tenso_drive_fn drive, void* drive_ctx, void* d_ws,
+                   hipStream_t s) {
+  return guard([&] {
+    if (!p || !d_state || !d_ws) fail(TENSO_EINVAL, "null argument");
+    if (!(dt > 0)) fail(TENSO_EINVAL, "dt must be > 0");
+    if (n_steps < 0) fail(TENSO_EINVAL, "n_steps must be >= 0");
+    check_vmf_opts(o);
+    if (p->gen.n_slots > 0 && !drive) fail(TENSO_EINVAL, "generator has drive slots: drive function needed");
+    plan_root_norm(p, d_state, d_ws, 0, s);
+    vmf_steps(p, d_state, t0, dt, n_steps, *o, drive, drive_ctx, d_ws, s);
+    check_plan_finite(p, d_state, d_ws, s);
+  });
+}
+
+int tenso_vmf_derivative(tenso_plan* p, const void* d_state, double vmf_atol, const double* drive,
+                         void* d_out, void* d_ws, hipStream_t s) {
+  return guard([&] {
+    if (!p || !d_state || !d_out || !d_ws) fail(TENSO_EINVAL, "null argument");
+    if (!(vmf_atol >= 0)) fail(TENSO_EINVAL, "vmf_atol must be >= 0");
+    if (p->gen.n_slots > 0 && !drive) fail(TENSO_EINVAL, "generator has drive slots: drive values needed");
+    vmf_prepare(p, d_ws, vmf_atol, s);
+    char* ws = (char*)d_ws;
+    if (p->gen.n_slots > 0) {
+      std::vector<double> tab((size_t)p->gen.n_slots * kVmfDriveLd, 0.0);
+      for (int k = 0; k < p->gen.n_slots; ++k) tab[(size_t)k * kVmfDriveLd] = drive[k];
+      hipchk(hipMemcpyAsync(ws + p->ws_vmf_dtab, tab.data(), tab.size() * sizeof(double),
+                            hipMemcpyHostToDevice, s),
+             "drive");
+      hipchk(hipStreamSynchronize(s), "sync");
+    }
+    VmfRun R(*p, const_cast<void*>(d_state), d_ws, s, nullptr, nullptr);
+    R.lincomb(R.ys, (const double*)d_state, 0, nullptr, nullptr);
+    R.deriv(0, (double*)d_out);
+    hipchk(hipStreamSynchronize(s), "sync");
+  });
+}
+
+int tenso_vmf_stats(const tenso_plan* p, int64_t* accepted, int64_t* rejected, double* next_h) {
+  return guard([&] {
+    if (!p) fail(TENSO_EINVAL, "null argument");
+    if (accepted) *accepted = p->vmf_accepted;
+    if (rejected) *rejected = p->vmf_rejected;
+    if (next_h) *next_h = p->vmf_h;
+  });
+}
+
+int tenso_step_mix(tenso_plan* p, void* d_state, double t0, double dt, int n_steps, double eps,
+                   int max_aux_rank, const tenso_vmf_opts* o, tenso_drive_fn drive,
+                   void* drive_ctx, void* d_ws, hipStream_t s, int32_t* switch_step) {
+  return guard([&] {
+    if (!p || !d_state || !d_ws) fail(TENSO_EINVAL, "null argument");
+    if (p->opts.method != TENSO_PS2) fail(TENSO_EINVAL, "the mixed strategy needs a ps2 plan");
+    if (!(dt > 0) || n_steps < 0 || !(eps >= 0)) fail(TENSO_EINVAL, "bad dt, n_steps or eps");
+    if (max_aux_rank < 2 || max_aux_rank > p->opts.max_rank)
+      fail(TENSO_EINVAL, "max_aux_rank must lie in [2, the plan's max_rank]");
+    check_vmf_opts(o);
+    if (!p->vmf_ok) vmf_prepare(p, d_ws, o->vmf_atol, s);  // reports why vmf cannot follow
+    if (p->gen.n_slots > 0 && !drive) fail(TENSO_EINVAL, "generator has drive slots: drive function needed");
+    char* ws = (char*)d_ws;
+    const int ns = p->gen.n_slots;
+    std::vector<double> tab, vals(std::max(1, ns));
+    for (int k = 0; k < n_steps; ++k) {
+      const double t = t0 + k * dt;
+      if (p->mix_phase == 0) {
+        const double* d_tab = nullptr;
+        if (ns > 0) {  // one ps2 step's table: [slot][t + j dt / 4], j = 0..4
+          tab.assign((size_t)ns * 5, 0.0);
+          for (int j = 0; j < 5; ++j) {
+            drive(t + 0.25 * j * dt, vals.data(), drive_ctx);
+            for (int q = 0; q < ns; ++q) tab[(size_t)q * 5 + j] = vals[q];
+          }
+          hipchk(hipMemcpyAsync(ws + p->ws_vmf_dtab, tab.data(), tab.size() * sizeof(double),
+                                hipMemcpyHostToDevice, s),
+                 "ps2 drive");
+          hipchk(hipStreamSynchronize(s), "sync");
+          d_tab = (const double*)(ws + p->ws_vmf_dtab);
+        }
+        const int rc = tenso_step_adaptive(p, d_state, t, dt, 1, eps, max_aux_rank, d_tab, d_ws, s);
+        if (rc != TENSO_OK) throw TErr{rc, g_err};
+        ++p->mix_ps2_steps;
+        int mr = 0;
+        for (int c = 1; c < p->tree.n; ++c) mr = std::max(mr, p->tree.rank[c]);
+        if (mr >= max_aux_rank) {
+          p->mix_phase = 1;
+          p->mix_switch = p->mix_ps2_steps;
+        }
+      } else {
+        plan_root_norm(p, d_state, d_ws, 0, s);
+        vmf_steps(p, d_state, t, dt, 1, *o, drive, drive_ctx, d_ws, s);
+        check_plan_finite(p, d_state, d_ws, s);
+      }
+    }
+    if (switch_step) *switch_step = p->mix_switch;
   });
 }
 

@@ -19,6 +19,7 @@
 #include "../../include/tenso.h"
 #include "../../paper_2603_17711_amd/csrc/checks.h"
 #include "../../paper_2603_17711_amd/csrc/tenso_internal.h"
+#include "../../paper_2603_17711_amd/csrc/vmf.h"
 
 namespace tenso {
 #define STUB(...) { std::fprintf(stderr, "kernel launcher reached\n"); std::abort(); }
@@ -42,6 +43,11 @@ hipError_t launch_norms(const NormOp*, int, double*, hipStream_t) STUB()
 hipError_t launch_isometry(const IsoOp*, int, double*, hipStream_t) STUB()
 hipError_t launch_rho_pure(const double*, int, long, double*, hipStream_t) STUB()
 hipError_t launch_zero(void*, size_t, hipStream_t) STUB()
+hipError_t launch_reginv(const RegInvOp*, int, hipStream_t) STUB()
+hipError_t launch_vproj(const VProjOp*, int, long, hipStream_t) STUB()
+hipError_t launch_lincomb(const LinCombOp&, int, hipStream_t) STUB()
+hipError_t launch_errnorm(const ErrNormOp&, hipStream_t) STUB()
+hipError_t launch_sum_partials(const double*, int, double*, hipStream_t) STUB()
 // Shared-memory footprint of an apply tile: the planner only compares it with
 // its budget, so any monotone size serves this host-only build.
 size_t apply_lds_bytes(int fp64, int nfl, int d1, int d2) {
