@@ -46,7 +46,7 @@ def measured_traffic():
 
 
 WORKLOADS = ["batch512", "spin-boson-train", "exciton-7site", "ps2-structured-ternary",
-             "tfd-mctdh",
+             "tfd-mctdh", "vmf-mix",
              "surrogate"]
 
 
@@ -616,6 +616,110 @@ def tfd_main(a):
     print(json.dumps(out))
 
 
+def vmf_main(a):
+    """The spin-boson train under the mixed strategy (Sec. VI, Sec. VII E): ps2
+    (eps 1e-8) from rank 2 until a bond reaches rank 8, then direct (vmf)
+    integration with adaptive dopri5, all FP64; value = output steps per second
+    of the vmf phase (dt = 0.01 per step)."""
+    import ctypes as C
+    import torch
+    import workloads
+    from paper_2603_17711_amd import api
+    from paper_2603_17711_amd._lib import check, lib
+    inst = workloads.spin_boson_train_mix()
+    dt, eps, cap = inst.dt, inst.eps, inst.rank
+
+    def to_vmf(extra):
+        plan = api.build_instance(inst, precision=api.FP64)
+        s, sw = 0, -1
+        while sw < 0:
+            sw = plan.step_mix(1, dt, eps, cap, t0=s * dt)
+            s += 1
+        if extra:
+            plan.step_mix(extra, dt, eps, cap, t0=s * dt)
+        return plan, s + extra, sw
+
+    log("vmf: ps2 phase, then timed vmf steps")
+    plan, s0, sw = to_vmf(a.warmup)
+    acc0, rej0, _ = plan.vmf_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.step_mix(a.steps, dt, eps, cap, t0=s0 * dt)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    acc1, rej1, h = plan.vmf_stats()
+    out = {
+        "metric": METRIC, "value": round(a.steps / el, 3), "unit": "steps/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(1e3 * el / a.steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 (contractions on FP64 MFMA)", "data": "synthetic",
+        "config": {"workload": inst.name + " (dopri5 rtol 1e-5, atol 1e-7; shift 1e-7)",
+                   "instances": 1, "precision": "fp64", "ps2_steps_before_switch": sw,
+                   "substeps_per_step": round((acc1 + rej1 - acc0 - rej0) / a.steps, 3)},
+    }
+    # accuracy: 100 steps against the stored oracle trajectory
+    from tests.golden.make_golden import load
+    g = load("mix_spin_boson_train_100.npz", [inst])
+    plan = api.build_instance(inst, precision=api.FP64)
+    dmax = trace_distance(plan.rho(), g["rho"][0])
+    for k in range(1, 11):
+        sw2 = plan.step_mix(10, dt, eps, cap, t0=10 * (k - 1) * dt)
+        dmax = max(dmax, trace_distance(plan.rho(), g["rho"][k]))
+    acc, rej, _ = plan.vmf_stats()
+    out["trace_distance_vs_oracle"] = {
+        "value": dmax, "steps": 100, "switch": [sw2, int(g["switch"])],
+        "substeps": [[acc, rej], [int(g["accepted"]), int(g["rejected"])]],
+        "sample": "every 10th step against the stored oracle trajectory (switch step and "
+                  "accepted / rejected substeps: library, oracle)"}
+    # contraction kernel inside the vmf derivative
+    prof = max(1, min(a.steps, 10))
+    plan, s0, _ = to_vmf(1)
+    torch.cuda.synchronize()
+    check(lib().tenso_profile(1))
+    plan.step_mix(prof, dt, eps, cap, t0=s0 * dt)
+    torch.cuda.synchronize()
+    ms, n, fl, by = C.c_double(), C.c_int64(), C.c_double(), C.c_double()
+    check(lib().tenso_profile_stats(C.byref(ms), C.byref(n), C.byref(fl), C.byref(by)))
+    check(lib().tenso_profile(0))
+    avg_ms = ms.value / max(1, n.value)
+    achieved = fl.value / max(1, n.value) / (avg_ms * 1e-3) / 1e12
+    out["roofline"] = {
+        "kernel": "k_apply<double> (SOP contraction of every node, MFMA 16x16x4 f64)",
+        "bound": "mfma", "achieved": round(achieved, 4), "peak": PEAK_FP64_MFMA,
+        "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_MFMA, 6), "traffic": None,
+        "avg_launch_us": round(1e3 * avg_ms, 3), "launches": int(n.value),
+        "algorithmic_flops_per_launch": fl.value / max(1, n.value),
+        "algorithmic_bytes_per_launch": by.value / max(1, n.value),
+    }
+    if not a.no_cpu:
+        import copy
+        from threadpoolctl import threadpool_limits
+        from oracle.integrators import Propagator
+        from oracle.run import build
+        from oracle.ttn import initial_state
+        from oracle.vmf import VmfPropagator
+        log("vmf: CPU oracle baseline")
+        terms, tree = build(inst)
+        tree = copy.deepcopy(tree)
+        with threadpool_limits(limits=1):
+            P = Propagator(tree, terms, initial_state(tree, inst.rho0))
+            k = 0
+            while max(tree.rank[1:]) < cap:
+                P.step_ps2(k * dt, dt, eps, cap)
+                k += 1
+            V = VmfPropagator(tree, terms, P.C)
+            n_sample = 20
+            t0 = time.perf_counter()
+            for j in range(n_sample):
+                V.step((k + j) * dt, dt)
+            t_cpu = time.perf_counter() - t0
+        out["cpu_baseline"] = {
+            "value": round(n_sample / t_cpu, 4), "unit": "steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_sample} vmf steps after the switch, FP64 NumPy oracle, 1 BLAS thread",
+        }
+    print(json.dumps(out))
+
+
 def run_main(a):
     import numpy as np
     import torch
@@ -627,6 +731,8 @@ def run_main(a):
         return ps2_main(a)
     if a.workload == "surrogate":
         return surrogate_main(a)
+    if a.workload == "vmf-mix":
+        return vmf_main(a)
     if a.workload == "tfd-mctdh":
         return tfd_main(a)
 

@@ -3,7 +3,7 @@
 Every stored value comes from the FP64 CPU oracle (``oracle/``) run on the seeded
 workloads of ``workloads.py``; nothing here touches the GPU library.
 
-    python tests/golden/make_golden.py [spin_boson|exciton|batch|batch200|ps2|pade|tfd|all] [--procs N]
+    python tests/golden/make_golden.py [spin_boson|exciton|batch|batch200|ps2|pade|tfd|mix|all] [--procs N]
 
 Files (numpy .npz, no pickles):
   spin_boson_train_2000.npz   spin-boson K=3 N=10 train R=8, ps1, 2000 steps,
@@ -31,6 +31,12 @@ Files (numpy .npz, no pickles):
                               (50 star modes of Fock dimension 8, binary tree R=16,
                               1 fs steps), ps1 on the wavefunction, 100 steps, rho_S
                               at every 10th step
+  mix_spin_boson_train_100.npz  the spin-boson train under the mixed strategy: ps2
+                              (eps 1e-8) until a bond reaches rank 8, then vmf with
+                              adaptive dopri5 (rtol 1e-5, atol 1e-7, shift 1e-7);
+                              100 steps, rho_S at every 10th step, the number of ps2
+                              steps before the switch (`switch`) and the accepted and
+                              rejected dopri5 substeps (`accepted`, `rejected`)
   ps2_ternary_cap8_10.npz     structured bath K=24 N=10 on the ternary tree, ps2 with
                               eps 1e-6 and rank cap 8, 10 steps: rho_S at every step
                               and the rank chosen at every split (`ranks`, one row
@@ -174,6 +180,24 @@ def write_tfd(n_steps, every, fname):
     print(f"{fname}: {len(steps)} records, {time.time() - t0:.1f} s", flush=True)
 
 
+def write_mix(n_steps, every, fname):
+    import copy
+    import workloads
+    from oracle.run import build
+    from oracle.ttn import initial_state
+    from oracle.vmf import propagate_mix
+    t0 = time.time()
+    inst = workloads.spin_boson_train_mix(n_steps)
+    terms, tree = build(inst)
+    steps, rhos, switch, prop = propagate_mix(copy.deepcopy(tree), terms,
+                                              initial_state(tree, inst.rho0), inst.dt, n_steps,
+                                              inst.eps, inst.rank, every=every)
+    np.savez_compressed(os.path.join(HERE, fname), steps=steps, rho=rhos, dt=inst.dt,
+                        switch=switch, accepted=prop.ode.accepted, rejected=prop.ode.rejected,
+                        digest=workload_digest([inst]))
+    print(f"{fname}: {len(steps)} records, switch {switch}, {time.time() - t0:.1f} s", flush=True)
+
+
 def write_batch(n_steps, every, fname, pool, ids=None, spread=False):
     import workloads
     insts = workloads.uneven_batch()
@@ -207,7 +231,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("what", nargs="?", default="all",
                     choices=["spin_boson", "exciton", "batch", "batch200", "ps2", "pade", "tfd",
-                             "all"])
+                             "mix", "all"])
     ap.add_argument("--procs", type=int, default=os.cpu_count())
     a = ap.parse_args()
     os.environ.setdefault("OMP_NUM_THREADS", "1")
@@ -226,6 +250,8 @@ def main():
             write_ps2(10, 8, "ps2_ternary_cap8_10.npz", pool)
         if a.what in ("tfd", "all"):
             write_tfd(100, 10, "tfd_spin_boson_100.npz")
+        if a.what in ("mix", "all"):
+            write_mix(100, 10, "mix_spin_boson_train_100.npz")
 
 
 if __name__ == "__main__":

@@ -196,3 +196,27 @@ def test_vmf_error_paths():
         p64.step_vmf(1, 0.01, rtol=0.0, atol=0.0)
     with pytest.raises(TensoError, match="EUNSUPPORTED"):
         api.build_instance(inst, precision=api.FP32, method=api.VMF)
+
+
+def test_mix_spin_boson_train_against_stored_oracle():
+    """The spin-boson train under the mixed strategy with the default
+    tolerances over 100 steps: the same switch, the same accepted and
+    rejected substeps, rho_S at every 10th step."""
+    require_gpu()
+    from paper_2603_17711_amd import api
+    from tests.golden.make_golden import load
+    inst = workloads.spin_boson_train_mix()
+    g = load("mix_spin_boson_train_100.npz", [inst])
+    print("[mix] spin-boson train, 100 steps, against the stored oracle", flush=True)
+    plan = api.build_instance(inst, precision=api.FP64)
+    ds = [trace_distance(plan.rho(), g["rho"][0])]
+    sw = -1
+    for k in range(1, 11):
+        sw = plan.step_mix(10, inst.dt, inst.eps, inst.rank, t0=10 * (k - 1) * inst.dt)
+        ds.append(trace_distance(plan.rho(), g["rho"][k]))
+    acc, rej, _ = plan.vmf_stats()
+    print(f"  switch {sw} (oracle {int(g['switch'])}), substeps {acc}/{rej} "
+          f"(oracle {int(g['accepted'])}/{int(g['rejected'])}), max trace distance {max(ds):.2e}")
+    assert sw == int(g["switch"])
+    assert (acc, rej) == (int(g["accepted"]), int(g["rejected"]))
+    assert max(ds) < 1e-9

@@ -127,6 +127,17 @@ def structured_spin_boson_pade(n_steps=50, depth=25, rank=16, dt_fs=0.1):
                     "train", rank, rho0, dt_fs * FS_TO_CM, n_steps)
 
 
+def spin_boson_train_mix(n_steps=100, eps=1e-8, max_aux_rank=8):
+    """The spin-boson train under the mixed strategy (Sec. VI, Sec. VII E):
+    ps2 from rank 2 with eps 1e-8 until a bond reaches rank 8, then direct
+    integration at the ranks reached (dopri5, ode_rtol 1e-5, ode_atol 1e-7,
+    vmf_atol 1e-7), output every dt = 0.01."""
+    base = spin_boson_train(n_steps)
+    return Instance("spin-boson K=3 N=10 train, ps2 (eps 1e-8) then vmf at rank 8", base.H,
+                    base.baths, base.depth, base.tree, max_aux_rank, base.rho0, base.dt, n_steps,
+                    method="ps2", eps=eps)
+
+
 class TfdInstance:
     """A thermofield ML-MCTDH problem: system H_S, coupling Q, one Brownian
     bath (lam, w0, eta) at T discretised into n_modes star modes on
