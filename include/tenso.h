@@ -289,6 +289,17 @@ int tenso_step_vmf(tenso_plan* p, void* d_state, double t0, double dt, int n_ste
 int tenso_vmf_derivative(tenso_plan* p, const void* d_state, double vmf_atol, const double* drive,
                          void* d_out, void* d_ws, hipStream_t s);
 
+/* The ps2 truncation rule by an absolute threshold (Sec. VII E: ps2_atol and
+ * ps2_ratio; paper defaults 1e-7 and 2): with ps2_ratio >= 1 every later ps2
+ * split (tenso_step_adaptive, the ps2 part of tenso_step_mix) keeps r' =
+ * min(max_rank, available, ceil(ps2_ratio r_atol)) directions, r_atol the
+ * number of singular values above ps2_atol (at least 1): the discarded part
+ * of the spectrum just below the threshold is partly taken back, in
+ * proportion to what was kept.  The eps argument is then ignored.
+ * ps2_ratio = 0 restores the eps rule (the default).  No device work.
+ * EINVAL on ps2_atol < 0 or 0 < ps2_ratio < 1. */
+int tenso_plan_set_ps2_truncation(tenso_plan* p, double ps2_atol, double ps2_ratio);
+
 /* Accepted and rejected dopri5 substeps since tenso_state_init / import,
  * and the next proposed substep size (0 before the first). Each nullable. */
 int tenso_vmf_stats(const tenso_plan* p, int64_t* accepted, int64_t* rejected, double* next_h);

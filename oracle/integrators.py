@@ -28,6 +28,12 @@ Readings (documented):
   spectrum).  ps2 starts from the padded initial state at rank 2: with
   rank-1 bonds every two-site tensor of a tree whose inner nodes carry no
   physical leg has a side of dimension 1 and no bond could ever grow.
+  Alternative rule (Sec. VII E, ps2_atol and ps2_ratio): r_atol = the number
+  of singular values above ps2_atol (at least 1), keep r' = min(max_rank,
+  available, ceil(ps2_ratio * r_atol)): of the discarded spectrum, the
+  directions just below the threshold are taken back in proportion to what
+  was kept (reading: the paper says only that a fraction set by the ratio is
+  reincorporated).
   Directions beyond the singular vectors with s_i > 1e-10 s_1 are completed
   by projecting e_0, e_1, ... onto the orthogonal complement of the kept
   singular subspace (deterministic, independent of the vectors' phases).
@@ -139,9 +145,10 @@ def qr_toward(C, leg):
 class Propagator:
     """ps1 / ps2 propagation of a TTN state (the paper's SparsePropagator)."""
 
-    def __init__(self, tree, terms, cores, drive_fn=None):
+    def __init__(self, tree, terms, cores, drive_fn=None, trunc=None):
         self.tree = tree
         self.terms = terms
+        self.trunc = trunc        # None: the eps rule; (ps2_atol, ps2_ratio): the atol rule
         self.C = [c.copy() for c in cores]
         self.drive_fn = drive_fn
         self.envs = Envs(tree, terms)
@@ -219,6 +226,13 @@ class Propagator:
         return max(1, min(max_rank, avail, r_eps + grow))
 
     @staticmethod
+    def truncation_rank_atol(s, atol, ratio, max_rank, avail):
+        """r_atol = #(s_i > atol), at least 1; keep r' = min(max_rank, avail,
+        ceil(ratio * r_atol))."""
+        r_atol = max(1, int(np.sum(np.asarray(s) > atol)))
+        return max(1, min(max_rank, avail, int(np.ceil(ratio * r_atol))))
+
+    @staticmethod
     def complete_isometry(U, r):
         """Columns U (n x k, orthonormal) completed to n x r: the unit vectors
         e_0, e_1, ... are projected onto the orthogonal complement of span(U)
@@ -250,7 +264,10 @@ class Propagator:
         rows = int(np.prod(shp[:ns]))
         mat = Th.reshape(rows, -1)
         U, S, Vh = np.linalg.svd(mat, full_matrices=False)
-        r = self.truncation_rank(S, eps, max_rank, min(mat.shape))
+        if self.trunc is not None:
+            r = self.truncation_rank_atol(S, self.trunc[0], self.trunc[1], max_rank, min(mat.shape))
+        else:
+            r = self.truncation_rank(S, eps, max_rank, min(mat.shape))
         k = int(np.sum(S > SVD_ZERO_TOL * S[0])) if S[0] > 0 else 0
         k = min(k, r)
         if center_to_child:

@@ -261,13 +261,15 @@ class VmfPropagator:
 
 
 def propagate_mix(tree, terms, cores, dt, n_steps, eps, max_aux_rank, drive_fn=None,
-                  reg=VMF_ATOL, rtol=ODE_RTOL, atol=ODE_ATOL, fixed_substeps=0, every=1):
+                  reg=VMF_ATOL, rtol=ODE_RTOL, atol=ODE_ATOL, fixed_substeps=0, every=1,
+                  trunc=None):
     """Mixed strategy: ps2 (eps rule, rank cap max_aux_rank) until a bond rank
     reaches max_aux_rank, then vmf at the ranks reached.  Returns (steps,
-    rho records, index of the first vmf step or n_steps, propagator)."""
+    rho records, index of the first vmf step or n_steps, propagator).  trunc:
+    (ps2_atol, ps2_ratio) for the atol truncation rule of ps2, None for eps."""
     from .integrators import Propagator
     from .ttn import reduced_rho
-    P = Propagator(tree, terms, cores, drive_fn=drive_fn)
+    P = Propagator(tree, terms, cores, drive_fn=drive_fn, trunc=trunc)
     V = None
     switch = n_steps
     rhos, steps = [P.rho()], [0]

@@ -66,6 +66,7 @@ SIGS = {
                                  DRIVE_FN, P, P, P]),
     "tenso_vmf_derivative": (C.c_int, [P, P, C.c_double, DP, P, P, P]),
     "tenso_vmf_stats": (C.c_int, [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), DP]),
+    "tenso_plan_set_ps2_truncation": (C.c_int, [P, C.c_double, C.c_double]),
     "tenso_step_mix": (C.c_int, [P, P, C.c_double, C.c_double, C.c_int, C.c_double, C.c_int,
                                  C.POINTER(VmfOpts), DRIVE_FN, P, P, P, I32P]),
     "tenso_reduced_rho": (C.c_int, [P, P, C128P, DP, P, P]),

@@ -244,6 +244,11 @@ class Plan:
             o += k
         return res
 
+    def set_ps2_truncation(self, atol=0.0, ratio=0.0):
+        """ps2 splits keep ceil(ratio * #(sigma > atol)) directions (ratio >= 1);
+        ratio = 0 restores the eps rule."""
+        check(lib().tenso_plan_set_ps2_truncation(self.h, float(atol), float(ratio)))
+
     def vmf_stats(self):
         """(accepted, rejected, next proposed substep) of direct integration."""
         a, r, h = C.c_int64(), C.c_int64(), C.c_double()

@@ -286,7 +286,9 @@ __global__ void __launch_bounds__(kJacThreads) k_svd_jacobi(const SvdJacobiOp* _
 // total (r_eps >= 1; eps = 0 keeps every direction); the kept rank is
 // r' = max(1, min(max_rank, cap_r, min(rows, cols), r_eps + 1)); k counts
 // the singular values above 1e-10 s_1, at most r'.  rec_i = {r', k, r_eps},
-// rec_d = {total, m}.
+// rec_d = {total, m}.  With ratio > 0 the count r_atol of singular values
+// above atol (at least 1) replaces r_eps, and r' = max(1, min(max_rank,
+// cap_r, min(rows, cols), ceil(ratio r_atol))).
 __global__ void __launch_bounds__(256) k_svd_finish(const SvdFinishOp* __restrict__ ops) {
   const SvdFinishOp op = ops[0];
   const int p = op.p;
@@ -325,7 +327,14 @@ __global__ void __launch_bounds__(256) k_svd_finish(const SvdFinishOp* __restric
           break;
         }
     r_eps = max(1, r_eps);
-    const int rp = max(1, min(min(op.max_rank, op.cap_r), min(avail, r_eps + 1)));
+    int want = r_eps + 1;
+    if (op.ratio > 0.0) {
+      int r_atol = 0;
+      for (int i = 0; i < p; ++i) r_atol += s[i] > op.atol ? 1 : 0;
+      r_eps = max(1, r_atol);
+      want = (int)ceil(op.ratio * (double)r_eps);
+    }
+    const int rp = max(1, min(min(op.max_rank, op.cap_r), min(avail, want)));
     int k = 0;
     if (s[0] > 0.0)
       for (int i = 0; i < p; ++i) k += s[i] > 1e-10 * s[0] ? 1 : 0;

@@ -441,6 +441,7 @@ struct tenso_plan {
   int mix_phase = 0;       // mixed strategy: 0 auxiliary ps2, 1 vmf
   int mix_switch = -1;     // steps of ps2 before the switch (-1: not yet)
   int mix_ps2_steps = 0;
+  double ps2_atol = 0, ps2_ratio = 0;  // ps2 truncation by an absolute threshold (ratio > 0)
   void reset_integrators() {
     vmf_accepted = vmf_rejected = 0;
     vmf_h = 0;
@@ -2126,7 +2127,8 @@ static int svd_width(long rows, long cols, int max_rank, int cap_r) {
 
 static int svd_truncate(const SvdScratch& sc, const double* theta, long rows, long cols, int iso,
                         double eps, int max_rank, int cap_r, hipStream_t s,
-                        std::vector<std::vector<char>>& hold, int rec_i[3], double rec_d[2]) {
+                        std::vector<std::vector<char>>& hold, int rec_i[3], double rec_d[2],
+                        double atol = 0.0, double ratio = 0.0) {
   const int full = (int)std::min<long>({(long)kSvdP, rows, cols});
   int p = svd_width(rows, cols, max_rank, cap_r);
   const int keep = std::max(1, std::min({max_rank, cap_r, p}));
@@ -2172,7 +2174,7 @@ static int svd_truncate(const SvdScratch& sc, const double* theta, long rows, lo
       hipchk(launch_svd_jacobi(svd_put(sc, 2, jo, s, hold), s), "svd jacobi");
       SvdFinishOp fo{sc.y, sc.z, sc.up, sc.wp, sc.sig, sc.norm, sc.e, (int*)sc.rec,
                      (double*)(sc.rec + 64), eps, n_norm, (int)rows, (int)cols, p, iso, max_rank,
-                     cap_r, 0};
+                     cap_r, 0, atol, ratio};
       hipchk(launch_svd_finish(svd_put(sc, 3, fo, s, hold), (iso == 0 ? rows : cols) * (long)p, s),
              "svd finish");
       hipchk(hipMemcpyAsync(rec_i, sc.rec, 3 * sizeof(int), hipMemcpyDeviceToHost, s), "decision");
@@ -2319,7 +2321,8 @@ struct Ps2Exec {
     int rec_i[3] = {0, 0, 0};
     double rec_d[2] = {0, 0};
     const int p =
-        svd_truncate(sc, theta, rows, cols, iso, eps, max_rank, P.cap.rank[c], s, hold, rec_i, rec_d);
+        svd_truncate(sc, theta, rows, cols, iso, eps, max_rank, P.cap.rank[c], s, hold, rec_i, rec_d,
+                     P.ps2_atol, P.ps2_ratio);
     const int rp = rec_i[0], k = rec_i[1];
     if (rp < 1 || rp > P.cap.rank[c] || k < 0 || k > rp)
       fail(TENSO_ENUMERIC, "ps2 truncation decision out of range");
@@ -3138,6 +3141,16 @@ int tenso_vmf_derivative(tenso_plan* p, const void* d_state, double vmf_atol, co
     R.lincomb(R.ys, (const double*)d_state, 0, nullptr, nullptr);
     R.deriv(0, (double*)d_out);
     hipchk(hipStreamSynchronize(s), "sync");
+  });
+}
+
+int tenso_plan_set_ps2_truncation(tenso_plan* p, double ps2_atol, double ps2_ratio) {
+  return guard([&] {
+    if (!p) fail(TENSO_EINVAL, "null argument");
+    if (!(ps2_atol >= 0) || !(ps2_ratio == 0 || ps2_ratio >= 1))
+      fail(TENSO_EINVAL, "ps2_atol must be >= 0 and ps2_ratio 0 or >= 1");
+    p->ps2_atol = ps2_atol;
+    p->ps2_ratio = ps2_ratio;
   });
 }
 

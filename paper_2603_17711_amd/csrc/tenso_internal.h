@@ -230,6 +230,9 @@ struct SvdFinishOp {
   double* rec_d;           // ||Theta||_F^2, energy outside the captured subspace
   double eps;
   int n_norm_part, rows, cols, p, iso, max_rank, cap_r, pad_;
+  // ratio > 0: keep ceil(ratio * r_atol) directions instead of r_eps + 1,
+  // r_atol = the number of singular values above atol (at least 1)
+  double atol, ratio;
 };
 
 // Split Theta into an isometry W (m_iso x r': the first k columns are the

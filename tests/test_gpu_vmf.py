@@ -220,3 +220,49 @@ def test_mix_spin_boson_train_against_stored_oracle():
     assert sw == int(g["switch"])
     assert (acc, rej) == (int(g["accepted"]), int(g["rejected"]))
     assert max(ds) < 1e-9
+
+
+@pytest.mark.parametrize("atol,ratio", [(1e-7, 2.0), (1e-5, 1.0)])
+def test_ps2_atol_rule_matches_oracle(atol, ratio):
+    """ps2 with the absolute-threshold rule (ps2_atol, ps2_ratio): the same
+    rank at every split as the oracle and the same rho_S."""
+    require_gpu()
+    from oracle.integrators import Propagator
+    from paper_2603_17711_amd import api
+    n, cap = 8, 8
+    inst = small("tree2", rank=cap, method="ps2", n_ltc=2, depth=5)
+    terms, tree = build(inst)
+    print(f"[ps2 atol] atol {atol} ratio {ratio}, {n} steps, cap {cap}", flush=True)
+    P = Propagator(copy.deepcopy(tree), terms, initial_state(tree, inst.rho0), trunc=(atol, ratio))
+    plan = api.build_instance(inst, precision=api.FP64)
+    plan.set_ps2_truncation(atol, ratio)
+    d = 0.0
+    for s in range(n):
+        ro = P.step_ps2(s * inst.dt, inst.dt, 0.0, cap)
+        plan.step_adaptive(1, inst.dt, 0.0, cap, t0=s * inst.dt)
+        assert plan.rank_log() == ro, (s, plan.rank_log(), ro)
+        d = max(d, trace_distance(plan.rho(), P.rho()))
+    print(f"  ranks of the last step {ro}; max trace distance {d:.2e}")
+    assert d < 1e-10
+
+
+def test_mix_with_the_atol_rule():
+    require_gpu()
+    from paper_2603_17711_amd import api
+    n, cap, trunc = 12, 8, (1e-6, 2.0)
+    inst = small("tree2", rank=cap, method="ps2", n_ltc=2, depth=5)
+    terms, tree = build(inst)
+    print(f"[mix] atol rule {trunc}, cap {cap}, {n} steps", flush=True)
+    steps, ro, switch, _ = propagate_mix(copy.deepcopy(tree), terms, initial_state(tree, inst.rho0),
+                                         inst.dt, n, 0.0, cap, fixed_substeps=2, trunc=trunc)
+    plan = api.build_instance(inst, precision=api.FP64)
+    plan.set_ps2_truncation(*trunc)
+    rg, sw = [plan.rho()], -1
+    for s in range(n):
+        sw = plan.step_mix(1, inst.dt, 0.0, cap, t0=s * inst.dt, fixed_substeps=2)
+        rg.append(plan.rho())
+    print(f"  switch after {sw} ps2 steps (oracle {switch})")
+    assert sw == switch and 0 < sw < n
+    d = max(trace_distance(a, b) for a, b in zip(ro, rg))
+    print(f"  max trace distance = {d:.2e}")
+    assert d < 1e-9

@@ -218,3 +218,37 @@ def test_truncated_rank_two_end_term_leaves_the_manifold():
         P.step_ps1(s * dt, dt)
     err = np.linalg.norm(contract_dense(tree, P.C).reshape(-1) - ref) / np.linalg.norm(ref)
     assert err > 1e-3, err
+
+
+def test_ps2_atol_rule_counts():
+    """The absolute-threshold ps2 rule (Sec. VII E: ps2_atol, ps2_ratio) on
+    spectra with a known count above the threshold."""
+    tr = Propagator.truncation_rank_atol
+    s = [1.0, 0.1, 1e-3, 1e-8, 1e-9]
+    assert tr(s, 1e-7, 1.0, 64, 5) == 3
+    assert tr(s, 1e-7, 2.0, 64, 5) == 5          # 6 wanted, 5 available
+    assert tr(s, 1e-7, 2.0, 4, 5) == 4           # rank cap
+    assert tr(s, 1e-7, 1.5, 64, 5) == 5          # ceil(4.5)
+    assert tr(s, 1e-2, 2.0, 64, 5) == 4
+    assert tr(s, 10.0, 2.0, 64, 5) == 2          # nothing above: r_atol counts as 1
+    assert tr([0.0, 0.0], 0.0, 1.0, 64, 2) == 1
+
+
+def test_ps2_atol_rule_limits():
+    """atol = 0 with ratio 1 keeps every non-zero direction (dense result);
+    raising atol lowers the ranks and moves the result away from it."""
+    terms, dims = spin_boson(5)
+    n = 40
+    ref = dense_propagate(terms, dims, RHO0, 0.01, n, every=n)[-1]
+    base = nary_tree(2, [5] * 3, 2, 1)
+    errs, top = [], []
+    for atol in (0.0, 1e-6, 1e-3):
+        tree = Tree(base.parent, base.end_node, base.end_dims, max_rank=2)
+        P = Propagator(tree, terms, initial_state(tree, RHO0), trunc=(atol, 1.0))
+        for s in range(n):
+            ranks = P.step_ps2(s * 0.01, 0.01, 0.0, 1000)
+        errs.append(trace_distance(P.rho(), ref))
+        top.append(max(ranks))
+    assert errs[0] < 1e-8
+    assert top[0] >= top[1] >= top[2] and top[0] > top[2]
+    assert errs[2] > errs[0]
