@@ -664,6 +664,11 @@ __global__ void __launch_bounds__(256) k_combine(const CombineOp* __restrict__ o
       op.y0[2 * e + 1] = ki;
       continue;
     }
+    if (op.stage == 5) {  // a sum in compute precision (an environment channel)
+      xin[2 * e] = (T)kr;
+      xin[2 * e + 1] = (T)ki;
+      continue;
+    }
     const double yr = op.y0[2 * e], yi = op.y0[2 * e + 1];
     if (op.stage == 1) {
       op.acc[2 * e] = kr;

@@ -277,7 +277,8 @@ static constexpr int kVmfDriveLd = 4 * 6 + 1;
 
 // operand reference resolved when a program is built
 struct ORef {
-  int kind = 0;  // 0 identity, 1 factor, 2 down slot, 3 up slot, 4 bond density (vmf)
+  int kind = 0;  // 0 identity, 1 factor, 2 down slot, 3 up slot, 4 bond density (vmf),
+                 // 5 down channel D0 of `node`, 6 up channel U0 of `node`
   int node = 0, idx = 0;
 };
 
@@ -374,7 +375,13 @@ struct tenso_plan {
   // env slots
   std::vector<std::vector<Key>> dkeys, ukeys;
   std::vector<std::map<Key, int>> dmap, umap;
-  std::vector<std::vector<int>> term_d, term_u;  // [node][term] -> slot or -1
+  std::vector<std::vector<int>> term_d, term_u;  // [node][term] -> slot, -1 (no factor on
+                                                 // that side) or kInChannel
+  // Channels of the operator on every bond (the tree-operator form of the
+  // generator): the sum, with coefficients, of every time-independent term
+  // entirely inside the subtree (down, D0) or entirely outside it (up, U0)
+  // costs one environment instead of one per distinct operator.
+  std::vector<char> has_d0, has_u0;
   // constant buffer (factor matrices in both precisions)
   void* cbuf = nullptr;
   std::vector<size_t> mat_off64, mat_off32;
@@ -470,6 +477,13 @@ static int key_mat(const Key& k, int end) {
   return -1;
 }
 
+// Env slots per bond: one per distinct restricted key of the terms that act on
+// both sides of the bond (or carry a drive slot); the time-independent terms
+// on one side only go into that side's channel (term_d / term_u =
+// kInChannel).  Every slot a bond's environments need from a neighbouring
+// bond exists there: a term with factors on both sides of bond x also has
+// factors on both sides of every bond between them.
+static constexpr int kInChannel = -2;
 static void analyse_slots(tenso_plan& P) {
   const tenso_tree& t = P.tree;
   const int nt = (int)P.gen.terms.size();
@@ -479,10 +493,23 @@ static void analyse_slots(tenso_plan& P) {
   P.umap.assign(t.n, {});
   P.term_d.assign(t.n, std::vector<int>(nt, -1));
   P.term_u.assign(t.n, std::vector<int>(nt, -1));
+  P.has_d0.assign(t.n, 0);
+  P.has_u0.assign(t.n, 0);
   for (int x = 1; x < t.n; ++x) {
     for (int m = 0; m < nt; ++m) {
       const Key& k = P.gen.terms[m].f;
       Key kd = restrict_key(t, k, x, true), ku = restrict_key(t, k, x, false);
+      const bool fixed = P.gen.terms[m].slot < 0;
+      if (fixed && ku.empty()) {
+        P.term_d[x][m] = kInChannel;
+        P.has_d0[x] = 1;
+        continue;
+      }
+      if (fixed && kd.empty()) {
+        P.term_u[x][m] = kInChannel;
+        P.has_u0[x] = 1;
+        continue;
+      }
       if (!kd.empty()) {
         auto it = P.dmap[x].find(kd);
         if (it == P.dmap[x].end()) {
@@ -534,20 +561,18 @@ static ORef leg_ref_for_key(const tenso_plan& P, int s, const Leg& l, const Key&
   return r;
 }
 
-// Effective-generator recipe over a list of (node, leg) legs.
-static Recipe make_recipe(const tenso_plan& P, const std::vector<std::pair<int, Leg>>& legs,
-                          const std::vector<int>& dims) {
+// Group the per-term leg operands of a tensor with legs of dimensions `dims`:
+// pair terms by leg pair, single-leg terms into the presummed sides of a group
+// holding their leg.  Term index -1 is a channel (coefficient 1, no drive).
+static Recipe build_groups(const std::vector<int>& dims,
+                           const std::vector<std::pair<int, std::vector<std::pair<int, ORef>>>>& tl) {
   Recipe R;
   R.dims = dims;
   std::map<std::pair<int, int>, int> gidx;
-  std::vector<std::vector<std::pair<int, ORef>>> singles(legs.size());
-  for (int m = 0; m < (int)P.gen.terms.size(); ++m) {
-    const Key& k = P.gen.terms[m].f;
-    std::vector<std::pair<int, ORef>> nz;
-    for (int i = 0; i < (int)legs.size(); ++i) {
-      ORef o = leg_ref_for_key(P, legs[i].first, legs[i].second, k);
-      if (o.kind) nz.push_back({i, o});
-    }
+  std::vector<std::vector<std::pair<int, ORef>>> singles(dims.size());
+  for (auto& te : tl) {
+    const int m = te.first;
+    const auto& nz = te.second;
     if (nz.empty()) fail(TENSO_EINVAL, "term with no factor in the network");
     if (nz.size() > 2)
       fail(TENSO_EUNSUPPORTED, "a term acts on more than two legs of one core");
@@ -566,7 +591,7 @@ static Recipe make_recipe(const tenso_plan& P, const std::vector<std::pair<int, 
       R.groups[it->second].pair_terms.push_back({m, {nz[0].second, nz[1].second}});
     }
   }
-  for (int l = 0; l < (int)legs.size(); ++l) {
+  for (int l = 0; l < (int)dims.size(); ++l) {
     if (singles[l].empty()) continue;
     int gi = -1;
     bool first_leg = false;
@@ -595,6 +620,103 @@ static Recipe make_recipe(const tenso_plan& P, const std::vector<std::pair<int, 
     dst.insert(dst.end(), singles[l].begin(), singles[l].end());
   }
   return R;
+}
+
+// Channel operands on a list of legs: D0 of every child leg's subtree and U0
+// of every parent leg's node.  A D0 channel on a leg of node s also carries
+// the density rho_s on s's parent leg while a vmf program is built (the
+// channel's terms have nothing outside s), unless that leg is `open`.
+static void add_channels(const tenso_plan& P, const std::vector<std::pair<int, Leg>>& legs, int open,
+                         std::vector<std::pair<int, std::vector<std::pair<int, ORef>>>>& tl) {
+  for (int i = 0; i < (int)legs.size(); ++i) {
+    if (i == open) continue;
+    const int node = legs[i].first;
+    const Leg& l = legs[i].second;
+    if (l.kind == 2 && P.has_d0[l.id]) {
+      ORef o;
+      o.kind = 5;
+      o.node = l.id;
+      std::vector<std::pair<int, ORef>> nz{{i, o}};
+      if (P.vmf_rho && node != 0)
+        for (int j = 0; j < (int)legs.size(); ++j)
+          if (j != open && legs[j].first == node && legs[j].second.kind == 0) {
+            ORef r;
+            r.kind = 4;
+            r.node = node;
+            nz.push_back({j, r});
+            if (nz[1].first < nz[0].first) std::swap(nz[0], nz[1]);
+          }
+      tl.push_back({-1, nz});
+    } else if (l.kind == 0 && P.has_u0[node]) {
+      ORef o;
+      o.kind = 6;
+      o.node = node;
+      tl.push_back({-1, {{i, o}}});
+    }
+  }
+}
+
+// Whether term m sits in a channel on one of the legs (all its factors
+// inside a child leg's subtree, or all outside a parent leg's node).
+static bool in_channel(const tenso_plan& P, const std::vector<std::pair<int, Leg>>& legs, int m) {
+  for (auto& nl : legs) {
+    const Leg& l = nl.second;
+    if (l.kind == 2 && P.term_d[l.id][m] == kInChannel) return true;
+    if (l.kind == 0 && P.term_u[nl.first][m] == kInChannel) return true;
+  }
+  return false;
+}
+
+// Effective-generator recipe over a list of (node, leg) legs: every term not
+// held by a channel, plus the channels.
+static Recipe make_recipe(const tenso_plan& P, const std::vector<std::pair<int, Leg>>& legs,
+                          const std::vector<int>& dims) {
+  std::vector<std::pair<int, std::vector<std::pair<int, ORef>>>> tl;
+  for (int m = 0; m < (int)P.gen.terms.size(); ++m) {
+    if (in_channel(P, legs, m)) continue;
+    const Key& k = P.gen.terms[m].f;
+    std::vector<std::pair<int, ORef>> nz;
+    for (int i = 0; i < (int)legs.size(); ++i) {
+      ORef o = leg_ref_for_key(P, legs[i].first, legs[i].second, k);
+      if (o.kind) nz.push_back({i, o});
+    }
+    tl.push_back({m, nz});
+  }
+  add_channels(P, legs, -1, tl);
+  return build_groups(dims, tl);
+}
+
+// The sum that defines a channel, as a recipe over the legs of `node` with
+// leg `open` left alone: D0(x) on core x (open = its parent leg): the
+// channels D0 of its children and every channel term of x that no child's
+// channel holds; U0(x) on core p = parent(x) (open = the leg to x): U0(p),
+// the D0 of x's siblings, and every term of U0(x) that neither holds.
+static Recipe channel_recipe(const tenso_plan& P, int node, int open, int x, bool down) {
+  const tenso_tree& t = P.tree;
+  std::vector<std::pair<int, Leg>> legs;
+  for (auto& l : t.legs[node]) legs.push_back({node, l});
+  std::vector<std::pair<int, std::vector<std::pair<int, ORef>>>> tl;
+  for (int m = 0; m < (int)P.gen.terms.size(); ++m) {
+    if ((down ? P.term_d[x][m] : P.term_u[x][m]) != kInChannel) continue;
+    bool held = false;
+    for (int i = 0; i < (int)legs.size(); ++i) {
+      if (i == open) continue;
+      const Leg& l = legs[i].second;
+      if (l.kind == 2 && P.term_d[l.id][m] == kInChannel) held = true;
+      if (l.kind == 0 && P.term_u[node][m] == kInChannel) held = true;
+    }
+    if (held) continue;
+    const Key& k = P.gen.terms[m].f;
+    std::vector<std::pair<int, ORef>> nz;
+    for (int i = 0; i < (int)legs.size(); ++i) {
+      if (i == open) continue;
+      ORef o = leg_ref_for_key(P, node, legs[i].second, k);
+      if (o.kind) nz.push_back({i, o});
+    }
+    tl.push_back({m, nz});
+  }
+  add_channels(P, legs, open, tl);
+  return build_groups(t.shape(node), tl);
 }
 
 static Recipe node_recipe(const tenso_plan& P, int s) {
@@ -626,6 +748,20 @@ static Recipe bond_recipe(const tenso_plan& P, int c) {
     if (a.kind && b.kind) g.pair_terms.push_back({m, {a, b}});
     else if (a.kind) g.sa.push_back({m, a});
     else if (b.kind) g.sb.push_back({m, b});
+  }
+  // the channels: everything outside c on the parent side, everything
+  // inside on the child side
+  if (P.has_u0[c]) {
+    ORef a;
+    a.kind = 6;
+    a.node = c;
+    g.sa.push_back({-1, a});
+  }
+  if (P.has_d0[c]) {
+    ORef b;
+    b.kind = 5;
+    b.node = c;
+    g.sb.push_back({-1, b});
   }
   R.groups.push_back(g);
   return R;
@@ -669,6 +805,14 @@ static void* oref_ptr(const tenso_plan& P, const ORef& o) {
     }
     case 4:
       return tagp(TAG_WS, P.vmf_rho_off[o.node]);
+    case 5: {
+      size_t r = P.slot_r[o.node];
+      return tagp(TAG_WS, P.envd_off[o.node] + P.dkeys[o.node].size() * r * r * P.tsz);
+    }
+    case 6: {
+      size_t r = P.slot_r[o.node];
+      return tagp(TAG_WS, P.envu_off[o.node] + P.ukeys[o.node].size() * r * r * P.tsz);
+    }
   }
   return nullptr;
 }
@@ -712,9 +856,22 @@ static void layout(tenso_plan& P) {
   for (int s = 0; s < t.n; ++s) {
     recipe_caps(node_recipe(P, s), t.size(s));
     if (s > 0) {
-      envscr = std::max(envscr, P.dkeys[s].size() * (size_t)t.size(s));
-      // (vmf: one more slab, the bond density)
-      envscr = std::max(envscr, (P.ukeys[s].size() + (P.vmf_ok ? 1 : 0)) * (size_t)t.size(t.parent[s]));
+      const int p = t.parent[s];
+      if (P.has_d0[s]) recipe_caps(channel_recipe(P, s, 0, s, true), t.size(s));
+      if (P.has_u0[s]) recipe_caps(channel_recipe(P, p, t.leg_of_child(p, s), s, false), t.size(p));
+      if (P.vmf_ok && P.has_u0[s]) {  // the vmf form of the up channel (with densities)
+        P.vmf_rho = true;
+        try {
+          recipe_caps(channel_recipe(P, p, t.leg_of_child(p, s), s, false), t.size(p));
+        } catch (const TErr&) {
+          P.vmf_ok = false;
+        }
+        P.vmf_rho = false;
+      }
+      // one slab per key, one for the channel (vmf: one more, the bond density)
+      envscr = std::max(envscr, (P.dkeys[s].size() + P.has_d0[s]) * (size_t)t.size(s));
+      envscr = std::max(envscr, (P.ukeys[s].size() + P.has_u0[s] + (P.vmf_ok ? 1 : 0)) *
+                                    (size_t)t.size(t.parent[s]));
       size_t r = t.rank[s];
       qrv = std::max(qrv, (size_t)t.size(s));
       qrv = std::max(qrv, (size_t)t.size(t.parent[s]));
@@ -745,8 +902,8 @@ static void layout(tenso_plan& P) {
   P.envu_off.assign(t.n, 0);
   for (int x = 1; x < t.n; ++x) {
     size_t r = t.rank[x];
-    P.envd_off[x] = take(std::max<size_t>(1, P.dkeys[x].size()) * r * r * P.tsz);
-    P.envu_off[x] = take(std::max<size_t>(1, P.ukeys[x].size()) * r * r * P.tsz);
+    P.envd_off[x] = take(std::max<size_t>(1, P.dkeys[x].size() + P.has_d0[x]) * r * r * P.tsz);
+    P.envu_off[x] = take(std::max<size_t>(1, P.ukeys[x].size() + P.has_u0[x]) * r * r * P.tsz);
   }
   P.presum_cap = presum;
   P.parts_cap = parts;
@@ -908,11 +1065,12 @@ struct Builder {
     return (int)G.terms.size() - 1;
   }
 
+  // m = -1: a channel (coefficient 1, no drive)
   TermRef term_ref(int m, void* A, void* B) {
     TermRef tr{};
-    tr.cre = P.gen.terms[m].coef.real();
-    tr.cim = P.gen.terms[m].coef.imag();
-    tr.slot = P.gen.terms[m].slot;
+    tr.cre = m < 0 ? 1.0 : P.gen.terms[m].coef.real();
+    tr.cim = m < 0 ? 0.0 : P.gen.terms[m].coef.imag();
+    tr.slot = m < 0 ? -1 : P.gen.terms[m].slot;
     tr.A = A;
     tr.B = B;
     return tr;
@@ -1161,9 +1319,9 @@ struct Builder {
     const int rels[4] = {rel0, rel0 + 1, rel0 + 1, rel0 + 2};
     bool td = false;
     for (auto& g : R.groups) {  // presummed coefficients that change within the sub-flow
-      for (auto& s : g.sa) td |= P.gen.terms[s.first].slot >= 0;
-      for (auto& s : g.sb) td |= P.gen.terms[s.first].slot >= 0;
-      for (auto& s : g.pair_terms) td |= P.gen.terms[s.first].slot >= 0;
+      for (auto& s : g.sa) td |= s.first >= 0 && P.gen.terms[s.first].slot >= 0;
+      for (auto& s : g.sb) td |= s.first >= 0 && P.gen.terms[s.first].slot >= 0;
+      for (auto& s : g.pair_terms) td |= s.first >= 0 && P.gen.terms[s.first].slot >= 0;
     }
     for (int st = 1; st <= 4; ++st) {
       void* X = st == 1 ? y0 : ws(P.ws_xin);
@@ -1172,72 +1330,88 @@ struct Builder {
     }
   }
 
-  void emit_env_down(int x) {
-    const tenso_tree& t = P.tree;
-    if (P.dkeys[x].empty()) return;
-    const std::vector<int> dims = t.shape(x);
-    const long Pn = t.size(x);
-    int gfirst = (int)G.groups.size(), tfirst = (int)G.atiles.size();
-    std::vector<std::vector<std::pair<int, ORef>>> nzs;
-    for (size_t k = 0; k < P.dkeys[x].size(); ++k) {
-      const Key& key = P.dkeys[x][k];
-      std::vector<std::pair<int, ORef>> nz;
-      for (int i = 1; i < (int)t.legs[x].size(); ++i) {
-        ORef o = leg_ref_for_key(P, x, t.legs[x][i], key);
-        if (o.kind) nz.push_back({i, o});
-      }
-      nzs.push_back(nz);
-    }
-    const std::vector<size_t> slab = add_env_groups(dims, Pn, 0, nzs, x, gfirst);
-    launch(LK_APPLY, 1, gfirst, (int)G.groups.size() - gfirst, tfirst,
-           (int)G.atiles.size() - tfirst);
-    int qf = (int)G.grams.size();
-    for (size_t k = 0; k < P.dkeys[x].size(); ++k) {
-      GramOp go{};
-      go.C = (const double*)core(x);
-      go.T = ws(P.ws_envscr + slab[k] * Pn * P.tsz);
-      go.E = ws(P.envd_off[x] + k * (size_t)P.slot_r[x] * P.slot_r[x] * P.tsz);
-      go.r = t.rank[x];
-      go.Ppre = 1;
-      go.Ppost = (int)(Pn / t.rank[x]);
-      G.grams.push_back(go);
-    }
-    launch(LK_GRAM, 0, qf, (int)G.grams.size() - qf, 0, 0);
-  }
+  void emit_env_down(int x) { emit_env(x, true, false); }
+  void emit_env_up(int x) { emit_env(x, false, false); }
 
-  void emit_env_up(int x) {
+  // Environments of bond x on one side: the slots of its keys (down: from
+  // core x, open leg its parent leg; up: from the parent core p, open leg
+  // the one to x) and the side's channel, in one contraction launch (per-key
+  // results in their own slabs, the channel's terms summed into partial
+  // outputs), the channel's partial sum, then one Gram launch for all.
+  // with_rho (up side of a vmf program): also the bond density rho_x, from
+  // p's core with rho_p on its parent leg (p's plain Gram at the root).
+  void emit_env(int x, bool down, bool with_rho) {
     const tenso_tree& t = P.tree;
-    if (P.ukeys[x].empty()) return;
-    const int p = t.parent[x];
-    const std::vector<int> dims = t.shape(p);
-    const long Pn = t.size(p);
-    const int open = t.leg_of_child(p, x);
-    int gfirst = (int)G.groups.size(), tfirst = (int)G.atiles.size();
+    const std::vector<Key>& keys = down ? P.dkeys[x] : P.ukeys[x];
+    const bool chan = down ? P.has_d0[x] : P.has_u0[x];
+    if (keys.empty() && !chan && !with_rho) return;
+    const int node = down ? x : t.parent[x];
+    const std::vector<int> dims = t.shape(node);
+    const long Pn = t.size(node);
+    const int open = down ? 0 : t.leg_of_child(node, x);
+    const int pfirst = (int)G.presums.size();
+    const int gfirst = (int)G.groups.size(), tfirst = (int)G.atiles.size();
     std::vector<std::vector<std::pair<int, ORef>>> nzs;
-    for (size_t k = 0; k < P.ukeys[x].size(); ++k) {
-      const Key& key = P.ukeys[x][k];
+    for (size_t k = 0; k < keys.size(); ++k) {
       std::vector<std::pair<int, ORef>> nz;
-      for (int i = 0; i < (int)t.legs[p].size(); ++i) {
+      for (int i = 0; i < (int)t.legs[node].size(); ++i) {
         if (i == open) continue;
-        ORef o = leg_ref_for_key(P, p, t.legs[p][i], key);
+        ORef o = leg_ref_for_key(P, node, t.legs[node][i], keys[k]);
         if (o.kind) nz.push_back({i, o});
       }
       nzs.push_back(nz);
     }
-    const std::vector<size_t> slab = add_env_groups(dims, Pn, open, nzs, p, gfirst);
-    launch(LK_APPLY, 1, gfirst, (int)G.groups.size() - gfirst, tfirst,
-           (int)G.atiles.size() - tfirst);
-    int qf = (int)G.grams.size();
-    for (size_t k = 0; k < P.ukeys[x].size(); ++k) {
+    const bool rho_direct = with_rho && node == 0;
+    if (with_rho && !rho_direct) {
+      ORef o;
+      o.kind = 4;
+      o.node = node;
+      nzs.push_back({{0, o}});
+    }
+    const std::vector<size_t> slab = add_env_groups(dims, Pn, open, nzs, node, gfirst);
+    int nparts = 0;
+    if (chan)
+      nparts = add_apply(channel_recipe(P, node, open, x, down), core(node), 1, Pn, 0, 1,
+                         P.par_target,
+                         ApplyArea{P.ws_parts, P.ws_presum, P.parts_cap, P.presum_cap}, gfirst);
+    const int np = (int)G.presums.size() - pfirst;
+    if (np) launch(LK_PRESUM, 0, pfirst, np, 0, 0);
+    if ((int)G.groups.size() > gfirst)
+      launch(LK_APPLY, 1, gfirst, (int)G.groups.size() - gfirst, tfirst,
+             (int)G.atiles.size() - tfirst);
+    const size_t chan_slab = nzs.size();
+    if (chan) {  // the channel's partial outputs summed into its slab
+      CombineOp op{};
+      op.y0 = (double*)ws(P.ws_acc);
+      op.xin = ws(P.ws_envscr + chan_slab * Pn * P.tsz);
+      op.acc = (double*)ws(P.ws_acc);
+      op.parts = ws(P.ws_parts);
+      op.n = Pn;
+      op.n_parts = nparts;
+      op.stage = 5;
+      const int oi = (int)G.combines.size();
+      G.combines.push_back(op);
+      const int tf = (int)G.ctiles.size();
+      for (long e = 0; e < Pn; e += 2048) G.ctiles.push_back({oi, 0, e, std::min(Pn, e + 2048)});
+      launch(LK_COMBINE, 0, oi, 1, tf, (int)G.ctiles.size() - tf);
+    }
+    const int qf = (int)G.grams.size();
+    const size_t rr = (size_t)P.slot_r[x] * P.slot_r[x] * P.tsz;
+    const size_t base = down ? P.envd_off[x] : P.envu_off[x];
+    auto gram = [&](const void* T, size_t e_off) {
       GramOp go{};
-      go.C = (const double*)core(p);
-      go.T = ws(P.ws_envscr + slab[k] * Pn * P.tsz);
-      go.E = ws(P.envu_off[x] + k * (size_t)P.slot_r[x] * P.slot_r[x] * P.tsz);
+      go.C = (const double*)core(node);
+      go.T = T;
+      go.E = ws(e_off);
       go.r = t.rank[x];
       go.Ppre = (int)prod(dims, 0, open);
       go.Ppost = (int)prod(dims, open + 1, (int)dims.size());
       G.grams.push_back(go);
-    }
+    };
+    for (size_t k = 0; k < keys.size(); ++k) gram(ws(P.ws_envscr + slab[k] * Pn * P.tsz), base + k * rr);
+    if (chan) gram(ws(P.ws_envscr + chan_slab * Pn * P.tsz), base + keys.size() * rr);
+    if (with_rho)
+      gram(rho_direct ? core(node) : ws(P.ws_envscr + slab.back() * Pn * P.tsz), P.vmf_rho_off[x]);
     launch(LK_GRAM, 0, qf, (int)G.grams.size() - qf, 0, 0);
   }
 
@@ -1458,50 +1632,7 @@ struct Builder {
   // p's own bond (a key with nothing outside p carries that density on p's
   // parent leg), and the bond density rho_x itself (p's core with rho_p on
   // its parent leg; the plain Gram of the root core when p is the root).
-  void emit_vmf_up(int x) {
-    const tenso_tree& t = P.tree;
-    const int p = t.parent[x];
-    const std::vector<int> dims = t.shape(p);
-    const long Pn = t.size(p);
-    const int open = t.leg_of_child(p, x);
-    const int gfirst = (int)G.groups.size(), tfirst = (int)G.atiles.size();
-    std::vector<std::vector<std::pair<int, ORef>>> nzs;
-    for (size_t k = 0; k < P.ukeys[x].size(); ++k) {
-      std::vector<std::pair<int, ORef>> nz;
-      for (int i = 0; i < (int)t.legs[p].size(); ++i) {
-        if (i == open) continue;
-        ORef o = leg_ref_for_key(P, p, t.legs[p][i], P.ukeys[x][k]);
-        if (o.kind) nz.push_back({i, o});
-      }
-      nzs.push_back(nz);
-    }
-    if (p != 0) {
-      ORef o;
-      o.kind = 4;
-      o.node = p;
-      nzs.push_back({{0, o}});
-    }
-    const std::vector<size_t> slab = add_env_groups(dims, Pn, open, nzs, p, gfirst);
-    if ((int)G.groups.size() > gfirst)
-      launch(LK_APPLY, 1, gfirst, (int)G.groups.size() - gfirst, tfirst,
-             (int)G.atiles.size() - tfirst);
-    const int qf = (int)G.grams.size();
-    auto gram = [&](const void* T, size_t e_off) {
-      GramOp go{};
-      go.C = (const double*)core(p);
-      go.T = T;
-      go.E = ws(e_off);
-      go.r = t.rank[x];
-      go.Ppre = (int)prod(dims, 0, open);
-      go.Ppost = (int)prod(dims, open + 1, (int)dims.size());
-      G.grams.push_back(go);
-    };
-    for (size_t k = 0; k < P.ukeys[x].size(); ++k)
-      gram(ws(P.ws_envscr + slab[k] * Pn * P.tsz),
-           P.envu_off[x] + k * (size_t)P.slot_r[x] * P.slot_r[x] * P.tsz);
-    gram(p == 0 ? core(p) : ws(P.ws_envscr + slab.back() * Pn * P.tsz), P.vmf_rho_off[x]);
-    launch(LK_GRAM, 0, qf, (int)G.grams.size() - qf, 0, 0);
-  }
+  void emit_vmf_up(int x) { emit_env(x, false, true); }
 
   // The time derivative of every core of the state at TAG_STATE into the
   // derivative buffer (same layout): down environments (children first),

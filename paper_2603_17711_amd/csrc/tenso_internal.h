@@ -91,7 +91,7 @@ struct CombineOp {
   const void* parts;   // n_parts consecutive slabs of n elements
   long n;
   int n_parts;
-  int stage;           // 1..4
+  int stage;           // 1..4; 0: y0 = sum of parts; 5: xin = sum of parts
   double h;            // sign * tau
 };
 
