@@ -10,6 +10,8 @@
 #include <functional>
 #include <map>
 #include <memory>
+#include <set>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -278,7 +280,8 @@ static constexpr int kVmfDriveLd = 4 * 6 + 1;
 // operand reference resolved when a program is built
 struct ORef {
   int kind = 0;  // 0 identity, 1 factor, 2 down slot, 3 up slot, 4 bond density (vmf),
-                 // 5 down channel D0 of `node`, 6 up channel U0 of `node`
+                 // 5 down channel D0 of `node`, 6 up channel U0 of `node`,
+                 // 7 partner channel `idx` of `node`
   int node = 0, idx = 0;
 };
 
@@ -382,6 +385,14 @@ struct tenso_plan {
   // entirely inside the subtree (down, D0) or entirely outside it (up, U0)
   // costs one environment instead of one per distinct operator.
   std::vector<char> has_d0, has_u0;
+  // Partner channels of the down side: a time-independent term with one
+  // factor inside the subtree and every other factor on the root's ends
+  // (a system operator P) is summed, with its coefficient, into the channel
+  // D_P of the bond; P's environment stays a plain up slot.  gkeys[x]: the
+  // keys P, term_g[x][m]: the term's channel (-1: none).
+  std::vector<std::vector<Key>> gkeys;
+  std::vector<std::map<Key, int>> gmap;
+  std::vector<std::vector<int>> term_g;
   // constant buffer (factor matrices in both precisions)
   void* cbuf = nullptr;
   std::vector<size_t> mat_off64, mat_off32;
@@ -484,6 +495,10 @@ static int key_mat(const Key& k, int end) {
 // bond exists there: a term with factors on both sides of bond x also has
 // factors on both sides of every bond between them.
 static constexpr int kInChannel = -2;
+static constexpr int kInGroup = -3;  // term_d: the term is in a partner channel (term_g)
+// Recipe term indices: m >= 0 a generator term; m = -w a channel standing for
+// w generator terms (coefficient 1, no drive; credited as w terms of work).
+static double term_weight(int m) { return m < 0 ? (double)-m : 1.0; }
 static void analyse_slots(tenso_plan& P) {
   const tenso_tree& t = P.tree;
   const int nt = (int)P.gen.terms.size();
@@ -495,11 +510,32 @@ static void analyse_slots(tenso_plan& P) {
   P.term_u.assign(t.n, std::vector<int>(nt, -1));
   P.has_d0.assign(t.n, 0);
   P.has_u0.assign(t.n, 0);
+  P.gkeys.assign(t.n, {});
+  P.gmap.assign(t.n, {});
+  P.term_g.assign(t.n, std::vector<int>(nt, -1));
   for (int x = 1; x < t.n; ++x) {
     for (int m = 0; m < nt; ++m) {
       const Key& k = P.gen.terms[m].f;
       Key kd = restrict_key(t, k, x, true), ku = restrict_key(t, k, x, false);
       const bool fixed = P.gen.terms[m].slot < 0;
+      bool at_root = !ku.empty();
+      for (auto& f : ku) at_root = at_root && t.end_node[f.first] == 0;
+      if (fixed && kd.size() == 1 && at_root) {  // a partner channel
+        auto gi = P.gmap[x].find(ku);
+        if (gi == P.gmap[x].end()) {
+          gi = P.gmap[x].emplace(ku, (int)P.gkeys[x].size()).first;
+          P.gkeys[x].push_back(ku);
+        }
+        P.term_g[x][m] = gi->second;
+        P.term_d[x][m] = kInGroup;
+        auto it = P.umap[x].find(ku);
+        if (it == P.umap[x].end()) {
+          it = P.umap[x].emplace(ku, (int)P.ukeys[x].size()).first;
+          P.ukeys[x].push_back(ku);
+        }
+        P.term_u[x][m] = it->second;
+        continue;
+      }
       if (fixed && ku.empty()) {
         P.term_d[x][m] = kInChannel;
         P.has_d0[x] = 1;
@@ -563,7 +599,7 @@ static ORef leg_ref_for_key(const tenso_plan& P, int s, const Leg& l, const Key&
 
 // Group the per-term leg operands of a tensor with legs of dimensions `dims`:
 // pair terms by leg pair, single-leg terms into the presummed sides of a group
-// holding their leg.  Term index -1 is a channel (coefficient 1, no drive).
+// holding their leg (term indices as for term_weight).
 static Recipe build_groups(const std::vector<int>& dims,
                            const std::vector<std::pair<int, std::vector<std::pair<int, ORef>>>>& tl) {
   Recipe R;
@@ -633,6 +669,8 @@ static void add_channels(const tenso_plan& P, const std::vector<std::pair<int, L
     const int node = legs[i].first;
     const Leg& l = legs[i].second;
     if (l.kind == 2 && P.has_d0[l.id]) {
+      int w = 0;
+      for (int m = 0; m < (int)P.gen.terms.size(); ++m) w += P.term_d[l.id][m] == kInChannel;
       ORef o;
       o.kind = 5;
       o.node = l.id;
@@ -646,13 +684,63 @@ static void add_channels(const tenso_plan& P, const std::vector<std::pair<int, L
             nz.push_back({j, r});
             if (nz[1].first < nz[0].first) std::swap(nz[0], nz[1]);
           }
-      tl.push_back({-1, nz});
+      tl.push_back({-w, nz});
     } else if (l.kind == 0 && P.has_u0[node]) {
+      int w = 0;
+      for (int m = 0; m < (int)P.gen.terms.size(); ++m) w += P.term_u[node][m] == kInChannel;
       ORef o;
       o.kind = 6;
       o.node = node;
-      tl.push_back({-1, {{i, o}}});
+      tl.push_back({-w, {{i, o}}});
     }
+  }
+}
+
+// A partner channel that holds term m on one of the legs (a child leg whose
+// bond sums m into its channel D_P): (leg, child, channel), or leg -1.
+static int group_size(const tenso_plan& P, int x, int gi) {
+  int w = 0;
+  for (int m = 0; m < (int)P.gen.terms.size(); ++m) w += P.term_g[x][m] == gi;
+  return w;
+}
+
+struct GroupUse {
+  int leg, child, idx;
+  bool operator<(const GroupUse& o) const {
+    return std::tie(leg, child, idx) < std::tie(o.leg, o.child, o.idx);
+  }
+};
+static GroupUse held_by_group(const tenso_plan& P, const std::vector<std::pair<int, Leg>>& legs,
+                              int open, int m) {
+  for (int i = 0; i < (int)legs.size(); ++i) {
+    const Leg& l = legs[i].second;
+    if (i != open && l.kind == 2 && P.term_g[l.id][m] >= 0) return {i, l.id, P.term_g[l.id][m]};
+  }
+  return {-1, 0, 0};
+}
+
+// The partner channels used on a list of legs, each as one term: D_P of the
+// child leg, with P's operators on the other legs (its up slot on a parent
+// leg, its factors on the root's ends).
+static void add_groups(const tenso_plan& P, const std::vector<std::pair<int, Leg>>& legs, int open,
+                       const std::set<GroupUse>& used,
+                       std::vector<std::pair<int, std::vector<std::pair<int, ORef>>>>& tl) {
+  for (const GroupUse& u : used) {
+    std::vector<std::pair<int, ORef>> nz;
+    for (int j = 0; j < (int)legs.size(); ++j) {
+      if (j == open) continue;
+      if (j == u.leg) {
+        ORef o;
+        o.kind = 7;
+        o.node = u.child;
+        o.idx = u.idx;
+        nz.push_back({j, o});
+        continue;
+      }
+      ORef o = leg_ref_for_key(P, legs[j].first, legs[j].second, P.gkeys[u.child][u.idx]);
+      if (o.kind) nz.push_back({j, o});
+    }
+    tl.push_back({-group_size(P, u.child, u.idx), nz});
   }
 }
 
@@ -672,8 +760,14 @@ static bool in_channel(const tenso_plan& P, const std::vector<std::pair<int, Leg
 static Recipe make_recipe(const tenso_plan& P, const std::vector<std::pair<int, Leg>>& legs,
                           const std::vector<int>& dims) {
   std::vector<std::pair<int, std::vector<std::pair<int, ORef>>>> tl;
+  std::set<GroupUse> used;
   for (int m = 0; m < (int)P.gen.terms.size(); ++m) {
     if (in_channel(P, legs, m)) continue;
+    const GroupUse g = held_by_group(P, legs, -1, m);
+    if (g.leg >= 0) {
+      used.insert(g);
+      continue;
+    }
     const Key& k = P.gen.terms[m].f;
     std::vector<std::pair<int, ORef>> nz;
     for (int i = 0; i < (int)legs.size(); ++i) {
@@ -683,6 +777,7 @@ static Recipe make_recipe(const tenso_plan& P, const std::vector<std::pair<int, 
     tl.push_back({m, nz});
   }
   add_channels(P, legs, -1, tl);
+  add_groups(P, legs, -1, used, tl);
   return build_groups(dims, tl);
 }
 
@@ -696,8 +791,14 @@ static Recipe channel_recipe(const tenso_plan& P, int node, int open, int x, boo
   std::vector<std::pair<int, Leg>> legs;
   for (auto& l : t.legs[node]) legs.push_back({node, l});
   std::vector<std::pair<int, std::vector<std::pair<int, ORef>>>> tl;
+  std::set<GroupUse> used;
   for (int m = 0; m < (int)P.gen.terms.size(); ++m) {
     if ((down ? P.term_d[x][m] : P.term_u[x][m]) != kInChannel) continue;
+    const GroupUse gu = held_by_group(P, legs, open, m);
+    if (gu.leg >= 0) {
+      used.insert(gu);
+      continue;
+    }
     bool held = false;
     for (int i = 0; i < (int)legs.size(); ++i) {
       if (i == open) continue;
@@ -716,7 +817,42 @@ static Recipe channel_recipe(const tenso_plan& P, int node, int open, int x, boo
     tl.push_back({m, nz});
   }
   add_channels(P, legs, open, tl);
+  add_groups(P, legs, open, used, tl);
   return build_groups(t.shape(node), tl);
+}
+
+// The sum that defines partner channel gi of bond x, over the legs of core
+// x (its parent leg left alone): the same channel of every child that holds
+// some of its terms, and c_m F_m for its terms whose factor sits on an end
+// of x.
+static Recipe group_recipe(const tenso_plan& P, int x, int gi) {
+  const tenso_tree& t = P.tree;
+  std::vector<std::pair<int, Leg>> legs;
+  for (auto& l : t.legs[x]) legs.push_back({x, l});
+  std::vector<std::pair<int, std::vector<std::pair<int, ORef>>>> tl;
+  std::set<std::pair<int, int>> kids;  // (leg, child)
+  for (int m = 0; m < (int)P.gen.terms.size(); ++m) {
+    if (P.term_g[x][m] != gi) continue;
+    const GroupUse gu = held_by_group(P, legs, 0, m);
+    if (gu.leg >= 0) {
+      kids.insert({gu.leg, gu.child});
+      continue;
+    }
+    std::vector<std::pair<int, ORef>> nz;
+    for (int i = 1; i < (int)legs.size(); ++i) {
+      ORef o = leg_ref_for_key(P, x, legs[i].second, P.gen.terms[m].f);
+      if (o.kind) nz.push_back({i, o});
+    }
+    tl.push_back({m, nz});
+  }
+  for (auto& k : kids) {
+    ORef o;
+    o.kind = 7;
+    o.node = k.second;
+    o.idx = P.gmap[k.second].at(P.gkeys[x][gi]);
+    tl.push_back({-group_size(P, k.second, o.idx), {{k.first, o}}});
+  }
+  return build_groups(t.shape(x), tl);
 }
 
 static Recipe node_recipe(const tenso_plan& P, int s) {
@@ -734,6 +870,7 @@ static Recipe bond_recipe(const tenso_plan& P, int c) {
   g.l1 = 0;
   g.l2 = 1;
   for (int m = 0; m < (int)P.gen.terms.size(); ++m) {
+    if (P.term_d[c][m] == kInGroup) continue;  // in a partner channel (below)
     ORef a, b;
     if (P.term_u[c][m] >= 0) {
       a.kind = 3;
@@ -749,19 +886,35 @@ static Recipe bond_recipe(const tenso_plan& P, int c) {
     else if (a.kind) g.sa.push_back({m, a});
     else if (b.kind) g.sb.push_back({m, b});
   }
+  // partner channels: P's up slot with the channel D_P
+  for (int gi = 0; gi < (int)P.gkeys[c].size(); ++gi) {
+    ORef a, b;
+    a.kind = 3;
+    a.node = c;
+    a.idx = P.umap[c].at(P.gkeys[c][gi]);
+    b.kind = 7;
+    b.node = c;
+    b.idx = gi;
+    g.pair_terms.push_back({-group_size(P, c, gi), {a, b}});
+  }
   // the channels: everything outside c on the parent side, everything
   // inside on the child side
+  int wu = 0, wd = 0;
+  for (int m = 0; m < (int)P.gen.terms.size(); ++m) {
+    wu += P.term_u[c][m] == kInChannel;
+    wd += P.term_d[c][m] == kInChannel;
+  }
   if (P.has_u0[c]) {
     ORef a;
     a.kind = 6;
     a.node = c;
-    g.sa.push_back({-1, a});
+    g.sa.push_back({-wu, a});
   }
   if (P.has_d0[c]) {
     ORef b;
     b.kind = 5;
     b.node = c;
-    g.sb.push_back({-1, b});
+    g.sb.push_back({-wd, b});
   }
   R.groups.push_back(g);
   return R;
@@ -813,6 +966,11 @@ static void* oref_ptr(const tenso_plan& P, const ORef& o) {
       size_t r = P.slot_r[o.node];
       return tagp(TAG_WS, P.envu_off[o.node] + P.ukeys[o.node].size() * r * r * P.tsz);
     }
+    case 7: {
+      size_t r = P.slot_r[o.node];
+      return tagp(TAG_WS, P.envd_off[o.node] +
+                              (P.dkeys[o.node].size() + P.has_d0[o.node] + o.idx) * r * r * P.tsz);
+    }
   }
   return nullptr;
 }
@@ -838,6 +996,20 @@ static void layout(tenso_plan& P) {
   for (int e = 0; e < t.n_ends; ++e) P.max_dim = std::max(P.max_dim, t.end_dim[e]);
   P.max_dim = std::max(P.max_dim, maxr);
   size_t presum = 0, parts = 0, envscr = 0, qrv = 0, theta = 0, wcap = 0, side = 0;
+  // presum elements and partial-output elements of a recipe on n elements
+  auto recipe_need = [&](const Recipe& R, long n) {
+    size_t ps = 0;
+    for (auto& g : R.groups) {
+      if (!g.sa.empty()) ps += (size_t)R.dims[g.l1] * R.dims[g.l1];
+      if (!g.sb.empty()) ps += (size_t)R.dims[g.l2] * R.dims[g.l2];
+      for (auto& c : cluster_pairs(g))
+        if (c.others.size() > 1) {
+          const size_t d = R.dims[c.shared_side == 0 ? g.l2 : g.l1];
+          ps += d * d;
+        }
+    }
+    return std::make_pair(ps, (size_t)R.groups.size() * 8 * (size_t)n);
+  };
   auto recipe_caps = [&](const Recipe& R, long n) {
     size_t ps = 0;
     for (auto& g : R.groups) {
@@ -857,7 +1029,18 @@ static void layout(tenso_plan& P) {
     recipe_caps(node_recipe(P, s), t.size(s));
     if (s > 0) {
       const int p = t.parent[s];
-      if (P.has_d0[s]) recipe_caps(channel_recipe(P, s, 0, s, true), t.size(s));
+      {  // the down channels of one environment update share the areas
+        std::pair<size_t, size_t> need{0, 0};
+        auto addn = [&](const Recipe& R) {
+          const auto q = recipe_need(R, t.size(s));
+          need.first += q.first;
+          need.second += q.second;
+        };
+        if (P.has_d0[s]) addn(channel_recipe(P, s, 0, s, true));
+        for (int gi = 0; gi < (int)P.gkeys[s].size(); ++gi) addn(group_recipe(P, s, gi));
+        presum = std::max(presum, need.first);
+        parts = std::max(parts, need.second);
+      }
       if (P.has_u0[s]) recipe_caps(channel_recipe(P, p, t.leg_of_child(p, s), s, false), t.size(p));
       if (P.vmf_ok && P.has_u0[s]) {  // the vmf form of the up channel (with densities)
         P.vmf_rho = true;
@@ -869,7 +1052,8 @@ static void layout(tenso_plan& P) {
         P.vmf_rho = false;
       }
       // one slab per key, one for the channel (vmf: one more, the bond density)
-      envscr = std::max(envscr, (P.dkeys[s].size() + P.has_d0[s]) * (size_t)t.size(s));
+      envscr = std::max(envscr, (P.dkeys[s].size() + P.has_d0[s] + P.gkeys[s].size()) *
+                                    (size_t)t.size(s));
       envscr = std::max(envscr, (P.ukeys[s].size() + P.has_u0[s] + (P.vmf_ok ? 1 : 0)) *
                                     (size_t)t.size(t.parent[s]));
       size_t r = t.rank[s];
@@ -902,7 +1086,8 @@ static void layout(tenso_plan& P) {
   P.envu_off.assign(t.n, 0);
   for (int x = 1; x < t.n; ++x) {
     size_t r = t.rank[x];
-    P.envd_off[x] = take(std::max<size_t>(1, P.dkeys[x].size() + P.has_d0[x]) * r * r * P.tsz);
+    P.envd_off[x] = take(std::max<size_t>(1, P.dkeys[x].size() + P.has_d0[x] + P.gkeys[x].size()) *
+                         r * r * P.tsz);
     P.envu_off[x] = take(std::max<size_t>(1, P.ukeys[x].size() + P.has_u0[x]) * r * r * P.tsz);
   }
   P.presum_cap = presum;
@@ -1065,7 +1250,7 @@ struct Builder {
     return (int)G.terms.size() - 1;
   }
 
-  // m = -1: a channel (coefficient 1, no drive)
+  // m < 0: a channel (coefficient 1, no drive)
   TermRef term_ref(int m, void* A, void* B) {
     TermRef tr{};
     tr.cre = m < 0 ? 1.0 : P.gen.terms[m].coef.real();
@@ -1147,7 +1332,7 @@ struct Builder {
   // (the first group of the launch they will join), partial slabs from A.parts.
   // Returns the number of partial slabs.
   int add_apply(const Recipe& R, void* X, int in_fp64, long Pn, int rel, int presum_now,
-                int target, const ApplyArea& A, int gfirst) {
+                int target, const ApplyArea& A, int gfirst, size_t* presum_bytes = nullptr) {
     // presums
     size_t poff = A.presum;
     std::vector<void*> sa_buf(R.groups.size(), nullptr), sb_buf(R.groups.size(), nullptr);
@@ -1206,6 +1391,7 @@ struct Builder {
       }
     }
     if (poff - A.presum > A.presum_cap * P.tsz + 1) fail(TENSO_EINVAL, "presum capacity");
+    if (presum_bytes) *presum_bytes = poff - A.presum;
     // groups, chunked over terms
     int part = 0;
     long free_total = 0;
@@ -1221,7 +1407,7 @@ struct Builder {
           void* sh = oref_ptr(P, c.shared);
           void* ot = oref_ptr(P, o.second);
           trs.push_back(c.shared_side == 0 ? term_ref(o.first, sh, ot) : term_ref(o.first, ot, sh));
-          trc.push_back(1.0);
+          trc.push_back(term_weight(o.first));
           continue;
         }
         TermRef tr{};
@@ -1230,7 +1416,9 @@ struct Builder {
         tr.A = c.shared_side == 0 ? oref_ptr(P, c.shared) : cl_buf[gi][ci];
         tr.B = c.shared_side == 0 ? cl_buf[gi][ci] : oref_ptr(P, c.shared);
         trs.push_back(tr);
-        trc.push_back((double)c.others.size());
+        double w = 0;
+        for (auto& o : c.others) w += term_weight(o.first);
+        trc.push_back(w);
       }
       if (sa_buf[gi]) {
         TermRef tr{};
@@ -1238,7 +1426,9 @@ struct Builder {
         tr.slot = -1;
         tr.A = sa_buf[gi];
         trs.push_back(tr);
-        trc.push_back((double)g.sa.size());
+        double w = 0;
+        for (auto& o : g.sa) w += term_weight(o.first);
+        trc.push_back(w);
       }
       if (sb_buf[gi]) {
         TermRef tr{};
@@ -1246,7 +1436,9 @@ struct Builder {
         tr.slot = -1;
         tr.B = sb_buf[gi];
         trs.push_back(tr);
-        trc.push_back((double)g.sb.size());
+        double w = 0;
+        for (auto& o : g.sb) w += term_weight(o.first);
+        trc.push_back(w);
       }
       const int d1 = R.dims[g.l1], d2 = R.dims[g.l2];
       const long F = Pn / ((long)d1 * d2);
@@ -1344,7 +1536,7 @@ struct Builder {
     const tenso_tree& t = P.tree;
     const std::vector<Key>& keys = down ? P.dkeys[x] : P.ukeys[x];
     const bool chan = down ? P.has_d0[x] : P.has_u0[x];
-    if (keys.empty() && !chan && !with_rho) return;
+    if (keys.empty() && !chan && !with_rho && !(down && !P.gkeys[x].empty())) return;
     const int node = down ? x : t.parent[x];
     const std::vector<int> dims = t.shape(node);
     const long Pn = t.size(node);
@@ -1369,31 +1561,49 @@ struct Builder {
       nzs.push_back({{0, o}});
     }
     const std::vector<size_t> slab = add_env_groups(dims, Pn, open, nzs, node, gfirst);
-    int nparts = 0;
-    if (chan)
-      nparts = add_apply(channel_recipe(P, node, open, x, down), core(node), 1, Pn, 0, 1,
-                         P.par_target,
-                         ApplyArea{P.ws_parts, P.ws_presum, P.parts_cap, P.presum_cap}, gfirst);
+    // channels: D0 / U0, then (down side) the partner channels, each summed
+    // into partial outputs of its own and then into its slab
+    std::vector<Recipe> chans;
+    if (chan) chans.push_back(channel_recipe(P, node, open, x, down));
+    if (down)
+      for (int gi = 0; gi < (int)P.gkeys[x].size(); ++gi) chans.push_back(group_recipe(P, x, gi));
+    std::vector<int> nparts(chans.size());
+    std::vector<size_t> pbase(chans.size());
+    size_t used_parts = 0, used_presum = 0;
+    for (size_t ci = 0; ci < chans.size(); ++ci) {
+      pbase[ci] = used_parts;
+      size_t pb = 0;
+      nparts[ci] = add_apply(chans[ci], core(node), 1, Pn, 0, 1, P.par_target,
+                             ApplyArea{P.ws_parts + used_parts * Pn * P.tsz,
+                                       P.ws_presum + used_presum,
+                                       P.parts_cap - std::min(P.parts_cap, used_parts * Pn),
+                                       P.presum_cap - std::min(P.presum_cap, used_presum / P.tsz)},
+                             gfirst, &pb);
+      used_parts += nparts[ci];
+      used_presum += pb;
+    }
     const int np = (int)G.presums.size() - pfirst;
     if (np) launch(LK_PRESUM, 0, pfirst, np, 0, 0);
     if ((int)G.groups.size() > gfirst)
       launch(LK_APPLY, 1, gfirst, (int)G.groups.size() - gfirst, tfirst,
              (int)G.atiles.size() - tfirst);
     const size_t chan_slab = nzs.size();
-    if (chan) {  // the channel's partial outputs summed into its slab
-      CombineOp op{};
-      op.y0 = (double*)ws(P.ws_acc);
-      op.xin = ws(P.ws_envscr + chan_slab * Pn * P.tsz);
-      op.acc = (double*)ws(P.ws_acc);
-      op.parts = ws(P.ws_parts);
-      op.n = Pn;
-      op.n_parts = nparts;
-      op.stage = 5;
-      const int oi = (int)G.combines.size();
-      G.combines.push_back(op);
-      const int tf = (int)G.ctiles.size();
-      for (long e = 0; e < Pn; e += 2048) G.ctiles.push_back({oi, 0, e, std::min(Pn, e + 2048)});
-      launch(LK_COMBINE, 0, oi, 1, tf, (int)G.ctiles.size() - tf);
+    if (!chans.empty()) {  // each channel's partial outputs summed into its slab
+      const int cf = (int)G.combines.size(), tf = (int)G.ctiles.size();
+      for (size_t ci = 0; ci < chans.size(); ++ci) {
+        CombineOp op{};
+        op.y0 = (double*)ws(P.ws_acc);
+        op.xin = ws(P.ws_envscr + (chan_slab + ci) * Pn * P.tsz);
+        op.acc = (double*)ws(P.ws_acc);
+        op.parts = ws(P.ws_parts + pbase[ci] * Pn * P.tsz);
+        op.n = Pn;
+        op.n_parts = nparts[ci];
+        op.stage = 5;
+        const int oi = (int)G.combines.size();
+        G.combines.push_back(op);
+        for (long e = 0; e < Pn; e += 2048) G.ctiles.push_back({oi, 0, e, std::min(Pn, e + 2048)});
+      }
+      launch(LK_COMBINE, 0, cf, (int)chans.size(), tf, (int)G.ctiles.size() - tf);
     }
     const int qf = (int)G.grams.size();
     const size_t rr = (size_t)P.slot_r[x] * P.slot_r[x] * P.tsz;
@@ -1409,7 +1619,9 @@ struct Builder {
       G.grams.push_back(go);
     };
     for (size_t k = 0; k < keys.size(); ++k) gram(ws(P.ws_envscr + slab[k] * Pn * P.tsz), base + k * rr);
-    if (chan) gram(ws(P.ws_envscr + chan_slab * Pn * P.tsz), base + keys.size() * rr);
+    // channel slabs: D0 / U0 right after the keys, then the partner channels
+    for (size_t ci = 0; ci < chans.size(); ++ci)
+      gram(ws(P.ws_envscr + (chan_slab + ci) * Pn * P.tsz), base + (keys.size() + ci) * rr);
     if (with_rho)
       gram(rho_direct ? core(node) : ws(P.ws_envscr + slab.back() * Pn * P.tsz), P.vmf_rho_off[x]);
     launch(LK_GRAM, 0, qf, (int)G.grams.size() - qf, 0, 0);
