@@ -1651,35 +1651,60 @@ struct AbsorbTile {
   int f0, f1;  // fiber range (fiber = (pre, post))
 };
 
+// The operator (as Mx, row a in column a of the LDS copy, so that lanes with
+// consecutive a read consecutive words) and the tile's fibers are staged in
+// LDS; thread (g, a) forms output row a of fibers g, g + G, ... (G = 256 / n
+// fiber groups), reading each operator entry once for all its fibers.  Every
+// output is the same sum over a' in the same order as a plain loop.
 __global__ void __launch_bounds__(256) k_absorb(const AbsorbOp* __restrict__ ops,
                                                 const AbsorbTile* __restrict__ tiles) {
   const AbsorbTile tl = tiles[blockIdx.x];
   const AbsorbOp op = ops[tl.op];
   extern __shared__ char smem_raw[];
-  z2* buf = reinterpret_cast<z2*>(smem_raw);
-  z2* C = reinterpret_cast<z2*>(op.C);
-  const z2* M = reinterpret_cast<const z2*>(op.M);
   const int n = op.n;
   const int nf = tl.f1 - tl.f0;
+  z2* Mt = reinterpret_cast<z2*>(smem_raw);  // Mt[b * n + a] = Mx[a][b]
+  z2* buf = Mt + n * n;                      // buf[fl * n + b]
+  z2* C = reinterpret_cast<z2*>(op.C);
+  const z2* M = reinterpret_cast<const z2*>(op.M);
   auto off = [&](int fib, int a) -> long {
     const int pre = fib / op.Ppost, post = fib % op.Ppost;
     return (long)pre * n * op.Ppost + (long)a * op.Ppost + post;
   };
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int a = e / n, b = e % n;  // reads of M row by row
+    Mt[b * n + a] = op.transposeM ? M[(long)b * n + a] : M[(long)a * n + b];
+  }
   for (int e = threadIdx.x; e < nf * n; e += blockDim.x) {
     const int fl = e / n, a = e % n;
     buf[e] = C[off(tl.f0 + fl, a)];
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < nf * n; e += blockDim.x) {
-    const int fl = e / n, a = e % n;
-    double sr = 0, si = 0;
+  constexpr int kMaxFib = 16;  // fibers per thread per pass
+  const int G = (int)blockDim.x / n;
+  const int g = (int)threadIdx.x / n, a = (int)threadIdx.x % n;
+  if (g >= G) return;
+  for (int f0 = g; f0 < nf; f0 += G * kMaxFib) {
+    double sr[kMaxFib], si[kMaxFib];
+#pragma unroll
+    for (int k = 0; k < kMaxFib; ++k) sr[k] = si[k] = 0.0;
     for (int b = 0; b < n; ++b) {
-      const z2 mv = op.transposeM ? M[(long)b * n + a] : M[(long)a * n + b];
-      const z2 x = buf[fl * n + b];
-      sr += mv.r * x.r - mv.i * x.i;
-      si += mv.r * x.i + mv.i * x.r;
+      const z2 mv = Mt[b * n + a];
+#pragma unroll
+      for (int k = 0; k < kMaxFib; ++k) {
+        const int fl = f0 + k * G;
+        if (fl < nf) {
+          const z2 x = buf[fl * n + b];
+          sr[k] += mv.r * x.r - mv.i * x.i;
+          si[k] += mv.r * x.i + mv.i * x.r;
+        }
+      }
     }
-    C[off(tl.f0 + fl, a)] = z2{sr, si};
+#pragma unroll
+    for (int k = 0; k < kMaxFib; ++k) {
+      const int fl = f0 + k * G;
+      if (fl < nf) C[off(tl.f0 + fl, a)] = z2{sr[k], si[k]};
+    }
   }
 }
 
@@ -2219,6 +2244,12 @@ hipError_t launch_qr(const QrOp* ops, int n, int form, hipStream_t s) {
 hipError_t launch_absorb(const AbsorbOp* ops, const void* tiles, int n_tiles, size_t lds,
                          hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
+  static bool attr = false;
+  if (!attr) {  // the operator (up to 64 x 64) plus the tile's fibers
+    (void)hipFuncSetAttribute((const void*)k_absorb, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kAbsorbLdsMax);
+    attr = true;
+  }
   hipLaunchKernelGGL(k_absorb, dim3(n_tiles), dim3(256), lds, s, ops,
                      reinterpret_cast<const AbsorbTile*>(tiles));
   return hipGetLastError();

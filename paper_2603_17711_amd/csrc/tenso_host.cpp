@@ -1741,6 +1741,7 @@ struct Builder {
     a.C = (double*)core(node);
     a.M = (const double*)ws(P.ws_bond);
     a.n = d[leg];
+    if (a.n > kAbsorbMaxN) fail(TENSO_EUNSUPPORTED, "bond wider than 64 in a gauge move");
     a.Ppost = (int)prod(d, leg + 1, (int)d.size());
     a.Ppre = (int)prod(d, 0, leg);
     a.transposeM = transposeM;
@@ -1750,7 +1751,7 @@ struct Builder {
     int fibers = a.Ppre * a.Ppost;
     int per = std::max(1, 2048 / a.n);
     for (int f = 0; f < fibers; f += per) G.abtiles.push_back({ai, f, std::min(fibers, f + per)});
-    launch(LK_ABSORB, 0, ai, 1, tf, (int)G.abtiles.size() - tf, (size_t)per * a.n * 16);
+    launch(LK_ABSORB, 0, ai, 1, tf, (int)G.abtiles.size() - tf, absorb_lds(a.n, per));
   }
 
   // ps1 first-order sweep and its adjoint (mirrors the recursive subflows)
@@ -1923,7 +1924,7 @@ struct Builder {
       const int fibers = a.Ppost;
       const int per = std::max(1, 2048 / a.n);
       for (int f = 0; f < fibers; f += per) G.abtiles.push_back({ai, f, std::min(fibers, f + per)});
-      lds = std::max(lds, (size_t)per * a.n * 16);
+      lds = std::max(lds, absorb_lds(a.n, per));
     }
     launch(LK_ABSORB, 0, af, t.n - 1, atf, (int)G.abtiles.size() - atf, lds);
     // S_x = U_x^H dU_x over the non-parent legs, then dU_x -= U_x S_x

@@ -136,6 +136,11 @@ inline int qr_form_join(int a, int b) {
 
 // In-place mode product of an FP64 core with an n x n FP64 matrix on one leg:
 // C[pre, a, post] <- sum_a' Mx[a, a'] C[pre, a', post], Mx = M or M^T.
+// A launch's dynamic LDS: the n x n operator plus its tiles' fibers (at most
+// 2048 elements per tile, or n when n is larger), 16 bytes per element.
+constexpr int kAbsorbMaxN = 64;
+constexpr size_t kAbsorbLdsMax = (size_t)(kAbsorbMaxN * kAbsorbMaxN + 2048) * 16;
+inline size_t absorb_lds(int n, int per) { return ((size_t)n * n + (size_t)per * n) * 16; }
 struct AbsorbOp {
   double* C;
   const double* M;
