@@ -140,7 +140,9 @@ int tenso_plan_create(const tenso_tree* t, const tenso_gen* g, const tenso_plan_
 /* Compile the same plan on the host only (no HIP call, no device memory) and
  * report what tenso_plan_create would need: state and workspace bytes (each
  * nullable), and for PS1 plans the kernel launches of one step and their
- * algorithmic apply flops (0 for PS2, whose sweep depends on the ranks).
+ * algorithmic apply flops, for VMF plans those of one evaluation of the
+ * derivative (a dopri5 substep takes six; 0 for PS2, whose sweep depends on
+ * the ranks).
  * Same errors as tenso_plan_create, minus EHIP. */
 int tenso_plan_query(const tenso_tree* t, const tenso_gen* g, const tenso_plan_opts* opts,
                      size_t* state_bytes, size_t* workspace_bytes, int64_t* launches_per_step,

@@ -3258,9 +3258,15 @@ int tenso_plan_query(const tenso_tree* t, const tenso_gen* g, const tenso_plan_o
     if (workspace_bytes) *workspace_bytes = P->ws_bytes;
     int64_t nl = 0;
     double fl = 0;
-    if (P->opts.method == TENSO_PS1) {
+    if (P->opts.method == TENSO_PS1 || P->opts.method == TENSO_VMF) {
       Program G;
-      build_step(*P, G);
+      if (P->opts.method == TENSO_PS1) {
+        build_step(*P, G);
+      } else {  // one evaluation of the vmf derivative (a dopri5 substep takes six)
+        P->par_target = 64;
+        Builder b(*P, G);
+        b.vmf_deriv(0.0);
+      }
       nl = (int64_t)G.launches.size();
       for (const auto& L : G.launches) fl += L.flops;
     }

@@ -190,3 +190,16 @@ def test_plan_query_ps2_two_site_budget():
     for cap in (32, 64):
         rc, _, _, _, _, msg = _plan_query(t, g, method=1, max_rank=cap)
         assert rc == ENOMEM and "two-site" in msg
+
+
+def test_plan_query_vmf():
+    """VMF plans: FP64 only (EUNSUPPORTED otherwise); the query reports one
+    evaluation of the derivative: every node's effective generator in one
+    contraction launch plus the environments, densities and projections."""
+    t, g = _instance_tree_gen(workloads.exciton_7site())
+    assert _plan_query(t, g, precision=1, method=2)[0] == EUNSUPPORTED
+    rc, sb, wb, nl, fl, msg = _plan_query(t, g, precision=0, method=2)
+    assert rc == 0, msg
+    rc1, sb1, wb1, nl1, fl1, _ = _plan_query(t, g, precision=0, method=0)
+    assert sb == sb1 and wb == wb1          # one layout serves ps1 and vmf
+    assert 0 < nl < nl1 and 0 < fl < fl1     # one derivative against a whole ps1 step
