@@ -451,6 +451,8 @@ struct tenso_plan {
          ws_vmf_segs = 0, ws_vmf_dtab = 0;
   int vmf_chunks = 1;      // workgroup chunks of the largest core (segment kernels)
   std::unique_ptr<DevProgram> dev_vmf;
+  StepGraph vmf_graph;     // the derivative program captured once it has run eagerly
+  bool vmf_eager_done = false;
   std::vector<int> vmf_ranks;   // ranks the cached vmf program was built for
   double vmf_reg = -1;
   const void* vmf_ws = nullptr;
@@ -2929,6 +2931,8 @@ static void vmf_prepare(tenso_plan* p, void* d_ws, double reg, hipStream_t s) {
   p->vmf_ranks = p->tree.rank;
   p->vmf_reg = reg;
   p->vmf_ws = d_ws;
+  p->vmf_graph.reset();
+  p->vmf_eager_done = false;
 }
 
 struct VmfRun {
@@ -2987,10 +2991,18 @@ struct VmfRun {
     hipchk(hipStreamSynchronize(s), "sync");  // the host table is rewritten next step
   }
 
-  // derivative at the stage input (ys) for stage i, into out
+  // derivative at the stage input (ys) for stage i, into out: replayed from
+  // a captured graph (as tenso_step_fixed's steps) once the program has run
+  // eagerly, unless graphs are off or the contraction is being timed
   void deriv(int i, double* out) {
     hipchk(launch_step_inc(ctr, i, s), "ctr");
-    run(*P.dev_vmf, 1, ctr, s);
+    if (P.graph.enabled && !g_prof.on && P.vmf_eager_done) {
+      if (!P.vmf_graph.exec) capture_step(P.vmf_graph, {P.dev_vmf.get()}, 1, ctr);
+      hipchk(hipGraphLaunch(P.vmf_graph.exec, s), "hipGraphLaunch");
+    } else {
+      run(*P.dev_vmf, 1, ctr, s);
+      P.vmf_eager_done = true;
+    }
     lincomb(out, kout, 0, nullptr, nullptr);
   }
 

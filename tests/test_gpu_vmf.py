@@ -266,3 +266,22 @@ def test_mix_with_the_atol_rule():
     d = max(trace_distance(a, b) for a, b in zip(ro, rg))
     print(f"  max trace distance = {d:.2e}")
     assert d < 1e-9
+
+
+def test_vmf_graph_replay_equals_eager():
+    """The derivative program replayed from a captured graph gives the same
+    bits as eager launches (adaptive steps: the same decisions too)."""
+    require_gpu()
+    inst = small("tree2")
+    _, tree = build(inst)
+    C0 = random_state(tree, 21)
+    print("[vmf] graph replay against eager launches, 10 adaptive steps", flush=True)
+    out = []
+    for graph in (True, False):
+        plan = plan_for(inst, C0)
+        plan.set_graph(graph)
+        plan.step_vmf(10, inst.dt, rtol=1e-6, atol=1e-9, reg=0.0)
+        out.append((plan.export_state(), plan.vmf_stats()))
+    assert out[0][1] == out[1][1]
+    for a, b in zip(out[0][0], out[1][0]):
+        assert np.array_equal(a, b)
