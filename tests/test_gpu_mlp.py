@@ -37,4 +37,4 @@ def test_mlp_forward_and_gradients_match_fp64_oracle():
         gw, gb = grads[l].cpu().numpy(), grads[L + l].cpu().numpy()
         ew, eb = rel(gw, g_ref[l][0]), rel(gb, g_ref[l][1])
         print(f"  layer {l}: dW rel {ew:.2e}, db rel {eb:.2e}")
-        assert ew < 3e-2 and eb < 3e-2
+        assert ew < 2e-2 and eb < 2e-2  # measured at most 4.7e-3
