@@ -76,6 +76,27 @@ __device__ inline cpx<T> ldc(const void* base, long idx) {
   return cpx<T>{(T)p[0], (T)p[1]};
 }
 
+// Input kind of an RK4 stage whose update is formed while the input is
+// staged (in_fp64 = 2): (T)(y0 + xp_s * k), k the previous stage's partial
+// outputs summed in order, in FP64, as the stage-combine kernel sums them.
+struct StageIn {};
+
+template <typename Tin, typename T>
+__device__ inline cpx<T> ld_input(const ApplyGroup& G, long idx) {
+  if constexpr (std::is_same<Tin, StageIn>::value) {
+    const gp<const double> y = gmem(reinterpret_cast<const double*>(G.X)) + 2 * idx;
+    const gp<const T> pp = gmem(reinterpret_cast<const T*>(G.xp)) + 2 * idx;
+    double kr = 0, ki = 0;
+    for (int p = 0; p < G.xp_np; ++p) {
+      kr += (double)pp[2 * (long)p * G.xp_n];
+      ki += (double)pp[2 * (long)p * G.xp_n + 1];
+    }
+    return cpx<T>{(T)(y[0] + G.xp_s * kr), (T)(y[1] + G.xp_s * ki)};
+  } else {
+    return ldc<Tin, T>(G.X, idx);
+  }
+}
+
 __device__ inline void coef_at(const TermRef& t, const double* drive, int ld, int j,
                                double& cr, double& ci) {
   cr = t.cre;
@@ -385,7 +406,7 @@ __device__ __forceinline__ void apply_tile(const ApplyGroup& G, const ApplyTile&
         v.x = 0;
         v.y = 0;
         if (a < d1 && colok) {
-          const cpx<T> x = ldc<Tin, T>(G.X, src + a * sa);
+          const cpx<T> x = ld_input<Tin, T>(G, src + a * sa);
           v.x = x.re;
           v.y = x.im;
         }
@@ -667,6 +688,27 @@ __global__ void __launch_bounds__(256) k_combine(const CombineOp* __restrict__ o
     if (op.stage == 5) {  // a sum in compute precision (an environment channel)
       xin[2 * e] = (T)kr;
       xin[2 * e + 1] = (T)ki;
+      continue;
+    }
+    if (op.stage == 6) {  // the whole RK4 update from the four stages' parts
+      // (kr, ki: stage 1's sum; the accumulator as stages 1-3 would build it)
+      double ar = kr, ai = ki;
+      double qr = 0, qi = 0;
+      for (int st = 1; st < 4; ++st) {
+        qr = 0;
+        qi = 0;
+        const T* ps = parts + 2 * st * op.stage_stride;
+        for (int p = 0; p < op.n_parts; ++p) {
+          qr += (double)ps[2 * (p * op.n + e)];
+          qi += (double)ps[2 * (p * op.n + e) + 1];
+        }
+        if (st < 3) {
+          ar += 2.0 * qr;
+          ai += 2.0 * qi;
+        }
+      }
+      op.y0[2 * e] = op.y0[2 * e] + (op.h / 6.0) * (ar + qr);
+      op.y0[2 * e + 1] = op.y0[2 * e + 1] + (op.h / 6.0) * (ai + qi);
       continue;
     }
     const double yr = op.y0[2 * e], yi = op.y0[2 * e + 1];
@@ -2186,7 +2228,9 @@ hipError_t launch_apply(int mode, int in_fp64, const ApplyGroup* groups, const A
     const void* ks[] = {(const void*)k_apply<float, float, 0>, (const void*)k_apply<float, double, 0>,
                         (const void*)k_apply<double, double, 0>, (const void*)k_apply<float, float, 1>,
                         (const void*)k_apply<float, double, 1>, (const void*)k_apply<float, float, 2>,
-                        (const void*)k_apply<float, double, 2>};
+                        (const void*)k_apply<float, double, 2>, (const void*)k_apply<float, StageIn, 0>,
+                        (const void*)k_apply<double, StageIn, 0>, (const void*)k_apply<float, StageIn, 1>,
+                        (const void*)k_apply<float, StageIn, 2>};
     for (const void* k : ks) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, cap);
     attr_set = true;
   }
@@ -2197,14 +2241,21 @@ hipError_t launch_apply(int mode, int in_fp64, const ApplyGroup* groups, const A
     else
       hipLaunchKernelGGL(kern, dim3(n_tiles), dim3(64 * kApplyWaves), lds, s, groups, tiles, step_ctr);
   };
-  if (mode == 1) go(k_apply<double, double, 0>);
-  else if (mode == 2) {
-    if (in_fp64) go(k_apply<float, double, 1>);
+  // in_fp64: 0 compute-precision input, 1 the FP64 master, 2 an RK4 stage
+  // input formed while staged
+  if (mode == 1) {
+    if (in_fp64 == 2) go(k_apply<double, StageIn, 0>);
+    else go(k_apply<double, double, 0>);
+  } else if (mode == 2) {
+    if (in_fp64 == 2) go(k_apply<float, StageIn, 1>);
+    else if (in_fp64) go(k_apply<float, double, 1>);
     else go(k_apply<float, float, 1>);
   } else if (mode == 3) {
-    if (in_fp64) go(k_apply<float, double, 2>);
+    if (in_fp64 == 2) go(k_apply<float, StageIn, 2>);
+    else if (in_fp64) go(k_apply<float, double, 2>);
     else go(k_apply<float, float, 2>);
-  } else if (in_fp64) go(k_apply<float, double, 0>);
+  } else if (in_fp64 == 2) go(k_apply<float, StageIn, 0>);
+  else if (in_fp64) go(k_apply<float, double, 0>);
   else go(k_apply<float, float, 0>);
   return hipGetLastError();
 }

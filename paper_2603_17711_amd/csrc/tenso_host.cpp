@@ -416,7 +416,12 @@ struct tenso_plan {
   void* opbuf = nullptr;  // device scratch for single-op descriptors (ps2): 8 slots of
                           // 512 bytes, then 4 slots for the SVD
   int par_target = 64;  // tiles wanted per apply (single-instance latency)
+  // RK4 sub-flows form each stage's input inside the next contraction (one
+  // combine per sub-flow) rather than with a combine per stage: fewer launches
+  // on a latency-bound chain, more input traffic; batches turn it off
+  bool fuse_stages = true;
   int built_target = -1;  // par_target the cached programs were built with
+  bool built_fuse = true;  // fuse_stages the cached programs were built with
   double tile_work = 16e6;        // flops per apply tile
   bool tile_work_set = false;     // set by the caller (else batches use their default)
   double built_tile_work = -1;    // tile_work the cached programs were built with
@@ -1101,7 +1106,8 @@ static void layout(tenso_plan& P) {
   P.ws_presum = take(std::max<size_t>(1, presum) * P.tsz);
   P.ws_xin = take((size_t)maxP * P.tsz);
   P.ws_acc = take((size_t)maxP * 16);
-  P.ws_parts = take(std::max<size_t>(1, parts) * P.tsz);
+  // four stage areas: an RK4 sub-flow keeps every stage's partial outputs
+  P.ws_parts = take(4 * std::max<size_t>(1, parts) * P.tsz);
   P.ws_envscr = take(std::max<size_t>(1, envscr) * P.tsz);
   P.ws_bond = take((size_t)maxr * maxr * 16);
   P.ws_qrv = take(std::max<size_t>(1, qrv) * 16);
@@ -1313,15 +1319,26 @@ struct Builder {
   struct ApplyArea {
     size_t parts, presum, parts_cap, presum_cap;
   };
+  // Input of an RK4 stage formed while staged (in_fp64 = 2): X plus
+  // sign * h (half: h / 2) times the sum of the np partial outputs at parts.
+  struct StageSrc {
+    void* parts;
+    long n;
+    int np;
+    double sign;
+    int half;
+  };
 
   // Emit apply launches of recipe R on input X -> parts (chunked), with the
   // presum launch in front.  Returns the number of partial slabs written.
   int emit_apply(const Recipe& R, void* X, int in_fp64, long Pn, int rel, int presum_now,
-                 int target) {
+                 int target, size_t parts_off = 0, const StageSrc* src = nullptr) {
     const int pfirst = (int)G.presums.size();
     const int gfirst = (int)G.groups.size(), tfirst = (int)G.atiles.size();
     const int part = add_apply(R, X, in_fp64, Pn, rel, presum_now, target,
-                               ApplyArea{P.ws_parts, P.ws_presum, P.parts_cap, P.presum_cap}, gfirst);
+                               ApplyArea{parts_off ? parts_off : P.ws_parts, P.ws_presum,
+                                         P.parts_cap, P.presum_cap},
+                               gfirst, nullptr, src);
     const int np = (int)G.presums.size() - pfirst;
     if (np) launch(LK_PRESUM, 0, pfirst, np, 0, 0);
     launch(LK_APPLY, in_fp64, gfirst, (int)G.groups.size() - gfirst, tfirst,
@@ -1334,7 +1351,8 @@ struct Builder {
   // (the first group of the launch they will join), partial slabs from A.parts.
   // Returns the number of partial slabs.
   int add_apply(const Recipe& R, void* X, int in_fp64, long Pn, int rel, int presum_now,
-                int target, const ApplyArea& A, int gfirst, size_t* presum_bytes = nullptr) {
+                int target, const ApplyArea& A, int gfirst, size_t* presum_bytes = nullptr,
+                const StageSrc* src = nullptr) {
     // presums
     size_t poff = A.presum;
     std::vector<void*> sa_buf(R.groups.size(), nullptr), sb_buf(R.groups.size(), nullptr);
@@ -1472,6 +1490,13 @@ struct Builder {
         }
         ag.terms = (const TermRef*)tagp(TAG_TERM, first);
         ag.in_fp64 = in_fp64;
+        if (src) {
+          ag.xp = src->parts;
+          ag.xp_n = src->n;
+          ag.xp_np = src->np;
+          ag.xp_s = src->sign;  // times h or h / 2 at bind time
+          ag.xp_half = src->half;
+        }
         ag.n_terms = (int)(b - a);
         ag.d1 = d1;
         ag.d2 = d2;
@@ -1517,11 +1542,50 @@ struct Builder {
       for (auto& s : g.sb) td |= s.first >= 0 && P.gen.terms[s.first].slot >= 0;
       for (auto& s : g.pair_terms) td |= s.first >= 0 && P.gen.terms[s.first].slot >= 0;
     }
-    for (int st = 1; st <= 4; ++st) {
-      void* X = st == 1 ? y0 : ws(P.ws_xin);
-      int np = emit_apply(R, X, st == 1, n, rels[st - 1], st == 1 || td, P.par_target);
-      emit_combine(y0, n, np, st, sign);
+    if (!P.fuse_stages) {  // a combine per stage: the next input in xin
+      for (int st = 1; st <= 4; ++st) {
+        void* X = st == 1 ? y0 : ws(P.ws_xin);
+        int np = emit_apply(R, X, st == 1, n, rels[st - 1], st == 1 || td, P.par_target);
+        emit_combine(y0, n, np, st, sign);
+      }
+      return;
     }
+    // every stage keeps its partial outputs (stage s at s - 1 part areas
+    // from the first): the next stage's input y0 + c k_s is formed while its
+    // contraction stages it, and one combine at the end applies the update
+    const size_t stride = std::max<size_t>(1, P.parts_cap);  // elements
+    int np_prev = 0, np1 = 0;
+    for (int st = 1; st <= 4; ++st) {
+      StageSrc src{};
+      if (st > 1) {
+        src.parts = ws(P.ws_parts + (size_t)(st - 2) * stride * P.tsz);
+        src.n = n;
+        src.np = np_prev;
+        src.sign = sign;
+        src.half = st <= 3;
+      }
+      const int np = emit_apply(R, y0, st == 1 ? 1 : 2, n, rels[st - 1], st == 1 || td,
+                                P.par_target, P.ws_parts + (size_t)(st - 1) * stride * P.tsz,
+                                st == 1 ? nullptr : &src);
+      if (st == 1) np1 = np;
+      else if (np != np1) fail(TENSO_EINVAL, "RK4 stages split into different parts");
+      np_prev = np;
+    }
+    CombineOp op{};
+    op.y0 = (double*)y0;
+    op.xin = ws(P.ws_xin);
+    op.acc = (double*)ws(P.ws_acc);
+    op.parts = ws(P.ws_parts);
+    op.n = n;
+    op.n_parts = np1;
+    op.stage = 6;
+    op.h = sign;  // multiplied by dt/2 at bind time
+    op.stage_stride = (long)stride;
+    const int oi = (int)G.combines.size();
+    G.combines.push_back(op);
+    const int tf = (int)G.ctiles.size();
+    for (long e = 0; e < n; e += 2048) G.ctiles.push_back({oi, 0, e, std::min(n, e + 2048)});
+    launch(LK_COMBINE, 0, oi, 1, tf, (int)G.ctiles.size() - tf);
   }
 
   void emit_env_down(int x) { emit_env(x, true, false); }
@@ -1989,6 +2053,11 @@ static void resolve(Program& G, void* state, void* ws, double dt, const double* 
     g.Y = res(g.Y, state, ws);
     g.drive = drive;
     g.drive_ld = drive_ld;
+    if (g.in_fp64 == 2) {  // the stage coefficient as the combine kernel forms it
+      g.xp = res((void*)g.xp, state, ws);
+      const double h = g.xp_s * 0.5 * dt;
+      g.xp_s = g.xp_half ? 0.5 * h : h;
+    }
   }
   for (auto& p : G.presums) {
     p.out = res(p.out, state, ws);
@@ -2117,7 +2186,7 @@ static Program merge_programs(std::vector<Program>& progs) {
     return (const TermRef*)tagp(TAG_TERM, (v & OFF_MASK) + off);
   };
   std::vector<size_t> pos(n, 0);
-  auto type_of = [](const LaunchRec& L) { return L.kind * 2 + L.in_fp64; };
+  auto type_of = [](const LaunchRec& L) { return L.kind * 4 + L.in_fp64; };
   while (true) {
     std::map<int, long> weight;
     for (size_t i = 0; i < n; ++i)
@@ -2131,8 +2200,8 @@ static Program merge_programs(std::vector<Program>& progs) {
         bw = kv.second;
         best = kv.first;
       }
-    LaunchRec ML{best / 2, best % 2, 0, 0, 0, 0, 0};
-    const int kind = best / 2;
+    LaunchRec ML{best / 4, best % 4, 0, 0, 0, 0, 0};
+    const int kind = best / 4;
     switch (kind) {
       case LK_APPLY: ML.first = (int)M.groups.size(); ML.tfirst = (int)M.atiles.size(); break;
       case LK_PRESUM: ML.first = (int)M.presums.size(); break;
@@ -2915,6 +2984,7 @@ static void vmf_prepare(tenso_plan* p, void* d_ws, double reg, hipStream_t s) {
          "(at most one factor of a term inside any non-root subtree) and bonds of at most 64");
   if (p->dev_vmf && p->vmf_ranks == p->tree.rank && p->vmf_reg == reg && p->vmf_ws == d_ws) return;
   p->par_target = 64;
+  p->fuse_stages = true;
   Program G;
   Builder b(*p, G);
   b.vmf_deriv(reg);
@@ -3276,6 +3346,7 @@ int tenso_plan_query(const tenso_tree* t, const tenso_gen* g, const tenso_plan_o
         build_step(*P, G);
       } else {  // one evaluation of the vmf derivative (a dopri5 substep takes six)
         P->par_target = 64;
+        P->fuse_stages = true;
         Builder b(*P, G);
         b.vmf_deriv(0.0);
       }
@@ -3398,13 +3469,16 @@ int tenso_step_fixed(tenso_plan* p, void* d_state, double t0, double dt, int n_s
       p->dev_init = std::make_unique<DevProgram>();
     }
     p->par_target = 64;
-    if (!p->prog_step || p->built_target != p->par_target || p->built_tile_work != p->tile_work) {
+    p->fuse_stages = true;
+    if (!p->prog_step || p->built_target != p->par_target || p->built_tile_work != p->tile_work ||
+        p->built_fuse != p->fuse_stages) {
       p->prog_step = std::make_unique<Program>();
       p->prog_init = std::make_unique<Program>();
       build_step(*p, *p->prog_step);
       build_init(*p, *p->prog_init);
       p->built_target = p->par_target;
       p->built_tile_work = p->tile_work;
+      p->built_fuse = p->fuse_stages;
       p->b_state = nullptr;
     }
     // the drive table's row length (4 n_steps + 1) is baked into the launch
@@ -3772,16 +3846,21 @@ static void batch_build(tenso_batch& B, hipStream_t s) {
   for (size_t i = 0; i < n; ++i) {
     tenso_plan& P = *B.plans[i];
     P.par_target = 4;  // the batch supplies the parallelism
+    // a batch is throughput-bound: a combine per RK4 stage costs less than
+    // staging every stage input from the previous stage's partial outputs
+    P.fuse_stages = false;
     // larger tiles in batches: fewer stagings of each term's operands (the
     // tile-size autotuner settles on this value for a 512-instance batch)
     if (!P.tile_work_set) P.tile_work = 64e6;
-    if (!P.prog_step || P.built_target != P.par_target || P.built_tile_work != P.tile_work) {
+    if (!P.prog_step || P.built_target != P.par_target || P.built_tile_work != P.tile_work ||
+        P.built_fuse != P.fuse_stages) {
       P.prog_step = std::make_unique<Program>();
       P.prog_init = std::make_unique<Program>();
       build_step(P, *P.prog_step);
       build_init(P, *P.prog_init);
       P.built_target = P.par_target;
       P.built_tile_work = P.tile_work;
+      P.built_fuse = P.fuse_stages;
       P.b_state = nullptr;
     }
     st[i] = *P.prog_step;

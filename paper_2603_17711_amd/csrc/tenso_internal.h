@@ -22,11 +22,11 @@ struct TermRef {
 // free index f = (p0, p1, p2) runs over F = P0*P1*P2 matrices X_f (d1 x d2).
 // Y (same view) receives sum_terms coef * A X_f B^T.
 struct ApplyGroup {
-  const void* X;       // input: FP64 master (in_fp64) or compute precision
+  const void* X;       // input: FP64 master (in_fp64 1 or 2) or compute precision (0)
   void* Y;             // output, compute precision
   const TermRef* terms;
   const double* drive; // drive table of the instance (nullable)
-  int in_fp64;
+  int in_fp64;         // 2: an RK4 stage input formed while staging (xp below)
   int n_terms;
   int d1, d2, P1, P2;
   int F;
@@ -34,7 +34,16 @@ struct ApplyGroup {
   int rel;             // stage time index relative to the step (0..4)
   int accumulate;      // 1: Y += result, 0: Y = result
   int per_term_out;    // 1: term m writes its own result to Y + m * F*d1*d2 (no sum)
-  int pad_;
+  int xp_half;         // in_fp64 2: xp_s is sign * h (0) or sign * h / 2 (1) before binding
+  // in_fp64 2: the input is (compute precision)(X + xp_s * k), X the FP64
+  // master and k the sum, in order, of the previous stage's xp_np partial
+  // outputs (compute precision, xp_n elements apart): the stage update of an
+  // RK4 sub-flow, formed while the input is staged instead of by a launch
+  const void* xp;
+  long xp_n;
+  int xp_np;
+  int pad2_;
+  double xp_s;
 };
 
 // Wavefronts of an apply workgroup, accumulator tiles per wavefront, and the
@@ -91,8 +100,11 @@ struct CombineOp {
   const void* parts;   // n_parts consecutive slabs of n elements
   long n;
   int n_parts;
-  int stage;           // 1..4; 0: y0 = sum of parts; 5: xin = sum of parts
+  int stage;           // 1..4; 0: y0 = sum of parts; 5: xin = sum of parts;
+                       // 6: y0 += h/6 (k1 + 2 k2 + 2 k3 + k4), k_s the sum of
+                       // stage s's parts, stage_stride elements after stage s-1's
   double h;            // sign * tau
+  long stage_stride;
 };
 
 // Householder QR (LAPACK geqr2/ung2r convention) of a core matricised as
