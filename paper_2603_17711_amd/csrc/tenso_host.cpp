@@ -420,6 +420,11 @@ struct tenso_plan {
   // combine per sub-flow) rather than with a combine per stage: fewer launches
   // on a latency-bound chain, more input traffic; batches turn it off
   bool fuse_stages = true;
+  // ... up to this many partial-output elements per stage (parts x core
+  // size): every contraction tile re-reads the parts of the slice it stages,
+  // which outgrows one combine pass on large cores (measured: cores of 4096
+  // elements in up to 8 parts gain, cores of 64000 in 5 parts lose)
+  long fuse_max_elems = 1L << 16;
   int built_target = -1;  // par_target the cached programs were built with
   bool built_fuse = true;  // fuse_stages the cached programs were built with
   double tile_work = 16e6;        // flops per apply tile
@@ -1542,10 +1547,13 @@ struct Builder {
       for (auto& s : g.sb) td |= s.first >= 0 && P.gen.terms[s.first].slot >= 0;
       for (auto& s : g.pair_terms) td |= s.first >= 0 && P.gen.terms[s.first].slot >= 0;
     }
-    if (!P.fuse_stages) {  // a combine per stage: the next input in xin
-      for (int st = 1; st <= 4; ++st) {
-        void* X = st == 1 ? y0 : ws(P.ws_xin);
-        int np = emit_apply(R, X, st == 1, n, rels[st - 1], st == 1 || td, P.par_target);
+    // stage 1 (input y0) leaves its partial outputs in the first part area
+    const int np1 = emit_apply(R, y0, 1, n, rels[0], 1, P.par_target);
+    if (!P.fuse_stages || (long)np1 * n > P.fuse_max_elems) {
+      // a combine per stage: the next input in xin
+      emit_combine(y0, n, np1, 1, sign);
+      for (int st = 2; st <= 4; ++st) {
+        int np = emit_apply(R, ws(P.ws_xin), 0, n, rels[st - 1], td, P.par_target);
         emit_combine(y0, n, np, st, sign);
       }
       return;
@@ -1554,21 +1562,17 @@ struct Builder {
     // from the first): the next stage's input y0 + c k_s is formed while its
     // contraction stages it, and one combine at the end applies the update
     const size_t stride = std::max<size_t>(1, P.parts_cap);  // elements
-    int np_prev = 0, np1 = 0;
-    for (int st = 1; st <= 4; ++st) {
+    int np_prev = np1;
+    for (int st = 2; st <= 4; ++st) {
       StageSrc src{};
-      if (st > 1) {
-        src.parts = ws(P.ws_parts + (size_t)(st - 2) * stride * P.tsz);
-        src.n = n;
-        src.np = np_prev;
-        src.sign = sign;
-        src.half = st <= 3;
-      }
-      const int np = emit_apply(R, y0, st == 1 ? 1 : 2, n, rels[st - 1], st == 1 || td,
-                                P.par_target, P.ws_parts + (size_t)(st - 1) * stride * P.tsz,
-                                st == 1 ? nullptr : &src);
-      if (st == 1) np1 = np;
-      else if (np != np1) fail(TENSO_EINVAL, "RK4 stages split into different parts");
+      src.parts = ws(P.ws_parts + (size_t)(st - 2) * stride * P.tsz);
+      src.n = n;
+      src.np = np_prev;
+      src.sign = sign;
+      src.half = st <= 3;
+      const int np = emit_apply(R, y0, 2, n, rels[st - 1], td, P.par_target,
+                                P.ws_parts + (size_t)(st - 1) * stride * P.tsz, &src);
+      if (np != np1) fail(TENSO_EINVAL, "RK4 stages split into different parts");
       np_prev = np;
     }
     CombineOp op{};
