@@ -224,6 +224,15 @@ struct LaunchRec {
 };
 enum { LK_APPLY, LK_PRESUM, LK_COMBINE, LK_QR, LK_ABSORB, LK_GRAM, LK_RHO, LK_REGINV, LK_VPROJ };
 
+// Elements per combine workgroup (256 threads, one element each), so that
+// loads of its elements' partial outputs are in flight together instead of
+// one element's round trip after another
+constexpr long kCombineTile = 256;
+// Core elements per absorb workgroup (the fibres of a tile times the leg):
+// short tiles for a single instance, whose chain of launches is latency-bound;
+// longer ones in a batch, where the workgroups of many instances fill the GPU
+inline int absorb_tile_elems(int par_target) { return par_target >= 64 ? 256 : 1024; }
+
 struct CombineTileH {
   int op;
   int pad;
@@ -1533,7 +1542,7 @@ struct Builder {
     int oi = (int)G.combines.size();
     G.combines.push_back(op);
     int tf = (int)G.ctiles.size();
-    for (long e = 0; e < n; e += 2048) G.ctiles.push_back({oi, 0, e, std::min(n, e + 2048)});
+    for (long e = 0; e < n; e += kCombineTile) G.ctiles.push_back({oi, 0, e, std::min(n, e + kCombineTile)});
     launch(LK_COMBINE, 0, oi, 1, tf, (int)G.ctiles.size() - tf);
   }
 
@@ -1588,7 +1597,7 @@ struct Builder {
     const int oi = (int)G.combines.size();
     G.combines.push_back(op);
     const int tf = (int)G.ctiles.size();
-    for (long e = 0; e < n; e += 2048) G.ctiles.push_back({oi, 0, e, std::min(n, e + 2048)});
+    for (long e = 0; e < n; e += kCombineTile) G.ctiles.push_back({oi, 0, e, std::min(n, e + kCombineTile)});
     launch(LK_COMBINE, 0, oi, 1, tf, (int)G.ctiles.size() - tf);
   }
 
@@ -1671,7 +1680,7 @@ struct Builder {
         op.stage = 5;
         const int oi = (int)G.combines.size();
         G.combines.push_back(op);
-        for (long e = 0; e < Pn; e += 2048) G.ctiles.push_back({oi, 0, e, std::min(Pn, e + 2048)});
+        for (long e = 0; e < Pn; e += kCombineTile) G.ctiles.push_back({oi, 0, e, std::min(Pn, e + kCombineTile)});
       }
       launch(LK_COMBINE, 0, cf, (int)chans.size(), tf, (int)G.ctiles.size() - tf);
     }
@@ -1819,7 +1828,7 @@ struct Builder {
     G.absorbs.push_back(a);
     int tf = (int)G.abtiles.size();
     int fibers = a.Ppre * a.Ppost;
-    int per = std::max(1, 2048 / a.n);
+    int per = std::max(1, absorb_tile_elems(P.par_target) / a.n);
     for (int f = 0; f < fibers; f += per) G.abtiles.push_back({ai, f, std::min(fibers, f + per)});
     launch(LK_ABSORB, 0, ai, 1, tf, (int)G.abtiles.size() - tf, absorb_lds(a.n, per));
   }
@@ -1974,7 +1983,7 @@ struct Builder {
       op.stage = 0;
       const int oi = (int)G.combines.size();
       G.combines.push_back(op);
-      for (long e = 0; e < n; e += 2048) G.ctiles.push_back({oi, 0, e, std::min(n, e + 2048)});
+      for (long e = 0; e < n; e += kCombineTile) G.ctiles.push_back({oi, 0, e, std::min(n, e + kCombineTile)});
     }
     launch(LK_COMBINE, 0, cf, t.n, ctf, (int)G.ctiles.size() - ctf);
     if (t.n == 1) return;
@@ -1992,7 +2001,7 @@ struct Builder {
       const int ai = (int)G.absorbs.size();
       G.absorbs.push_back(a);
       const int fibers = a.Ppost;
-      const int per = std::max(1, 2048 / a.n);
+      const int per = std::max(1, absorb_tile_elems(P.par_target) / a.n);
       for (int f = 0; f < fibers; f += per) G.abtiles.push_back({ai, f, std::min(fibers, f + per)});
       lds = std::max(lds, absorb_lds(a.n, per));
     }
