@@ -66,8 +66,9 @@ struct ErrNormOp {
   int pad_;
 };
 
-// Elements (complex) of one workgroup chunk of the segment kernels.
-constexpr int kVmfChunk = 2048;
+// Elements (complex) of one workgroup chunk of the segment kernels: one per
+// thread, so that a workgroup's loads are in flight together.
+constexpr int kVmfChunk = 256;
 
 hipError_t launch_reginv(const RegInvOp* ops, int n, hipStream_t s);
 hipError_t launch_vproj(const VProjOp* ops, int n, long max_elems, hipStream_t s);
