@@ -1346,6 +1346,10 @@ __global__ void __launch_bounds__(QR_NT) k_qr(const QrOp* __restrict__ ops) {
 
 // Launches with an op taller than kQrLdsMaxM: the blocked form (and the
 // column-by-column form in global memory above QR_MAX_M).
+// SPLIT: stop once R is written and leave Q to k_qr_formq, which forms its
+// columns in parallel from the reflectors in V and tau (not when V is the
+// core itself: then Q is formed here, over the reflectors).
+template <bool SPLIT>
 __global__ void __launch_bounds__(QR_NT) k_qr_blocked(const QrOp* __restrict__ ops) {
   const QrOp op = ops[blockIdx.x];
   if (op.m > QR_MAX_M) {
@@ -1402,8 +1406,9 @@ __global__ void __launch_bounds__(QR_NT) k_qr_blocked(const QrOp* __restrict__ o
   const int nbk = (k + QR_PB - 1) / QR_PB;
   int nbf = nbk;  // panels actually factored (fewer after an early exit)
   int par = 1;
+  const bool split = SPLIT && !in_place && k <= 64;  // k_qr_formq's grid covers 64 columns
 
-  for (int st = 0; st < 2 * nbk; ++st) {
+  for (int st = 0; st < (split ? nbk + 1 : 2 * nbk); ++st) {
     const bool fact = st < nbk;
     if (fact && st >= nbf) continue;  // past an early exit (uniform)
     const int bk = fact ? st : 2 * nbk - 1 - st;
@@ -1424,6 +1429,7 @@ __global__ void __launch_bounds__(QR_NT) k_qr_blocked(const QrOp* __restrict__ o
         if (op.transposeR) R[c * n + i] = v;
         else R[i * n + c] = v;
       }
+      if (split) return;  // V keeps the reflectors for k_qr_formq
       // Q is formed in V (column-major): column c starts as the unit column
       // e_c once its reflector has been read; the columns of the identity
       // blocks (past an early exit) start so now, after R has been read out
@@ -1670,6 +1676,187 @@ __global__ void __launch_bounds__(QR_NT) k_qr_blocked(const QrOp* __restrict__ o
       for (int u = 0; u < 16; ++u) {
         const int c = c0 + u;
         if (c < k) C[cb + c * ppost] = zmul(t[u], z2{ph[2 * c], ph[2 * c + 1]});
+      }
+    }
+  }
+}
+
+// Q of a factorisation that k_qr_blocked<true> left in V (reflectors below
+// the diagonal, R on and above it) and tau.  Column c of Q is H_0 ... H_c e_c
+// and needs no other column, so the columns are dealt to wavefronts of
+// several workgroups (grid: ops x groups of QR_NW columns).  A workgroup takes
+// the panels from that of its last column down to the first: the panel's
+// explicit reflectors go to LDS, thread 0 forms its T factor from their Gram
+// products, and every wavefront whose column has started (at its own panel,
+// as e_c) applies I - V T V^H to it, the column held in registers (row
+// lane + 64 q).  The finished columns go into the core with the phases that
+// make diag(R) real non-negative.  Panels whose taus are all zero (past an
+// early exit of the rank rule) are identities and are skipped.
+__global__ void __launch_bounds__(QR_NT) k_qr_formq(const QrOp* __restrict__ ops) {
+  const QrOp op = ops[blockIdx.x];
+  const int m = op.m, n = op.n, k = m < n ? m : n;
+  if (m > QR_MAX_M || op.V == op.C || k > 64) return;  // formed by the factoring kernel
+  const int c_lo = (int)blockIdx.y * QR_NW;
+  if (c_lo >= k) return;
+  const int c_hi = min(k, c_lo + QR_NW);  // this workgroup's columns [c_lo, c_hi)
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int c = c_lo + wave;  // this wavefront's column (none when c >= c_hi)
+  __shared__ double red[QR_NW][2 * QR_NPAIR];
+  __shared__ z2 S[QR_PB * QR_PB];
+  extern __shared__ char smem_raw[];
+  z2* __restrict__ L = reinterpret_cast<z2*>(smem_raw);  // QR_MAX_M x QR_PB, absolute rows
+  const gp<const z2> V = gmem(reinterpret_cast<const z2*>(op.V));
+  const gp<const z2> tau = gmem(reinterpret_cast<const z2*>(op.tau));
+  const gp<z2> C = gmem(reinterpret_cast<z2*>(op.C));
+  z2 x[QR_RPL];
+#pragma unroll
+  for (int q = 0; q < QR_RPL; ++q) x[q] = z2{0.0, 0.0};
+  for (int bk = (c_hi - 1) / QR_PB; bk >= 0; --bk) {
+    const int p = bk * QR_PB, pb = min(QR_PB, k - p);
+    z2 tp[QR_PB];
+    bool any = false;
+#pragma unroll
+    for (int i = 0; i < QR_PB; ++i) {
+      tp[i] = z2{0.0, 0.0};
+      if (i < pb) tp[i] = tau[p + i];
+      any = any || tp[i].r != 0.0 || tp[i].i != 0.0;
+    }
+    if (c < c_hi && c >= p && c < p + pb) {  // the column starts at its own panel
+#pragma unroll
+      for (int q = 0; q < QR_RPL; ++q) x[q] = z2{lane + 64 * q == c ? 1.0 : 0.0, 0.0};
+    }
+    if (!any) continue;  // identity reflectors (the same taus in every thread)
+    __syncthreads();     // the previous panel's LDS reads are done
+    double g[2 * QR_NPAIR];
+#pragma unroll
+    for (int e = 0; e < 2 * QR_NPAIR; ++e) g[e] = 0;
+#pragma unroll
+    for (int j = 0; j < QR_RPT; ++j) {
+      const int row = tid + QR_NT * j;  // < QR_MAX_M
+      z2 v[QR_PB];
+#pragma unroll
+      for (int i = 0; i < QR_PB; ++i) {
+        const int d = p + i;  // the reflector's unit entry
+        if (i >= pb || row < d || row >= m) v[i] = z2{0.0, 0.0};
+        else if (row == d) v[i] = z2{1.0, 0.0};
+        else v[i] = V[(long)d * m + row];
+        L[i * QR_MAX_M + row] = v[i];
+      }
+      int e = 0;
+#pragma unroll
+      for (int jc = 1; jc < QR_PB; ++jc)
+#pragma unroll
+        for (int ic = 0; ic < jc; ++ic, ++e) {  // y_ic,jc = v_ic^H v_jc
+          g[2 * e] = fma(v[ic].r, v[jc].r, fma(v[ic].i, v[jc].i, g[2 * e]));
+          g[2 * e + 1] = fma(v[ic].r, v[jc].i, fma(-v[ic].i, v[jc].r, g[2 * e + 1]));
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 2 * QR_NPAIR; ++e) g[e] = wave_sum(g[e]);
+    if (lane == 0) {
+#pragma unroll
+      for (int e = 0; e < 2 * QR_NPAIR; ++e) red[wave][e] = g[e];
+    }
+    __syncthreads();
+    if (tid == 0) {
+      // T (forward column-wise): T[j][j] = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] y[0:j, j]
+      z2 T[QR_PB][QR_PB];
+#pragma unroll
+      for (int i = 0; i < QR_PB; ++i)
+#pragma unroll
+        for (int j = 0; j < QR_PB; ++j) T[i][j] = z2{0.0, 0.0};
+      int e0 = 0;
+#pragma unroll
+      for (int j = 0; j < QR_PB; ++j) {
+        if (j < pb) {
+          z2 y[QR_PB];
+#pragma unroll
+          for (int l = 0; l < j; ++l) {
+            y[l] = z2{0.0, 0.0};
+            for (int w = 0; w < QR_NW; ++w) {
+              y[l].r += red[w][2 * (e0 + l)];
+              y[l].i += red[w][2 * (e0 + l) + 1];
+            }
+          }
+#pragma unroll
+          for (int i = 0; i < j; ++i) {
+            double sr = 0, si = 0;
+#pragma unroll
+            for (int l = i; l < j; ++l) {
+              const z2 pr = zmul(T[i][l], y[l]);
+              sr += pr.r;
+              si += pr.i;
+            }
+            const z2 pr = zmul(tp[j], z2{sr, si});
+            T[i][j] = z2{-pr.r, -pr.i};
+          }
+          T[j][j] = tp[j];
+        }
+        e0 += j;
+      }
+#pragma unroll
+      for (int i = 0; i < QR_PB; ++i)
+#pragma unroll
+        for (int l = 0; l < QR_PB; ++l) S[i * QR_PB + l] = T[i][l];
+    }
+    __syncthreads();
+    if (c < c_hi && c >= p) {
+      // w = V^H x, u = T w, x -= V u
+      const double2* __restrict__ Ll = reinterpret_cast<const double2*>(L) + lane;
+      double w[2 * QR_PB];
+#pragma unroll
+      for (int i = 0; i < 2 * QR_PB; ++i) w[i] = 0;
+#pragma unroll
+      for (int q = 0; q < QR_RPL; ++q) {
+#pragma unroll
+        for (int i = 0; i < QR_PB; ++i) {
+          const double2 t = Ll[i * QR_MAX_M + q * 64];
+          w[2 * i] = fma(t.x, x[q].r, fma(t.y, x[q].i, w[2 * i]));
+          w[2 * i + 1] = fma(t.x, x[q].i, fma(-t.y, x[q].r, w[2 * i + 1]));
+        }
+        if (q % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+      }
+#pragma unroll
+      for (int i = 0; i < 2 * QR_PB; ++i) w[i] = wave_sum(w[i]);
+      double u[2 * QR_PB];
+#pragma unroll
+      for (int i = 0; i < QR_PB; ++i) {
+        double ur = 0, ui = 0;
+#pragma unroll
+        for (int l = 0; l < QR_PB; ++l) {
+          const z2 t = S[i * QR_PB + l];
+          ur = fma(t.r, w[2 * l], fma(-t.i, w[2 * l + 1], ur));
+          ui = fma(t.r, w[2 * l + 1], fma(t.i, w[2 * l], ui));
+        }
+        u[2 * i] = ur;
+        u[2 * i + 1] = ui;
+      }
+#pragma unroll
+      for (int q = 0; q < QR_RPL; ++q) {
+        double ar = x[q].r, ai = x[q].i;
+#pragma unroll
+        for (int i = 0; i < QR_PB; ++i) {  // x -= v_i u_i
+          const double2 t = Ll[i * QR_MAX_M + q * 64];
+          ar = fma(-t.x, u[2 * i], fma(t.y, u[2 * i + 1], ar));
+          ai = fma(-t.x, u[2 * i + 1], fma(-t.y, u[2 * i], ai));
+        }
+        x[q] = z2{ar, ai};
+        if (q % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  }
+  if (c < c_hi) {
+    const z2 dd = V[(long)c * m + c];
+    const double a = sqrt(dd.r * dd.r + dd.i * dd.i);
+    const z2 ph{a > 0 ? dd.r / a : 1.0, a > 0 ? dd.i / a : 0.0};
+    const int ppost = op.Ppost, cstride = n * ppost;
+    const double pinv = 1.0 / ppost;
+#pragma unroll
+    for (int q = 0; q < QR_RPL; ++q) {
+      const int row = lane + 64 * q;
+      if (row < m) {
+        const int qq = qr_div(row, ppost, pinv);
+        C[qq * cstride + (row - qq * ppost) + c * ppost] = zmul(x[q], ph);
       }
     }
   }
@@ -2282,13 +2469,20 @@ hipError_t launch_qr(const QrOp* ops, int n, int form, hipStream_t s) {
   if (!attr) {
     (void)hipFuncSetAttribute((const void*)k_qr_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
                               kQrLdsElems * 16);
-    (void)hipFuncSetAttribute((const void*)k_qr_blocked,
+    (void)hipFuncSetAttribute((const void*)k_qr_blocked<true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, QR_MAX_M * QR_PB * 16);
+    (void)hipFuncSetAttribute((const void*)k_qr_formq,
                               hipFuncAttributeMaxDynamicSharedMemorySize, QR_MAX_M * QR_PB * 16);
     attr = true;
   }
   if (form == kQrFormLds) hipLaunchKernelGGL(k_qr_lds, dim3(n), dim3(QR_NT), kQrLdsElems * 16, s, ops);
   else if (form == kQrFormColumns) hipLaunchKernelGGL(k_qr, dim3(n), dim3(QR_NT), 0, s, ops);
-  else hipLaunchKernelGGL(k_qr_blocked, dim3(n), dim3(QR_NT), QR_MAX_M * QR_PB * 16, s, ops);
+  else {
+    hipLaunchKernelGGL(k_qr_blocked<true>, dim3(n), dim3(QR_NT), QR_MAX_M * QR_PB * 16, s, ops);
+    // Q: columns in groups of QR_NW (n <= 64 columns), after the factoring
+    hipLaunchKernelGGL(k_qr_formq, dim3(n, 64 / QR_NW), dim3(QR_NT), QR_MAX_M * QR_PB * 16, s,
+                       ops);
+  }
   return hipGetLastError();
 }
 
